@@ -1,0 +1,41 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def model_path():
+    from synth import default_model_file
+    return default_model_file()
+
+
+@pytest.fixture(scope="session")
+def omodel(model_path):
+    from oracle import load_model
+    return load_model(model_path)
+
+
+@pytest.fixture(scope="session")
+def water192():
+    from synth import config_system
+    return config_system("water192")
+
+
+@pytest.fixture(scope="session")
+def oracle_water192(omodel, water192):
+    from oracle.dp import evaluate
+    s = water192
+    return evaluate(omodel, s.coords, s.types, s.box)
