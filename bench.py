@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of one deep-potential MD step (neighbour lists -> E, F, virial) on one MI355X.
+
+A step is one dp_compute_device call on a synthetic protein-in-water-shaped
+box with coordinates already resident in HBM: cell-list neighbour search,
+environment matrix, type-embedded embedding net, two gated self-attention
+layers, descriptor contraction, fitting net, energy reduction, hand-written
+backward, force gather and virial.  `value` is atoms evaluated (E and F) per
+second of wall clock over the timed steps.
+
+The JSON line also carries the roofline of the dominant kernel (its average
+duration from HIP events recorded on the launch stream inside the library),
+the same path at the other precision, the force error of the run on sampled
+atoms against the FP64 oracle, and the oracle's own throughput on the host
+cores (a bounded sample of the same workload).
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision bf16|fp32]
+                       [--workload chain10k] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}     # MI355X dense MFMA peaks, FLOP/s
+HBM_PEAK = 8.0e12
+
+# Multiply-accumulates per atom with n neighbours (model sizes: embedding 25/50/100,
+# fused attention products 100x100, descriptor 100x16, fitting 1600-240-240-240-1).
+EMB = 25 * 50 + 50 * 100          # per neighbour, one embedding pass
+LAYER_FWD = (2 * 100 * 100, 2 * 100)          # (per n, per n^2): U = G Wqk, Y = H Wvo ; S = U G^T, H = A G
+LAYER_BWD = (2 * 100 * 100, 4 * 100)          # dH, dU Wqk^T ; dA, A^T dH, dS G, dS^T U
+FIT_FWD = 1600 * 240 + 2 * 240 * 240 + 240
+FIT_BWD = 2 * 240 * 240 + 240 * 1600
+
+
+def mac_desc_fwd(n):
+    return EMB * n + 2 * (LAYER_FWD[0] * n + LAYER_FWD[1] * n * n) + 400 * n + 1600 * 4
+
+
+def mac_desc_bwd_alg(n):
+    """Backward work proper: attention backward, embedding backward, contraction backward (no recompute)."""
+    return 2 * (LAYER_BWD[0] * n + LAYER_BWD[1] * n * n) + (50 * 100 + 25 * 50) * n + 800 * n + 1600 * 4 * 2
+
+
+def mac_desc_bwd_exec(n):
+    """As executed: the layer forwards and the embedding are recomputed inside the backward kernel."""
+    return mac_desc_bwd_alg(n) + 2 * (LAYER_FWD[0] * n + LAYER_FWD[1] * n * n) + EMB * n
+
+
+def cpu_baseline(system, budget_s=15.0):
+    """The FP64 oracle on the host: E_i and dE_i/dDelta for sampled centre atoms until the budget is spent."""
+    from synth import default_model_file
+    from oracle import load_model
+    from oracle.dp import evaluate_subset
+    from oracle.neighbors import neighbor_list_cells
+    m = load_model(default_model_file())
+    nl, nn, _ = neighbor_list_cells(system.coords, system.box, m.rc, m.sel)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(system.natoms)
+    done, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < system.natoms:
+        evaluate_subset(m, system.coords, system.types, system.box, order[done:done + 16], nl, nn)
+        done += 16
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    return {"value": done / dt, "unit": "atom-evals/s", "cores": 1, "blas_threads": threads, "kind": "oracle",
+            "sample": f"{done} random centre atoms of the same box (E_i and dE_i/dDelta_ij, float64 NumPy, "
+                      f"per-atom loop on one core), {dt:.1f} s; neighbour search excluded",
+            "host_cores_visible": len(os.sched_getaffinity(0))}
+
+
+def sampled_force_error(model_path, system, F, k=6, seed=1):
+    """Force RMSE / max of the GPU forces on k random atoms against the oracle (local evaluation)."""
+    from oracle import load_model
+    from oracle.dp import evaluate_subset
+    from oracle.neighbors import neighbor_list_cells
+    m = load_model(model_path)
+    nl, nn, _ = neighbor_list_cells(system.coords, system.box, m.rc, m.sel)
+    atoms = np.random.default_rng(seed).choice(system.natoms, size=k, replace=False)
+    errs = []
+    for i in atoms:
+        centres = [int(i)] + nl[i, :nn[i]].tolist()
+        _, nbrs, gs, _ = evaluate_subset(m, system.coords, system.types, system.box, centres, nl, nn)
+        f = gs[0].sum(0)
+        for c, js, g in zip(centres[1:], nbrs[1:], gs[1:]):
+            f -= g[np.nonzero(js == i)[0][0]]
+        errs.append(F[i] - f)
+    e = np.array(errs)
+    return float(np.sqrt(np.mean(e ** 2))), float(np.max(np.abs(e)))
+
+
+def time_path(model, X, T, box, F, V, E, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        model.compute_device(X, T, box, forces=F, virial=V, energy=E)
+    torch.cuda.synchronize()
+    model.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        model.compute_device(X, T, box, forces=F, virial=V, energy=E)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = model.profile_read()
+    model.profile(False)
+    return dt, prof
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--workload", default="chain10k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2602_02234_amd import Model
+    from synth import config_system, default_model_file
+
+    dev = torch.device("cuda:0")
+    system = config_system(args.workload)
+    N = system.natoms
+    path = default_model_file()
+    X = torch.tensor(system.coords, dtype=torch.float64, device=dev).contiguous()
+    T = torch.tensor(system.types, dtype=torch.int32, device=dev).contiguous()
+    F = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    V = torch.empty(9, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    box = system.box
+
+    results = {}
+    precs = [args.precision] + ([] if args.no_compare else [p for p in ("bf16", "fp32") if p != args.precision])
+    nnei = None
+    for prec in precs:
+        model = Model(path, precision=prec)
+        if nnei is None:
+            _, nnei, _ = model.neighbors(system.coords, box)
+        steps = args.steps if prec == args.precision else max(3, args.steps // 4)
+        dt, prof = time_path(model, X, T, box, F, V, E, steps, args.warmup)
+        f_rmse, f_max = sampled_force_error(path, system, F.cpu().numpy())
+        results[prec] = dict(dt=dt, steps=steps, prof=prof, f_rmse=f_rmse, f_max=f_max, E=float(E.item()))
+        print(f"[bench] {prec}: {steps} steps in {dt:.3f} s -> {N * steps / dt:.4g} atom-evals/s; "
+              f"sampled force RMSE {f_rmse:.2e}", file=sys.stderr, flush=True)
+        model.close()
+
+    r = results[args.precision]
+    value = N * r["steps"] / r["dt"]
+    n = nnei.astype(np.float64)
+    alg = {
+        "descriptor_fwd": 2.0 * float(np.sum(mac_desc_fwd(n))),
+        "fitting": 2.0 * N * (FIT_FWD + FIT_BWD),
+        "descriptor_bwd": 2.0 * float(np.sum(mac_desc_bwd_alg(n))),
+    }
+    executed_bwd = 2.0 * float(np.sum(mac_desc_bwd_exec(n)))
+    prof = r["prof"]
+    avg = {k: (ms / c if c else 0.0) for k, (ms, c) in prof.items()}
+    dom = max(("descriptor_fwd", "fitting", "descriptor_bwd"), key=lambda k: avg[k])
+    achieved = alg[dom] / (avg[dom] * 1e-3)
+    step_alg = sum(alg.values())
+    out = {
+        "metric": "atom-evals/s (E+F)",
+        "value": value,
+        "unit": "atom-evals/s",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["dt"] / r["steps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: seeded solvated chain, {N} atoms, periodic cubic "
+                               f"{system.box[0, 0]:.2f} A box, rc 6 A, sel 120; energy+forces+virial per step",
+                   "precision_path": args.precision, "natoms": N, "mean_neighbors": float(n.mean())},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "avg_ms": avg[dom], "alg_flop_per_launch": alg[dom],
+                     "executed_flop_per_launch": executed_bwd if dom == "descriptor_bwd" else alg[dom]},
+        "step_roofline": {"alg_flop_per_step": step_alg,
+                          "frac": step_alg / (r["dt"] / r["steps"]) / PEAK[args.precision]},
+        "phase_ms": avg,
+        "accuracy": {"force_rmse_sampled": r["f_rmse"], "force_max_sampled": r["f_max"], "unit": "eV/A"},
+    }
+    for prec in precs[1:]:
+        o = results[prec]
+        out[f"{prec}_value"] = N * o["steps"] / o["dt"]
+        out[f"{prec}_ms_per_step"] = 1e3 * o["dt"] / o["steps"]
+        out[f"{prec}_force_rmse_sampled"] = o["f_rmse"]
+        out[f"{prec}_phase_ms"] = {k: (ms / c if c else 0.0) for k, (ms, c) in o["prof"].items()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(system)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,126 @@
+/*
+ * dp.h -- C ABI of the MI355X (gfx950) deep-potential energy/force/virial library.
+ *
+ * The operation: for one configuration of atoms (the atom group an MD engine
+ * hands to the potential each step -- positions, types, periodic box; paper,
+ * Section III), evaluate the attention-based deep potential (Section II: a
+ * type-embedded per-neighbour embedding net, self-attention layers that update
+ * that representation residually, a fitting net giving each atom's energy,
+ * E = sum of atomic energies) and its forces F = -dE/dx (Section II) and
+ * virial, using neighbour lists within the model cutoff over periodic
+ * boundaries (Sections I, II, IV).
+ *
+ * Conventions
+ *   Units: Angstrom, eV, eV/Angstrom.  coords are [natoms][3] row-major float64;
+ *   types are int32 in [0, ntypes); box is 3 row vectors [3][3] float64 and must
+ *   be orthorhombic with every edge >= 2 * rc, or NULL for open boundaries.
+ *   forces [natoms][3] float64; virial [3][3] row-major float64,
+ *   Xi_ab = -sum_i sum_{j in N(i)} Delta_ij,a dE/dDelta_ij,b (Delta_ij = x_j - x_i, minimum image).
+ *   atom_energy [natoms] float64, may be NULL.
+ * Ownership
+ *   The caller owns every input and output buffer; calls borrow them for their
+ *   duration only.  A dp_model owns its device weights and a grow-only device
+ *   workspace: after the first call at a given natoms no further device
+ *   allocation happens for natoms <= that size.  A dp_model is not thread-safe.
+ * Errors
+ *   Every int-returning call returns DP_OK (0), a positive warning (outputs
+ *   valid but flagged) or a negative error (outputs untouched).  dp_last_error()
+ *   gives a thread-local human-readable detail of the last failure.
+ */
+#ifndef DP_MI355X_H
+#define DP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dp_model dp_model;
+
+/* Arithmetic of the dense products (embedding, attention, fitting).  DP_FP32:
+ * float32 operands, float32 accumulation.  DP_BF16: bfloat16 operands (round to
+ * nearest even) with float32 accumulation; environment, softmax, LayerNorm,
+ * tanh, descriptor contraction and force assembly stay float32 in both. */
+enum { DP_FP32 = 0, DP_BF16 = 1 };
+
+enum {
+  DP_OK = 0,
+  DP_WARN_SEL_OVERFLOW = 1, /* some atom had more than sel neighbours; the sel
+                               nearest (ties by index) were kept               */
+  DP_ERR_ARG = -1,          /* NULL pointer, natoms < 1, bad precision/device  */
+  DP_ERR_MODEL_FILE = -2,   /* unreadable or malformed model file             */
+  DP_ERR_TYPE = -3,         /* an atom type outside [0, ntypes)               */
+  DP_ERR_BOX = -4,          /* non-orthorhombic box or an edge < 2 rc         */
+  DP_ERR_OVERLAP = -5,      /* two atoms at distance 0                        */
+  DP_ERR_NONFINITE = -6,    /* NaN or infinite coordinate or box              */
+  DP_ERR_OOM = -7,          /* device allocation failed                       */
+  DP_ERR_TOO_LARGE = -8,    /* natoms beyond the library limit, or more than
+                               DP_MAX_CANDIDATES atoms within rc of one atom  */
+  DP_ERR_HIP = -9,          /* a HIP runtime call failed                      */
+  DP_ERR_TIMEOUT = -10
+};
+
+#define DP_MAX_CANDIDATES 512
+
+/* Load a model file (format: 128-byte header 'DPAMDv01' + float64 arrays) onto
+ * HIP device `device`, converting the weights to `precision` (DP_FP32 or
+ * DP_BF16).  On success *out owns the model; free it with dp_model_free. */
+int dp_model_load(const char *path, int precision, int device, dp_model **out);
+void dp_model_free(dp_model *m);
+
+/* Cutoff rc (Angstrom), neighbour capacity sel, number of atom types. Any
+ * output pointer may be NULL. */
+int dp_model_info(const dp_model *m, double *rc, int *sel, int *ntypes);
+
+/* Energy, forces and virial of one configuration; host buffers, synchronous.
+ * energy: 1 double; forces: [natoms][3]; virial: [3][3]; atom_energy: [natoms]
+ * or NULL.  forces and virial may be NULL to skip the backward pass. */
+int dp_compute(dp_model *m, int64_t natoms, const double *coords, const int32_t *types,
+               const double *box, double *energy, double *forces, double *virial,
+               double *atom_energy);
+
+/* Same on device buffers, enqueued on the HIP stream `hip_stream` (NULL = the
+ * null stream).  box_host is a host pointer (or NULL).  d_energy: 1 double,
+ * d_forces [natoms][3], d_virial [9], d_atom_energy [natoms] (or NULL); d_forces
+ * and d_virial may both be NULL to run the energy pass only (see
+ * dp_backward_device).  Inputs are validated on the device; the call waits for
+ * the stream once at the end to read the status word, so results are ready on
+ * return. */
+int dp_compute_device(dp_model *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
+                      const double *box_host, double *d_energy, double *d_forces, double *d_virial,
+                      double *d_atom_energy, void *hip_stream);
+
+/* After an energy-only dp_compute_device on this model (and no other call in
+ * between), run the hand-written backward pass: d_grad_coords[natoms][3] =
+ * grad_energy * dE/dx, where grad_energy is one double on the device.
+ * d_virial (9 doubles, or NULL) receives the virial scaled by grad_energy. */
+int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_coords,
+                       double *d_virial, void *hip_stream);
+
+/* Neighbour lists as the library builds them: nlist [natoms][sel] int32 sorted
+ * ascending per atom and padded with -1, nnei [natoms], *overflow = number of
+ * atoms whose list was truncated to sel.  Host buffers, synchronous. */
+int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const double *box,
+                       int32_t *nlist, int32_t *nnei, int64_t *overflow);
+
+/* Per-phase device timing with HIP events recorded on each call's stream.
+ * enable != 0 clears and starts accumulating, 0 stops.  dp_profile_read fills,
+ * for up to `max` phases, the summed milliseconds and the number of calls:
+ * phase 0 neighbour lists, 1 descriptor forward, 2 fitting net, 3 energy
+ * reduction, 4 descriptor backward, 5 forces and virial.  Returns the number
+ * of phases (DP_NPHASES). */
+#define DP_NPHASES 6
+int dp_profile_enable(dp_model *m, int enable);
+int dp_profile_read(const dp_model *m, double *ms, int64_t *calls, int max);
+
+/* Static description of a status code; never NULL. */
+const char *dp_status_string(int status);
+/* Thread-local detail of the last failure in this thread ("" if none). */
+const char *dp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DP_MI355X_H */

@@ -1,0 +1,168 @@
+"""Python surface over the C ABI: a model handle, host and device evaluation,
+and a ``torch.autograd.Function`` whose backward is the library's hand-written
+backward pass.  PyTorch provides device memory and the stream only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import DP_BF16, DP_FP32, check
+
+_PREC = {"fp32": DP_FP32, "bf16": DP_BF16}
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _box9(box):
+    if box is None:
+        return None
+    b = np.asarray(box, dtype=np.float64)
+    if b.shape == (3,):
+        b = np.diag(b)
+    return np.ascontiguousarray(b.reshape(3, 3))
+
+
+class Model:
+    """A model file loaded onto one GPU in one precision ("fp32" or "bf16")."""
+
+    def __init__(self, path: str, precision: str = "fp32", device: int = 0):
+        lib = _lib.load()
+        h = C.c_void_p()
+        check(lib.dp_model_load(path.encode(), _PREC[precision], device, C.byref(h)), "dp_model_load")
+        self._h = h
+        self.precision = precision
+        self.device = device
+        rc, sel, nt = C.c_double(), C.c_int(), C.c_int()
+        check(lib.dp_model_info(h, C.byref(rc), C.byref(sel), C.byref(nt)), "dp_model_info")
+        self.rc, self.sel, self.ntypes = rc.value, sel.value, nt.value
+        self.last_status = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().dp_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- host buffers
+    def compute(self, coords, types, box=None, forces: bool = True, atom_energy: bool = False):
+        """E (eV), F [N][3] (eV/A), virial [3][3] (eV) and optionally E_i, from host arrays."""
+        X = np.ascontiguousarray(coords, dtype=np.float64)
+        T = np.ascontiguousarray(types, dtype=np.int32)
+        n = X.shape[0]
+        E = np.zeros(1)
+        F = np.zeros((n, 3)) if forces else None
+        V = np.zeros((3, 3)) if forces else None
+        AE = np.zeros(n) if atom_energy else None
+        b = _box9(box)
+        st = _lib.load().dp_compute(self._h, n, _ptr(X), _ptr(T), _ptr(b), _ptr(E), _ptr(F), _ptr(V), _ptr(AE))
+        self.last_status = check(st, "dp_compute")
+        out = {"E": float(E[0])}
+        if forces:
+            out["F"], out["virial"] = F, V
+        if atom_energy:
+            out["E_i"] = AE
+        return out
+
+    def neighbors(self, coords, box=None):
+        X = np.ascontiguousarray(coords, dtype=np.float64)
+        n = X.shape[0]
+        nl = np.zeros((n, self.sel), dtype=np.int32)
+        nn = np.zeros(n, dtype=np.int32)
+        ov = C.c_int64()
+        b = _box9(box)
+        st = _lib.load().dp_debug_neighbors(self._h, n, _ptr(X), _ptr(b), _ptr(nl), _ptr(nn), C.byref(ov))
+        self.last_status = check(st, "dp_debug_neighbors")
+        return nl, nn, int(ov.value)
+
+    # ---------------------------------------------------------------- timing
+    PHASES = ("neighbors", "descriptor_fwd", "fitting", "energy_reduce", "descriptor_bwd", "forces_virial")
+
+    def profile(self, enable: bool = True):
+        check(_lib.load().dp_profile_enable(self._h, 1 if enable else 0), "dp_profile_enable")
+
+    def profile_read(self):
+        """{phase: (total ms, calls)} accumulated since profile(True)."""
+        ms = np.zeros(8)
+        calls = np.zeros(8, dtype=np.int64)
+        k = _lib.load().dp_profile_read(self._h, _ptr(ms), _ptr(calls), 8)
+        return {self.PHASES[i]: (float(ms[i]), int(calls[i])) for i in range(min(k, len(self.PHASES)))}
+
+    # ---------------------------------------------------------------- device buffers
+    def compute_device(self, coords, types, box=None, forces=None, virial=None, energy=None, atom_energy=None,
+                       stream=None):
+        """Evaluate on torch CUDA tensors (float64 coords [N][3], int32 types [N]); outputs are written in place.
+
+        Returns the energy tensor [1].  ``forces``/``virial`` None (both) runs the energy pass only.
+        """
+        import torch
+        n = coords.shape[0]
+        assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
+        assert types.is_cuda and types.dtype == torch.int32 and types.is_contiguous()
+        if energy is None:
+            energy = torch.empty(1, dtype=torch.float64, device=coords.device)
+        s = stream if stream is not None else torch.cuda.current_stream(coords.device).cuda_stream
+        b = _box9(box)
+
+        def dp(t):
+            return C.c_void_p(t.data_ptr()) if t is not None else None
+
+        st = _lib.load().dp_compute_device(self._h, n, dp(coords), dp(types), _ptr(b), dp(energy), dp(forces),
+                                           dp(virial), dp(atom_energy), C.c_void_p(s))
+        self.last_status = check(st, "dp_compute_device")
+        return energy
+
+    def backward_device(self, grad_energy, grad_coords, virial=None, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(grad_coords.device).cuda_stream
+        st = _lib.load().dp_backward_device(self._h, C.c_void_p(grad_energy.data_ptr()),
+                                            C.c_void_p(grad_coords.data_ptr()),
+                                            C.c_void_p(virial.data_ptr()) if virial is not None else None,
+                                            C.c_void_p(s))
+        check(st, "dp_backward_device")
+
+
+def _autograd_function():
+    import torch
+
+    class DPEnergy(torch.autograd.Function):
+        """E = DPEnergy.apply(coords, types, model, box); dE/dcoords from the library's backward kernels."""
+
+        @staticmethod
+        def forward(ctx, coords, types, model, box):
+            x = coords.detach().contiguous()
+            E = model.compute_device(x, types.contiguous(), box)
+            ctx.model = model
+            ctx.shape = x.shape
+            ctx.save_for_backward(x, types)
+            return E.reshape(())
+
+        @staticmethod
+        def backward(ctx, gE):
+            x, types = ctx.saved_tensors
+            g = torch.empty(ctx.shape, dtype=torch.float64, device=x.device)
+            gE = gE.detach().reshape(1).to(torch.float64).contiguous()
+            ctx.model.backward_device(gE, g)
+            return g, None, None, None
+
+    return DPEnergy
+
+
+_DPEnergy = None
+
+
+def energy(model: Model, coords, types, box=None):
+    """Differentiable total energy of torch CUDA coordinates: forces = -autograd.grad(E, coords)."""
+    global _DPEnergy
+    if _DPEnergy is None:
+        _DPEnergy = _autograd_function()
+    return _DPEnergy.apply(coords, types, model, box)

@@ -1,0 +1,626 @@
+// C ABI of the library (declared in include/dp.h): model loading, argument
+// validation, the device workspace and the order of the kernels of one step.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "../../include/dp.h"
+#include "dp_internal.h"
+
+namespace dp {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &s) { g_last_error = s; }
+
+namespace {
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+      return e_ == hipErrorOutOfMemory ? DP_ERR_OOM : DP_ERR_HIP;                          \
+    }                                                                                      \
+  } while (0)
+
+uint16_t to_bf16(float f) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct HostModel {
+  int ntypes, tebd, e1, e2, M_, natt, d, m2, fh, nfh, sel;
+  double rc, rcs, eps, fscale;
+  std::vector<double> TE, W1, b1, W2, b2, W3, b3, F1, c1, F2, c2, F3, c3, F4, c4, ebias;
+  std::vector<double> WQ[NATTN], WK[NATTN], WV[NATTN], WO[NATTN], gam[NATTN], bet[NATTN];
+};
+
+int read_model(const char *path, HostModel &h) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) {
+    set_error(std::string("cannot open model file ") + path);
+    return DP_ERR_MODEL_FILE;
+  }
+  std::vector<char> raw((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  if (raw.size() < 128 || std::memcmp(raw.data(), "DPAMDv01", 8) != 0) {
+    set_error("model file: bad magic or short header");
+    return DP_ERR_MODEL_FILE;
+  }
+  int32_t iv[16];
+  std::memcpy(iv, raw.data() + 8, 64);
+  double dv[4];
+  std::memcpy(dv, raw.data() + 72, 32);
+  if (iv[0] != 1) {
+    set_error("model file: unsupported version");
+    return DP_ERR_MODEL_FILE;
+  }
+  h.ntypes = iv[1]; h.tebd = iv[2]; h.e1 = iv[3]; h.e2 = iv[4]; h.M_ = iv[5]; h.natt = iv[6]; h.d = iv[7];
+  h.m2 = iv[8]; h.fh = iv[9]; h.nfh = iv[10]; h.sel = iv[11];
+  h.rc = dv[0]; h.rcs = dv[1]; h.eps = dv[2]; h.fscale = dv[3];
+  if (h.ntypes != NTYPES || h.tebd != TEBD || h.e1 != E1 || h.e2 != E2 || h.M_ != M || h.natt != NATTN ||
+      h.d != DATTN || h.m2 != M2 || h.fh != FH || h.nfh != 3 || h.sel != SEL) {
+    set_error("model file: dimensions differ from the compiled kernels");
+    return DP_ERR_MODEL_FILE;
+  }
+  if (!(h.rc > h.rcs && h.rcs > 0 && h.eps > 0)) {
+    set_error("model file: bad rc/rcs/eps");
+    return DP_ERR_MODEL_FILE;
+  }
+  size_t off = 128;
+  bool bad = false;
+  auto take = [&](std::vector<double> &v, size_t cnt) {
+    if (off + 8 * cnt > raw.size()) { bad = true; return; }
+    v.resize(cnt);
+    std::memcpy(v.data(), raw.data() + off, 8 * cnt);
+    off += 8 * cnt;
+  };
+  take(h.TE, NTYPES * TEBD);
+  take(h.W1, (1 + 2 * TEBD) * E1); take(h.b1, E1);
+  take(h.W2, E1 * E2); take(h.b2, E2);
+  take(h.W3, E2 * M); take(h.b3, M);
+  for (int a = 0; a < NATTN; ++a) {
+    take(h.WQ[a], M * DATTN); take(h.WK[a], M * DATTN); take(h.WV[a], M * DATTN); take(h.WO[a], DATTN * M);
+    take(h.gam[a], M); take(h.bet[a], M);
+  }
+  take(h.F1, ND * FH); take(h.c1, FH);
+  take(h.F2, FH * FH); take(h.c2, FH);
+  take(h.F3, FH * FH); take(h.c3, FH);
+  take(h.F4, FH); take(h.c4, 1);
+  take(h.ebias, NTYPES);
+  if (bad || off != raw.size()) {
+    set_error("model file: size does not match its header");
+    return DP_ERR_MODEL_FILE;
+  }
+  return DP_OK;
+}
+
+// Device image of the weights: float tables + GEMM operands in T, 256-byte aligned pieces.
+struct Packer {
+  std::vector<unsigned char> bytes;
+  size_t add(const void *p, size_t n) {
+    size_t o = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(o + n);
+    std::memcpy(bytes.data() + o, p, n);
+    return o;
+  }
+  size_t addf(const std::vector<float> &v) { return add(v.data(), v.size() * 4); }
+  size_t addT(const std::vector<float> &v, int prec) {
+    if (prec == DP_FP32) return addf(v);
+    std::vector<uint16_t> b(v.size());
+    for (size_t i = 0; i < v.size(); ++i) b[i] = to_bf16(v[i]);
+    return add(b.data(), b.size() * 2);
+  }
+};
+
+std::vector<float> tof(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+// [rows][cols] -> [cols][rows]
+std::vector<float> transpose(const std::vector<double> &v, int rows, int cols) {
+  std::vector<float> o((size_t)rows * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) o[(size_t)c * rows + r] = (float)v[(size_t)r * cols + c];
+  return o;
+}
+
+template <typename T>
+void bind(Weights<T> &w, const unsigned char *base, const std::vector<size_t> &o, float c4) {
+  int k = 0;
+  auto F = [&]() { return (const float *)(base + o[k++]); };
+  auto P = [&]() { return (const T *)(base + o[k++]); };
+  w.w1s = F(); w.Bt = F();
+  w.W2T = P(); w.W2 = P(); w.b2 = F();
+  w.W3T = P(); w.W3 = P(); w.b3 = F();
+  for (int a = 0; a < NATTN; ++a) {
+    w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P(); w.gamma[a] = F(); w.beta[a] = F();
+  }
+  w.F1T = P(); w.F1 = P(); w.F2T = P(); w.F2 = P(); w.F3T = P(); w.F3 = P();
+  w.c1 = F(); w.c2 = F(); w.c3 = F(); w.F4 = F();
+  w.c4 = c4;
+  w.ebias = F();
+}
+
+int build_weights(dp_model *m, const HostModel &h) {
+  const int pr = m->prec;
+  Packer pk;
+  std::vector<size_t> o;
+  // first embedding layer: s column, and the type part folded with the bias
+  std::vector<float> w1s(E1), Bt(NTYPES * NTYPES * E1);
+  for (int e = 0; e < E1; ++e) w1s[e] = (float)h.W1[e];
+  for (int ti = 0; ti < NTYPES; ++ti)
+    for (int tj = 0; tj < NTYPES; ++tj)
+      for (int e = 0; e < E1; ++e) {
+        double acc = h.b1[e];
+        for (int q = 0; q < TEBD; ++q) {
+          acc += h.TE[tj * TEBD + q] * h.W1[(1 + q) * E1 + e];
+          acc += h.TE[ti * TEBD + q] * h.W1[(1 + TEBD + q) * E1 + e];
+        }
+        Bt[(ti * NTYPES + tj) * E1 + e] = (float)acc;
+      }
+  o.push_back(pk.addf(w1s));
+  o.push_back(pk.addf(Bt));
+  o.push_back(pk.addT(transpose(h.W2, E1, E2), pr));
+  o.push_back(pk.addT(tof(h.W2), pr));
+  o.push_back(pk.addf(tof(h.b2)));
+  o.push_back(pk.addT(transpose(h.W3, E2, M), pr));
+  o.push_back(pk.addT(tof(h.W3), pr));
+  o.push_back(pk.addf(tof(h.b3)));
+  const double isd = 1.0 / std::sqrt((double)DATTN);
+  for (int a = 0; a < NATTN; ++a) {
+    std::vector<double> qk((size_t)M * M), vo((size_t)M * M);
+    for (int r = 0; r < M; ++r)
+      for (int c = 0; c < M; ++c) {
+        double s1 = 0, s2 = 0;
+        for (int q = 0; q < DATTN; ++q) {
+          s1 += h.WQ[a][(size_t)r * DATTN + q] * h.WK[a][(size_t)c * DATTN + q];
+          s2 += h.WV[a][(size_t)r * DATTN + q] * h.WO[a][(size_t)q * M + c];
+        }
+        qk[(size_t)r * M + c] = s1 * isd;
+        vo[(size_t)r * M + c] = s2;
+      }
+    o.push_back(pk.addT(transpose(qk, M, M), pr));
+    o.push_back(pk.addT(tof(qk), pr));
+    o.push_back(pk.addT(transpose(vo, M, M), pr));
+    o.push_back(pk.addT(tof(vo), pr));
+    o.push_back(pk.addf(tof(h.gam[a])));
+    o.push_back(pk.addf(tof(h.bet[a])));
+  }
+  o.push_back(pk.addT(transpose(h.F1, ND, FH), pr));
+  o.push_back(pk.addT(tof(h.F1), pr));
+  o.push_back(pk.addT(transpose(h.F2, FH, FH), pr));
+  o.push_back(pk.addT(tof(h.F2), pr));
+  o.push_back(pk.addT(transpose(h.F3, FH, FH), pr));
+  o.push_back(pk.addT(tof(h.F3), pr));
+  o.push_back(pk.addf(tof(h.c1)));
+  o.push_back(pk.addf(tof(h.c2)));
+  o.push_back(pk.addf(tof(h.c3)));
+  o.push_back(pk.addf(tof(h.F4)));
+  o.push_back(pk.addf(tof(h.ebias)));
+  HIP_TRY(hipMalloc(&m->wbuf, pk.bytes.size()));
+  HIP_TRY(hipMemcpy(m->wbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
+  const float c4 = (float)h.c4[0];
+  bind(m->wf, (const unsigned char *)m->wbuf, o, c4);
+  bind(m->wb, (const unsigned char *)m->wbuf, o, c4);
+  return DP_OK;
+}
+
+void free_ws(Workspace &ws) {
+  void *ps[] = {ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev,
+                ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart, ws.red, ws.grid, ws.flags, ws.gE};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  if (ws.flags_host) (void)hipHostFree(ws.flags_host);
+  ws = Workspace{};
+}
+
+int ensure_ws(dp_model *m, int64_t n) {
+  Workspace &ws = m->ws;
+  if (!ws.flags) {
+    HIP_TRY(hipMalloc(&ws.flags, 4 * sizeof(unsigned)));
+    HIP_TRY(hipHostMalloc(&ws.flags_host, 4 * sizeof(unsigned), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&ws.cell_count, (MAX_CELLS + 1) * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.cell_start, (MAX_CELLS + 1) * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.cell_cursor, MAX_CELLS * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.grid, sizeof(Grid)));
+    HIP_TRY(hipMalloc(&ws.red, 64 * sizeof(double)));
+    HIP_TRY(hipMalloc(&ws.gE, sizeof(double)));
+  }
+  if (n <= ws.cap) return DP_OK;
+  int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
+  void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  ws.cap = 0;
+  HIP_TRY(hipMalloc(&ws.cell_of, cap * sizeof(int)));
+  HIP_TRY(hipMalloc(&ws.cell_atoms, cap * sizeof(int)));
+  HIP_TRY(hipMalloc(&ws.nlist, cap * SEL * sizeof(int)));
+  HIP_TRY(hipMalloc(&ws.nnei, cap * sizeof(int)));
+  HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
+  HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
+  HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
+  HIP_TRY(hipMalloc(&ws.D, cap * (size_t)ND * sizeof(float)));
+  HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(float)));
+  HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
+  HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
+  ws.cap = cap;
+  return DP_OK;
+}
+
+constexpr int64_t MAX_ATOMS = 1 << 24;
+
+int check_box(const dp_model *m, const double *box, Grid &g) {
+  std::memset(&g, 0, sizeof(g));
+  if (!box) return DP_OK;
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(box[k])) {
+      set_error("box has a non-finite entry");
+      return DP_ERR_NONFINITE;
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      if (a != b && box[3 * a + b] != 0.0) {
+        set_error("box must be orthorhombic (off-diagonal entries exactly 0)");
+        return DP_ERR_BOX;
+      }
+  g.periodic = 1;
+  int nct = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double L = box[4 * a];
+    if (!(L >= 2.0 * m->rc)) {
+      set_error("every box edge must be at least 2 rc");
+      return DP_ERR_BOX;
+    }
+    int nc = (int)std::floor(L / (m->rc * (1.0 + 1e-9)));
+    nc = std::max(1, std::min(nc, MAX_CELLS_PER_DIM));
+    g.L[a] = L;
+    g.invL[a] = 1.0 / L;
+    g.nc[a] = nc;
+    g.cw[a] = L / nc;
+    g.icw[a] = nc / L;
+    nct *= nc;
+  }
+  g.ncells = nct;
+  return DP_OK;
+}
+
+int flags_status(unsigned f) {
+  if (f & FLAG_NONFINITE) { set_error("non-finite coordinate"); return DP_ERR_NONFINITE; }
+  if (f & FLAG_TYPE) { set_error("atom type outside [0, ntypes)"); return DP_ERR_TYPE; }
+  if (f & FLAG_OVERLAP) { set_error("two atoms at distance 0"); return DP_ERR_OVERLAP; }
+  if (f & FLAG_TOO_DENSE) { set_error("more than DP_MAX_CANDIDATES neighbours within rc"); return DP_ERR_TOO_LARGE; }
+  return DP_OK;
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// Event k is recorded before phase k (k = 0..5) and after the last phase.
+void mark(dp_model *m, int k, hipStream_t st) {
+  if (m->prof) (void)hipEventRecord(m->ev[k], st);
+}
+void collect(dp_model *m, int last) {
+  if (!m->prof) return;
+  for (int k = 0; k < last; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m->ev[k], m->ev[k + 1]) == hipSuccess) {
+      m->prof_ms[k] += ms;
+      m->prof_calls[k] += 1;
+    }
+  }
+}
+
+template <typename T>
+int run_step(dp_model *m, const Weights<T> &w, int n, const double *X, const int *types, const Grid &g, bool gdev,
+             double *d_energy, double *d_forces, double *d_virial, double *d_atom_energy, hipStream_t st,
+             int *status_out) {
+  Workspace &ws = m->ws;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
+  mark(m, 0, st);
+  launch_neighbors(ws, X, types, n, m->ntypes, g, gdev, m->rc, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int s = flags_status(ws.flags_host[0]);
+  if (s != DP_OK) return s;
+  const unsigned overflow = ws.flags_host[1];
+  const float rc = (float)m->rc, rcs = (float)m->rcs, eps = (float)m->ln_eps;
+  const bool bwd = d_forces || d_virial;
+  mark(m, 1, st);
+  launch_descriptor_fwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+  mark(m, 2, st);
+  launch_fitting<T>(w, ws, types, n, bwd, st);
+  mark(m, 3, st);
+  launch_energy(ws, n, d_energy, d_atom_energy, st);
+  mark(m, 4, st);
+  if (bwd) {
+    launch_descriptor_bwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+    mark(m, 5, st);
+    double *F = d_forces;
+    if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
+    launch_forces(ws, X, n, g, gdev, nullptr, F, d_virial, st);
+    mark(m, 6, st);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  collect(m, bwd ? 6 : 4);
+  *status_out = overflow ? DP_WARN_SEL_OVERFLOW : DP_OK;
+  return DP_OK;
+}
+
+}  // namespace
+}  // namespace dp
+
+using namespace dp;
+
+extern "C" {
+
+const char *dp_status_string(int s) {
+  switch (s) {
+    case DP_OK: return "ok";
+    case DP_WARN_SEL_OVERFLOW: return "warning: neighbour list truncated to sel";
+    case DP_ERR_ARG: return "invalid argument";
+    case DP_ERR_MODEL_FILE: return "bad model file";
+    case DP_ERR_TYPE: return "atom type out of range";
+    case DP_ERR_BOX: return "unsupported box";
+    case DP_ERR_OVERLAP: return "overlapping atoms";
+    case DP_ERR_NONFINITE: return "non-finite input";
+    case DP_ERR_OOM: return "device out of memory";
+    case DP_ERR_TOO_LARGE: return "system too large or too dense";
+    case DP_ERR_HIP: return "HIP runtime error";
+    case DP_ERR_TIMEOUT: return "timeout";
+    default: return "unknown status";
+  }
+}
+
+const char *dp_last_error(void) { return g_last_error.c_str(); }
+
+int dp_model_load(const char *path, int precision, int device, dp_model **out) {
+  g_last_error.clear();
+  if (!path || !out || (precision != DP_FP32 && precision != DP_BF16)) {
+    set_error("dp_model_load: bad argument");
+    return DP_ERR_ARG;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    set_error("dp_model_load: no such HIP device");
+    return DP_ERR_ARG;
+  }
+  HostModel h;
+  int s = read_model(path, h);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipSetDevice(device));
+  dp_model *m = new dp_model();
+  m->device = device;
+  m->prec = precision;
+  m->rc = h.rc;
+  m->rcs = h.rcs;
+  m->ln_eps = h.eps;
+  m->sel = h.sel;
+  m->ntypes = h.ntypes;
+  s = build_weights(m, h);
+  if (s != DP_OK) {
+    dp_model_free(m);
+    return s;
+  }
+  *out = m;
+  return DP_OK;
+}
+
+void dp_model_free(dp_model *m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  for (int k = 0; k < 8; ++k)
+    if (m->ev[k]) (void)hipEventDestroy(m->ev[k]);
+  free_ws(m->ws);
+  if (m->wbuf) (void)hipFree(m->wbuf);
+  delete m;
+}
+
+int dp_profile_enable(dp_model *m, int enable) {
+  if (!m) return DP_ERR_ARG;
+  HIP_TRY(hipSetDevice(m->device));
+  if (enable && !m->ev[0])
+    for (int k = 0; k < 8; ++k) HIP_TRY(hipEventCreate(&m->ev[k]));
+  for (int k = 0; k < 8; ++k) {
+    m->prof_ms[k] = 0;
+    m->prof_calls[k] = 0;
+  }
+  m->prof = enable != 0;
+  return DP_OK;
+}
+
+int dp_profile_read(const dp_model *m, double *ms, int64_t *calls, int max) {
+  if (!m) return DP_ERR_ARG;
+  for (int k = 0; k < max && k < DP_NPHASES; ++k) {
+    if (ms) ms[k] = m->prof_ms[k];
+    if (calls) calls[k] = m->prof_calls[k];
+  }
+  return DP_NPHASES;
+}
+
+int dp_model_info(const dp_model *m, double *rc, int *sel, int *ntypes) {
+  if (!m) return DP_ERR_ARG;
+  if (rc) *rc = m->rc;
+  if (sel) *sel = m->sel;
+  if (ntypes) *ntypes = m->ntypes;
+  return DP_OK;
+}
+
+int dp_compute_device(dp_model *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
+                      const double *box_host, double *d_energy, double *d_forces, double *d_virial,
+                      double *d_atom_energy, void *hip_stream) {
+  g_last_error.clear();
+  if (!m || natoms < 1 || !d_coords || !d_types || !d_energy) {
+    set_error("dp_compute_device: bad argument");
+    return DP_ERR_ARG;
+  }
+  if (natoms > MAX_ATOMS) {
+    set_error("natoms above the library limit");
+    return DP_ERR_TOO_LARGE;
+  }
+  Grid g;
+  int s = check_box(m, box_host, g);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipSetDevice(m->device));
+  s = ensure_ws(m, natoms);
+  if (s != DP_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool gdev = !g.periodic;
+  if (gdev) g.cw[0] = m->rc;
+  int status = DP_OK;
+  if (m->prec == DP_FP32)
+    s = run_step<float>(m, m->wf, (int)natoms, d_coords, d_types, g, gdev, d_energy, d_forces, d_virial,
+                        d_atom_energy, st, &status);
+  else
+    s = run_step<bf16_t>(m, m->wb, (int)natoms, d_coords, d_types, g, gdev, d_energy, d_forces, d_virial,
+                         d_atom_energy, st, &status);
+  if (s != DP_OK) {
+    m->fwd_valid = false;
+    return s;
+  }
+  m->fwd_valid = !(d_forces || d_virial);
+  m->fwd_natoms = natoms;
+  m->fwd_coords = d_coords;
+  m->fwd_types = d_types;
+  m->fwd_grid = g;
+  return status;
+}
+
+int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_coords, double *d_virial,
+                       void *hip_stream) {
+  g_last_error.clear();
+  if (!m || !d_grad_energy || !d_grad_coords) {
+    set_error("dp_backward_device: bad argument");
+    return DP_ERR_ARG;
+  }
+  if (!m->fwd_valid) {
+    set_error("dp_backward_device: no energy-only forward pass to differentiate");
+    return DP_ERR_ARG;
+  }
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int n = (int)m->fwd_natoms;
+  const Grid &g = m->fwd_grid;
+  const bool gdev = !g.periodic;
+  const float rc = (float)m->rc, rcs = (float)m->rcs, eps = (float)m->ln_eps;
+  Workspace &ws = m->ws;
+  // the energy-only pass left D in place; rerun the fitting net with its backward
+  if (m->prec == DP_FP32) {
+    launch_fitting<float>(m->wf, ws, m->fwd_types, n, true, st);
+    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
+  } else {
+    launch_fitting<bf16_t>(m->wb, ws, m->fwd_types, n, true, st);
+    launch_descriptor_bwd<bf16_t>(m->wb, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
+  }
+  launch_forces(ws, m->fwd_coords, n, g, gdev, d_grad_energy, d_grad_coords, d_virial, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  m->fwd_valid = false;
+  return DP_OK;
+}
+
+int dp_compute(dp_model *m, int64_t natoms, const double *coords, const int32_t *types, const double *box,
+               double *energy, double *forces, double *virial, double *atom_energy) {
+  g_last_error.clear();
+  if (!m || natoms < 1 || !coords || !types || !energy) {
+    set_error("dp_compute: bad argument");
+    return DP_ERR_ARG;
+  }
+  if (natoms > MAX_ATOMS) {
+    set_error("natoms above the library limit");
+    return DP_ERR_TOO_LARGE;
+  }
+  HIP_TRY(hipSetDevice(m->device));
+  double *dX = nullptr, *dE = nullptr, *dF = nullptr, *dV = nullptr, *dAE = nullptr;
+  int *dT = nullptr;
+  const size_t n = (size_t)natoms;
+  auto cleanup = [&]() {
+    void *ps[] = {dX, dE, dF, dV, dAE, dT};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+  };
+  if (hipMalloc(&dX, n * 3 * 8) != hipSuccess || hipMalloc(&dT, n * 4) != hipSuccess ||
+      hipMalloc(&dE, 8) != hipSuccess || hipMalloc(&dF, n * 3 * 8) != hipSuccess ||
+      hipMalloc(&dV, 9 * 8) != hipSuccess || (atom_energy && hipMalloc(&dAE, n * 8) != hipSuccess)) {
+    cleanup();
+    set_error("dp_compute: device allocation failed");
+    return DP_ERR_OOM;
+  }
+  int s = DP_OK;
+  if (hipMemcpy(dX, coords, n * 3 * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dT, types, n * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    cleanup();
+    set_error("dp_compute: host to device copy failed");
+    return DP_ERR_HIP;
+  }
+  const bool bwd = forces || virial;
+  s = dp_compute_device(m, natoms, dX, dT, box, dE, bwd ? dF : nullptr, bwd ? dV : nullptr, dAE, nullptr);
+  if (s >= 0) {
+    bool ok = hipMemcpy(energy, dE, 8, hipMemcpyDeviceToHost) == hipSuccess;
+    if (forces) ok &= hipMemcpy(forces, dF, n * 3 * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    if (virial) ok &= hipMemcpy(virial, dV, 9 * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    if (atom_energy) ok &= hipMemcpy(atom_energy, dAE, n * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) {
+      set_error("dp_compute: device to host copy failed");
+      s = DP_ERR_HIP;
+    }
+  }
+  m->fwd_valid = false;
+  cleanup();
+  return s;
+}
+
+int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const double *box, int32_t *nlist,
+                       int32_t *nnei, int64_t *overflow) {
+  g_last_error.clear();
+  if (!m || natoms < 1 || !coords || !nlist || !nnei) {
+    set_error("dp_debug_neighbors: bad argument");
+    return DP_ERR_ARG;
+  }
+  if (natoms > MAX_ATOMS) return DP_ERR_TOO_LARGE;
+  Grid g;
+  int s = check_box(m, box, g);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipSetDevice(m->device));
+  s = ensure_ws(m, natoms);
+  if (s != DP_OK) return s;
+  const size_t n = (size_t)natoms;
+  double *dX = nullptr;
+  int *dT = nullptr;
+  if (hipMalloc(&dX, n * 24) != hipSuccess || hipMalloc(&dT, n * 4) != hipSuccess) {
+    if (dX) (void)hipFree(dX);
+    set_error("dp_debug_neighbors: allocation failed");
+    return DP_ERR_OOM;
+  }
+  Workspace &ws = m->ws;
+  const bool gdev = !g.periodic;
+  if (gdev) g.cw[0] = m->rc;
+  s = DP_OK;
+  if (hipMemcpy(dX, coords, n * 24, hipMemcpyHostToDevice) != hipSuccess || hipMemset(dT, 0, n * 4) != hipSuccess) {
+    s = DP_ERR_HIP;
+  } else {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, nullptr, ws.flags, 4);
+    launch_neighbors(ws, dX, dT, (int)natoms, m->ntypes, g, gdev, m->rc, nullptr);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(nlist, ws.nlist, n * SEL * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(nnei, ws.nnei, n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ws.flags_host, ws.flags, 16, hipMemcpyDeviceToHost) != hipSuccess) {
+      s = DP_ERR_HIP;
+    } else {
+      s = flags_status(ws.flags_host[0]);
+      if (overflow) *overflow = ws.flags_host[1];
+      if (s == DP_OK && ws.flags_host[1]) s = DP_WARN_SEL_OVERFLOW;
+    }
+  }
+  (void)hipFree(dX);
+  (void)hipFree(dT);
+  if (s == DP_ERR_HIP) set_error("dp_debug_neighbors: HIP call failed");
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Fitting net on gfx950: per-atom energy from the descriptor and, for the
+// backward pass, dE_i/dD (paper, Section II: a fitting net maps each atom's
+// representation to its energy; E is the sum of the atomic energies).
+//   y1 = tanh(D F1 + c1);  y2 = tanh(y1 F2 + c2) + y1;  y3 = tanh(y2 F3 + c3) + y2
+//   E_i = y3 . F4 + c4 + ebias[t_i]
+// Batched over 16 atoms per workgroup so each weight fragment is fetched once per
+// 16 atoms; the 1600 -> 240 products and their transposes run on MFMA.
+// dE/dD overwrites D in place (each workgroup owns its 16 rows).
+#include "dp_internal.h"
+
+namespace dp {
+namespace {
+
+constexpr int LDF = FH + 4;
+
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS)
+k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D, float *__restrict__ Ei,
+      int backward) {
+  __shared__ float y1[16 * LDF], t2[16 * LDF], y2[16 * LDF], t3[16 * LDF], bA[16 * LDF], bB[16 * LDF];
+  const int a0 = blockIdx.x * 16;
+  const int wv = wave_id();
+  constexpr int NT = FH / 16;  // 15 column tiles of the hidden width
+  // layer 1: y1 = tanh(D F1 + c1)
+  for (int t = wv; t < NT; t += NW) {
+    const int c0 = t * 16;
+    f4 acc = {0, 0, 0, 0};
+    Mma<T>::tile(acc, [&](int r, int k) { return (a0 + r < n) ? D[(size_t)(a0 + r) * ND + k] : 0.f; },
+                 [&](int c, int k) { return ldw(w.F1T, (c0 + c) * ND + k); }, ND);
+    const int col = c0 + acc_col();
+    for (int i = 0; i < 4; ++i) y1[acc_row(i) * LDF + col] = tanhf(acc[i] + w.c1[col]);
+  }
+  __syncthreads();
+  for (int t = wv; t < NT; t += NW) {
+    const int c0 = t * 16;
+    f4 acc = {0, 0, 0, 0};
+    Mma<T>::tile(acc, [&](int r, int k) { return y1[r * LDF + k]; },
+                 [&](int c, int k) { return ldw(w.F2T, (c0 + c) * FH + k); }, FH);
+    const int col = c0 + acc_col();
+    for (int i = 0; i < 4; ++i) {
+      const int r = acc_row(i);
+      const float tt = tanhf(acc[i] + w.c2[col]);
+      t2[r * LDF + col] = tt;
+      y2[r * LDF + col] = tt + y1[r * LDF + col];
+    }
+  }
+  __syncthreads();
+  for (int t = wv; t < NT; t += NW) {
+    const int c0 = t * 16;
+    f4 acc = {0, 0, 0, 0};
+    Mma<T>::tile(acc, [&](int r, int k) { return y2[r * LDF + k]; },
+                 [&](int c, int k) { return ldw(w.F3T, (c0 + c) * FH + k); }, FH);
+    const int col = c0 + acc_col();
+    for (int i = 0; i < 4; ++i) {
+      const int r = acc_row(i);
+      const float tt = tanhf(acc[i] + w.c3[col]);
+      t3[r * LDF + col] = tt;
+      bA[r * LDF + col] = tt + y2[r * LDF + col];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) {
+    const int r = threadIdx.x;
+    int ty = types[a0 + r];
+    ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
+    float e = 0.f;
+    for (int o = 0; o < FH; ++o) e += bA[r * LDF + o] * w.F4[o];
+    Ei[a0 + r] = e + w.c4 + w.ebias[ty];
+  }
+  if (!backward) return;
+  for (int q = threadIdx.x; q < 16 * FH; q += NTHREADS) {
+    const int r = q / FH, o = q % FH;
+    const float tt = t3[r * LDF + o];
+    bB[r * LDF + o] = w.F4[o] * (1.f - tt * tt);
+  }
+  __syncthreads();
+  // dy2 = dpre3 F3^T + dy3  (dy3 = F4);  dpre2 = dy2 (1 - t2^2)
+  for (int t = wv; t < NT; t += NW) {
+    const int c0 = t * 16;
+    f4 acc = {0, 0, 0, 0};
+    Mma<T>::tile(acc, [&](int r, int k) { return bB[r * LDF + k]; },
+                 [&](int c, int k) { return ldw(w.F3, (c0 + c) * FH + k); }, FH);
+    const int col = c0 + acc_col();
+    for (int i = 0; i < 4; ++i) {
+      const int r = acc_row(i);
+      const float dy2 = acc[i] + w.F4[col];
+      const float tt = t2[r * LDF + col];
+      bA[r * LDF + col] = dy2;
+      t3[r * LDF + col] = dy2 * (1.f - tt * tt);
+    }
+  }
+  __syncthreads();
+  // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
+  for (int t = wv; t < NT; t += NW) {
+    const int c0 = t * 16;
+    f4 acc = {0, 0, 0, 0};
+    Mma<T>::tile(acc, [&](int r, int k) { return t3[r * LDF + k]; },
+                 [&](int c, int k) { return ldw(w.F2, (c0 + c) * FH + k); }, FH);
+    const int col = c0 + acc_col();
+    for (int i = 0; i < 4; ++i) {
+      const int r = acc_row(i);
+      const float dy1 = acc[i] + bA[r * LDF + col];
+      const float yy = y1[r * LDF + col];
+      bB[r * LDF + col] = dy1 * (1.f - yy * yy);
+    }
+  }
+  __syncthreads();
+  // dE/dD = dpre1 F1^T, written over D
+  for (int t = wv; t < ND / 16; t += NW) {
+    const int c0 = t * 16;
+    f4 acc = {0, 0, 0, 0};
+    Mma<T>::tile(acc, [&](int r, int k) { return bB[r * LDF + k]; },
+                 [&](int c, int k) { return ldw(w.F1, (c0 + c) * FH + k); }, FH);
+    const int col = c0 + acc_col();
+    for (int i = 0; i < 4; ++i) {
+      const int r = acc_row(i);
+      if (a0 + r < n) D[(size_t)(a0 + r) * ND + col] = acc[i];
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward, hipStream_t st) {
+  hipLaunchKernelGGL(k_fit<T>, dim3((n + 15) / 16), dim3(NTHREADS), 0, st, w, types, n, ws.D, ws.Ei,
+                     backward ? 1 : 0);
+}
+template void launch_fitting<float>(const Weights<float> &, const Workspace &, const int *, int, bool, hipStream_t);
+template void launch_fitting<bf16_t>(const Weights<bf16_t> &, const Workspace &, const int *, int, bool, hipStream_t);
+
+}  // namespace dp

@@ -39,3 +39,23 @@ def oracle_water192(omodel, water192):
     from oracle.dp import evaluate
     s = water192
     return evaluate(omodel, s.coords, s.types, s.box)
+
+
+def _gpu_model(model_path, precision):
+    from paper_2602_02234_amd import Model
+    return Model(model_path, precision=precision)
+
+
+@pytest.fixture(scope="session")
+def gpu_fp32(model_path):
+    return _gpu_model(model_path, "fp32")
+
+
+@pytest.fixture(scope="session")
+def gpu_bf16(model_path):
+    return _gpu_model(model_path, "bf16")
+
+
+@pytest.fixture(scope="session")
+def gpu_models(gpu_fp32, gpu_bf16):
+    return {"fp32": gpu_fp32, "bf16": gpu_bf16}

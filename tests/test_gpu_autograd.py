@@ -1,0 +1,92 @@
+"""The torch.autograd.Function over the library's hand-written backward, and finite differences.
+
+Finite differences of the GPU's own float32-path energy are limited by the
+rounding noise of the per-atom energies (about 1e-6 of |E_i| ~ 20 eV per atom,
+summed over the ~90 atoms a displacement touches): at h = 1e-4 A that noise is
+~1e-5 eV / 2e-4 A ~ 0.05 eV/A, so the h = 1e-4 comparison bound is 0.2 eV/A
+(about 20 % of the unit force RMS).  A Richardson pair at h = 1e-2 / 5e-3
+cancels the O(h^2) truncation and divides the noise by 100: its bound is 2e-3
+eV/A.  The tight check of the gradient is against the oracle's forces.
+"""
+import numpy as np
+import pytest
+
+from oracle.dp import evaluate
+from oracle.neighbors import neighbor_list_cells
+from synth import config_system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_autograd_forces_equal_library_forces(torch_cuda, gpu_fp32, water192, oracle_water192):
+    torch = torch_cuda
+    from paper_2602_02234_amd import energy
+    s = water192
+    x = torch.tensor(s.coords, dtype=torch.float64, device="cuda", requires_grad=True)
+    t = torch.tensor(s.types, dtype=torch.int32, device="cuda")
+    E = energy(gpu_fp32, x, t, s.box)
+    E.backward()
+    F_auto = -x.grad.cpu().numpy()
+    F_lib = gpu_fp32.compute(s.coords, s.types, s.box)["F"]
+    assert np.max(np.abs(F_auto - F_lib)) <= 1e-12 * max(1.0, np.max(np.abs(F_lib)))
+    rmse = np.sqrt(np.mean((F_auto - oracle_water192["F"]) ** 2))
+    assert rmse <= 1e-5
+    assert abs(float(E.item()) - oracle_water192["E"]) / s.natoms < 2e-5
+
+
+def test_autograd_upstream_gradient_scales(torch_cuda, gpu_bf16, water192):
+    torch = torch_cuda
+    from paper_2602_02234_amd import energy
+    s = water192
+    t = torch.tensor(s.types, dtype=torch.int32, device="cuda")
+    x1 = torch.tensor(s.coords, dtype=torch.float64, device="cuda", requires_grad=True)
+    energy(gpu_bf16, x1, t, s.box).backward()
+    x2 = torch.tensor(s.coords, dtype=torch.float64, device="cuda", requires_grad=True)
+    (-2.5 * energy(gpu_bf16, x2, t, s.box)).backward()
+    assert torch.allclose(x2.grad, -2.5 * x1.grad, rtol=1e-12, atol=1e-12)
+
+
+def _local_energy(model, X, types, box, atoms):
+    out = model.compute(X, types, box, forces=False, atom_energy=True)
+    return float(np.sum(out["E_i"][atoms]))
+
+
+def test_central_differences_of_gpu_energy(gpu_fp32, omodel):
+    s = config_system("chain1k")
+    out = gpu_fp32.compute(s.coords, s.types, s.box)
+    nl, nn, _ = neighbor_list_cells(s.coords, s.box, 6.2, 400)
+    rng = np.random.default_rng(7)
+    worst_h4, worst_rich = 0.0, 0.0
+    for i in rng.choice(s.natoms, size=32, replace=False):
+        atoms = np.array([i] + nl[i, :nn[i]].tolist())
+        a = int(rng.integers(3))
+
+        def fd(h):
+            Xp = s.coords.copy(); Xp[i, a] += h
+            Xm = s.coords.copy(); Xm[i, a] -= h
+            return -(_local_energy(gpu_fp32, Xp, s.types, s.box, atoms)
+                     - _local_energy(gpu_fp32, Xm, s.types, s.box, atoms)) / (2 * h)
+
+        f = out["F"][i, a]
+        worst_h4 = max(worst_h4, abs(fd(1e-4) - f))
+        worst_rich = max(worst_rich, abs((4 * fd(5e-3) - fd(1e-2)) / 3 - f))
+    print("fd worst h=1e-4:", worst_h4, "richardson:", worst_rich)
+    assert worst_h4 < 0.2
+    assert worst_rich < 2e-3
+
+
+def test_backward_without_forward_is_an_error(torch_cuda, gpu_fp32):
+    torch = torch_cuda
+    from paper_2602_02234_amd import DPError
+    g = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    gE = torch.ones(1, dtype=torch.float64, device="cuda")
+    gpu_fp32.compute(np.zeros((2, 3)) + np.array([[0, 0, 0], [1.5, 0, 0]]), np.array([0, 1]), None)
+    with pytest.raises(DPError, match="DP_ERR_ARG"):
+        gpu_fp32.backward_device(gE, g)

@@ -1,0 +1,152 @@
+"""GPU path vs the FP64 oracle: neighbour lists bit-exact, E/F/virial within the stated bounds.
+
+All cases are seeded synthetic systems (water boxes, solvated chains, open
+clusters) small enough for the oracle to finish in seconds while spanning
+several 16-token tiles per atom and ragged tails (n not a multiple of 16).
+"""
+import numpy as np
+import pytest
+
+from oracle.dp import evaluate
+from oracle.neighbors import neighbor_list_bruteforce
+from synth import config_system
+from tolerances import compare, assert_within
+
+pytestmark = pytest.mark.gpu
+
+
+def _cluster(n, seed, spread=6.0, dmin=1.0):
+    rng = np.random.default_rng(seed)
+    X = []
+    while len(X) < n:
+        p = rng.uniform(-spread, spread, size=3)
+        if all(np.linalg.norm(p - q) > dmin for q in X):
+            X.append(p)
+    return np.array(X), rng.integers(0, 5, size=n).astype(np.int32)
+
+
+def _check_lists(gpu, X, box):
+    nl, nn, ov = gpu.neighbors(X, box)
+    rl, rn, rov = neighbor_list_bruteforce(X, box, gpu.rc, gpu.sel)
+    assert ov == rov
+    assert np.array_equal(nn, rn)
+    assert np.array_equal(nl, rl)
+
+
+def test_neighbors_water192(gpu_fp32, water192):
+    _check_lists(gpu_fp32, water192.coords, water192.box)
+
+
+def test_neighbors_chain1k(gpu_fp32):
+    s = config_system("chain1k")
+    _check_lists(gpu_fp32, s.coords, s.box)
+
+
+def test_neighbors_open_cluster(gpu_fp32):
+    X, _ = _cluster(80, 3, spread=9.0)
+    _check_lists(gpu_fp32, X, None)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_neighbors_dyadic_boxes(gpu_fp32, seed):
+    """Coordinates on a 1/8 grid put pairs at exactly rc and exactly L/2."""
+    rng = np.random.default_rng(100 + seed)
+    L = [12.0, 12.5, 19.0][seed % 3]
+    n = 60 + 20 * seed
+    pts = rng.choice(int(L * 8) ** 3, size=n, replace=False)
+    k = int(L * 8)
+    X = np.stack([pts // (k * k), (pts // k) % k, pts % k], 1).astype(float) / 8.0
+    _check_lists(gpu_fp32, X, np.diag([L, L, L]))
+
+
+def test_neighbors_overflow_keeps_nearest(gpu_fp32):
+    """A dense cluster: every atom has > sel neighbours; lists keep the sel nearest by (d2, j)."""
+    X, _ = _cluster(200, 5, spread=2.6, dmin=0.35)
+    nl, nn, ov = gpu_fp32.neighbors(X, None)
+    assert ov > 0 and gpu_fp32.last_status == 1
+    rl, rn, rov = neighbor_list_bruteforce(X, None, gpu_fp32.rc, gpu_fp32.sel)
+    assert ov == rov and np.array_equal(nl, rl) and np.array_equal(nn, rn)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_water192_matches_oracle(gpu_models, omodel, water192, oracle_water192, prec):
+    s = water192
+    out = gpu_models[prec].compute(s.coords, s.types, s.box, atom_energy=True)
+    m = compare(out, oracle_water192, s.natoms)
+    print(prec, m)
+    assert_within(m, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_chain1k_matches_oracle(gpu_models, omodel, prec):
+    s = config_system("chain1k")
+    ref = evaluate(omodel, s.coords, s.types, s.box)
+    out = gpu_models[prec].compute(s.coords, s.types, s.box, atom_energy=True)
+    m = compare(out, ref, s.natoms)
+    print(prec, m)
+    assert_within(m, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_open_cluster_matches_oracle(gpu_models, omodel, prec):
+    X, t = _cluster(60, 11, spread=7.0)
+    ref = evaluate(omodel, X, t, None)
+    out = gpu_models[prec].compute(X, t, None, atom_energy=True)
+    m = compare(out, ref, len(t))
+    assert_within(m, prec)
+
+
+def test_sparse_atoms_and_isolated_atom(gpu_fp32, omodel):
+    """Atoms with 0, 1 and 2 neighbours (single-token attention, empty descriptor)."""
+    X = np.array([[0.0, 0.0, 0.0], [1.2, 0.3, -0.4], [30.0, 0.0, 0.0], [33.5, 1.0, 0.0], [31.0, 2.5, 1.0],
+                  [-40.0, 5.0, 5.0]])
+    t = np.array([0, 1, 2, 3, 4, 1], dtype=np.int32)
+    ref = evaluate(omodel, X, t, None)
+    out = gpu_fp32.compute(X, t, None, atom_energy=True)
+    assert_within(compare(out, ref, len(t)), "fp32")
+
+
+def test_net_force_and_virial_symmetry(gpu_fp32):
+    s = config_system("chain1k")
+    out = gpu_fp32.compute(s.coords, s.types, s.box)
+    assert np.max(np.abs(out["F"].sum(0))) < 1e-5 * s.natoms ** 0.5
+    v = out["virial"]
+    assert np.max(np.abs(v - v.T)) < 1e-5 * np.max(np.abs(v))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_bitwise_reproducible(gpu_models, water192, prec):
+    s = water192
+    a = gpu_models[prec].compute(s.coords, s.types, s.box, atom_energy=True)
+    b = gpu_models[prec].compute(s.coords, s.types, s.box, atom_energy=True)
+    assert a["E"] == b["E"]
+    assert np.array_equal(a["F"], b["F"]) and np.array_equal(a["virial"], b["virial"])
+    assert np.array_equal(a["E_i"], b["E_i"])
+
+
+def test_energy_only_call(gpu_fp32, water192, oracle_water192):
+    s = water192
+    out = gpu_fp32.compute(s.coords, s.types, s.box, forces=False)
+    assert abs(out["E"] - oracle_water192["E"]) / s.natoms < 2e-5
+
+
+def test_error_statuses(gpu_fp32, water192):
+    from paper_2602_02234_amd import DPError
+    s = water192
+    bad_t = s.types.copy(); bad_t[3] = 7
+    with pytest.raises(DPError, match="DP_ERR_TYPE"):
+        gpu_fp32.compute(s.coords, bad_t, s.box)
+    bad_x = s.coords.copy(); bad_x[5, 1] = np.nan
+    with pytest.raises(DPError, match="DP_ERR_NONFINITE"):
+        gpu_fp32.compute(bad_x, s.types, s.box)
+    with pytest.raises(DPError, match="DP_ERR_BOX"):
+        gpu_fp32.compute(s.coords, s.types, np.diag([11.0, 12.42, 12.42]))
+    tri = s.box.copy(); tri[1, 0] = 0.5
+    with pytest.raises(DPError, match="DP_ERR_BOX"):
+        gpu_fp32.compute(s.coords, s.types, tri)
+    dup = s.coords.copy(); dup[7] = dup[8]
+    with pytest.raises(DPError, match="DP_ERR_OVERLAP"):
+        gpu_fp32.compute(dup, s.types, s.box)
+    # the model still works after errors
+    out = gpu_fp32.compute(s.coords, s.types, s.box)
+    assert np.isfinite(out["E"])

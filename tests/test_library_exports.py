@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every function include/dp.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for f in ("dp_model_load", "dp_model_free", "dp_compute", "dp_compute_device", "dp_backward_device",
+              "dp_debug_neighbors", "dp_status_string", "dp_last_error", "dp_model_info"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2602_02234_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libdp.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.SIGNATURES) == set(_declared())
+
+
+def test_status_strings_without_gpu():
+    from paper_2602_02234_amd import _lib
+    lib = _lib.load()
+    assert lib.dp_status_string(0) == b"ok"
+    assert b"type" in lib.dp_status_string(-3)
+    assert lib.dp_status_string(12345) == b"unknown status"
+
+
+def test_model_load_without_device_fails_cleanly(model_path):
+    """Here there is no GPU: loading must return an error, never fall back to a CPU path."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2602_02234_amd import Model, DPError
+    with pytest.raises(DPError):
+        Model(model_path)
