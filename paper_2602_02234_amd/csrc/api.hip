@@ -128,7 +128,7 @@ std::vector<float> transpose(const std::vector<double> &v, int rows, int cols) {
 }
 
 template <typename T>
-void bind(Weights<T> &w, const unsigned char *base, const std::vector<size_t> &o, float c4) {
+void bind_weights(Weights<T> &w, const unsigned char *base, const std::vector<size_t> &o, float c4) {
   int k = 0;
   auto F = [&]() { return (const float *)(base + o[k++]); };
   auto P = [&]() { return (const T *)(base + o[k++]); };
@@ -203,8 +203,8 @@ int build_weights(dp_model *m, const HostModel &h) {
   HIP_TRY(hipMalloc(&m->wbuf, pk.bytes.size()));
   HIP_TRY(hipMemcpy(m->wbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
   const float c4 = (float)h.c4[0];
-  bind(m->wf, (const unsigned char *)m->wbuf, o, c4);
-  bind(m->wb, (const unsigned char *)m->wbuf, o, c4);
+  bind_weights(m->wf, (const unsigned char *)m->wbuf, o, c4);
+  bind_weights(m->wb, (const unsigned char *)m->wbuf, o, c4);
   return DP_OK;
 }
 
@@ -243,7 +243,7 @@ int ensure_ws(dp_model *m, int64_t n) {
   HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
   HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
   HIP_TRY(hipMalloc(&ws.D, cap * (size_t)ND * sizeof(float)));
-  HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(float)));
+  HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));
   HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
   HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
   ws.cap = cap;

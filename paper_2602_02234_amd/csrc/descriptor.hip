@@ -39,12 +39,14 @@ struct Env {
 
 // Environment of atom i: tokens j < n from the neighbour list, padded tokens zero.
 __device__ void build_env(Env &e, const double *__restrict__ X, const int *__restrict__ types,
-                          const int *__restrict__ nlist, int i, int n, const Grid &g, float rc, float rcs) {
+                          const int *__restrict__ nlist, int i, int n, int natoms, const Grid &g, float rc,
+                          float rcs) {
   for (int j = threadIdx.x; j < NPMAX; j += NTHREADS) {
     float s = 0.f, sw = 0.f, dsw = 0.f, r = 1.f, hx = 0.f, hy = 0.f, hz = 0.f;
     int tj = 0;
     if (j < n) {
-      const int nj = nlist[(size_t)i * SEL + j];
+      int nj = nlist[(size_t)i * SEL + j];
+      if (nj < 0 || nj >= natoms) nj = i;  // never read outside the coordinate array
       tj = clamp_type(types[nj]);
       double d[3];
       for (int a = 0; a < 3; ++a) {
@@ -229,18 +231,18 @@ struct SmemFwd {
 
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
-k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types,
+k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms,
            const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dg,
            float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
            float *__restrict__ D) {
   __shared__ SmemFwd sm;
   const int i = blockIdx.x;
   const Grid g = dg ? *dg : hg;
-  const int n = nnei[i];
+  const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
-  build_env(sm.e, X, types, nlist, i, n, g, rc, rcs);
+  build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   __syncthreads();
   for (int jb = 0; jb < nb; ++jb) embed_block(w, sm.e, ti, jb, sm.Ub, sm.Hb, sm.G[0]);
   for (int layer = 0; layer < NATTN; ++layer) {
@@ -300,19 +302,19 @@ struct SmemBwd {
 
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
-k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types,
+k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms,
            const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dg,
            float rc, float rcs, float ln_eps, const float *__restrict__ Gsave, const float *__restrict__ Tsave,
            const float *__restrict__ dD, float4 *__restrict__ gout) {
   __shared__ SmemBwd sm;
   const int i = blockIdx.x;
   const Grid g = dg ? *dg : hg;
-  const int n = nnei[i];
+  const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
   const int wv = wave_id();
-  build_env(sm.e, X, types, nlist, i, n, g, rc, rcs);
+  build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   for (int q = threadIdx.x; q < NPMAX; q += NTHREADS) {
     sm.dswa[q] = 0.f;
     for (int a = 0; a < 3; ++a) sm.drh[3 * q + a] = 0.f;
@@ -650,14 +652,14 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
                            const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, ws.nlist, ws.nnei, g,
+  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, g,
                      grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
 }
 
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
                            const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, ws.nlist, ws.nnei, g,
+  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, g,
                      grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
 }
 

@@ -70,7 +70,7 @@ struct Workspace {
   float *Gsave = nullptr;     // [cap][NATTN][NPMAX][M]  inputs of each attention layer
   float *Tsave = nullptr;     // [cap][M][4]
   float *D = nullptr;         // [cap][ND]  descriptor, then dE/dD
-  float *Ei = nullptr;        // [cap]
+  double *Ei = nullptr;       // [cap] atomic energies
   float4 *g = nullptr;        // [cap][SEL]  dE_i/dDelta_ij
   double *vpart = nullptr;    // [cap][9]   per-atom virial
   double *red = nullptr;      // scratch for the compensated reductions

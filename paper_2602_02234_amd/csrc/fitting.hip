@@ -15,7 +15,7 @@ constexpr int LDF = FH + 4;
 
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
-k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D, float *__restrict__ Ei,
+k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D, double *__restrict__ Ei,
       int backward) {
   __shared__ float y1[16 * LDF], t2[16 * LDF], y2[16 * LDF], t3[16 * LDF], bA[16 * LDF], bB[16 * LDF];
   const int a0 = blockIdx.x * 16;
@@ -63,9 +63,9 @@ k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D,
     const int r = threadIdx.x;
     int ty = types[a0 + r];
     ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
-    float e = 0.f;
-    for (int o = 0; o < FH; ++o) e += bA[r * LDF + o] * w.F4[o];
-    Ei[a0 + r] = e + w.c4 + w.ebias[ty];
+    double e = 0.0;  // the last layer's dot product in float64: E_i is O(100) eV
+    for (int o = 0; o < FH; ++o) e += (double)bA[r * LDF + o] * (double)w.F4[o];
+    Ei[a0 + r] = e + (double)w.c4 + (double)w.ebias[ty];
   }
   if (!backward) return;
   for (int q = threadIdx.x; q < 16 * FH; q += NTHREADS) {

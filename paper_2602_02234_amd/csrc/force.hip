@@ -27,14 +27,15 @@ __global__ void __launch_bounds__(256) k_forces(const float4 *__restrict__ g, co
   if (i >= n) return;
   const Grid gr = dg ? *dg : hg;
   double f[3] = {0, 0, 0}, v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const int nn = nnei[i];
+  const int nn = min(max(nnei[i], 0), SEL);
   for (int s = lane; s < nn; s += 64) {
     const size_t is = (size_t)i * SEL + s;
     const float4 gi = g[is];
-    const int j = nlist[is];
+    int j = nlist[is];
+    if (j < 0 || j >= n) j = i;  // never read outside the arrays
     f[0] += gi.x; f[1] += gi.y; f[2] += gi.z;
     const int r = rev[is];
-    if (r >= 0) {
+    if (r >= 0 && r < SEL) {
       const float4 gj = g[(size_t)j * SEL + r];
       f[0] -= gj.x; f[1] -= gj.y; f[2] -= gj.z;
     }
@@ -67,6 +68,7 @@ __global__ void k_forces_onesided(const float4 *__restrict__ g, const int *__res
   const int i = (int)(t / SEL), s = (int)(t % SEL);
   if (s >= nnei[i] || rev[t] >= 0) return;
   const int j = nlist[t];
+  if (j < 0 || j >= n) return;
   const float4 gi = g[t];
   const double sF = gE ? -gE[0] : 1.0;
   atomicAdd(&Fout[3 * j], -sF * gi.x);
@@ -131,7 +133,7 @@ void launch_forces(const Workspace &ws, const double *coords, int n, const Grid 
 }
 
 void launch_energy(const Workspace &ws, int n, double *energy, double *atom_energy, hipStream_t st) {
-  hipLaunchKernelGGL(k_neumaier<float>, dim3(1), dim3(1024), 0, st, ws.Ei, n, 1, energy, atom_energy);
+  hipLaunchKernelGGL(k_neumaier<double>, dim3(1), dim3(1024), 0, st, ws.Ei, n, 1, energy, atom_energy);
 }
 
 }  // namespace dp

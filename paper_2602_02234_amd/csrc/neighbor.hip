@@ -247,8 +247,12 @@ __global__ void k_rev(const int *__restrict__ nlist, const int *__restrict__ nne
   int r = -1;
   if (s < nnei[i]) {
     const int j = nlist[t];
+    if (j < 0 || j >= n) {
+      rev[t] = -1;
+      return;
+    }
     const int *row = nlist + (size_t)j * SEL;
-    int lo = 0, hi = nnei[j] - 1;
+    int lo = 0, hi = min(nnei[j], SEL) - 1;
     while (lo <= hi) {
       const int mid = (lo + hi) >> 1;
       const int v = row[mid];

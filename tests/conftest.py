@@ -59,3 +59,12 @@ def gpu_bf16(model_path):
 @pytest.fixture(scope="session")
 def gpu_models(gpu_fp32, gpu_bf16):
     return {"fp32": gpu_fp32, "bf16": gpu_bf16}
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name each test before it runs (flushed), so a run cut short still shows where it was."""
+    import sys
+    sys.stdout.write(f"\n[start] {request.node.nodeid}\n")
+    sys.stdout.flush()
+    yield
