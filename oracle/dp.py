@@ -14,7 +14,7 @@ Gated self-attention over the neighbours of i (tokens = neighbours), twice:
     Q, K, V = G WQ, G WK, G WV;  S = Q K^T / sqrt(d);  m_j = max_k S_jk
     P_jk = sw_k exp(S_jk - m_j) / sum_k' sw_k' exp(S_jk' - m_j)
     A_jk = P_jk (rhat_j . rhat_k);  Y = (A V) WO
-    G <- G + gamma * (Y - mean(Y)) / sqrt(var(Y) + eps) + beta   (population variance, per token)
+    X = G + Y;  G <- gamma * (X - mean(X)) / sqrt(var(X) + eps) + beta   (population variance, per token)
 Descriptor:  T = G^T Rt / sel  [M x 4];  D = T T_{<M2}^T  [M x M2], flattened row-major (16 m + a)
 Fitting (1600 -> 240 -> 240 -> 240 -> 1):
     y1 = tanh(D F1 + c1);  y2 = tanh(y1 F2 + c2) + y1;  y3 = tanh(y2 F3 + c3) + y2
@@ -86,12 +86,13 @@ def atom_energy_and_grad(m, t_i: int, t_j: np.ndarray, dR: np.ndarray, want_grad
         A = P * C
         O = A @ V
         Y = O @ p[f"WO{a}"]
-        mu = Y.mean(axis=1, keepdims=True)
-        var = ((Y - mu) ** 2).mean(axis=1, keepdims=True)
+        X = Gin + Y                        # residual, then LayerNorm over the features
+        mu = X.mean(axis=1, keepdims=True)
+        var = ((X - mu) ** 2).mean(axis=1, keepdims=True)
         sig = np.sqrt(var + m.ln_eps)
-        Yh = (Y - mu) / sig
-        G = Gin + p[f"gamma{a}"] * Yh + p[f"beta{a}"]
-        saved.append((Gin, Q, K, V, Ex, Z, P, A, sig, Yh))
+        Xh = (X - mu) / sig
+        G = p[f"gamma{a}"] * Xh + p[f"beta{a}"]
+        saved.append((Gin, Q, K, V, Ex, Z, P, A, sig, Xh))
         if keep is not None:
             keep[f"G{a + 1}"] = G.copy()
     # -- descriptor
@@ -126,11 +127,12 @@ def atom_energy_and_grad(m, t_i: int, t_j: np.ndarray, dR: np.ndarray, want_grad
     drhat = np.zeros_like(rhat)
     dsw_acc = np.zeros(n)
     for a in reversed(range(m.n_attn)):
-        Gin, Q, K, V, Ex, Z, P, A, sig, Yh = saved[a]
-        dGin = dG.copy()                                   # residual path
-        dYh = dG * p[f"gamma{a}"]
-        dY = (dYh - dYh.mean(axis=1, keepdims=True)
-              - Yh * (dYh * Yh).mean(axis=1, keepdims=True)) / sig
+        Gin, Q, K, V, Ex, Z, P, A, sig, Xh = saved[a]
+        dXh = dG * p[f"gamma{a}"]
+        dX = (dXh - dXh.mean(axis=1, keepdims=True)
+              - Xh * (dXh * Xh).mean(axis=1, keepdims=True)) / sig
+        dGin = dX.copy()                                   # residual path (through the LayerNorm)
+        dY = dX
         dO = dY @ p[f"WO{a}"].T
         dA = dO @ V.T
         dV = A.T @ dO

@@ -43,7 +43,7 @@ MAGIC = b"DPAMDv01"
 VERSION = 1
 # Chosen with oracle/calibrate_force_scale.py so that the per-component force
 # RMS of the 192-atom water box is 1 eV/A for seed 2602.
-FORCE_SCALE = 85.41688219278356
+FORCE_SCALE = 2627.7633828759604
 
 
 @dataclass(frozen=True)

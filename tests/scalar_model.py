@@ -5,8 +5,8 @@ numbers (``num`` selects the number type), with no matrix library, so that a
 transposed operand, a wrong index or a dropped term in the vectorised oracle
 shows up as a mismatch.  It follows the same reading of the model: quintic
 switch, environment row (s, s rhat), [s, TE[t_j], TE[t_i]] embedding with
-[h, h] residuals, switch-weighted gated softmax attention with a LayerNorm
-residual update, 1/sel descriptor T and D = T T_<M2^T, fitting net with
+[h, h] residuals, switch-weighted gated softmax attention with a residual update
+followed by LayerNorm, 1/sel descriptor T and D = T T_<M2^T, fitting net with
 residuals on the hidden layers.
 """
 import math
@@ -78,11 +78,11 @@ def atom_energy_scalar(m, t_i, t_j, dR, num=float, tanh=math.tanh, exp=math.exp,
                 for c in range(d):
                     O[c] += w * V[k][c]
             Y = dense(O, p[f"WO{a}"], None, d, M)
-            mu = sum(Y) / M
-            var = sum((y - mu) ** 2 for y in Y) / M
+            X = [G[j][o] + Y[o] for o in range(M)]
+            mu = sum(X) / M
+            var = sum((x - mu) ** 2 for x in X) / M
             sg = sqrt(var + num(m.ln_eps))
-            newG.append([G[j][o] + N(p[f"gamma{a}"][o]) * (Y[o] - mu) / sg + N(p[f"beta{a}"][o])
-                         for o in range(M)])
+            newG.append([N(p[f"gamma{a}"][o]) * (X[o] - mu) / sg + N(p[f"beta{a}"][o]) for o in range(M)])
         G = newG
 
     T = [[sum(G[j][mm] * Rt[j][c] for j in range(n)) / m.sel for c in range(4)] for mm in range(M)]

@@ -63,8 +63,13 @@ def test_single_pair_force_matches_high_precision_derivative(omodel):
     assert np.allclose(out["F"][0], -out["F"][1], atol=1e-12)
 
 
+def _ln(x, eps):
+    mu = x.mean(axis=1, keepdims=True)
+    return (x - mu) / np.sqrt(((x - mu) ** 2).mean(axis=1, keepdims=True) + eps)
+
+
 def _deeppot_se(m, t_i, t_j, dR):
-    """Attention-free reference: environment, embedding, descriptor and fitting only."""
+    """Attention-free reference: environment, embedding, a LayerNorm per layer, descriptor and fitting."""
     p = m.p
     r = np.linalg.norm(dR, axis=1)
     sw, _ = switch(r, m.rc, m.rcs)
@@ -74,6 +79,8 @@ def _deeppot_se(m, t_i, t_j, dR):
     h1 = np.tanh(z @ p["W1"] + p["b1"])
     h2 = np.tanh(h1 @ p["W2"] + p["b2"]) + np.tile(h1, 2)
     G = np.tanh(h2 @ p["W3"] + p["b3"]) + np.tile(h2, 2)
+    for _ in range(m.n_attn):           # Y = 0: each layer only normalises (gamma 1, beta 0)
+        G = _ln(G, m.ln_eps)
     T = np.einsum("jm,jc->mc", G, R) / m.sel
     D = np.einsum("mc,ac->ma", T, T[:m.M2]).ravel()
     y = np.tanh(D @ p["F1"] + p["c1"])
@@ -85,7 +92,7 @@ def _deeppot_se(m, t_i, t_j, dR):
 def test_attention_off_reduces_to_deeppot_se(omodel):
     m = copy.deepcopy(omodel)
     for a in range(m.n_attn):
-        m.p[f"WO{a}"] = np.zeros_like(m.p[f"WO{a}"])   # Y = 0 -> LN(0) = beta = 0 -> identity layer
+        m.p[f"WO{a}"] = np.zeros_like(m.p[f"WO{a}"])   # Y = 0 -> each layer is G <- LN(G)
     rng = np.random.default_rng(7)
     for n in (1, 5, 40):
         dR = _neigh(rng, n)

@@ -22,13 +22,16 @@ def test_forces_match_central_differences(omodel, water192, oracle_water192):
     worst_fd, worst_rich = 0.0, 0.0
     for i in rng.choice(s.natoms, size=6, replace=False):
         for a in range(3):
-            f1 = _fd_force(omodel, s, int(i), a, 1e-4)
-            f2 = _fd_force(omodel, s, int(i), a, 5e-5)
+            f0 = _fd_force(omodel, s, int(i), a, 1e-4)
+            f1 = _fd_force(omodel, s, int(i), a, 1e-3)
+            f2 = _fd_force(omodel, s, int(i), a, 5e-4)
             rich = (4 * f2 - f1) / 3
-            worst_fd = max(worst_fd, abs(f1 - oracle_water192["F"][i, a]))
+            worst_fd = max(worst_fd, abs(f0 - oracle_water192["F"][i, a]))
             worst_rich = max(worst_rich, abs(rich - oracle_water192["F"][i, a]))
     print(worst_fd, worst_rich)
-    assert worst_fd < 2e-5          # O(h^2) truncation at h = 1e-4 on unit-RMS forces
+    # h = 1e-4: O(h^2) truncation plus float64 noise of O(1e3) eV atomic energies over 2h
+    assert worst_fd < 2e-6
+    # Richardson on (1e-3, 5e-4) cancels the h^2 term; the h^4 term and the noise stay below 1e-7
     assert worst_rich < 1e-7
 
 
@@ -41,14 +44,14 @@ def test_net_force_zero_and_virial_symmetric(oracle_water192):
 def test_virial_diagonal_by_box_strain(omodel, water192, oracle_water192):
     """dE/d eps_aa = -Xi_aa when coordinates and box edge a are scaled by (1 + eps)."""
     s = water192
-    h = 1e-6
+    h = 1e-4        # total energies are O(1e5) eV: smaller steps drown in float64 rounding
     for a in range(3):
         sc = np.ones(3); sc[a] += h
         Ep = energy_only(omodel, s.coords * sc, s.types, s.box * sc)
         sc = np.ones(3); sc[a] -= h
         Em = energy_only(omodel, s.coords * sc, s.types, s.box * sc)
         dE = (Ep - Em) / (2 * h)
-        assert abs(dE + oracle_water192["virial"][a, a]) < 1e-7 * max(1.0, abs(dE)) + 1e-6
+        assert abs(dE + oracle_water192["virial"][a, a]) < 1e-5 * max(1.0, abs(dE))
 
 
 def _cluster(n=40, seed=0):
@@ -64,13 +67,13 @@ def _cluster(n=40, seed=0):
 def test_virial_off_diagonal_open_cluster(omodel):
     X, t = _cluster(24, 1)
     out = evaluate(omodel, X, t, None)
-    h = 1e-6
+    h = 1e-4
     for a, b in ((0, 1), (1, 2), (2, 0)):
         eps = np.zeros((3, 3)); eps[a, b] = h
         Ep = energy_only(omodel, X @ (np.eye(3) + eps).T, t, None)
         Em = energy_only(omodel, X @ (np.eye(3) - eps).T, t, None)
         dE = (Ep - Em) / (2 * h)            # dE/d eps_ab = sum g_a Delta_b = -Xi_ba
-        assert abs(dE + out["virial"][b, a]) < 1e-7
+        assert abs(dE + out["virial"][b, a]) < 1e-6 * max(1.0, abs(dE))
 
 
 def test_translation_and_wrap_invariance(omodel, water192, oracle_water192):
