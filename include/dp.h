@@ -105,6 +105,11 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
 int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const double *box,
                        int32_t *nlist, int32_t *nnei, int64_t *overflow);
 
+/* Pair gradients of the last step that ran the backward pass on this model:
+ * g[natoms][sel][4] float32, g[i][s] = dE_i/dDelta_ij for j = nlist[i][s]
+ * (x, y, z, 0; padded slots zero).  Host buffer, synchronous.  For diagnostics. */
+int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g);
+
 /* Per-phase device timing with HIP events recorded on each call's stream.
  * enable != 0 clears and starts accumulating, 0 stops.  dp_profile_read fills,
  * for up to `max` phases, the summed milliseconds and the number of calls:

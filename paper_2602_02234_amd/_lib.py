@@ -31,6 +31,7 @@ SIGNATURES = {
     "dp_compute_device": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dp_backward_device": (C.c_int, [_P, _P, _P, _P, _P]),
     "dp_debug_neighbors": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
+    "dp_debug_pair_grads": (C.c_int, [_P, _I64, _P]),
     "dp_profile_enable": (C.c_int, [_P, C.c_int]),
     "dp_profile_read": (C.c_int, [_P, _P, _P, C.c_int]),
     "dp_status_string": (C.c_char_p, [C.c_int]),
@@ -45,6 +46,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2602_02234_amd.build`")
+    # PyTorch-ROCm bundles its own HIP runtime.  Loading it first makes this
+    # library bind to that same runtime (same soname), so device pointers and
+    # streams from torch are valid here; loading ours first would put two HIP
+    # runtimes into the process and torch would then find no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)

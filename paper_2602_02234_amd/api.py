@@ -84,6 +84,12 @@ class Model:
         self.last_status = check(st, "dp_debug_neighbors")
         return nl, nn, int(ov.value)
 
+    def pair_grads(self, natoms: int):
+        """g[i][s] = dE_i/dDelta_ij of the last backward pass, [natoms][sel][3]."""
+        g = np.zeros((natoms, self.sel, 4), dtype=np.float32)
+        check(_lib.load().dp_debug_pair_grads(self._h, natoms, _ptr(g)), "dp_debug_pair_grads")
+        return g[:, :, :3]
+
     # ---------------------------------------------------------------- timing
     PHASES = ("neighbors", "descriptor_fwd", "fitting", "energy_reduce", "descriptor_bwd", "forces_virial")
 

@@ -421,6 +421,17 @@ void dp_model_free(dp_model *m) {
   delete m;
 }
 
+int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g) {
+  if (!m || !g || natoms < 1 || natoms > m->ws.cap) {
+    set_error("dp_debug_pair_grads: bad argument");
+    return DP_ERR_ARG;
+  }
+  HIP_TRY(hipSetDevice(m->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(g, m->ws.g, (size_t)natoms * SEL * sizeof(float4), hipMemcpyDeviceToHost));
+  return DP_OK;
+}
+
 int dp_profile_enable(dp_model *m, int enable) {
   if (!m) return DP_ERR_ARG;
   HIP_TRY(hipSetDevice(m->device));

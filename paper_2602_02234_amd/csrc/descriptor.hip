@@ -11,7 +11,7 @@
 //   h1 = tanh(s w1s + B[t_i][t_j]) (type part of the first layer folded into B),
 //   h2 = tanh(h1 W2 + b2) + [h1, h1], G = tanh(h2 W3 + b3) + [h2, h2];
 //   per layer: S = G (WQ WK^T / sqrt d) G^T, P = sw-weighted row softmax of S,
-//   A = P * (rhat_j . rhat_k), Y = A G (WV WO), G <- G + gamma LN(Y) + beta;
+//   A = P * (rhat_j . rhat_k), Y = A G (WV WO), G <- gamma LN(G + Y) + beta;
 //   T = G^T Rt / sel, D = T T_<16^T.
 // With one head and no projection biases, Q K^T = G (WQ WK^T) G^T and
 // (A V) WO = (A G)(WV WO), so each layer needs the two 100x100 products only;
@@ -178,11 +178,11 @@ __device__ void attn_block_front(const Weights<T> &w, int layer, const Env &e, c
   __syncthreads();
 }
 
-// Y = H Wvo for the block held by wave wv (< 7), with per-row LayerNorm statistics.
-// Returns yh (normalised Y) and sets mu/isig per accumulator row.
+// Y = H Wvo for the block held by wave wv (< 7), then the residual X = G_in + Y and its
+// per-row LayerNorm statistics.  Returns xh (normalised X) and isig per accumulator row.
 template <typename T>
-__device__ void attn_block_ln(const Weights<T> &w, int layer, const float *Hb, float *red, float ln_eps,
-                              f4 &yh, float isig[4]) {
+__device__ void attn_block_ln(const Weights<T> &w, int layer, const float *Hb, const float *Gin, int jb, float *red,
+                              float ln_eps, f4 &yh, float isig[4]) {
   const int wv = wave_id();
   const int col = wv * 16 + acc_col();
   const bool cval = wv < 7 && col < M;
@@ -193,6 +193,8 @@ __device__ void attn_block_ln(const Weights<T> &w, int layer, const float *Hb, f
     Mma<T>::tile(y, [&](int r, int k) { return Hb[r * LDM + k]; },
                  [&](int c, int k) { return (c0 + c < M) ? ldw(WvoT, (c0 + c) * M + k) : 0.f; }, M);
   }
+  if (cval)
+    for (int i = 0; i < 4; ++i) y[i] += Gin[(jb * 16 + acc_row(i)) * LDM + col];
   for (int i = 0; i < 4; ++i) {
     const float p = sum16(cval ? y[i] : 0.f);
     if ((lane_id() & 15) == 0) red[(wv * 16 + acc_row(i)) * 8 + 2] = p;
@@ -254,13 +256,13 @@ k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
       attn_block_front(w, layer, sm.e, Gin, jb, n, NP, sm.Ub, nullptr, sm.Ab, sm.Hb, sm.red);
       f4 yh;
       float isig[4];
-      attn_block_ln(w, layer, sm.Hb, sm.red, ln_eps, yh, isig);
+      attn_block_ln(w, layer, sm.Hb, Gin, jb, sm.red, ln_eps, yh, isig);
       const int wv = wave_id();
       const int col = wv * 16 + acc_col();
       if (wv < 7 && col < M)
         for (int ii = 0; ii < 4; ++ii) {
           const int j = jb * 16 + acc_row(ii);
-          Gout[j * LDM + col] = Gin[j * LDM + col] + w.gamma[layer][col] * yh[ii] + w.beta[layer][col];
+          Gout[j * LDM + col] = w.gamma[layer][col] * yh[ii] + w.beta[layer][col];
         }
       __syncthreads();
     }
@@ -346,9 +348,10 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
       attn_block_front(w, layer, sm.e, sm.Gin, jb, n, NP, sm.Ub, sm.Eb, sm.Ab, sm.Hb, sm.red);
       f4 yh;
       float isig[4];
-      attn_block_ln(w, layer, sm.Hb, sm.red, ln_eps, yh, isig);
+      attn_block_ln(w, layer, sm.Hb, sm.Gin, jb, sm.red, ln_eps, yh, isig);
       // (d) LayerNorm backward; for the top layer the incoming gradient is
       // dG = Rt dT^T / sel and the layer output also feeds dRt = G_out dT / sel.
+      // The residual runs through the LayerNorm: dG_in starts as dX and dY = dX.
       const int col = wv * 16 + acc_col();
       const bool cval = wv < 7 && col < M;
       float dyh[4];
@@ -360,9 +363,8 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
           if (top) {
             go = (sm.e.Rt[4 * j] * sm.dT[4 * col] + sm.e.Rt[4 * j + 1] * sm.dT[4 * col + 1] +
                   sm.e.Rt[4 * j + 2] * sm.dT[4 * col + 2] + sm.e.Rt[4 * j + 3] * sm.dT[4 * col + 3]) * inv_sel;
-            const float gout_v = sm.Gin[j * LDM + col] + w.gamma[layer][col] * yh[ii] + w.beta[layer][col];
+            const float gout_v = w.gamma[layer][col] * yh[ii] + w.beta[layer][col];
             for (int c = 0; c < 4; ++c) prt[ii][c] = gout_v * sm.dT[4 * col + c] * inv_sel;
-            sm.dG[j * LDM + col] = go;
           } else {
             go = sm.dG[j * LDM + col];
             for (int c = 0; c < 4; ++c) prt[ii][c] = 0.f;
@@ -388,8 +390,11 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
           s0 += sm.red[(q * 16 + r) * 8 + 4];
           s1 += sm.red[(q * 16 + r) * 8 + 5];
         }
-        const float dY = (dyh[ii] - s0 / (float)M - (cval ? yh[ii] : 0.f) * (s1 / (float)M)) * isig[ii];
-        if (cval) sm.Hb[r * LDM + col] = dY;
+        const float dX = (dyh[ii] - s0 / (float)M - (cval ? yh[ii] : 0.f) * (s1 / (float)M)) * isig[ii];
+        if (cval) {
+          sm.Hb[r * LDM + col] = dX;
+          sm.dG[(jb * 16 + r) * LDM + col] = dX;
+        }
       }
       // dRt row sums for the top layer: 4 values per row, reduced in two rounds of 2
       if (top) {
