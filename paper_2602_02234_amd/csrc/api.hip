@@ -200,11 +200,80 @@ int build_weights(dp_model *m, const HostModel &h) {
   o.push_back(pk.addf(tof(h.c3)));
   o.push_back(pk.addf(tof(h.F4)));
   o.push_back(pk.addf(tof(h.ebias)));
+  // padded [rows][k] bf16 operands of the bfloat16 kernels (zero outside the real extent)
+  std::vector<size_t> op;
+  if (pr == DP_BF16) {
+    auto mat = [](int R, int K, auto f) {
+      std::vector<float> v((size_t)R * K, 0.f);
+      for (int r = 0; r < R; ++r)
+        for (int k = 0; k < K; ++k) v[(size_t)r * K + k] = (float)f(r, k);
+      return v;
+    };
+    auto hi_lo = [&](const std::vector<float> &v, int part) {
+      std::vector<uint16_t> b(v.size());
+      for (size_t i = 0; i < v.size(); ++i) {
+        const uint16_t hb = to_bf16(v[i]);
+        uint32_t hu = (uint32_t)hb << 16;
+        float hf;
+        std::memcpy(&hf, &hu, 4);
+        b[i] = part == 0 ? hb : to_bf16(v[i] - hf);
+      }
+      return pk.add(b.data(), b.size() * 2);
+    };
+    auto W2 = [&](int a, int b) { return h.W2[(size_t)a * E2 + b]; };
+    auto W3 = [&](int a, int b) { return h.W3[(size_t)a * M + b]; };
+    op.push_back(hi_lo(mat(64, 32, [&](int c, int k) { return (c < E2 && k < E1) ? W2(k, c) : 0.0; }), 0));
+    op.push_back(hi_lo(mat(112, 64, [&](int c, int k) { return (c < M && k < E2) ? W3(k, c) : 0.0; }), 0));
+    op.push_back(hi_lo(mat(64, 112, [&](int c, int k) { return (c < E2 && k < M) ? W3(c, k) : 0.0; }), 0));
+    op.push_back(hi_lo(mat(32, 64, [&](int c, int k) { return (c < E1 && k < E2) ? W2(c, k) : 0.0; }), 0));
+    for (int a = 0; a < NATTN; ++a) {
+      std::vector<double> qk((size_t)M * M), vo((size_t)M * M);
+      for (int r = 0; r < M; ++r)
+        for (int c = 0; c < M; ++c) {
+          double s1 = 0, s2 = 0;
+          for (int q = 0; q < DATTN; ++q) {
+            s1 += h.WQ[a][(size_t)r * DATTN + q] * h.WK[a][(size_t)c * DATTN + q];
+            s2 += h.WV[a][(size_t)r * DATTN + q] * h.WO[a][(size_t)q * M + c];
+          }
+          qk[(size_t)r * M + c] = s1 * isd;
+          vo[(size_t)r * M + c] = s2;
+        }
+      auto at = [](const std::vector<double> &v, int r, int c) { return (r < M && c < M) ? v[(size_t)r * M + c] : 0.0; };
+      op.push_back(hi_lo(mat(112, 112, [&](int c, int k) { return at(qk, k, c); }), 0));
+      op.push_back(hi_lo(mat(112, 112, [&](int c, int k) { return at(qk, c, k); }), 0));
+      op.push_back(hi_lo(mat(112, 112, [&](int c, int k) { return at(vo, k, c); }), 0));
+      op.push_back(hi_lo(mat(112, 112, [&](int c, int k) { return at(vo, c, k); }), 0));
+    }
+    auto F = [&](const std::vector<double> &v, int ld, int r, int c) { return v[(size_t)r * ld + c]; };
+    const auto f1t = mat(FH, ND, [&](int c, int k) { return F(h.F1, FH, k, c); });
+    const auto f1 = mat(ND, 256, [&](int c, int k) { return k < FH ? F(h.F1, FH, c, k) : 0.0; });
+    const auto f2t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, k, c) : 0.0; });
+    const auto f2 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, c, k) : 0.0; });
+    const auto f3t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, k, c) : 0.0; });
+    const auto f3 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, c, k) : 0.0; });
+    for (const auto *v : {&f1t, &f1, &f2t, &f2, &f3t, &f3}) {
+      op.push_back(hi_lo(*v, 0));
+      op.push_back(hi_lo(*v, 1));
+    }
+  }
   HIP_TRY(hipMalloc(&m->wbuf, pk.bytes.size()));
   HIP_TRY(hipMemcpy(m->wbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
   const float c4 = (float)h.c4[0];
-  bind_weights(m->wf, (const unsigned char *)m->wbuf, o, c4);
-  bind_weights(m->wb, (const unsigned char *)m->wbuf, o, c4);
+  const unsigned char *base = (const unsigned char *)m->wbuf;
+  bind_weights(m->wf, base, o, c4);
+  bind_weights(m->wb, base, o, c4);
+  if (pr == DP_BF16) {
+    int k = 0;
+    auto P = [&]() { return (const bf16_t *)(base + op[k++]); };
+    WeightsB16 &w = m->wp;
+    w.W2T = P(); w.W3T = P(); w.W3 = P(); w.W2 = P();
+    for (int a = 0; a < NATTN; ++a) {
+      w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P();
+    }
+    w.F1T[0] = P(); w.F1T[1] = P(); w.F1[0] = P(); w.F1[1] = P();
+    w.F2T[0] = P(); w.F2T[1] = P(); w.F2[0] = P(); w.F2[1] = P();
+    w.F3T[0] = P(); w.F3T[1] = P(); w.F3[0] = P(); w.F3[1] = P();
+  }
   return DP_OK;
 }
 
@@ -242,7 +311,8 @@ int ensure_ws(dp_model *m, int64_t n) {
   HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
   HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
   HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
-  HIP_TRY(hipMalloc(&ws.D, cap * (size_t)ND * sizeof(float)));
+  HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
+  HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
   HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));
   HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
   HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
@@ -331,14 +401,23 @@ int run_step(dp_model *m, const Weights<T> &w, int n, const double *X, const int
   const float rc = (float)m->rc, rcs = (float)m->rcs, eps = (float)m->ln_eps;
   const bool bwd = d_forces || d_virial;
   mark(m, 1, st);
-  launch_descriptor_fwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+  if (m->prec == DP_BF16)
+    launch_descriptor_fwd_b16(m->wb, m->wp, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+  else
+    launch_descriptor_fwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
   mark(m, 2, st);
-  launch_fitting<T>(w, ws, types, n, bwd, st);
+  if (m->prec == DP_BF16)
+    launch_fitting_b16(m->wb, m->wp, ws, types, n, bwd, st);
+  else
+    launch_fitting<T>(w, ws, types, n, bwd, st);
   mark(m, 3, st);
   launch_energy(ws, n, d_energy, d_atom_energy, st);
   mark(m, 4, st);
   if (bwd) {
-    launch_descriptor_bwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+    if (m->prec == DP_BF16)
+      launch_descriptor_bwd_b16(m->wb, m->wp, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+    else
+      launch_descriptor_bwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
     mark(m, 5, st);
     double *F = d_forces;
     if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
@@ -525,8 +604,8 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
     launch_fitting<float>(m->wf, ws, m->fwd_types, n, true, st);
     launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
   } else {
-    launch_fitting<bf16_t>(m->wb, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd<bf16_t>(m->wb, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
+    launch_fitting_b16(m->wb, m->wp, ws, m->fwd_types, n, true, st);
+    launch_descriptor_bwd_b16(m->wb, m->wp, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
   }
   launch_forces(ws, m->fwd_coords, n, g, gdev, d_grad_energy, d_grad_coords, d_virial, st);
   HIP_TRY(hipGetLastError());

@@ -23,55 +23,10 @@
 // NP x NP score matrix never exists as a whole.  All cross-wave sums go through
 // per-wave partial arrays added in a fixed order: results do not depend on
 // scheduling.
-#include "dp_internal.h"
+#include "dp_env.h"
 
 namespace dp {
 namespace {
-
-__device__ __forceinline__ int clamp_type(int t) { return t < 0 ? 0 : (t >= NTYPES ? NTYPES - 1 : t); }
-
-struct Env {
-  float s[NPMAX], sw[NPMAX], dsw[NPMAX], r[NPMAX];
-  float rh[NPMAX * 3];
-  float Rt[NPMAX * 4];
-  int tj[NPMAX];
-};
-
-// Environment of atom i: tokens j < n from the neighbour list, padded tokens zero.
-__device__ void build_env(Env &e, const double *__restrict__ X, const int *__restrict__ types,
-                          const int *__restrict__ nlist, int i, int n, int natoms, const Grid &g, float rc,
-                          float rcs) {
-  for (int j = threadIdx.x; j < NPMAX; j += NTHREADS) {
-    float s = 0.f, sw = 0.f, dsw = 0.f, r = 1.f, hx = 0.f, hy = 0.f, hz = 0.f;
-    int tj = 0;
-    if (j < n) {
-      int nj = nlist[(size_t)i * SEL + j];
-      if (nj < 0 || nj >= natoms) nj = i;  // never read outside the coordinate array
-      tj = clamp_type(types[nj]);
-      double d[3];
-      for (int a = 0; a < 3; ++a) {
-        double v = X[3 * nj + a] - X[3 * i + a];
-        if (g.periodic) v -= g.L[a] * rint(v * g.invL[a]);
-        d[a] = v;
-      }
-      const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
-      r = sqrtf(dx * dx + dy * dy + dz * dz);
-      const float u = (r - rcs) / (rc - rcs);
-      if (r < rcs) {
-        sw = 1.f;
-      } else if (r < rc) {
-        sw = u * u * u * (-6.f * u * u + 15.f * u - 10.f) + 1.f;
-        dsw = -30.f * u * u * (1.f - u) * (1.f - u) / (rc - rcs);
-      }
-      s = sw / r;
-      hx = dx / r; hy = dy / r; hz = dz / r;
-    }
-    e.s[j] = s; e.sw[j] = sw; e.dsw[j] = dsw; e.r[j] = r;
-    e.rh[3 * j] = hx; e.rh[3 * j + 1] = hy; e.rh[3 * j + 2] = hz;
-    e.Rt[4 * j] = s; e.Rt[4 * j + 1] = s * hx; e.Rt[4 * j + 2] = s * hy; e.Rt[4 * j + 3] = s * hz;
-    e.tj[j] = tj;
-  }
-}
 
 // Embedding net for the 16 rows of block jb: writes h1 -> h1b, h2 -> h2b, G rows -> Gout.
 template <typename T>
@@ -631,19 +586,7 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
       float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
       if (j < n) {
         const float ds_emb = sm.red[(0 * 16 + r) * 8] + sm.red[(1 * 16 + r) * 8];
-        const float s = sm.e.s[j], sw = sm.e.sw[j], rr = sm.e.r[j];
-        const float hx = sm.e.rh[3 * j], hy = sm.e.rh[3 * j + 1], hz = sm.e.rh[3 * j + 2];
-        const float *dR = sm.dRt + 4 * j;
-        const float ds = ds_emb + dR[0] + dR[1] * hx + dR[2] * hy + dR[3] * hz;
-        const float gx = sm.drh[3 * j] + s * dR[1];
-        const float gy = sm.drh[3 * j + 1] + s * dR[2];
-        const float gz = sm.drh[3 * j + 2] + s * dR[3];
-        const float dswt = sm.dswa[j] + ds / rr;
-        const float dr = -ds * sw / (rr * rr) + dswt * sm.e.dsw[j];
-        const float proj = gx * hx + gy * hy + gz * hz;
-        out.x = (gx - proj * hx) / rr + dr * hx;
-        out.y = (gy - proj * hy) / rr + dr * hy;
-        out.z = (gz - proj * hz) / rr + dr * hz;
+        out = pair_gradient(sm.e, j, ds_emb, sm.dRt + 4 * j, sm.drh + 3 * j, sm.dswa[j]);
       }
       if (j < SEL) gout[(size_t)i * SEL + j] = out;
     }

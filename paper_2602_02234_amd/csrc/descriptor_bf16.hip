@@ -1,0 +1,781 @@
+// Per-atom descriptor kernels of the bfloat16 path (gfx950 MFMA, fp32 accumulation).
+//
+// Same model as descriptor.hip (environment, type-embedded embedding net, two
+// switch-weighted gated self-attention layers with a residual LayerNorm update,
+// descriptor T = G^T Rt / sel, D = T T_<16^T), organised for throughput:
+//
+//  * every wave owns whole 16-token row blocks and carries them through a layer
+//    (U = G Wqk, S = U G^T, softmax, H = A G, Y = H Wvo, LayerNorm) in registers,
+//    so a layer needs two workgroup barriers instead of one per product;
+//  * the representation G lives in LDS twice as bf16, token-major (Gb) and
+//    feature-major (GbT), so that every MFMA fragment -- whichever index is the
+//    reduction index -- is one 16-byte load; the fp32 master copy of the wave's
+//    own rows stays in registers (residual and LayerNorm in fp32);
+//  * weights come pre-padded and k-contiguous from global memory (L2-resident);
+//  * feature width 100 is padded to 112 and contracted as 3 x 32 + 16 along k.
+// Backward: the forward is recomputed in the kernel (nothing is stored between
+// the two kernels but T); the terms of dG that couple a token to every query row
+// (A^T dH and dS^T U) are gathered in a second pass in which wave w recomputes
+// the score and score-gradient tiles of its own token block against every query
+// block from U and dH kept in LDS.  That pass uses the 16x16x16 MFMA, whose
+// A-operand lane layout equals the accumulator layout, so the recomputed tiles
+// feed the transposed product without any data movement.
+#include "dp_env.h"
+
+namespace dp {
+namespace {
+
+constexpr int KM = 112;   // padded feature width
+constexpr int LDK = 120;  // stride (elements) of [token][feature] bf16 arrays
+constexpr int LDT = 136;  // stride of [feature or row][token] bf16 arrays (tokens padded to 128)
+constexpr int NWF = 8;    // waves per workgroup, forward
+constexpr int NWB = 4;    // waves per workgroup, backward
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf8 ld8(const bf16_t *p) { return *(const bf8 *)p; }
+__device__ __forceinline__ s4 ld4(const bf16_t *p) { return *(const s4 *)p; }
+__device__ __forceinline__ short bfbits(float x) {
+  const bf16_t b = (bf16_t)x;
+  return *(const short *)&b;
+}
+// Orders this wave's LDS accesses across a point (the wave reuses its staging buffer).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// acc[t] += A(16 x K) . B_t(16 x K)^T for t < nt; A rows at a (stride lda); B_t rows
+// at b + 16 t ldb (stride ldb); K a multiple of 16; operands bf16, k contiguous.
+template <int NT>
+__device__ __forceinline__ void mm(f4 (&acc)[NT], const bf16_t *a, int lda, const bf16_t *b, int ldb, int K, int nt) {
+  const int l = lane_id(), r = l & 15, q = l >> 4;
+  int k0 = 0;
+  for (; k0 + 32 <= K; k0 += 32) {
+    const bf8 x = ld8(a + r * lda + k0 + 8 * q);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (t < nt) {
+        const bf8 y = ld8(b + (16 * t + r) * ldb + k0 + 8 * q);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[t], 0, 0, 0);
+      }
+  }
+  if (k0 < K) {
+    const s4 x = ld4(a + r * lda + k0 + 4 * q);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (t < nt) {
+        const s4 y = ld4(b + (16 * t + r) * ldb + k0 + 4 * q);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc[t], 0, 0, 0);
+      }
+  }
+}
+
+// Same with the A operand held as fp32 in LDS (rounded to bf16 when loaded); K multiple of 32.
+template <int NT>
+__device__ __forceinline__ void mm_a32(f4 (&acc)[NT], const float *a, int lda, const bf16_t *b, int ldb, int K) {
+  const int l = lane_id(), r = l & 15, q = l >> 4;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf8 x;
+    const float *ap = a + r * lda + k0 + 8 * q;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = (__bf16)ap[e];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bf8 y = ld8(b + (16 * t + r) * ldb + k0 + 8 * q);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+template <int NT> __device__ __forceinline__ void zero(f4 (&a)[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) a[t] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Writes the wave's 16 rows (block jb; fp32 tiles gv, columns 16 t + lane%16) into
+// Gb (token-major) and GbT (feature-major) as bf16; columns >= M are written as zero.
+__device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)[7], int jb) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const int m = 16 * t + cl;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = jb * 16 + 4 * q + ii;
+      const bf16_t v = (bf16_t)(m < M ? gv[t][ii] : 0.f);
+      Gb[j * LDK + m] = v;
+      GbT[m * LDT + j] = v;
+    }
+  }
+}
+
+// Embedding net for the wave's rows (block jb) -> G (fp32 tiles).  h1 is staged (fp32) in
+// scr1 (>= 512 floats), h2 in scr2 (>= 1024 floats); both wave-private.
+__device__ void embed_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, const Env &e, int ti, int jb, float *scr1,
+                           float *scr2, f4 (&gv)[7]) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+  for (int x = l; x < 16 * 32; x += 64) {
+    const int r = x >> 5, c = x & 31, j = jb * 16 + r;
+    scr1[r * 32 + c] = c < E1 ? tanhf(e.s[j] * w.w1s[c] + w.Bt[(ti * NTYPES + e.tj[j]) * E1 + c]) : 0.f;
+  }
+  wave_fence();
+  f4 a2[4];
+  zero(a2);
+  mm_a32<4>(a2, scr1, 32, wp.W2T, 32, 32);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = 16 * t + cl;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = 4 * q + ii;
+      scr2[r * 64 + c] = c < E2 ? tanhf(a2[t][ii] + w.b2[c]) + scr1[r * 32 + (c % E1)] : 0.f;
+    }
+  }
+  wave_fence();
+  f4 a3[7];
+  zero(a3);
+  mm_a32<7>(a3, scr2, 64, wp.W3T, 64, 64);
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const int m = 16 * t + cl;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = 4 * q + ii;
+      gv[t][ii] = m < M ? tanhf(a3[t][ii] + w.b3[m]) + scr2[r * 64 + (m % E2)] : 0.f;
+    }
+  }
+  wave_fence();
+}
+
+// Scores of the wave's rows (block jb) against every token -> row softmax weights.
+// sv holds S on entry and E = exp(S - m)/Z on exit (0 for invalid tokens); the
+// attention weights A = sw_k E gate_jk are written (bf16) to stg [16][LDT].
+// Optionally records the row max and 1/Z (rmax, rz) for a later recomputation.
+__device__ __forceinline__ void softmax_rows(f4 (&sv)[8], const Env &e, int jb, int n, int nb, bf16_t *stg,
+                                             float *rmax, float *rz) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const int r = 4 * q + ii, j = jb * 16 + r;
+    float mx = -INFINITY;
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct)
+      if (ct < nb && 16 * ct + cl < n) mx = fmaxf(mx, sv[ct][ii]);
+    mx = max16(mx);
+    if (mx == -INFINITY) mx = 0.f;
+    float z = 0.f;
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+      const int k = 16 * ct + cl;
+      const float ex = (ct < nb && k < n) ? expf(sv[ct][ii] - mx) : 0.f;
+      sv[ct][ii] = ex;
+      z += (ct < nb) ? e.sw[k] * ex : 0.f;
+    }
+    z = sum16(z);
+    const float iz = z > 0.f ? 1.f / z : 0.f;
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct)
+      if (ct < nb) {
+        const int k = 16 * ct + cl;
+        const float E = sv[ct][ii] * iz;
+        sv[ct][ii] = E;
+        stg[r * LDT + k] = (bf16_t)(e.sw[k] * E * gate(e, j, k));
+      }
+    if (rmax && cl == 0) {
+      rmax[j] = mx;
+      rz[j] = iz;
+    }
+  }
+}
+
+// Stages fp32 tiles (columns 16 t + lane%16, t < 7) into stg [16][LDT] as bf16.
+__device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+#pragma unroll
+  for (int t = 0; t < 7; ++t)
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) stg[(4 * q + ii) * LDT + 16 * t + cl] = (bf16_t)v[t][ii];
+}
+
+// One attention layer forward for the wave's rows: gv (G_in, fp32) -> gv (G_out).
+// Also returns xh (normalised residual) and isig (1/sigma per accumulator row).
+// If Uall is given, U rows are written there (and read from there for S).
+__device__ void layer_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, const Env &e, const bf16_t *Gb,
+                           const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
+                           f4 (&gv)[7], f4 (&sv)[8], f4 (&xh)[7], float (&isig)[4], float *rmax, float *rz) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+  f4 acc[7];
+  zero(acc);
+  mm<7>(acc, Gb + jb * 16 * LDK, LDK, wp.WqkT[layer], KM, KM, 7);  // U = G Wqk
+  const bf16_t *ua;
+  int lda;
+  if (Uall) {
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) Uall[(jb * 16 + 4 * q + ii) * LDK + 16 * t + cl] = (bf16_t)acc[t][ii];
+    ua = Uall + jb * 16 * LDK;
+    lda = LDK;
+  } else {
+    stage7(stg, acc);
+    ua = stg;
+    lda = LDT;
+  }
+  wave_fence();
+  zero(sv);
+  mm<8>(sv, ua, lda, Gb, LDK, KM, nb);  // S = U G^T
+  wave_fence();
+  softmax_rows(sv, e, jb, n, nb, stg, rmax, rz);
+  wave_fence();
+  zero(acc);
+  mm<7>(acc, stg, LDT, GbT, LDT, NP, 7);  // H = A G
+  wave_fence();
+  stage7(stg, acc);
+  wave_fence();
+  zero(acc);
+  mm<7>(acc, stg, LDT, wp.WvoT[layer], KM, KM, 7);  // Y = H Wvo
+  wave_fence();
+  // X = G + Y;  G <- gamma (X - mu) / sigma + beta
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    float s1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      const float x = (16 * t + cl < M) ? gv[t][ii] + acc[t][ii] : 0.f;
+      xh[t][ii] = x;
+      s1 += x;
+    }
+    const float mu = sum16(s1) * (1.f / M);
+    float s2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      const float d = (16 * t + cl < M) ? xh[t][ii] - mu : 0.f;
+      s2 += d * d;
+    }
+    isig[ii] = 1.f / sqrtf(sum16(s2) * (1.f / M) + ln_eps);
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      const int m = 16 * t + cl;
+      const float xn = (m < M) ? (xh[t][ii] - mu) * isig[ii] : 0.f;
+      xh[t][ii] = xn;
+      gv[t][ii] = (m < M) ? w.gamma[layer][m] * xn + w.beta[layer][m] : 0.f;
+    }
+  }
+}
+
+// ======================================================================== forward
+struct __align__(16) SmemF16 {
+  bf16_t Gb[NPMAX * LDK];
+  bf16_t GbT[KM * LDT];
+  bf16_t stg[NWF][16 * LDT];
+  Env e;
+};
+
+__global__ void __launch_bounds__(NWF * 64)
+k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+               const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dg,
+               float rc, float rcs, float ln_eps, float *__restrict__ Tsave, float *__restrict__ D) {
+  __shared__ SmemF16 sm;
+  const int i = blockIdx.x;
+  const Grid g = dg ? *dg : hg;
+  const int n = min(max(nnei[i], 0), SEL);
+  const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
+  const int nb = NP / 16;
+  const int ti = clamp_type(types[i]);
+  const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
+  build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
+  __syncthreads();
+  const bool act = wv < nb;
+  const int jb = wv;
+  bf16_t *stg = sm.stg[wv];
+  f4 gv[7];
+  if (act) {
+    // h1 scratch in this wave's own (not yet written) rows of Gb, h2 in its staging buffer
+    embed_rows(w, wp, sm.e, ti, jb, (float *)(sm.Gb + jb * 16 * LDK), (float *)stg, gv);
+    put_rows(sm.Gb, sm.GbT, gv, jb);
+  }
+  __syncthreads();
+  for (int layer = 0; layer < NATTN; ++layer) {
+    f4 sv[8], xh[7];
+    float isig[4];
+    if (act)
+      layer_rows(w, wp, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv, sv, xh, isig, nullptr,
+                 nullptr);
+    __syncthreads();
+    if (act) put_rows(sm.Gb, sm.GbT, gv, jb);
+    __syncthreads();
+  }
+  // T = G^T Rt / sel: per-wave partial over its rows, then a fixed-order sum over waves
+  float *tp = (float *)sm.stg[wv];
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      const int m = 16 * t + cl;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float p = 0.f;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = jb * 16 + 4 * q + ii;
+          p += (j < n) ? gv[t][ii] * sm.e.Rt[4 * j + c] : 0.f;
+        }
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        if (q == 0 && m < M) tp[m * 4 + c] = p;
+      }
+    }
+  }
+  __syncthreads();
+  float *T = (float *)sm.GbT;
+  for (int x = threadIdx.x; x < M * 4; x += NWF * 64) {
+    float acc = 0.f;
+    for (int v = 0; v < nb; ++v) acc += ((float *)sm.stg[v])[x];
+    acc *= 1.f / (float)SEL;
+    T[x] = acc;
+    Tsave[(size_t)i * M * 4 + x] = acc;
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < ND; x += NWF * 64) {
+    const int m = x / M2, a = x % M2;
+    const float *tm = T + 4 * m, *ta = T + 4 * a;
+    D[(size_t)i * ND + x] = tm[0] * ta[0] + tm[1] * ta[1] + tm[2] * ta[2] + tm[3] * ta[3];
+  }
+}
+
+// ======================================================================== backward
+struct __align__(16) SmemB16 {
+  bf16_t Gb[NPMAX * LDK];
+  bf16_t GbT[KM * LDT];
+  bf16_t Uall[NPMAX * LDK];
+  bf16_t dHall[NPMAX * LDK];
+  bf16_t stg[NWB][16 * LDT];
+  Env e;
+  float rmax[NPMAX], rz[NPMAX], rrho[NPMAX];
+  float drh[NPMAX * 3];
+  float dswa[NPMAX];
+  float dRt[NPMAX * 4];
+  float T[M * 4], dT[M * 4];
+};
+
+// Backward of one layer for the wave's blocks.  gin: layer input rows (fp32), dg: on entry
+// the gradient w.r.t. the layer output (ignored for the top layer, whose output gradient
+// is Rt dT^T / sel), on exit w.r.t. the layer input.  colw/colc: per-lane column sums of the
+// softmax-weight gradient W and of dC rhat_j over this wave's rows (token columns 16 ct + lane%16).
+__device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top, SmemB16 &sm, int n,
+                          int nb, int NP, float ln_eps, const f4 (&gin)[2][7], f4 (&dg)[2][7], float (&colw)[8],
+                          float (&colc)[8][3]) {
+  const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
+  bf16_t *stg = sm.stg[wv];
+  const float inv_sel = 1.f / (float)SEL;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int jb = wv + NWB * b;
+    if (jb >= nb) continue;
+    f4 gcur[7], sv[8], xh[7];
+    float isig[4];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) gcur[t] = gin[b][t];
+    layer_rows(w, wp, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP, ln_eps, gcur, sv, xh, isig, sm.rmax,
+               sm.rz);
+    // incoming gradient of the layer output and, for the top layer, dRt = G_out dT / sel
+    f4 go[7];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = jb * 16 + 4 * q + ii;
+      float pr[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const int m = 16 * t + cl;
+        float v = 0.f;
+        if (m < M) {
+          if (top) {
+            const float *dTm = sm.dT + 4 * m;
+            const float *R = sm.e.Rt + 4 * j;
+            v = (R[0] * dTm[0] + R[1] * dTm[1] + R[2] * dTm[2] + R[3] * dTm[3]) * inv_sel;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pr[c] += gcur[t][ii] * dTm[c];
+          } else {
+            v = dg[b][t][ii];
+          }
+        }
+        go[t][ii] = v;
+      }
+      if (top) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float p = sum16(pr[c]) * inv_sel;
+          if (cl == 0) sm.dRt[4 * j + c] += p;
+        }
+      }
+    }
+    // LayerNorm backward: dX = (dxh - mean(dxh) - xh mean(dxh xh)) / sigma, dxh = gamma dG_out
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const int m = 16 * t + cl;
+        const float d = (m < M) ? w.gamma[layer][m] * go[t][ii] : 0.f;
+        go[t][ii] = d;
+        s0 += d;
+        s1 += d * xh[t][ii];
+      }
+      s0 = sum16(s0) * (1.f / M);
+      s1 = sum16(s1) * (1.f / M);
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const int m = 16 * t + cl;
+        dg[b][t][ii] = (m < M) ? (go[t][ii] - s0 - xh[t][ii] * s1) * isig[ii] : 0.f;  // dG_in starts as dX
+      }
+    }
+    wave_fence();
+    stage7(stg, dg[b]);  // dY = dX
+    wave_fence();
+    f4 acc[7];
+    zero(acc);
+    mm<7>(acc, stg, LDT, wp.Wvo[layer], KM, KM, 7);  // dH = dY Wvo^T
+#pragma unroll
+    for (int t = 0; t < 7; ++t)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) sm.dHall[(jb * 16 + 4 * q + ii) * LDK + 16 * t + cl] = (bf16_t)acc[t][ii];
+    wave_fence();
+    f4 da[8];
+    zero(da);
+    mm<8>(da, sm.dHall + jb * 16 * LDK, LDK, sm.Gb, LDK, KM, nb);  // dA = dH G^T
+    wave_fence();
+    // weighted-softmax and gate backward
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = 4 * q + ii, j = jb * 16 + r;
+      const bool jv = j < n;
+      float rho = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct) {
+        const int k = 16 * ct + cl;
+        if (ct < nb && jv && k < n) {
+          const float P = sm.e.sw[k] * sv[ct][ii];
+          const float gt = gate(sm.e, j, k);
+          const float dP = da[ct][ii] * gt;
+          const float dC = da[ct][ii] * P;
+          rho += P * dP;
+          hx += dC * sm.e.rh[3 * k];
+          hy += dC * sm.e.rh[3 * k + 1];
+          hz += dC * sm.e.rh[3 * k + 2];
+          colc[ct][0] += dC * sm.e.rh[3 * j];
+          colc[ct][1] += dC * sm.e.rh[3 * j + 1];
+          colc[ct][2] += dC * sm.e.rh[3 * j + 2];
+          da[ct][ii] = dP;
+        } else {
+          da[ct][ii] = 0.f;
+        }
+      }
+      rho = sum16(rho);
+      hx = sum16(hx);
+      hy = sum16(hy);
+      hz = sum16(hz);
+      if (cl == 0) {
+        sm.rrho[j] = rho;
+        sm.drh[3 * j] += hx;
+        sm.drh[3 * j + 1] += hy;
+        sm.drh[3 * j + 2] += hz;
+      }
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct)
+        if (ct < nb) {
+          const int k = 16 * ct + cl;
+          const float W = (jv && k < n) ? sv[ct][ii] * (da[ct][ii] - rho) : 0.f;
+          colw[ct] += W;
+          stg[r * LDT + k] = (bf16_t)(sm.e.sw[k] * W);  // dS
+        }
+    }
+    wave_fence();
+    zero(acc);
+    mm<7>(acc, stg, LDT, sm.GbT, LDT, NP, 7);  // dU = dS G
+    wave_fence();
+    stage7(stg, acc);
+    wave_fence();
+    zero(acc);
+    mm<7>(acc, stg, LDT, wp.Wqk[layer], KM, KM, 7);  // dG += dU Wqk^T
+#pragma unroll
+    for (int t = 0; t < 7; ++t) dg[b][t] += acc[t];
+    wave_fence();
+  }
+  __syncthreads();
+  // column pass: dG[k] += sum_j A_jk dH_j + dS_jk U_j for the wave's own token blocks
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int kb = wv + NWB * b;
+    if (kb >= nb) continue;
+    const int k = kb * 16 + cl;
+    const bool kv = k < n;
+    f4 cacc[7];
+    zero(cacc);
+    for (int jb = 0; jb < nb; ++jb) {
+      f4 st[1], dt[1];
+      zero(st);
+      zero(dt);
+      mm<1>(st, sm.Uall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
+      mm<1>(dt, sm.dHall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
+      s4 xa, xs;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int j = jb * 16 + 4 * q + ii;
+        float A = 0.f, dS = 0.f;
+        if (kv && j < n) {
+          const float E = expf(st[0][ii] - sm.rmax[j]) * sm.rz[j];
+          const float P = sm.e.sw[k] * E;
+          const float gt = gate(sm.e, j, k);
+          A = P * gt;
+          dS = sm.e.sw[k] * E * (dt[0][ii] * gt - sm.rrho[j]);
+        }
+        xa[ii] = bfbits(A);
+        xs[ii] = bfbits(dS);
+      }
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const int m = 16 * t + cl;
+        s4 yh, yu;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = jb * 16 + 4 * q + ii;
+          const bf16_t vh = sm.dHall[j * LDK + m], vu = sm.Uall[j * LDK + m];
+          yh[ii] = *(const short *)&vh;
+          yu[ii] = *(const short *)&vu;
+        }
+        cacc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, yh, cacc[t], 0, 0, 0);
+        cacc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xs, yu, cacc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 7; ++t) dg[b][t] += cacc[t];
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(NWB * 64)
+k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+               const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dgr,
+               float rc, float rcs, float ln_eps, const float *__restrict__ Tsave, const float *__restrict__ dD,
+               float4 *__restrict__ gout) {
+  __shared__ SmemB16 sm;
+  const int i = blockIdx.x;
+  const Grid g = dgr ? *dgr : hg;
+  const int n = min(max(nnei[i], 0), SEL);
+  const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
+  const int nb = NP / 16;
+  const int ti = clamp_type(types[i]);
+  const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
+  build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
+  for (int x = threadIdx.x; x < NPMAX; x += NWB * 64) {
+    sm.dswa[x] = 0.f;
+    for (int a = 0; a < 3; ++a) sm.drh[3 * x + a] = 0.f;
+    for (int a = 0; a < 4; ++a) sm.dRt[4 * x + a] = 0.f;
+  }
+  for (int x = threadIdx.x; x < M * 4; x += NWB * 64) sm.T[x] = Tsave[(size_t)i * M * 4 + x];
+  __syncthreads();
+  const float *dDi = dD + (size_t)i * ND;
+  for (int x = threadIdx.x; x < M * 4; x += NWB * 64) {
+    const int m = x >> 2, c = x & 3;
+    float acc = 0.f;
+    for (int a = 0; a < M2; ++a) acc += dDi[m * M2 + a] * sm.T[4 * a + c];
+    if (m < M2)
+      for (int mm2 = 0; mm2 < M; ++mm2) acc += dDi[mm2 * M2 + m] * sm.T[4 * mm2 + c];
+    sm.dT[x] = acc;
+  }
+  // G0 = embedding of the wave's rows (fp32 in registers, bf16 in LDS)
+  f4 g0[2][7], g1[2][7], dg[2][7];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int jb = wv + NWB * b;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) g0[b][t] = g1[b][t] = dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
+    if (jb < nb) {
+      embed_rows(w, wp, sm.e, ti, jb, (float *)(sm.Uall + jb * 16 * LDK), (float *)sm.stg[wv], g0[b]);
+      put_rows(sm.Gb, sm.GbT, g0[b], jb);
+    }
+  }
+  __syncthreads();
+  // G1 = first layer applied to G0
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int jb = wv + NWB * b;
+    if (jb >= nb) continue;
+    f4 sv[8], xh[7];
+    float isig[4];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) g1[b][t] = g0[b][t];
+    layer_rows(w, wp, 0, sm.e, sm.Gb, sm.GbT, sm.stg[wv], nullptr, jb, n, nb, NP, ln_eps, g1[b], sv, xh, isig, nullptr,
+               nullptr);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+    if (wv + NWB * b < nb) put_rows(sm.Gb, sm.GbT, g1[b], wv + NWB * b);
+  __syncthreads();
+  float colw[8], colc[8][3];
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct) colw[ct] = colc[ct][0] = colc[ct][1] = colc[ct][2] = 0.f;
+  layer_bwd(w, wp, 1, true, sm, n, nb, NP, ln_eps, g1, dg, colw, colc);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+    if (wv + NWB * b < nb) put_rows(sm.Gb, sm.GbT, g0[b], wv + NWB * b);
+  __syncthreads();
+  layer_bwd(w, wp, 0, false, sm, n, nb, NP, ln_eps, g0, dg, colw, colc);
+  // column sums of the softmax-weight and gate gradients: lanes -> per-wave -> fixed-order total
+  float *cp = (float *)sm.Uall;  // [NWB][NPMAX][4]
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct) {
+    float v0 = colw[ct], v1 = colc[ct][0], v2 = colc[ct][1], v3 = colc[ct][2];
+    v0 = sum_cols4(v0);
+    v1 = sum_cols4(v1);
+    v2 = sum_cols4(v2);
+    v3 = sum_cols4(v3);
+    if (q == 0) {
+      float *o = cp + (wv * NPMAX + 16 * ct + cl) * 4;
+      o[0] = v0; o[1] = v1; o[2] = v2; o[3] = v3;
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < NP; x += NWB * 64) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int v = 0; v < NWB; ++v) {
+      const float *o = cp + (v * NPMAX + x) * 4;
+      a0 += o[0]; a1 += o[1]; a2 += o[2]; a3 += o[3];
+    }
+    sm.dswa[x] += a0;
+    sm.drh[3 * x] += a1;
+    sm.drh[3 * x + 1] += a2;
+    sm.drh[3 * x + 2] += a3;
+  }
+  __syncthreads();
+  // embedding backward and the pair gradients of the wave's rows
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int jb = wv + NWB * b;
+    if (jb >= nb) continue;
+    float *h1 = (float *)(sm.dHall + jb * 16 * LDK);  // [16][32]
+    float *h2 = (float *)sm.stg[wv];                  // [16][64]
+    float *sc = (float *)sm.GbT + wv * 16 * 104;      // [16][104] fp32: dG0 rows, then dh2 (GbT is free now)
+    // recompute h1, t2, h2 (fp32) for these rows
+    for (int x = l; x < 16 * 32; x += 64) {
+      const int r = x >> 5, c = x & 31, j = jb * 16 + r;
+      h1[r * 32 + c] = c < E1 ? tanhf(sm.e.s[j] * w.w1s[c] + w.Bt[(ti * NTYPES + sm.e.tj[j]) * E1 + c]) : 0.f;
+    }
+    wave_fence();
+    f4 a2[4];
+    zero(a2);
+    mm_a32<4>(a2, h1, 32, wp.W2T, 32, 32);
+    float t2v[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 16 * t + cl;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 4 * q + ii;
+        const float tt = c < E2 ? tanhf(a2[t][ii] + w.b2[c]) : 0.f;
+        t2v[t][ii] = tt;
+        h2[r * 64 + c] = c < E2 ? tt + h1[r * 32 + (c % E1)] : 0.f;
+      }
+    }
+    wave_fence();
+    f4 a3[7];
+    zero(a3);
+    mm_a32<7>(a3, h2, 64, wp.W3T, 64, 64);
+    // dpre3 = dG0 (1 - t3^2) staged as bf16; dG0 half sums (cols c and c + 50) into sc
+    wave_fence();
+    bf16_t *stg = sm.stg[wv];  // aliases h2, which is no longer needed
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      const int m = 16 * t + cl;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 4 * q + ii;
+        const float t3 = m < M ? tanhf(a3[t][ii] + w.b3[m]) : 0.f;
+        a3[t][ii] = m < M ? dg[b][t][ii] * (1.f - t3 * t3) : 0.f;
+        if (m < M) sc[r * 104 + m] = dg[b][t][ii];
+      }
+    }
+    wave_fence();
+    stage7(stg, a3);  // dpre3 (bf16) over h2 (no longer needed)
+    wave_fence();
+    // dh2 = dpre3 W3^T + (dG0[:, :50] + dG0[:, 50:]);  dpre2 = dh2 (1 - t2^2)
+    f4 d2[4];
+    zero(d2);
+    mm<4>(d2, stg, LDT, wp.W3, KM, KM, 4);
+    wave_fence();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 16 * t + cl;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 4 * q + ii;
+        const float v = c < E2 ? d2[t][ii] + sc[r * 104 + c] + sc[r * 104 + c + E2] : 0.f;
+        d2[t][ii] = v;  // dh2
+      }
+    }
+    wave_fence();
+    // stage dpre2 (bf16, [16][64]) and dh2 halves sum (fp32, for dh1) in sc
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 16 * t + cl;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 4 * q + ii;
+        stg[r * LDT + c] = (bf16_t)(c < E2 ? d2[t][ii] * (1.f - t2v[t][ii] * t2v[t][ii]) : 0.f);
+        if (c < E2) sc[r * 104 + c] = d2[t][ii];
+      }
+    }
+    wave_fence();
+    // dh1 = dpre2 W2^T + (dh2[:, :25] + dh2[:, 25:]);  ds_emb = sum_c dh1 (1 - h1^2) w1s
+    f4 d1[2];
+    zero(d1);
+    mm<2>(d1, stg, LDT, wp.W2, 64, 64, 2);
+    float dse[4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = 4 * q + ii;
+      float p = 0.f;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = 16 * t + cl;
+        if (c < E1) {
+          const float dh1 = d1[t][ii] + sc[r * 104 + c] + sc[r * 104 + c + E1];
+          const float hv = h1[r * 32 + c];
+          p += dh1 * (1.f - hv * hv) * w.w1s[c];
+        }
+      }
+      dse[ii] = sum16(p);
+    }
+    // pair gradients (lane cl == ii handles row 4q + ii)
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = jb * 16 + 4 * q + ii;
+      if (cl == ii && j < SEL) {
+        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < n) out = pair_gradient(sm.e, j, dse[ii], sm.dRt + 4 * j, sm.drh + 3 * j, sm.dswa[j]);
+        gout[(size_t)i * SEL + j] = out;
+      }
+    }
+    wave_fence();
+  }
+  for (int j = NP + threadIdx.x; j < SEL; j += NWB * 64) gout[(size_t)i * SEL + j] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+}  // namespace
+
+void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
+                               float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, g,
+                     grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Tsave, ws.D);
+}
+
+void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
+                               float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_bwd_b16, dim3(n), dim3(NWB * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, g,
+                     grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Tsave, ws.D, ws.g);
+}
+
+}  // namespace dp

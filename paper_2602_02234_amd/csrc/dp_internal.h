@@ -57,6 +57,28 @@ template <typename T> struct Weights {
   const float *ebias; // [NTYPES]
 };
 
+// Extra device weights of the bfloat16 path: GEMM operands zero-padded to MFMA
+// tile multiples and stored [output column][k] (k contiguous, 16-byte rows), so
+// every MFMA fragment is one 16-byte load.  Feature width 100 is padded to 112,
+// embedding widths 25/50 to 32/64, the fitting width 240 to 256 along k.  The
+// fitting operands come as a two-term split w = hi + lo (both bf16).
+struct WeightsB16 {
+  const bf16_t *W2T;           // [64][32]    W2T[c][k] = W2[k][c]
+  const bf16_t *W3T;           // [112][64]   W3T[m][k] = W3[k][m]
+  const bf16_t *W3;            // [64][112]   W3[c][m]
+  const bf16_t *W2;            // [32][64]    W2[e1][e2]
+  const bf16_t *WqkT[NATTN];   // [112][112]  WqkT[c][k] = Wqk[k][c]
+  const bf16_t *Wqk[NATTN];    // [112][112]
+  const bf16_t *WvoT[NATTN];   // [112][112]
+  const bf16_t *Wvo[NATTN];    // [112][112]
+  const bf16_t *F1T[2];        // [240][1600] hi, lo
+  const bf16_t *F1[2];         // [1600][256]
+  const bf16_t *F2T[2];        // [240][256]
+  const bf16_t *F2[2];         // [240][256]
+  const bf16_t *F3T[2];        // [240][256]
+  const bf16_t *F3[2];         // [240][256]
+};
+
 struct Workspace {
   int64_t cap = 0;            // atoms
   int *cell_of = nullptr;     // [cap]
@@ -90,6 +112,7 @@ struct dp_model {
   void *wbuf = nullptr;
   dp::Weights<float> wf{};
   dp::Weights<dp::bf16_t> wb{};
+  dp::WeightsB16 wp{};
   dp::Workspace ws;
   // state kept between dp_compute_device (energy only) and dp_backward_device
   int64_t fwd_natoms = 0;
@@ -117,6 +140,14 @@ void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const doubl
 template <typename T>
 void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward,
                     hipStream_t st);
+void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
+                               float rc, float rcs, float ln_eps, hipStream_t st);
+void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
+                               float rc, float rcs, float ln_eps, hipStream_t st);
+void launch_fitting_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
+                        bool backward, hipStream_t st);
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
                            int n, const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps,
