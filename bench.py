@@ -30,28 +30,41 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}     # MI355X dense MFMA peaks, FLOP/s
 HBM_PEAK = 8.0e12
+METRIC = "atom-evals/s (E+F), BF16 vs FP32 path at fixed force RMSE; p50/p99 latency"
 
-# Multiply-accumulates per atom with n neighbours (model sizes: embedding 25/50/100,
-# fused attention products 100x100, descriptor 100x16, fitting 1600-240-240-240-1).
-EMB = 25 * 50 + 50 * 100          # per neighbour, one embedding pass
-LAYER_FWD = (2 * 100 * 100, 2 * 100)          # (per n, per n^2): U = G Wqk, Y = H Wvo ; S = U G^T, H = A G
-LAYER_BWD = (2 * 100 * 100, 4 * 100)          # dH, dU Wqk^T ; dA, A^T dH, dS G, dS^T U
-FIT_FWD = 1600 * 240 + 2 * 240 * 240 + 240
-FIT_BWD = 2 * 240 * 240 + 240 * 1600
+# Algorithmic multiply-accumulates per atom-eval with n neighbours, split by kernel.
+# Model sizes: embedding 1->25->50->100 (6,275 MAC per neighbour with the type part of
+# the first layer folded into a bias), attention M = 100, d = 128, two layers (forward
+# 4nMd + 2n^2 d, backward 4nMd + 4n^2 d; input gradients only), contraction T = G^T Rt
+# (400 n) and D = T T<^T (6,400), fitting 1600-240-240-240-1 (499,440 each way).
+# Sum: 218,550 n + 1,536 n^2 + 1,018,080 MAC.
+M_EMB, M_ATT, D_ATT, N_LAYERS = 6275, 100, 128, 2
+FIT_MAC = 1600 * 240 + 2 * 240 * 240 + 240
 
 
 def mac_desc_fwd(n):
-    return EMB * n + 2 * (LAYER_FWD[0] * n + LAYER_FWD[1] * n * n) + 400 * n + 1600 * 4
+    return M_EMB * n + N_LAYERS * (4 * n * M_ATT * D_ATT + 2 * n * n * D_ATT) + 400 * n + 6400
 
 
 def mac_desc_bwd_alg(n):
-    """Backward work proper: attention backward, embedding backward, contraction backward (no recompute)."""
-    return 2 * (LAYER_BWD[0] * n + LAYER_BWD[1] * n * n) + (50 * 100 + 25 * 50) * n + 800 * n + 1600 * 4 * 2
+    """Backward proper (attention, embedding and contraction backward), no recompute credited."""
+    return M_EMB * n + N_LAYERS * (4 * n * M_ATT * D_ATT + 4 * n * n * D_ATT) + 800 * n + 12800
+
+
+def mac_desc_fwd_exec(n):
+    """As executed: Wqk = WQ WK^T / sqrt(d) and Wvo = WV WO are fused, so each layer costs
+    2 n M^2 + 2 n^2 M; the embedding runs 1250 + 5000 MAC per neighbour on MFMA."""
+    return 6250 * n + N_LAYERS * (2 * n * M_ATT * M_ATT + 2 * n * n * M_ATT) + 400 * n + 6400
 
 
 def mac_desc_bwd_exec(n):
-    """As executed: the layer forwards and the embedding are recomputed inside the backward kernel."""
-    return mac_desc_bwd_alg(n) + 2 * (LAYER_FWD[0] * n + LAYER_FWD[1] * n * n) + EMB * n
+    """As executed: both layer forwards and the embedding are recomputed inside the backward."""
+    layer_bwd = 2 * n * M_ATT * M_ATT + 4 * n * n * M_ATT
+    return mac_desc_fwd_exec(n) + 6250 * n + N_LAYERS * layer_bwd + 800 * n + 12800
+
+
+def flop_per_atom_eval(n):
+    return 2.0 * (mac_desc_fwd(n) + mac_desc_bwd_alg(n) + 2 * FIT_MAC)
 
 
 def cpu_baseline(system, budget_s=15.0):
@@ -125,6 +138,8 @@ def main():
     ap.add_argument("--workload", default="chain10k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 512 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -135,6 +150,14 @@ def main():
     from synth import config_system, default_model_file
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4}))
+        return
     system = config_system(args.workload)
     N = system.natoms
     path = default_model_file()
@@ -165,17 +188,21 @@ def main():
     n = nnei.astype(np.float64)
     alg = {
         "descriptor_fwd": 2.0 * float(np.sum(mac_desc_fwd(n))),
-        "fitting": 2.0 * N * (FIT_FWD + FIT_BWD),
+        "fitting": 2.0 * N * 2 * FIT_MAC,
         "descriptor_bwd": 2.0 * float(np.sum(mac_desc_bwd_alg(n))),
     }
-    executed_bwd = 2.0 * float(np.sum(mac_desc_bwd_exec(n)))
+    executed = {
+        "descriptor_fwd": 2.0 * float(np.sum(mac_desc_fwd_exec(n))),
+        "fitting": 2.0 * N * 2 * FIT_MAC * (3 if args.precision == "bf16" else 1),
+        "descriptor_bwd": 2.0 * float(np.sum(mac_desc_bwd_exec(n))),
+    }
     prof = r["prof"]
     avg = {k: (ms / c if c else 0.0) for k, (ms, c) in prof.items()}
     dom = max(("descriptor_fwd", "fitting", "descriptor_bwd"), key=lambda k: avg[k])
     achieved = alg[dom] / (avg[dom] * 1e-3)
     step_alg = sum(alg.values())
     out = {
-        "metric": "atom-evals/s (E+F)",
+        "metric": METRIC,
         "value": value,
         "unit": "atom-evals/s",
         "n_gpus": 1,
@@ -193,7 +220,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
                      "avg_ms": avg[dom], "alg_flop_per_launch": alg[dom],
-                     "executed_flop_per_launch": executed_bwd if dom == "descriptor_bwd" else alg[dom]},
+                     "executed_flop_per_launch": executed[dom]},
         "step_roofline": {"alg_flop_per_step": step_alg,
                           "frac": step_alg / (r["dt"] / r["steps"]) / PEAK[args.precision]},
         "phase_ms": avg,

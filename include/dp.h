@@ -38,6 +38,7 @@ extern "C" {
 #endif
 
 typedef struct dp_model dp_model;
+typedef struct dp_server dp_server;
 
 /* Arithmetic of the dense products (embedding, attention, fitting).  DP_FP32:
  * float32 operands, float32 accumulation.  DP_BF16: bfloat16 operands (round to
@@ -119,6 +120,83 @@ int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g);
 #define DP_NPHASES 6
 int dp_profile_enable(dp_model *m, int enable);
 int dp_profile_read(const dp_model *m, double *ms, int64_t *calls, int max);
+
+/* Several independent periodic systems in one step (paper, Section III: the
+ * engine hands the potential one atom group per step; a server batches many).
+ * System k has natoms[k] atoms, stored consecutively in d_coords [sum][3] and
+ * d_types [sum], and the periodic box boxes[9k .. 9k+8] (host array; every box
+ * orthorhombic with edges >= 2 rc -- open boundaries are not accepted here).
+ * Outputs on the device: d_energy [nsys], d_forces [sum][3] (or NULL),
+ * d_virial [nsys][9] (or NULL).  Each system's results are those of a
+ * dp_compute_device call on it alone.  Enqueued on hip_stream; waits for it at
+ * the end.  The batch's lists may not need more than 64^3 cells in total. */
+int dp_compute_batch_device(dp_model *m, int nsys, const int64_t *natoms, const double *boxes,
+                            const double *d_coords, const int32_t *d_types, double *d_energy,
+                            double *d_forces, double *d_virial, void *hip_stream);
+
+/* Neighbour-list reuse across calls (paper, Section IV: Verlet lists with a
+ * buffer, rebuilt every 10 steps).  With skin > 0 a list within rc + skin
+ * (at most 192 entries per atom) is built on the first call and then every
+ * rebuild_every calls with the same natoms and box; every call in between
+ * filters it to rc at the current coordinates.  The filtered lists equal a fresh
+ * search bit for bit: each call checks on the device that no atom moved by half
+ * the skin since the build (and that no skin row was full), and if one did the
+ * call is redone with a fresh build.  Boxes with an edge < 2 (rc + skin) use a
+ * fresh search every call.  skin = 0 switches reuse off.  dp_skin_stats: skin
+ * lists built so far and, of those, the builds forced by the check. */
+int dp_set_skin(dp_model *m, double skin, int rebuild_every);
+int dp_skin_stats(const dp_model *m, int64_t *builds, int64_t *forced);
+
+/* enable != 0: dp_compute_device captures its step (every kernel launch and
+ * the small host-to-device copies of the cell grid) into a HIP graph the first
+ * time it sees a configuration (natoms, buffer pointers, box, stream, list mode)
+ * and replays the graph on later calls with the same configuration; up to 4
+ * configurations are kept.  The graph reads the coordinates at replay time.
+ * Per-phase profiling (dp_profile_enable) runs the eager path instead.  With
+ * hip_stream NULL a graph runs on a stream of the model's own, ordered after the
+ * work already queued on the null stream. */
+int dp_set_graph(dp_model *m, int enable);
+
+/* Continuous-batching server over one model (the model must not be used
+ * otherwise while the server exists).  Requests are periodic systems; each is
+ * copied on submit, queued, packed with other queued requests into one batched
+ * step (dp_compute_batch_device semantics) as soon as one of two in-flight
+ * slots is free, and completed asynchronously.  Admission by device memory:
+ * a batch holds at most as many atoms as half of hbm_budget_bytes allows
+ * (dp_server_footprint bytes per system), so the two in-flight batches stay
+ * within the budget; a system that does not fit half the budget is rejected by
+ * dp_submit with DP_ERR_TOO_LARGE.  dp_submit validates the request (types,
+ * finite coordinates, box) and never waits for the GPU.  dp_wait blocks up to
+ * timeout_s seconds (< 0: no limit; DP_ERR_TIMEOUT on expiry, the request stays
+ * pending), copies energy (1), forces ([natoms][3]) and virial (9) to host
+ * buffers (any may be NULL), gives the latency from submit to completion, and
+ * releases the request.  A request whose batch fails is re-run alone so that
+ * its own status is reported.  dp_server_stats: nearest-rank p50/p99 latency
+ * over completed requests, atoms completed per second from the first submit to
+ * the last completion, completed requests, batches launched, largest batch in
+ * atoms (any output may be NULL).  dp_submit/dp_wait/dp_server_stats may be
+ * called from any thread; dp_server_free waits for queued work to finish. */
+size_t dp_server_footprint(const dp_model *m, int64_t natoms);
+int dp_server_create(dp_model *m, size_t hbm_budget_bytes, dp_server **out);
+int dp_submit(dp_server *s, int64_t natoms, const double *coords, const int32_t *types,
+              const double *box, uint64_t *request_id);
+int dp_wait(dp_server *s, uint64_t request_id, double timeout_s, double *energy, double *forces,
+            double *virial, double *latency_s);
+int dp_server_stats(dp_server *s, double *p50_s, double *p99_s, double *atom_evals_per_s,
+                    int64_t *completed, int64_t *batches, int64_t *max_batch_atoms);
+void dp_server_free(dp_server *s);
+
+/* Velocity-Verlet NVE on the device with this model's forces (paper, Section IV:
+ * MD with a fixed time step; a test harness for energy conservation, not part
+ * of the timed step).  d_coords [natoms][3] (Angstrom) and d_vel [natoms][3]
+ * (Angstrom/fs) are device float64 arrays advanced in place by nsteps steps of
+ * dt_fs; masses[ntypes] in amu (host).  epot and ekin (host, nsteps + 1 doubles
+ * each, or NULL) receive the potential and kinetic energy (eV) before the first
+ * step and after each step.  Uses dp_compute_device for every force call, so
+ * dp_set_skin and dp_set_graph apply.  Returns the worst status of the steps. */
+int dp_nve_run(dp_model *m, int64_t natoms, double *d_coords, double *d_vel, const int32_t *d_types,
+               const double *masses, const double *box, double dt_fs, int nsteps, double *epot, double *ekin,
+               void *hip_stream);
 
 /* Static description of a status code; never NULL. */
 const char *dp_status_string(int status);

@@ -29,6 +29,11 @@ def kinetic(types, v):
 
 def run_nve(model, X, types, box, v, dt: float, steps: int):
     """Returns the total energy after each step (index 0 = initial)."""
+    return run_nve_traj(model, X, types, box, v, dt, steps)[0]
+
+
+def run_nve_traj(model, X, types, box, v, dt: float, steps: int):
+    """Total energy after each step (index 0 = initial), final positions and velocities."""
     X = np.array(X, dtype=np.float64)
     v = np.array(v, dtype=np.float64)
     inv_m = (ACC / MASSES[types])[:, None]
@@ -42,4 +47,4 @@ def run_nve(model, X, types, box, v, dt: float, steps: int):
         F = out["F"]
         v += 0.5 * dt * F * inv_m
         etot.append(out["E"] + kinetic(types, v))
-    return np.array(etot)
+    return np.array(etot), X, v

@@ -34,6 +34,17 @@ SIGNATURES = {
     "dp_debug_pair_grads": (C.c_int, [_P, _I64, _P]),
     "dp_profile_enable": (C.c_int, [_P, C.c_int]),
     "dp_profile_read": (C.c_int, [_P, _P, _P, C.c_int]),
+    "dp_compute_batch_device": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dp_set_skin": (C.c_int, [_P, C.c_double, C.c_int]),
+    "dp_skin_stats": (C.c_int, [_P, _P, _P]),
+    "dp_set_graph": (C.c_int, [_P, C.c_int]),
+    "dp_server_footprint": (C.c_size_t, [_P, _I64]),
+    "dp_server_create": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "dp_submit": (C.c_int, [_P, _I64, _P, _P, _P, C.POINTER(C.c_uint64)]),
+    "dp_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P, _P, _P]),
+    "dp_server_stats": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "dp_server_free": (None, [_P]),
+    "dp_nve_run": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, C.c_double, C.c_int, _P, _P, _P]),
     "dp_status_string": (C.c_char_p, [C.c_int]),
     "dp_last_error": (C.c_char_p, []),
 }

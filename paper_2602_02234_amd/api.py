@@ -90,6 +90,20 @@ class Model:
         check(_lib.load().dp_debug_pair_grads(self._h, natoms, _ptr(g)), "dp_debug_pair_grads")
         return g[:, :, :3]
 
+    # ---------------------------------------------------------------- step options
+    def set_skin(self, skin: float, rebuild_every: int = 10):
+        """Reuse neighbour lists built within rc + skin for up to rebuild_every calls (0 = off)."""
+        check(_lib.load().dp_set_skin(self._h, float(skin), int(rebuild_every)), "dp_set_skin")
+
+    def skin_stats(self):
+        b, f = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+        check(_lib.load().dp_skin_stats(self._h, _ptr(b), _ptr(f)), "dp_skin_stats")
+        return {"builds": int(b[0]), "forced": int(f[0])}
+
+    def set_graph(self, enable: bool = True):
+        """Capture each step configuration in a HIP graph and replay it."""
+        check(_lib.load().dp_set_graph(self._h, 1 if enable else 0), "dp_set_graph")
+
     # ---------------------------------------------------------------- timing
     PHASES = ("neighbors", "descriptor_fwd", "fitting", "energy_reduce", "descriptor_bwd", "forces_virial")
 
@@ -127,6 +141,56 @@ class Model:
         self.last_status = check(st, "dp_compute_device")
         return energy
 
+    def compute_batch(self, systems, forces: bool = True):
+        """Several periodic systems [(coords, types, box), ...] in one batched step (through
+        device buffers).  Returns one dict per system (E, F, virial)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        ns = np.array([len(t) for _, t, _ in systems], dtype=np.int64)
+        X = torch.tensor(np.concatenate([np.asarray(c, dtype=np.float64) for c, _, _ in systems]), device=dev)
+        T = torch.tensor(np.concatenate([np.asarray(t, dtype=np.int32) for _, t, _ in systems]), device=dev)
+        boxes = np.ascontiguousarray(np.stack([_box9(b) for _, _, b in systems]))
+        k = len(systems)
+        E = torch.zeros(k, dtype=torch.float64, device=dev)
+        F = torch.zeros((int(ns.sum()), 3), dtype=torch.float64, device=dev) if forces else None
+        V = torch.zeros((k, 9), dtype=torch.float64, device=dev) if forces else None
+
+        def dp(t):
+            return C.c_void_p(t.data_ptr()) if t is not None else None
+
+        s = torch.cuda.current_stream(dev).cuda_stream
+        st = _lib.load().dp_compute_batch_device(self._h, k, _ptr(ns), _ptr(boxes), dp(X), dp(T), dp(E), dp(F),
+                                                 dp(V), C.c_void_p(s))
+        self.last_status = check(st, "dp_compute_batch_device")
+        out, off = [], 0
+        Eh = E.cpu().numpy()
+        Fh = F.cpu().numpy() if forces else None
+        Vh = V.cpu().numpy() if forces else None
+        for q in range(k):
+            d = {"E": float(Eh[q])}
+            if forces:
+                d["F"] = Fh[off:off + ns[q]]
+                d["virial"] = Vh[q].reshape(3, 3)
+            off += ns[q]
+            out.append(d)
+        return out
+
+    def nve(self, coords, velocities, types, masses, box, dt_fs: float, steps: int):
+        """Velocity-Verlet NVE on the device (torch float64 coords/velocities advanced in place).
+        Returns (epot, ekin), arrays of steps + 1 energies in eV."""
+        import torch
+        assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
+        assert velocities.is_cuda and velocities.dtype == torch.float64 and velocities.is_contiguous()
+        assert types.is_cuda and types.dtype == torch.int32
+        m = np.ascontiguousarray(masses, dtype=np.float64)
+        ep, ek = np.zeros(steps + 1), np.zeros(steps + 1)
+        s = torch.cuda.current_stream(coords.device).cuda_stream
+        st = _lib.load().dp_nve_run(self._h, coords.shape[0], C.c_void_p(coords.data_ptr()),
+                                    C.c_void_p(velocities.data_ptr()), C.c_void_p(types.data_ptr()), _ptr(m),
+                                    _ptr(_box9(box)), float(dt_fs), int(steps), _ptr(ep), _ptr(ek), C.c_void_p(s))
+        self.last_status = check(st, "dp_nve_run")
+        return ep, ek
+
     def backward_device(self, grad_energy, grad_coords, virial=None, stream=None):
         import torch
         s = stream if stream is not None else torch.cuda.current_stream(grad_coords.device).cuda_stream
@@ -135,6 +199,58 @@ class Model:
                                             C.c_void_p(virial.data_ptr()) if virial is not None else None,
                                             C.c_void_p(s))
         check(st, "dp_backward_device")
+
+
+class Server:
+    """Continuous-batching server (dp_server_*): submit host systems, wait for results."""
+
+    def __init__(self, model: Model, hbm_budget_bytes: int):
+        lib = _lib.load()
+        h = C.c_void_p()
+        check(lib.dp_server_create(model._h, int(hbm_budget_bytes), C.byref(h)), "dp_server_create")
+        self._h = h
+        self.model = model
+        self._n = {}
+
+    def footprint(self, natoms: int) -> int:
+        return int(_lib.load().dp_server_footprint(self.model._h, int(natoms)))
+
+    def submit(self, coords, types, box) -> int:
+        X = np.ascontiguousarray(coords, dtype=np.float64)
+        T = np.ascontiguousarray(types, dtype=np.int32)
+        b = _box9(box)
+        rid = C.c_uint64()
+        check(_lib.load().dp_submit(self._h, X.shape[0], _ptr(X), _ptr(T), _ptr(b), C.byref(rid)), "dp_submit")
+        self._n[rid.value] = X.shape[0]
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = -1.0):
+        n = self._n[rid]
+        E, F, V, lat = np.zeros(1), np.zeros((n, 3)), np.zeros((3, 3)), np.zeros(1)
+        st = _lib.load().dp_wait(self._h, C.c_uint64(rid), float(timeout), _ptr(E), _ptr(F), _ptr(V), _ptr(lat))
+        if st != -10:
+            self._n.pop(rid, None)
+        check(st, "dp_wait")
+        return {"E": float(E[0]), "F": F, "virial": V, "latency": float(lat[0]), "status": st}
+
+    def stats(self):
+        p50, p99, rate = np.zeros(1), np.zeros(1), np.zeros(1)
+        done, nb, mb = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+        check(_lib.load().dp_server_stats(self._h, _ptr(p50), _ptr(p99), _ptr(rate), _ptr(done), _ptr(nb), _ptr(mb)),
+              "dp_server_stats")
+        return {"p50_s": float(p50[0]), "p99_s": float(p99[0]), "atom_evals_per_s": float(rate[0]),
+                "completed": int(done[0]), "batches": int(nb[0]), "max_batch_atoms": int(mb[0])}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().dp_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _autograd_function():

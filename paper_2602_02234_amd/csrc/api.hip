@@ -277,52 +277,103 @@ int build_weights(dp_model *m, const HostModel &h) {
   return DP_OK;
 }
 
+}  // namespace
+
 void free_ws(Workspace &ws) {
   void *ps[] = {ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev,
-                ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart, ws.red, ws.grid, ws.flags, ws.gE};
+                ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart, ws.red, ws.grids, ws.sys_off, ws.sys_of, ws.slist,
+                ws.snnei, ws.xref, ws.flags, ws.gE};
   for (void *p : ps)
     if (p) (void)hipFree(p);
-  if (ws.flags_host) (void)hipHostFree(ws.flags_host);
+  void *hs[] = {ws.flags_host, ws.grids_host, ws.off_host};
+  for (void *p : hs)
+    if (p) (void)hipHostFree(p);
   ws = Workspace{};
 }
 
-int ensure_ws(dp_model *m, int64_t n) {
-  Workspace &ws = m->ws;
+// Device bytes the workspace holds per atom (the serving admission model uses it).
+size_t ws_bytes_per_atom(int prec) {
+  size_t b = 4 * sizeof(int)                              // cell_of, cell_atoms, nnei, sys_of
+             + 2 * (size_t)SEL * sizeof(int)              // nlist, rev
+             + (size_t)M * 4 * sizeof(float)              // Tsave
+             + (size_t)ND * sizeof(float)                 // D
+             + sizeof(double)                             // Ei
+             + (size_t)SEL * sizeof(float4)               // g
+             + 9 * sizeof(double);                        // vpart
+  if (prec == DP_FP32) b += (size_t)NATTN * NPMAX * M * sizeof(float);  // Gsave
+  return b;
+}
+
+int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
   if (!ws.flags) {
     HIP_TRY(hipMalloc(&ws.flags, 4 * sizeof(unsigned)));
     HIP_TRY(hipHostMalloc(&ws.flags_host, 4 * sizeof(unsigned), hipHostMallocDefault));
     HIP_TRY(hipMalloc(&ws.cell_count, (MAX_CELLS + 1) * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.cell_start, (MAX_CELLS + 1) * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.cell_cursor, MAX_CELLS * sizeof(int)));
-    HIP_TRY(hipMalloc(&ws.grid, sizeof(Grid)));
     HIP_TRY(hipMalloc(&ws.red, 64 * sizeof(double)));
     HIP_TRY(hipMalloc(&ws.gE, sizeof(double)));
   }
-  if (n <= ws.cap) return DP_OK;
-  int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
-  void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart};
-  for (void *p : ps)
-    if (p) (void)hipFree(p);
-  ws.cap = 0;
-  HIP_TRY(hipMalloc(&ws.cell_of, cap * sizeof(int)));
-  HIP_TRY(hipMalloc(&ws.cell_atoms, cap * sizeof(int)));
-  HIP_TRY(hipMalloc(&ws.nlist, cap * SEL * sizeof(int)));
-  HIP_TRY(hipMalloc(&ws.nnei, cap * sizeof(int)));
-  HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
-  HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
-  HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
-  HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
-  HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
-  HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));
-  HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
-  HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
-  ws.cap = cap;
+  if (nsys > ws.cap_sys) {
+    const int cs = std::max(nsys, 8);
+    if (ws.grids) (void)hipFree(ws.grids);
+    if (ws.sys_off) (void)hipFree(ws.sys_off);
+    if (ws.grids_host) (void)hipHostFree(ws.grids_host);
+    if (ws.off_host) (void)hipHostFree(ws.off_host);
+    ws.grids = nullptr; ws.sys_off = nullptr; ws.grids_host = nullptr; ws.off_host = nullptr;
+    ws.cap_sys = 0;
+    HIP_TRY(hipMalloc(&ws.grids, cs * sizeof(Grid)));
+    HIP_TRY(hipMalloc(&ws.sys_off, (cs + 1) * sizeof(int)));
+    HIP_TRY(hipHostMalloc(&ws.grids_host, cs * sizeof(Grid), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&ws.off_host, (cs + 1) * sizeof(int), hipHostMallocDefault));
+    ws.cap_sys = cs;
+  }
+  if (n > ws.cap) {
+    const int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
+    void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g,
+                  ws.vpart, ws.sys_of, ws.slist, ws.snnei, ws.xref};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+    ws.cell_of = ws.cell_atoms = ws.nlist = ws.nnei = ws.rev = ws.sys_of = ws.slist = ws.snnei = nullptr;
+    ws.Gsave = ws.Tsave = ws.D = nullptr;
+    ws.Ei = ws.vpart = ws.xref = nullptr;
+    ws.g = nullptr;
+    ws.cap = 0;
+    HIP_TRY(hipMalloc(&ws.cell_of, cap * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.cell_atoms, cap * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.sys_of, cap * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.nlist, cap * SEL * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.nnei, cap * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
+    if (prec == DP_FP32) HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
+    HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
+    HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
+    HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
+    HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));
+    HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
+    HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
+    ws.cap = cap;
+    ws.skin_cap = 0;
+  }
+  if (skin && ws.skin_cap < ws.cap) {
+    void *ps[] = {ws.slist, ws.snnei, ws.xref};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+    ws.slist = ws.snnei = nullptr;
+    ws.xref = nullptr;
+    HIP_TRY(hipMalloc(&ws.slist, ws.cap * (size_t)SKIN_CAP * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.snnei, ws.cap * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.xref, ws.cap * 3 * sizeof(double)));
+    ws.skin_cap = ws.cap;
+  }
   return DP_OK;
 }
 
 constexpr int64_t MAX_ATOMS = 1 << 24;
 
-int check_box(const dp_model *m, const double *box, Grid &g) {
+// Validates a box and fills the cell grid for cells of edge >= cutoff.  box == NULL:
+// open boundaries (the grid is then built on the device from the coordinates).
+int make_grid(double rc, double cutoff, const double *box, Grid &g) {
   std::memset(&g, 0, sizeof(g));
   if (!box) return DP_OK;
   for (int k = 0; k < 9; ++k)
@@ -340,11 +391,12 @@ int check_box(const dp_model *m, const double *box, Grid &g) {
   int nct = 1;
   for (int a = 0; a < 3; ++a) {
     const double L = box[4 * a];
-    if (!(L >= 2.0 * m->rc)) {
+    if (!(L >= 2.0 * rc)) {
       set_error("every box edge must be at least 2 rc");
       return DP_ERR_BOX;
     }
-    int nc = (int)std::floor(L / (m->rc * (1.0 + 1e-9)));
+    if (!(L >= 2.0 * cutoff)) return DP_ERR_BOX;  // only for the skin cutoff: caller falls back
+    int nc = (int)std::floor(L / (cutoff * (1.0 + 1e-9)));
     nc = std::max(1, std::min(nc, MAX_CELLS_PER_DIM));
     g.L[a] = L;
     g.invL[a] = 1.0 / L;
@@ -356,6 +408,8 @@ int check_box(const dp_model *m, const double *box, Grid &g) {
   g.ncells = nct;
   return DP_OK;
 }
+
+namespace {
 
 int flags_status(unsigned f) {
   if (f & FLAG_NONFINITE) { set_error("non-finite coordinate"); return DP_ERR_NONFINITE; }
@@ -384,51 +438,192 @@ void collect(dp_model *m, int last) {
   }
 }
 
-template <typename T>
-int run_step(dp_model *m, const Weights<T> &w, int n, const double *X, const int *types, const Grid &g, bool gdev,
-             double *d_energy, double *d_forces, double *d_virial, double *d_atom_energy, hipStream_t st,
-             int *status_out) {
-  Workspace &ws = m->ws;
+}  // namespace
+
+// Enqueues one step (no host synchronisation; nothing here allocates).  The per-system
+// grids and atom offsets must already be in ws.grids_host / ws.off_host; they are
+// copied to the device first unless `open_single` (one open system, grid built on the
+// device).  Outputs are written only if the step raised no error flag.
+int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, bool profile) {
+  dp_model *pm = profile ? m : nullptr;
+  const int n = (int)a.n;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
-  mark(m, 0, st);
-  launch_neighbors(ws, X, types, n, m->ntypes, g, gdev, m->rc, st);
+  if (!a.open_single) HIP_TRY(hipMemcpyAsync(ws.grids, ws.grids_host, a.nsys * sizeof(Grid), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, (a.nsys + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  launch_sys_of(ws, a.nsys, n, st);
+  if (pm) mark(pm, 0, st);
+  switch (a.lists) {
+    case LISTS_FRESH:
+      launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc, st);
+      launch_nlist(ws, a.X, n, m->rc, false, st);
+      break;
+    case LISTS_SKIN_BUILD:
+      launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc + m->skin, st);
+      launch_nlist(ws, a.X, n, m->rc + m->skin, true, st);
+      launch_skin_ref(ws, a.X, n, st);
+      launch_filter(ws, a.X, n, m->rc, st);
+      break;
+    case LISTS_SKIN_REUSE: {
+      const double h = 0.5 * m->skin * (1.0 - 1e-9);
+      launch_skin_check(ws, a.X, a.types, n, m->ntypes, h * h, st);
+      launch_filter(ws, a.X, n, m->rc, st);
+      break;
+    }
+  }
+  launch_rev(ws, n, st);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  int s = flags_status(ws.flags_host[0]);
-  if (s != DP_OK) return s;
-  const unsigned overflow = ws.flags_host[1];
   const float rc = (float)m->rc, rcs = (float)m->rcs, eps = (float)m->ln_eps;
-  const bool bwd = d_forces || d_virial;
-  mark(m, 1, st);
+  const bool bwd = a.forces || a.virial;
+  if (pm) mark(pm, 1, st);
   if (m->prec == DP_BF16)
-    launch_descriptor_fwd_b16(m->wb, m->wp, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+    launch_descriptor_fwd_b16(m->wb, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
   else
-    launch_descriptor_fwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
-  mark(m, 2, st);
+    launch_descriptor_fwd<float>(m->wf, ws, a.X, a.types, n, rc, rcs, eps, st);
+  if (pm) mark(pm, 2, st);
   if (m->prec == DP_BF16)
-    launch_fitting_b16(m->wb, m->wp, ws, types, n, bwd, st);
+    launch_fitting_b16(m->wb, m->wp, ws, a.types, n, bwd, st);
   else
-    launch_fitting<T>(w, ws, types, n, bwd, st);
-  mark(m, 3, st);
-  launch_energy(ws, n, d_energy, d_atom_energy, st);
-  mark(m, 4, st);
+    launch_fitting<float>(m->wf, ws, a.types, n, bwd, st);
+  if (pm) mark(pm, 3, st);
+  launch_energy(ws, a.nsys, a.energy, a.atom_energy, st);
+  if (pm) mark(pm, 4, st);
   if (bwd) {
     if (m->prec == DP_BF16)
-      launch_descriptor_bwd_b16(m->wb, m->wp, ws, X, types, n, g, gdev, rc, rcs, eps, st);
+      launch_descriptor_bwd_b16(m->wb, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
     else
-      launch_descriptor_bwd<T>(w, ws, X, types, n, g, gdev, rc, rcs, eps, st);
-    mark(m, 5, st);
-    double *F = d_forces;
+      launch_descriptor_bwd<float>(m->wf, ws, a.X, a.types, n, rc, rcs, eps, st);
+    if (pm) mark(pm, 5, st);
+    double *F = a.forces;
     if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
-    launch_forces(ws, X, n, g, gdev, nullptr, F, d_virial, st);
-    mark(m, 6, st);
+    launch_forces(ws, a.X, n, a.nsys, nullptr, F, a.virial, st);
+    if (pm) mark(pm, 6, st);
   }
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(st));
-  collect(m, bwd ? 6 : 4);
-  *status_out = overflow ? DP_WARN_SEL_OVERFLOW : DP_OK;
   return DP_OK;
+}
+
+// Status of a finished step from the flag words copied to ws.flags_host.
+int step_status(const Workspace &ws) {
+  const unsigned f = ws.flags_host[0];
+  const int s = flags_status(f);
+  if (s != DP_OK) return s;
+  if (f & (FLAG_STALE | FLAG_SKIN_FULL)) return DP_RETRY;
+  return ws.flags_host[1] ? DP_WARN_SEL_OVERFLOW : DP_OK;
+}
+
+namespace {
+
+bool same_bits(const double *a, const double *b, int n) { return std::memcmp(a, b, n * sizeof(double)) == 0; }
+
+// One step of a single system through a captured graph: captured on first use of a
+// configuration (list mode, sizes, pointers, box, stream), replayed afterwards.
+int launch_graph(dp_model *m, const StepArgs &a, hipStream_t st) {
+  GraphKey k{};
+  k.lists = a.lists;
+  k.n = a.n;
+  k.X = a.X; k.types = a.types; k.energy = a.energy; k.forces = a.forces; k.virial = a.virial;
+  k.atom_energy = a.atom_energy;
+  k.stream = st;
+  k.open_single = a.open_single;
+  if (!a.open_single) std::memcpy(k.box, m->ws.grids_host[0].L, 3 * sizeof(double));
+  for (auto &e : m->graphs)
+    if (e.exec && std::memcmp(&e.key, &k, sizeof(k)) == 0) {
+      // the host-side grid table is uploaded outside the graph (same values as at capture)
+      if (!a.open_single)
+        HIP_TRY(hipMemcpyAsync(m->ws.grids, m->ws.grids_host, sizeof(Grid), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipGraphLaunch(e.exec, st));
+      return DP_OK;
+    }
+  GraphEntry &slot = m->graphs[m->graph_next];
+  m->graph_next = (m->graph_next + 1) % (int)(sizeof(m->graphs) / sizeof(m->graphs[0]));
+  if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  slot.exec = nullptr;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int s = enqueue_step(m, m->ws, a, st, false);
+  const hipError_t e = hipStreamEndCapture(st, &graph);
+  if (s != DP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  HIP_TRY(e);
+  const hipError_t ei = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_TRY(ei);
+  slot.key = k;
+  HIP_TRY(hipGraphLaunch(slot.exec, st));
+  return DP_OK;
+}
+
+// One step of one system: list mode from the skin state, eager or graph launch, the
+// flag words read back, and a redo with fresh lists when the skin list was stale.
+int run_single(dp_model *m, StepArgs a, const double *box, hipStream_t st) {
+  Workspace &ws = m->ws;
+  Grid g, gs;
+  int s = make_grid(m->rc, m->rc, box, g);
+  if (s != DP_OK) return s;
+  bool skin = m->skin > 0.0;
+  if (skin && box) skin = make_grid(m->rc, m->rc + m->skin, box, gs) == DP_OK;
+  a.open_single = box == nullptr;
+  a.nsys = 1;
+  s = ensure_ws(ws, m->prec, a.n, 1, skin);
+  if (s != DP_OK) return s;
+  ws.off_host[0] = 0;
+  ws.off_host[1] = (int)a.n;
+  if (skin) {
+    const bool same = m->skin_valid && m->skin_n == a.n && m->skin_open == a.open_single &&
+                      (a.open_single || same_bits(m->skin_box, box, 9));
+    a.lists = (same && m->skin_age < m->rebuild_every) ? LISTS_SKIN_REUSE : LISTS_SKIN_BUILD;
+  } else {
+    a.lists = LISTS_FRESH;
+  }
+  // the legacy default stream cannot be captured: a graph then runs on the model's own
+  // stream, ordered after the work already queued on the default stream
+  const bool graph = m->use_graph && !m->prof;
+  if (graph && st == nullptr) {
+    HIP_TRY(hipEventRecord(m->dep_ev, nullptr));
+    st = m->own_stream;
+    HIP_TRY(hipStreamWaitEvent(st, m->dep_ev, 0));
+  }
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    const bool skin_cells = a.lists != LISTS_FRESH;
+    ws.grids_host[0] = skin_cells && !a.open_single ? gs : g;
+    a.ncells = a.open_single ? MAX_CELLS : ws.grids_host[0].ncells;
+    if (graph) {
+      s = launch_graph(m, a, st);
+    } else {
+      s = enqueue_step(m, ws, a, st, m->prof);
+    }
+    if (s != DP_OK) return s;
+    HIP_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    s = step_status(ws);
+    if (s == DP_RETRY) {
+      m->skin_valid = false;
+      // stale skin list: rebuild it; a full skin row: fresh lists for this step
+      a.lists = (a.lists == LISTS_SKIN_REUSE) ? LISTS_SKIN_BUILD : LISTS_FRESH;
+      m->skin_rebuilds_forced += 1;
+      continue;
+    }
+    if (s < 0) {
+      m->skin_valid = false;
+      return s;
+    }
+    if (!graph) collect(m, (a.forces || a.virial) ? 6 : 4);
+    if (a.lists == LISTS_SKIN_BUILD) {
+      m->skin_valid = true;
+      m->skin_age = 1;
+      m->skin_n = a.n;
+      m->skin_open = a.open_single;
+      if (box) std::memcpy(m->skin_box, box, 9 * sizeof(double));
+      m->skin_builds += 1;
+    } else if (a.lists == LISTS_SKIN_REUSE) {
+      m->skin_age += 1;
+    }
+    return s;
+  }
+  set_error("neighbour lists could not be rebuilt");
+  return DP_ERR_HIP;
 }
 
 }  // namespace
@@ -482,6 +677,11 @@ int dp_model_load(const char *path, int precision, int device, dp_model **out) {
   m->sel = h.sel;
   m->ntypes = h.ntypes;
   s = build_weights(m, h);
+  if (s == DP_OK && (hipStreamCreateWithFlags(&m->own_stream, hipStreamNonBlocking) != hipSuccess ||
+                     hipEventCreateWithFlags(&m->dep_ev, hipEventDisableTiming) != hipSuccess)) {
+    set_error("dp_model_load: stream creation failed");
+    s = DP_ERR_HIP;
+  }
   if (s != DP_OK) {
     dp_model_free(m);
     return s;
@@ -493,8 +693,13 @@ int dp_model_load(const char *path, int precision, int device, dp_model **out) {
 void dp_model_free(dp_model *m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
   for (int k = 0; k < 8; ++k)
     if (m->ev[k]) (void)hipEventDestroy(m->ev[k]);
+  for (auto &e : m->graphs)
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (m->own_stream) (void)hipStreamDestroy(m->own_stream);
+  if (m->dep_ev) (void)hipEventDestroy(m->dep_ev);
   free_ws(m->ws);
   if (m->wbuf) (void)hipFree(m->wbuf);
   delete m;
@@ -553,23 +758,17 @@ int dp_compute_device(dp_model *m, int64_t natoms, const double *d_coords, const
     set_error("natoms above the library limit");
     return DP_ERR_TOO_LARGE;
   }
-  Grid g;
-  int s = check_box(m, box_host, g);
-  if (s != DP_OK) return s;
   HIP_TRY(hipSetDevice(m->device));
-  s = ensure_ws(m, natoms);
-  if (s != DP_OK) return s;
-  hipStream_t st = (hipStream_t)hip_stream;
-  const bool gdev = !g.periodic;
-  if (gdev) g.cw[0] = m->rc;
-  int status = DP_OK;
-  if (m->prec == DP_FP32)
-    s = run_step<float>(m, m->wf, (int)natoms, d_coords, d_types, g, gdev, d_energy, d_forces, d_virial,
-                        d_atom_energy, st, &status);
-  else
-    s = run_step<bf16_t>(m, m->wb, (int)natoms, d_coords, d_types, g, gdev, d_energy, d_forces, d_virial,
-                         d_atom_energy, st, &status);
-  if (s != DP_OK) {
+  StepArgs a;
+  a.n = natoms;
+  a.X = d_coords;
+  a.types = d_types;
+  a.energy = d_energy;
+  a.forces = d_forces;
+  a.virial = d_virial;
+  a.atom_energy = d_atom_energy;
+  const int s = run_single(m, a, box_host, (hipStream_t)hip_stream);
+  if (s < 0) {
     m->fwd_valid = false;
     return s;
   }
@@ -577,8 +776,97 @@ int dp_compute_device(dp_model *m, int64_t natoms, const double *d_coords, const
   m->fwd_natoms = natoms;
   m->fwd_coords = d_coords;
   m->fwd_types = d_types;
-  m->fwd_grid = g;
-  return status;
+  return s;
+}
+
+int dp_compute_batch_device(dp_model *m, int nsys, const int64_t *natoms, const double *boxes,
+                            const double *d_coords, const int32_t *d_types, double *d_energy, double *d_forces,
+                            double *d_virial, void *hip_stream) {
+  g_last_error.clear();
+  if (!m || nsys < 1 || !natoms || !boxes || !d_coords || !d_types || !d_energy) {
+    set_error("dp_compute_batch_device: bad argument");
+    return DP_ERR_ARG;
+  }
+  int64_t tot = 0;
+  for (int k = 0; k < nsys; ++k) {
+    if (natoms[k] < 1) {
+      set_error("dp_compute_batch_device: a system has no atoms");
+      return DP_ERR_ARG;
+    }
+    tot += natoms[k];
+  }
+  if (tot > MAX_ATOMS) {
+    set_error("natoms above the library limit");
+    return DP_ERR_TOO_LARGE;
+  }
+  HIP_TRY(hipSetDevice(m->device));
+  Workspace &ws = m->ws;
+  int s = ensure_ws(ws, m->prec, tot, nsys, false);
+  if (s != DP_OK) return s;
+  int cells = 0;
+  ws.off_host[0] = 0;
+  for (int k = 0; k < nsys; ++k) {
+    Grid g;
+    s = make_grid(m->rc, m->rc, boxes + 9 * k, g);
+    if (s != DP_OK) return s;
+    if (cells + g.ncells > MAX_CELLS) {
+      set_error("dp_compute_batch_device: too many cells in one batch");
+      return DP_ERR_TOO_LARGE;
+    }
+    g.cell_base = cells;
+    cells += g.ncells;
+    ws.grids_host[k] = g;
+    ws.off_host[k + 1] = (int)(ws.off_host[k] + natoms[k]);
+  }
+  StepArgs a;
+  a.n = tot;
+  a.nsys = nsys;
+  a.X = d_coords;
+  a.types = d_types;
+  a.energy = d_energy;
+  a.forces = d_forces;
+  a.virial = d_virial;
+  a.ncells = cells;
+  a.lists = LISTS_FRESH;
+  hipStream_t st = (hipStream_t)hip_stream;
+  s = enqueue_step(m, ws, a, st, false);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  m->fwd_valid = false;
+  return step_status(ws);
+}
+
+int dp_set_skin(dp_model *m, double skin, int rebuild_every) {
+  g_last_error.clear();
+  if (!m || !(skin >= 0.0) || !std::isfinite(skin) || rebuild_every < 1) {
+    set_error("dp_set_skin: bad argument");
+    return DP_ERR_ARG;
+  }
+  m->skin = skin;
+  m->rebuild_every = rebuild_every;
+  m->skin_valid = false;
+  return DP_OK;
+}
+
+int dp_skin_stats(const dp_model *m, int64_t *builds, int64_t *forced) {
+  if (!m) return DP_ERR_ARG;
+  if (builds) *builds = m->skin_builds;
+  if (forced) *forced = m->skin_rebuilds_forced;
+  return DP_OK;
+}
+
+int dp_set_graph(dp_model *m, int enable) {
+  g_last_error.clear();
+  if (!m) return DP_ERR_ARG;
+  HIP_TRY(hipSetDevice(m->device));
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto &e : m->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    e.exec = nullptr;
+  }
+  m->use_graph = enable != 0;
+  return DP_OK;
 }
 
 int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_coords, double *d_virial,
@@ -595,19 +883,18 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t st = (hipStream_t)hip_stream;
   const int n = (int)m->fwd_natoms;
-  const Grid &g = m->fwd_grid;
-  const bool gdev = !g.periodic;
   const float rc = (float)m->rc, rcs = (float)m->rcs, eps = (float)m->ln_eps;
   Workspace &ws = m->ws;
-  // the energy-only pass left D in place; rerun the fitting net with its backward
+  // the energy-only pass left D, the lists and the grid in place; rerun the fitting
+  // net with its backward
   if (m->prec == DP_FP32) {
     launch_fitting<float>(m->wf, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
+    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
   } else {
     launch_fitting_b16(m->wb, m->wp, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd_b16(m->wb, m->wp, ws, m->fwd_coords, m->fwd_types, n, g, gdev, rc, rcs, eps, st);
+    launch_descriptor_bwd_b16(m->wb, m->wp, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
   }
-  launch_forces(ws, m->fwd_coords, n, g, gdev, d_grad_energy, d_grad_coords, d_virial, st);
+  launch_forces(ws, m->fwd_coords, n, 1, d_grad_energy, d_grad_coords, d_virial, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   m->fwd_valid = false;
@@ -674,10 +961,11 @@ int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const 
   }
   if (natoms > MAX_ATOMS) return DP_ERR_TOO_LARGE;
   Grid g;
-  int s = check_box(m, box, g);
+  int s = make_grid(m->rc, m->rc, box, g);
   if (s != DP_OK) return s;
   HIP_TRY(hipSetDevice(m->device));
-  s = ensure_ws(m, natoms);
+  Workspace &ws = m->ws;
+  s = ensure_ws(ws, m->prec, natoms, 1, false);
   if (s != DP_OK) return s;
   const size_t n = (size_t)natoms;
   double *dX = nullptr;
@@ -687,16 +975,22 @@ int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const 
     set_error("dp_debug_neighbors: allocation failed");
     return DP_ERR_OOM;
   }
-  Workspace &ws = m->ws;
-  const bool gdev = !g.periodic;
-  if (gdev) g.cw[0] = m->rc;
+  const bool open = box == nullptr;
+  ws.grids_host[0] = g;
+  ws.off_host[0] = 0;
+  ws.off_host[1] = (int)natoms;
+  hipStream_t st = m->own_stream;
   s = DP_OK;
-  if (hipMemcpy(dX, coords, n * 24, hipMemcpyHostToDevice) != hipSuccess || hipMemset(dT, 0, n * 4) != hipSuccess) {
+  if (hipMemcpy(dX, coords, n * 24, hipMemcpyHostToDevice) != hipSuccess || hipMemset(dT, 0, n * 4) != hipSuccess ||
+      hipMemcpy(ws.grids, ws.grids_host, sizeof(Grid), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ws.sys_off, ws.off_host, 2 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     s = DP_ERR_HIP;
   } else {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, nullptr, ws.flags, 4);
-    launch_neighbors(ws, dX, dT, (int)natoms, m->ntypes, g, gdev, m->rc, nullptr);
-    if (hipDeviceSynchronize() != hipSuccess ||
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
+    launch_sys_of(ws, 1, (int)natoms, st);
+    launch_cells(ws, dX, dT, (int)natoms, m->ntypes, open, open ? MAX_CELLS : g.ncells, m->rc, st);
+    launch_nlist(ws, dX, (int)natoms, m->rc, false, st);
+    if (hipStreamSynchronize(st) != hipSuccess ||
         hipMemcpy(nlist, ws.nlist, n * SEL * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(nnei, ws.nnei, n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(ws.flags_host, ws.flags, 16, hipMemcpyDeviceToHost) != hipSuccess) {
@@ -709,6 +1003,7 @@ int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const 
   }
   (void)hipFree(dX);
   (void)hipFree(dT);
+  m->skin_valid = false;
   if (s == DP_ERR_HIP) set_error("dp_debug_neighbors: HIP call failed");
   return s;
 }

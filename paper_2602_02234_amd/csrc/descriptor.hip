@@ -189,12 +189,12 @@ struct SmemFwd {
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
 k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms,
-           const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dg,
+           const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
            float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
            float *__restrict__ D) {
   __shared__ SmemFwd sm;
   const int i = blockIdx.x;
-  const Grid g = dg ? *dg : hg;
+  const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
@@ -260,12 +260,12 @@ struct SmemBwd {
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
 k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms,
-           const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dg,
+           const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
            float rc, float rcs, float ln_eps, const float *__restrict__ Gsave, const float *__restrict__ Tsave,
            const float *__restrict__ dD, float4 *__restrict__ gout) {
   __shared__ SmemBwd sm;
   const int i = blockIdx.x;
-  const Grid g = dg ? *dg : hg;
+  const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
@@ -599,25 +599,25 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
 
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
-                           const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, g,
-                     grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
+                           float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
 }
 
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
-                           const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, g,
-                     grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
+                           float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
 }
 
 template void launch_descriptor_fwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
-                                           int, const Grid &, bool, float, float, float, hipStream_t);
+                                           int, float, float, float, hipStream_t);
 template void launch_descriptor_fwd<bf16_t>(const Weights<bf16_t> &, const Workspace &, const double *, const int *,
-                                            int, const Grid &, bool, float, float, float, hipStream_t);
+                                            int, float, float, float, hipStream_t);
 template void launch_descriptor_bwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
-                                           int, const Grid &, bool, float, float, float, hipStream_t);
+                                           int, float, float, float, hipStream_t);
 template void launch_descriptor_bwd<bf16_t>(const Weights<bf16_t> &, const Workspace &, const double *, const int *,
-                                            int, const Grid &, bool, float, float, float, hipStream_t);
+                                            int, float, float, float, hipStream_t);
 
 }  // namespace dp

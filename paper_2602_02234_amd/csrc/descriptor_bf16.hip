@@ -274,11 +274,11 @@ struct __align__(16) SmemF16 {
 
 __global__ void __launch_bounds__(NWF * 64)
 k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
-               const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dg,
+               const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
                float rc, float rcs, float ln_eps, float *__restrict__ Tsave, float *__restrict__ D) {
   __shared__ SmemF16 sm;
   const int i = blockIdx.x;
-  const Grid g = dg ? *dg : hg;
+  const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
@@ -555,12 +555,12 @@ __device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int la
 
 __global__ void __launch_bounds__(NWB * 64)
 k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
-               const int *__restrict__ nlist, const int *__restrict__ nnei, Grid hg, const Grid *__restrict__ dgr,
+               const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
                float rc, float rcs, float ln_eps, const float *__restrict__ Tsave, const float *__restrict__ dD,
                float4 *__restrict__ gout) {
   __shared__ SmemB16 sm;
   const int i = blockIdx.x;
-  const Grid g = dgr ? *dgr : hg;
+  const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
@@ -765,17 +765,17 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 }  // namespace
 
 void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
+                               const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, g,
-                     grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Tsave, ws.D);
+  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                     ws.sys_of, rc, rcs, ln_eps, ws.Tsave, ws.D);
 }
 
 void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
+                               const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_bwd_b16, dim3(n), dim3(NWB * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, g,
-                     grid_on_device ? ws.grid : nullptr, rc, rcs, ln_eps, ws.Tsave, ws.D, ws.g);
+  hipLaunchKernelGGL(k_desc_bwd_b16, dim3(n), dim3(NWB * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                     ws.sys_of, rc, rcs, ln_eps, ws.Tsave, ws.D, ws.g);
 }
 
 }  // namespace dp

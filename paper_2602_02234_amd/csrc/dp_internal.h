@@ -18,15 +18,22 @@ struct Grid {
   int nc[3];
   int periodic;
   int ncells;
+  int cell_base;    // first cell of this system in a multi-system cell array
+  int pad_;
 };
 
 constexpr int MAX_CELLS_PER_DIM = 64;
 constexpr int MAX_CELLS = MAX_CELLS_PER_DIM * MAX_CELLS_PER_DIM * MAX_CELLS_PER_DIM;
 constexpr int CAND_CAP = 512;  // neighbours within rc one atom may have before DP_ERR_TOO_LARGE
+constexpr int SKIN_CAP = 192;  // entries per row of the skin list (within rc + skin)
 
-// Status bits written by kernels into the workspace flag word.
+// Status bits written by kernels into the workspace flag word.  STALE: an atom moved by
+// half the skin since the skin list was built; SKIN_FULL: a skin row overflowed.  Both
+// make the host redo the step with a fresh search.
 enum : unsigned {
-  FLAG_OVERLAP = 1u, FLAG_TYPE = 2u, FLAG_NONFINITE = 4u, FLAG_TOO_DENSE = 8u,
+  FLAG_OVERLAP = 1u, FLAG_TYPE = 2u, FLAG_NONFINITE = 4u, FLAG_TOO_DENSE = 8u, FLAG_STALE = 16u,
+  FLAG_SKIN_FULL = 32u,
+  FLAG_ERRORS = 63u,  // any of the above: outputs are not written
 };
 
 // Device weights; T is float (DP_FP32) or __bf16 (DP_BF16) for GEMM operands.
@@ -81,6 +88,16 @@ struct WeightsB16 {
 
 struct Workspace {
   int64_t cap = 0;            // atoms
+  int cap_sys = 0;            // systems
+  Grid *grids = nullptr;      // [cap_sys]  per-system cell grid (device)
+  Grid *grids_host = nullptr; // [cap_sys]  pinned staging
+  int *sys_off = nullptr;     // [cap_sys + 1]  first atom of each system (device)
+  int *off_host = nullptr;    // [cap_sys + 1]  pinned staging
+  int *sys_of = nullptr;      // [cap]  system of each atom
+  int *slist = nullptr;       // [cap][SKIN_CAP]  skin list (within rc + skin)
+  int *snnei = nullptr;       // [cap]
+  double *xref = nullptr;     // [cap][3]  coordinates when the skin list was built
+  int64_t skin_cap = 0;       // atoms the skin arrays hold
   int *cell_of = nullptr;     // [cap]
   int *cell_count = nullptr;  // [MAX_CELLS + 1]
   int *cell_start = nullptr;  // [MAX_CELLS + 1]
@@ -96,10 +113,40 @@ struct Workspace {
   float4 *g = nullptr;        // [cap][SEL]  dE_i/dDelta_ij
   double *vpart = nullptr;    // [cap][9]   per-atom virial
   double *red = nullptr;      // scratch for the compensated reductions
-  Grid *grid = nullptr;       // device copy of the grid (open boundaries)
   unsigned *flags = nullptr;  // [4] status words: flags, overflow count, rev misses, spare
   unsigned *flags_host = nullptr;  // pinned mirror
   double *gE = nullptr;       // [1] scale of the backward pass
+};
+
+// How the neighbour lists of a step are made.
+enum ListMode { LISTS_FRESH = 0, LISTS_SKIN_BUILD = 1, LISTS_SKIN_REUSE = 2 };
+constexpr int DP_RETRY = 100;  // internal: redo the step with fresh lists
+
+// One step: nsys systems, atoms concatenated (system s owns atoms off[s] .. off[s+1]-1).
+struct StepArgs {
+  int64_t n = 0;
+  int nsys = 1;
+  const double *X = nullptr;
+  const int *types = nullptr;
+  double *energy = nullptr;       // [nsys]
+  double *forces = nullptr;       // [n][3] or NULL
+  double *virial = nullptr;       // [nsys][9] or NULL
+  double *atom_energy = nullptr;  // [n] or NULL
+  bool open_single = false;       // one open-boundary system (grid made on the device)
+  int ncells = 0;                 // cells over all systems
+  int lists = LISTS_FRESH;
+};
+
+struct GraphKey {
+  int lists;
+  int open_single;
+  int64_t n;
+  const void *X, *types, *energy, *forces, *virial, *atom_energy, *stream;
+  double box[3];
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace dp
@@ -120,6 +167,21 @@ struct dp_model {
   const int32_t *fwd_types = nullptr;
   dp::Grid fwd_grid{};
   bool fwd_valid = false;
+  // neighbour-list reuse with a skin (dp_set_skin)
+  double skin = 0.0;
+  int rebuild_every = 10;
+  bool skin_valid = false;
+  int skin_age = 0;
+  int64_t skin_n = 0;
+  bool skin_open = false;
+  double skin_box[9] = {};
+  int64_t skin_builds = 0, skin_rebuilds_forced = 0;
+  // step graphs (dp_set_graph)
+  bool use_graph = false;
+  dp::GraphEntry graphs[4];
+  int graph_next = 0;
+  hipStream_t own_stream = nullptr;
+  hipEvent_t dep_ev = nullptr;
   // per-phase timing (dp_profile_enable)
   bool prof = false;
   hipEvent_t ev[8] = {};
@@ -130,29 +192,45 @@ struct dp_model {
 namespace dp {
 void set_error(const std::string &s);
 
-// Launchers (defined in the kernel translation units); all enqueue on `st`.
-void launch_neighbors(const Workspace &ws, const double *coords, const int *types, int n, int ntypes,
-                      const Grid &g, bool grid_on_device, double rc, hipStream_t st);
+// Launchers (defined in the kernel translation units); all enqueue on `st` and read the
+// per-system grids (ws.grids), atom ranges (ws.sys_off) and atom -> system map (ws.sys_of).
+void launch_sys_of(const Workspace &ws, int nsys, int n, hipStream_t st);
+void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
+                  int ncells_total, double cell_cutoff, hipStream_t st);
+void launch_nlist(const Workspace &ws, const double *coords, int n, double cutoff, bool skin, hipStream_t st);
+void launch_filter(const Workspace &ws, const double *coords, int n, double rc, hipStream_t st);
+void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
+                       hipStream_t st);
+void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st);
+void launch_rev(const Workspace &ws, int n, hipStream_t st);
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
-                           int n, const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps,
-                           hipStream_t st);
+                           int n, float rc, float rcs, float ln_eps, hipStream_t st);
 template <typename T>
 void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward,
                     hipStream_t st);
 void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
-                               float rc, float rcs, float ln_eps, hipStream_t st);
+                               const double *coords, const int *types, int n, float rc, float rcs, float ln_eps,
+                               hipStream_t st);
 void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, const Grid &g, bool grid_on_device,
-                               float rc, float rcs, float ln_eps, hipStream_t st);
+                               const double *coords, const int *types, int n, float rc, float rcs, float ln_eps,
+                               hipStream_t st);
 void launch_fitting_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
                         bool backward, hipStream_t st);
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
-                           int n, const Grid &g, bool grid_on_device, float rc, float rcs, float ln_eps,
-                           hipStream_t st);
-void launch_forces(const Workspace &ws, const double *coords, int n, const Grid &g, bool grid_on_device,
-                   const double *gE, double *forces, double *virial_out, hipStream_t st);
-void launch_energy(const Workspace &ws, int n, double *energy, double *atom_energy, hipStream_t st);
+                           int n, float rc, float rcs, float ln_eps, hipStream_t st);
+void launch_forces(const Workspace &ws, const double *coords, int n, int nsys, const double *gE, double *forces,
+                   double *virial_out, hipStream_t st);
+void launch_energy(const Workspace &ws, int nsys, double *energy, double *atom_energy, hipStream_t st);
+// out[0] = Neumaier sum of src over the atoms of system 0 (fixed order).
+void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st);
+
+// Step orchestration (api.hip), shared with the serving loop.
+size_t ws_bytes_per_atom(int prec);
+int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin);
+void free_ws(Workspace &ws);
+int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, bool profile);
+int step_status(const Workspace &ws);
+int make_grid(double rc, double cutoff, const double *box, Grid &g);
 }  // namespace dp

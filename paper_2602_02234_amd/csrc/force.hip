@@ -16,16 +16,21 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One wavefront per atom.  mode 0: out = F;  mode 1: out = -gE * F = gE dE/dx, virial scaled by gE.
+// Outputs are written only when the step raised no error flag, so that a failed step
+// leaves the caller's buffers as they were (the status is read back after the step).
+__device__ __forceinline__ bool step_failed(const unsigned *flags) { return (flags[0] & FLAG_ERRORS) != 0u; }
+
+// One wavefront per atom.  gE == NULL: out = F;  else out = -gE F = gE dE/dx, virial scaled by gE.
 __global__ void __launch_bounds__(256) k_forces(const float4 *__restrict__ g, const int *__restrict__ nlist,
                                                 const int *__restrict__ nnei, const int *__restrict__ rev,
-                                                const double *__restrict__ X, Grid hg, const Grid *__restrict__ dg,
-                                                int n, const double *__restrict__ gE, double *__restrict__ Fout,
-                                                double *__restrict__ vpart) {
+                                                const double *__restrict__ X, const Grid *__restrict__ grids,
+                                                const int *__restrict__ sys_of, int n, const double *__restrict__ gE,
+                                                double *__restrict__ Fout, double *__restrict__ vpart,
+                                                const unsigned *__restrict__ flags) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const Grid gr = dg ? *dg : hg;
+  if (i >= n || step_failed(flags)) return;
+  const Grid gr = grids[sys_of[i]];
   double f[3] = {0, 0, 0}, v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int nn = min(max(nnei[i], 0), SEL);
   for (int s = lane; s < nn; s += 64) {
@@ -62,9 +67,10 @@ __global__ void __launch_bounds__(256) k_forces(const float4 *__restrict__ g, co
 // One-sided pairs (only after a list overflow): subtract g_ij from F_j.
 __global__ void k_forces_onesided(const float4 *__restrict__ g, const int *__restrict__ nlist,
                                   const int *__restrict__ nnei, const int *__restrict__ rev, int n,
-                                  const double *__restrict__ gE, double *__restrict__ Fout) {
+                                  const double *__restrict__ gE, double *__restrict__ Fout,
+                                  const unsigned *__restrict__ flags) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)n * SEL) return;
+  if (t >= (long long)n * SEL || flags[2] == 0u || step_failed(flags)) return;
   const int i = (int)(t / SEL), s = (int)(t % SEL);
   if (s >= nnei[i] || rev[t] >= 0) return;
   const int j = nlist[t];
@@ -90,15 +96,21 @@ __device__ __forceinline__ void neu_merge(Neu &a, const Neu &b) {
   a.c += b.c;
 }
 
-// Block-wide Neumaier sum of src[k * stride] for k < count (fixed order); one block per output.
-template <typename S>
-__global__ void __launch_bounds__(1024) k_neumaier(const S *__restrict__ src, int count, int stride,
-                                                   double *__restrict__ out, double *__restrict__ copy_out) {
+// Per-system Neumaier sums in a fixed order: block b reduces component c = b % ncomp of
+// system s = b / ncomp, i.e. src[k * ncomp + c] for off[s] <= k < off[s + 1], into
+// out[s * ncomp + c].  Thread t takes the elements off[s] + t, off[s] + t + 1024, ...,
+// so a system's sums do not depend on which other systems share the step.
+__global__ void __launch_bounds__(1024) k_seg_neumaier(const double *__restrict__ src, const int *__restrict__ off,
+                                                       int ncomp, double *__restrict__ out,
+                                                       double *__restrict__ copy_out,
+                                                       const unsigned *__restrict__ flags) {
   __shared__ double ss[1024], sc[1024];
-  const int comp = blockIdx.x;
+  if (step_failed(flags)) return;
+  const int comp = blockIdx.x % ncomp, s = blockIdx.x / ncomp;
+  const int k0 = off[s], k1 = off[s + 1];
   Neu a{0.0, 0.0};
-  for (int k = threadIdx.x; k < count; k += 1024) {
-    const double x = (double)src[(size_t)k * stride + comp];
+  for (int k = k0 + threadIdx.x; k < k1; k += 1024) {
+    const double x = src[(size_t)k * ncomp + comp];
     neu_add(a, x);
     if (copy_out) copy_out[k] = x;
   }
@@ -114,26 +126,31 @@ __global__ void __launch_bounds__(1024) k_neumaier(const S *__restrict__ src, in
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[comp] = ss[0] + sc[0];
+  if (threadIdx.x == 0) out[(size_t)s * ncomp + comp] = ss[0] + sc[0];
 }
 
 }  // namespace
 
-void launch_forces(const Workspace &ws, const double *coords, int n, const Grid &g, bool grid_on_device,
-                   const double *gE, double *forces, double *virial_out, hipStream_t st) {
-  const Grid *dg = grid_on_device ? ws.grid : nullptr;
-  hipLaunchKernelGGL(k_forces, dim3((n + 3) / 4), dim3(256), 0, st, ws.g, ws.nlist, ws.nnei, ws.rev, coords, g, dg,
-                     n, gE, forces, ws.vpart);
+void launch_forces(const Workspace &ws, const double *coords, int n, int nsys, const double *gE, double *forces,
+                   double *virial_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_forces, dim3((n + 3) / 4), dim3(256), 0, st, ws.g, ws.nlist, ws.nnei, ws.rev, coords,
+                     ws.grids, ws.sys_of, n, gE, forces, ws.vpart, ws.flags);
   const long long tot = (long long)n * SEL;
   hipLaunchKernelGGL(k_forces_onesided, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.g, ws.nlist,
-                     ws.nnei, ws.rev, n, gE, forces);
+                     ws.nnei, ws.rev, n, gE, forces, ws.flags);
   if (virial_out)
-    hipLaunchKernelGGL(k_neumaier<double>, dim3(9), dim3(1024), 0, st, ws.vpart, n, 9, virial_out,
-                       (double *)nullptr);
+    hipLaunchKernelGGL(k_seg_neumaier, dim3(9 * nsys), dim3(1024), 0, st, ws.vpart, ws.sys_off, 9, virial_out,
+                       (double *)nullptr, ws.flags);
 }
 
-void launch_energy(const Workspace &ws, int n, double *energy, double *atom_energy, hipStream_t st) {
-  hipLaunchKernelGGL(k_neumaier<double>, dim3(1), dim3(1024), 0, st, ws.Ei, n, 1, energy, atom_energy);
+void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_neumaier, dim3(1), dim3(1024), 0, st, src, ws.sys_off, 1, out, (double *)nullptr,
+                     ws.flags);
+}
+
+void launch_energy(const Workspace &ws, int nsys, double *energy, double *atom_energy, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_neumaier, dim3(nsys), dim3(1024), 0, st, ws.Ei, ws.sys_off, 1, energy, atom_energy,
+                     ws.flags);
 }
 
 }  // namespace dp

@@ -17,12 +17,10 @@
 namespace dp {
 namespace {
 
-__device__ __forceinline__ Grid load_grid(const Grid &g, const Grid *dg) { return dg ? *dg : g; }
-
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Bounding box of the atoms for open boundaries; one workgroup.
-__global__ void __launch_bounds__(1024) k_grid_open(const double *__restrict__ X, int n, double rc,
+// Bounding box of the atoms of a single open-boundary system -> grids[0]; one workgroup.
+__global__ void __launch_bounds__(1024) k_grid_open(const double *__restrict__ X, int n, double cutoff,
                                                     Grid *__restrict__ out, unsigned *__restrict__ flags) {
   __shared__ double smin[3][1024], smax[3][1024];
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -49,12 +47,13 @@ __global__ void __launch_bounds__(1024) k_grid_open(const double *__restrict__ X
   if (threadIdx.x == 0) {
     Grid g;
     g.periodic = 0;
+    g.cell_base = 0;
     int nct = 1;
     for (int a = 0; a < 3; ++a) {
       double o = smin[a][0], e = smax[a][0] - smin[a][0];
       if (!(e > 0.0)) e = 1.0;
       if (!isfinite(o)) { o = 0.0; e = 1.0; }
-      int nc = (int)floor(e / (rc * (1.0 + 1e-9)));
+      int nc = (int)floor(e / (cutoff * (1.0 + 1e-9)));
       nc = clampi(nc, 1, MAX_CELLS_PER_DIM);
       g.origin[a] = o;
       g.L[a] = e;
@@ -74,12 +73,24 @@ __global__ void k_fill_int(int *__restrict__ p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// sys_of[a] = s for off[s] <= a < off[s + 1].
+__global__ void k_sys_of(const int *__restrict__ off, int nsys, int n, int *__restrict__ sys_of) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= a) lo = mid; else hi = mid - 1;
+  }
+  sys_of[a] = lo;
+}
+
 __global__ void k_cell_assign(const double *__restrict__ X, const int *__restrict__ types, int n, int ntypes,
-                              Grid hg, const Grid *__restrict__ dg, int *__restrict__ cell_of,
+                              const Grid *__restrict__ grids, const int *__restrict__ sys_of, int *__restrict__ cell_of,
                               int *__restrict__ cell_count, unsigned *__restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const Grid g = load_grid(hg, dg);
+  const Grid g = grids[sys_of[i]];
   const int t = types[i];
   if (t < 0 || t >= ntypes) atomicOr(flags, FLAG_TYPE);
   int c[3];
@@ -93,17 +104,18 @@ __global__ void k_cell_assign(const double *__restrict__ X, const int *__restric
     c[a] = clampi((int)floor(w * g.icw[a]), 0, g.nc[a] - 1);
   }
   if (!ok) atomicOr(flags, FLAG_NONFINITE);
-  const int cell = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+  const int cell = g.cell_base + (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
   cell_of[i] = cell;
   atomicAdd(&cell_count[cell], 1);
 }
 
-// Exclusive scan of the cell counts; one workgroup of 1024 threads.
+// Exclusive scan of the cell counts; one workgroup of 1024 threads.  The number of
+// cells is nc_host, or the cell count of *open_grid when that is given.
 __global__ void __launch_bounds__(1024) k_cell_scan(const int *__restrict__ count, int *__restrict__ start,
-                                                    int *__restrict__ cursor, Grid hg, const Grid *__restrict__ dg) {
+                                                    int *__restrict__ cursor, int nc_host,
+                                                    const Grid *__restrict__ open_grid) {
   __shared__ int part[1024];
-  const Grid g = load_grid(hg, dg);
-  const int nc = g.ncells;
+  const int nc = open_grid ? open_grid->ncells : nc_host;
   const int per = (nc + 1023) / 1024;
   const int b = threadIdx.x * per, e = min(nc, b + per);
   int s = 0;
@@ -147,10 +159,58 @@ __device__ __forceinline__ int stencil_axis(int c, int nc, int periodic, int out
   return k;
 }
 
-// One wavefront (one workgroup of 64) per atom.
-__global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int n, Grid hg, const Grid *__restrict__ dg,
-                                              double rc2, const int *__restrict__ cell_of,
-                                              const int *__restrict__ cell_start, const int *__restrict__ cell_atoms,
+// The canonical float64 squared distance (every operation rounded on its own).
+__device__ __forceinline__ double pair_d2(const Grid &g, double xi, double yi, double zi, const double *__restrict__ xj) {
+  double dx = __dsub_rn(xj[0], xi), dy = __dsub_rn(xj[1], yi), dz = __dsub_rn(xj[2], zi);
+  if (g.periodic) {
+    dx = __dsub_rn(dx, __dmul_rn(g.L[0], rint(__dmul_rn(dx, g.invL[0]))));
+    dy = __dsub_rn(dy, __dmul_rn(g.L[1], rint(__dmul_rn(dy, g.invL[1]))));
+    dz = __dsub_rn(dz, __dmul_rn(g.L[2], rint(__dmul_rn(dz, g.invL[2]))));
+  }
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Writes a list row from count candidates (cj, cd2) in LDS: sorted by j; with more than
+// cap candidates only the cap smallest by (d2, j) are kept.  Returns true on overflow.
+__device__ bool write_row(const int *cj, const double *cd2, int *keep, int count, int cap, int *row, int *nnei_out,
+                          int lane) {
+  if (count <= cap) {
+    for (int e = lane; e < count; e += 64) {
+      const int j = cj[e];
+      int rank = 0;
+      for (int f = 0; f < count; ++f) rank += cj[f] < j;
+      row[rank] = j;
+    }
+    for (int r = count + lane; r < cap; r += 64) row[r] = -1;
+    if (lane == 0) *nnei_out = count;
+    return false;
+  }
+  for (int e = lane; e < count; e += 64) {
+    const int j = cj[e];
+    const double d = cd2[e];
+    int rank = 0;
+    for (int f = 0; f < count; ++f) rank += (cd2[f] < d) || (cd2[f] == d && cj[f] < j);
+    keep[e] = rank < cap;
+  }
+  __syncthreads();
+  for (int e = lane; e < count; e += 64) {
+    if (!keep[e]) continue;
+    const int j = cj[e];
+    int rank = 0;
+    for (int f = 0; f < count; ++f) rank += keep[f] && cj[f] < j;
+    row[rank] = j;
+  }
+  if (lane == 0) *nnei_out = cap;
+  return true;
+}
+
+// One wavefront (one workgroup of 64) per atom: every atom of the 27 stencil cells with
+// d2 < cut2 (cell edges >= the cutoff), rows of `cap` entries.  skin = 0: the model list
+// (overflow counted in flags[1]); skin = 1: the skin list (overflow sets FLAG_SKIN_FULL).
+__global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int n, const Grid *__restrict__ grids,
+                                              const int *__restrict__ sys_of, double cut2,
+                                              const int *__restrict__ cell_of, const int *__restrict__ cell_start,
+                                              const int *__restrict__ cell_atoms, int cap, int skin,
                                               int *__restrict__ nlist, int *__restrict__ nnei,
                                               unsigned *__restrict__ flags) {
   __shared__ int cj[CAND_CAP];
@@ -159,9 +219,9 @@ __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int 
   const int i = blockIdx.x;
   if (i >= n) return;
   const int lane = threadIdx.x;
-  const Grid g = load_grid(hg, dg);
+  const Grid g = grids[sys_of[i]];
   const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
-  const int cell = cell_of[i];
+  const int cell = clampi(cell_of[i] - g.cell_base, 0, g.ncells - 1);
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[1] * g.nc[2]);
   int sx[3], sy[3], sz[3];
   const int nx = stencil_axis(cx, g.nc[0], g.periodic, sx);
@@ -172,7 +232,7 @@ __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int 
   for (int a = 0; a < nx; ++a)
     for (int b = 0; b < ny; ++b)
       for (int c = 0; c < nz; ++c) {
-        const int cc = (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[c];
+        const int cc = g.cell_base + (sx[a] * g.nc[1] + sy[b]) * g.nc[2] + sz[c];
         const int s0 = cell_start[cc], s1 = cell_start[cc + 1];
         for (int p = s0; p < s1; p += 64) {
           const int q = p + lane;
@@ -182,14 +242,8 @@ __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int 
           if (q < s1) {
             j = cell_atoms[q];
             if (j != i) {
-              double dx = __dsub_rn(X[3 * j], xi), dy = __dsub_rn(X[3 * j + 1], yi), dz = __dsub_rn(X[3 * j + 2], zi);
-              if (g.periodic) {
-                dx = __dsub_rn(dx, __dmul_rn(g.L[0], rint(__dmul_rn(dx, g.invL[0]))));
-                dy = __dsub_rn(dy, __dmul_rn(g.L[1], rint(__dmul_rn(dy, g.invL[1]))));
-                dz = __dsub_rn(dz, __dmul_rn(g.L[2], rint(__dmul_rn(dz, g.invL[2]))));
-              }
-              d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-              acc = d2 < rc2;
+              d2 = pair_d2(g, xi, yi, zi, X + 3 * j);
+              acc = d2 < cut2;
               overlap |= (d2 == 0.0);
             }
           }
@@ -205,37 +259,84 @@ __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int 
     count = CAND_CAP;
   }
   __syncthreads();
-  int *row = nlist + (size_t)i * SEL;
-  if (count <= SEL) {
-    for (int e = lane; e < count; e += 64) {
-      const int j = cj[e];
-      int rank = 0;
-      for (int f = 0; f < count; ++f) rank += cj[f] < j;
-      row[rank] = j;
-    }
-    for (int r = count + lane; r < SEL; r += 64) row[r] = -1;
-    if (lane == 0) nnei[i] = count;
-  } else {
-    for (int e = lane; e < count; e += 64) {
-      const int j = cj[e];
-      const double d = cd2[e];
-      int rank = 0;
-      for (int f = 0; f < count; ++f) rank += (cd2[f] < d) || (cd2[f] == d && cj[f] < j);
-      keep[e] = rank < SEL;
-    }
-    __syncthreads();
-    for (int e = lane; e < count; e += 64) {
-      if (!keep[e]) continue;
-      const int j = cj[e];
-      int rank = 0;
-      for (int f = 0; f < count; ++f) rank += keep[f] && cj[f] < j;
-      row[rank] = j;
-    }
-    if (lane == 0) {
-      nnei[i] = SEL;
-      atomicAdd(flags + 1, 1u);
-    }
+  const bool ovf = write_row(cj, cd2, keep, count, cap, nlist + (size_t)i * cap, nnei + i, lane);
+  if (ovf && lane == 0) {
+    if (skin) atomicOr(flags, FLAG_SKIN_FULL);
+    else atomicAdd(flags + 1, 1u);
   }
+}
+
+// Model list from the skin list: the entries of atom i's skin row with d2 < rc2 at the
+// current coordinates, by the same rule as k_nlist (the skin row is sorted by j, and a
+// wave-ordered compaction keeps that order).  Identical to a fresh search as long as
+// no atom has moved by half the skin since the skin list was built.
+__global__ void __launch_bounds__(64) k_filter(const double *__restrict__ X, int n, const Grid *__restrict__ grids,
+                                               const int *__restrict__ sys_of, double rc2,
+                                               const int *__restrict__ slist, const int *__restrict__ snnei,
+                                               int *__restrict__ nlist, int *__restrict__ nnei,
+                                               unsigned *__restrict__ flags) {
+  __shared__ int cj[SKIN_CAP];
+  __shared__ double cd2[SKIN_CAP];
+  __shared__ int keep[SKIN_CAP];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int lane = threadIdx.x;
+  const Grid g = grids[sys_of[i]];
+  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
+  const int ns = min(max(snnei[i], 0), SKIN_CAP);
+  int count = 0;
+  bool overlap = false;
+  for (int p = 0; p < ns; p += 64) {
+    const int e = p + lane;
+    int j = -1;
+    double d2 = 0.0;
+    bool acc = false;
+    if (e < ns) {
+      j = slist[(size_t)i * SKIN_CAP + e];
+      if (j >= 0 && j < n && j != i) {
+        d2 = pair_d2(g, xi, yi, zi, X + 3 * j);
+        acc = d2 < rc2;
+        overlap |= (d2 == 0.0);
+      }
+    }
+    const unsigned long long mask = __ballot(acc);
+    const int pos = count + __popcll(mask & ((1ull << lane) - 1ull));
+    if (acc) { cj[pos] = j; cd2[pos] = d2; }
+    count += __popcll(mask);
+  }
+  if (overlap) atomicOr(flags, FLAG_OVERLAP);
+  __syncthreads();
+  const bool ovf = write_row(cj, cd2, keep, count, SEL, nlist + (size_t)i * SEL, nnei + i, lane);
+  if (ovf && lane == 0) atomicAdd(flags + 1, 1u);
+}
+
+// Per-step checks of the skin path (the cell pass, which makes them otherwise, is
+// skipped): finite coordinates, types in range, and every displacement since the
+// skin list was built below half the skin (else FLAG_STALE).
+__global__ void k_skin_check(const double *__restrict__ X, const double *__restrict__ Xref,
+                             const int *__restrict__ types, int n, int ntypes, const Grid *__restrict__ grids,
+                             const int *__restrict__ sys_of, double lim2, unsigned *__restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Grid g = grids[sys_of[i]];
+  const int t = types[i];
+  if (t < 0 || t >= ntypes) atomicOr(flags, FLAG_TYPE);
+  double d2 = 0.0;
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    const double x = X[3 * i + a];
+    if (!isfinite(x)) ok = false;
+    double d = x - Xref[3 * i + a];
+    if (g.periodic) d -= g.L[a] * rint(d * g.invL[a]);
+    d2 += d * d;
+  }
+  if (!ok) atomicOr(flags, FLAG_NONFINITE);
+  else if (!(d2 < lim2)) atomicOr(flags, FLAG_STALE);
+}
+
+__global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 // rev[i][s] = slot of i in the list of j = nlist[i][s], or -1 (lists sorted ascending).
@@ -266,21 +367,47 @@ __global__ void k_rev(const int *__restrict__ nlist, const int *__restrict__ nne
 
 }  // namespace
 
-void launch_neighbors(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, const Grid &g,
-                      bool grid_on_device, double rc, hipStream_t st) {
-  const Grid *dg = grid_on_device ? ws.grid : nullptr;
-  if (grid_on_device)
-    hipLaunchKernelGGL(k_grid_open, dim3(1), dim3(1024), 0, st, coords, n, rc, ws.grid, ws.flags);
-  const int ncell_alloc = grid_on_device ? MAX_CELLS : g.ncells;
+void launch_sys_of(const Workspace &ws, int nsys, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_sys_of, dim3((n + 255) / 256), dim3(256), 0, st, ws.sys_off, nsys, n, ws.sys_of);
+}
+
+void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
+                  int ncells_total, double cell_cutoff, hipStream_t st) {
+  if (open_single)
+    hipLaunchKernelGGL(k_grid_open, dim3(1), dim3(1024), 0, st, coords, n, cell_cutoff, ws.grids, ws.flags);
+  const int ncell_alloc = open_single ? MAX_CELLS : ncells_total;
   hipLaunchKernelGGL(k_fill_int, dim3((ncell_alloc + 1 + 255) / 256), dim3(256), 0, st, ws.cell_count,
                      ncell_alloc + 1, 0);
-  hipLaunchKernelGGL(k_cell_assign, dim3((n + 255) / 256), dim3(256), 0, st, coords, types, n, ntypes, g, dg,
-                     ws.cell_of, ws.cell_count, ws.flags);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, ws.cell_count, ws.cell_start, ws.cell_cursor, g, dg);
+  hipLaunchKernelGGL(k_cell_assign, dim3((n + 255) / 256), dim3(256), 0, st, coords, types, n, ntypes, ws.grids,
+                     ws.sys_of, ws.cell_of, ws.cell_count, ws.flags);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, ws.cell_count, ws.cell_start, ws.cell_cursor,
+                     ncells_total, open_single ? ws.grids : (const Grid *)nullptr);
   hipLaunchKernelGGL(k_cell_fill, dim3((n + 255) / 256), dim3(256), 0, st, ws.cell_of, ws.cell_cursor,
                      ws.cell_atoms, n);
-  hipLaunchKernelGGL(k_nlist, dim3(n), dim3(64), 0, st, coords, n, g, dg, rc * rc, ws.cell_of, ws.cell_start,
-                     ws.cell_atoms, ws.nlist, ws.nnei, ws.flags);
+}
+
+void launch_nlist(const Workspace &ws, const double *coords, int n, double cutoff, bool skin, hipStream_t st) {
+  hipLaunchKernelGGL(k_nlist, dim3(n), dim3(64), 0, st, coords, n, ws.grids, ws.sys_of, cutoff * cutoff, ws.cell_of,
+                     ws.cell_start, ws.cell_atoms, skin ? SKIN_CAP : SEL, skin ? 1 : 0, skin ? ws.slist : ws.nlist,
+                     skin ? ws.snnei : ws.nnei, ws.flags);
+}
+
+void launch_filter(const Workspace &ws, const double *coords, int n, double rc, hipStream_t st) {
+  hipLaunchKernelGGL(k_filter, dim3(n), dim3(64), 0, st, coords, n, ws.grids, ws.sys_of, rc * rc, ws.slist, ws.snnei,
+                     ws.nlist, ws.nnei, ws.flags);
+}
+
+void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_skin_check, dim3((n + 255) / 256), dim3(256), 0, st, coords, ws.xref, types, n, ntypes,
+                     ws.grids, ws.sys_of, lim2, ws.flags);
+}
+
+void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f64, dim3((3 * n + 255) / 256), dim3(256), 0, st, coords, ws.xref, 3 * n);
+}
+
+void launch_rev(const Workspace &ws, int n, hipStream_t st) {
   const long long tot = (long long)n * SEL;
   hipLaunchKernelGGL(k_rev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.nlist, ws.nnei, ws.rev, n,
                      ws.flags);

@@ -1,0 +1,190 @@
+"""Step modes of the GPU path: batched systems, neighbour-list reuse with a skin,
+graph replay, the continuous-batching server and the NVE harness.
+
+Each mode must reproduce the plain single-system call bit for bit (the per-atom
+kernels see the same data in the same order), and the NVE harness must follow
+the oracle's trajectory.
+"""
+import numpy as np
+import pytest
+
+from oracle import load_model
+from oracle.nve import MASSES, maxwell_boltzmann, run_nve_traj
+from tolerances import FP32
+from synth import config_system, request_system
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(a, b):
+    return a["E"] == b["E"] and np.array_equal(a["F"], b["F"]) and np.array_equal(a["virial"], b["virial"])
+
+
+def _systems():
+    out = []
+    for name in ("water192", "chain1k"):
+        s = config_system(name)
+        out.append((s.coords, s.types, s.box))
+    w = request_system(300, "water", seed=21)
+    out.append((w.coords, w.types, w.box))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_equals_alone(gpu_models, prec):
+    m = gpu_models[prec]
+    systems = _systems()
+    alone = [m.compute(*s) for s in systems]
+    batch = m.compute_batch(systems)
+    for a, b in zip(alone, batch):
+        assert _same(a, b)
+
+
+def test_skin_lists_equal_fresh(model_path):
+    from paper_2602_02234_amd import Model
+    fresh = Model(model_path, "bf16")
+    skin = Model(model_path, "bf16")
+    skin.set_skin(1.0, 5)
+    s = config_system("chain1k")
+    rng = np.random.default_rng(5)
+    X = s.coords.copy()
+    for step in range(12):
+        X = X + rng.normal(scale=0.02, size=X.shape)
+        if step == 7:
+            X[10] += np.array([0.0, 0.7, 0.0])  # more than half the skin: the reuse check must catch it
+        a, b = fresh.compute(X, s.types, s.box), skin.compute(X, s.types, s.box)
+        assert _same(a, b), step
+        nl_a = fresh.neighbors(X, s.box)
+        assert np.array_equal(nl_a[0], fresh.neighbors(X, s.box)[0])
+    st = skin.skin_stats()
+    assert st["forced"] >= 1 and st["builds"] >= 3, st
+    fresh.close()
+    skin.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_graph_replay_matches_eager(model_path, prec):
+    import torch
+    from paper_2602_02234_amd import Model
+    eager, graph = Model(model_path, prec), Model(model_path, prec)
+    graph.set_graph(True)
+    s = config_system("water192")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(s.coords, device=dev)
+    T = torch.tensor(s.types, device=dev)
+    outs = {}
+    for name, m in (("eager", eager), ("graph", graph)):
+        F = torch.zeros((s.natoms, 3), dtype=torch.float64, device=dev)
+        V = torch.zeros(9, dtype=torch.float64, device=dev)
+        E = torch.zeros(1, dtype=torch.float64, device=dev)
+        rows = []
+        Xw = X.clone()
+        for k in range(5):
+            Xw.copy_(X + 0.01 * k)                     # same buffer, new coordinates
+            junk = torch.randn(1000, device=dev).sum()  # unrelated eager work between replays
+            m.compute_device(Xw, T, s.box, forces=F, virial=V, energy=E)
+            torch.cuda.synchronize()
+            rows.append((E.item(), F.cpu().numpy().copy(), V.cpu().numpy().copy(), float(junk)))
+        outs[name] = rows
+    for (e1, f1, v1, _), (e2, f2, v2, _) in zip(outs["eager"], outs["graph"]):
+        assert e1 == e2 and np.array_equal(f1, f2) and np.array_equal(v1, v2)
+    eager.close()
+    graph.close()
+
+
+def test_server_results_same_alone_and_in_mix(model_path):
+    from paper_2602_02234_amd import Model, Server
+    m = Model(model_path, "bf16")
+    systems = _systems() + [(w.coords, w.types, w.box) for w in (request_system(192, "water", 22), request_system(450, "water", 23))]
+    s3 = config_system("chain3k")
+    systems.append((s3.coords, s3.types, s3.box))
+    alone = [m.compute(*s) for s in systems]
+    srv = Server(m, 8 << 30)
+    ids = [srv.submit(*s) for s in systems]
+    outs = [srv.wait(i, 120.0) for i in ids]
+    for a, o in zip(alone, outs):
+        assert _same(a, o)
+    st = srv.stats()
+    assert st["completed"] == len(systems)
+    assert st["p50_s"] > 0 and st["p99_s"] >= st["p50_s"]
+    print(st)
+    srv.close()
+    m.close()
+
+
+def test_server_admission_by_footprint(model_path):
+    from paper_2602_02234_amd import DPError, Model, Server
+    m = Model(model_path, "bf16")
+    s = config_system("chain1k")
+    probe = Server(m, 1 << 30)
+    budget = 2 * probe.footprint(1200)
+    probe.close()
+    srv = Server(m, budget)
+    ids = [srv.submit(s.coords + 0.001 * k, s.types, s.box) for k in range(6)]
+    outs = [srv.wait(i, 120.0) for i in ids]
+    ref = m.compute(s.coords, s.types, s.box)
+    assert outs[0]["E"] == ref["E"]
+    st = srv.stats()
+    assert st["completed"] == 6 and st["max_batch_atoms"] <= 1200 and st["batches"] == 6, st
+    big = config_system("chain3k")
+    with pytest.raises(DPError, match="DP_ERR_TOO_LARGE"):
+        srv.submit(big.coords, big.types, big.box)
+    srv.close()
+    m.close()
+
+
+def test_nve_follows_oracle(model_path, omodel):
+    import torch
+    from paper_2602_02234_amd import Model
+    s = config_system("water192")
+    v0 = maxwell_boltzmann(s.types, 300.0, seed=9)
+    steps, dt = 12, 0.5
+    et_ref, X_ref, v_ref = run_nve_traj(omodel, s.coords, s.types, s.box, v0, dt, steps)
+    m = Model(model_path, "fp32")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(s.coords, device=dev)
+    V = torch.tensor(v0, device=dev)
+    T = torch.tensor(s.types, device=dev)
+    ep, ek = m.nve(X, V, T, MASSES, s.box, dt, steps)
+    et = ep + ek
+    dx = np.max(np.abs(X.cpu().numpy() - X_ref))
+    dv = np.max(np.abs(V.cpu().numpy() - v_ref))
+    de = np.max(np.abs(et - et_ref))
+    print(f"NVE water192 fp32 vs oracle after {steps} steps: max|dx| {dx:.2e} A, max|dv| {dv:.2e} A/fs, "
+          f"max|dEtot| {de:.2e} eV")
+    assert dx < 1e-6 and dv < 1e-7
+    # the total energy differs from the oracle's by the FP32 path's energy error at each step
+    assert de <= FP32["e_rel"] * abs(et_ref[0])
+    m.close()
+
+
+def test_nve_skin_trajectory_and_drift(model_path):
+    """100 steps of 0.5 fs on the 10k-atom solvated chain: the skin-list run (rebuilt every
+    10 steps, and earlier whenever an atom has moved by half the skin) is bitwise the
+    fresh-list run; the energy drift is reported."""
+    import torch
+    from paper_2602_02234_amd import Model
+    s = config_system("chain10k")
+    v0 = maxwell_boltzmann(s.types, 300.0, seed=10)
+    dev = torch.device("cuda:0")
+    T = torch.tensor(s.types, device=dev)
+    res = {}
+    for skin in (0.0, 1.0):
+        m = Model(model_path, "fp32")
+        m.set_skin(skin, 10)
+        X = torch.tensor(s.coords, device=dev)
+        V = torch.tensor(v0, device=dev)
+        ep, ek = m.nve(X, V, T, MASSES, s.box, 0.5, 100)
+        res[skin] = (ep + ek, X.cpu().numpy(), m.skin_stats(), ek)
+        m.close()
+    et0, X0, _, _ = res[0.0]
+    et1, X1, st, ek = res[1.0]
+    assert np.array_equal(et0, et1) and np.array_equal(X0, X1)
+    assert st["builds"] >= 10, st
+    print(f"skin lists: {st['builds']} builds, {st['forced']} forced by the half-skin check; "
+          f"kinetic energy {ek[0]:.1f} -> {ek[-1]:.1f} eV")
+    t_ps = np.arange(101) * 0.5e-3
+    drift = np.polyfit(t_ps, et1 / s.natoms, 1)[0]
+    fluct = np.std(et1 - np.polyval(np.polyfit(t_ps, et1, 1), t_ps)) / s.natoms
+    print(f"NVE chain10k fp32: drift {drift:.3e} eV/atom/ps, fluctuation {fluct:.3e} eV/atom")
+    assert abs(drift) < 1e-2 and fluct < 1e-3
