@@ -113,6 +113,87 @@ def sampled_force_error(model_path, system, F, k=6, seed=1):
     return float(np.sqrt(np.mean(e ** 2))), float(np.max(np.abs(e)))
 
 
+def _make_request(r):
+    from synth import request_system
+    s = request_system(r["natoms"], r["kind"], r["seed"])
+    return s.coords, s.types, s.box
+
+
+def _pct(v, p):
+    """Nearest-rank percentile."""
+    v = np.sort(np.asarray(v))
+    k = min(max(int(np.ceil(p * len(v))), 1), len(v))
+    return float(v[k - 1])
+
+
+def make_trace(n_req, workers):
+    """The first n_req requests of the serving trace, generated on host worker processes
+    (called before anything touches the GPU)."""
+    import multiprocessing as mp
+    from synth import serving_trace
+    trace = serving_trace(n_req)
+    with mp.get_context("fork").Pool(workers) as pool:
+        systems = pool.map(_make_request, trace, chunksize=1)
+    return trace, systems
+
+
+def serving_bench(model_path, trace, systems, rates, budget_bytes):
+    """The Poisson request trace (sizes log-uniform 192..40,000 atoms, water boxes or solvated
+    chains) replayed in real time against the BF16 continuous-batching server and against the
+    FP32 path evaluating one request at a time (host API), at each arrival rate."""
+    import time as _t
+    from paper_2602_02234_amd import Model, Server
+    n_req = len(trace)
+    atoms = np.array([len(t) for _, t, _ in systems])
+    out = {"requests": n_req, "atoms_total": int(atoms.sum()), "atoms_median": float(np.median(atoms)),
+           "hbm_budget_GB": budget_bytes / 2**30, "rates": {}}
+    base_t = np.array([r["t"] for r in trace])
+    for rate in rates:
+        arr = base_t * (200.0 / rate)
+        row = {}
+        # BF16 server, continuous batching
+        m = Model(model_path, "bf16")
+        srv = Server(m, budget_bytes)
+        srv.wait(srv.submit(*systems[0]), 120.0)
+        srv.close()
+        srv = Server(m, budget_bytes)
+        t0 = _t.perf_counter()
+        ids = []
+        for a, sysk in zip(arr, systems):
+            d = t0 + a - _t.perf_counter()
+            if d > 0:
+                _t.sleep(d)
+            ids.append(srv.submit(*sysk))
+        lat = [srv.wait(i, 600.0)["latency"] for i in ids]
+        st = srv.stats()
+        srv.close()
+        m.close()
+        row["bf16_server"] = {"p50_ms": 1e3 * _pct(lat, 0.5), "p99_ms": 1e3 * _pct(lat, 0.99),
+                              "atom_evals_per_s": st["atom_evals_per_s"], "batches": st["batches"],
+                              "max_batch_atoms": st["max_batch_atoms"]}
+        # FP32, one request at a time in arrival order
+        m = Model(model_path, "fp32")
+        m.compute(*systems[0])
+        t0 = _t.perf_counter()
+        lat, last = [], 0.0
+        for a, sysk in zip(arr, systems):
+            d = t0 + a - _t.perf_counter()
+            if d > 0:
+                _t.sleep(d)
+            m.compute(*sysk)
+            last = _t.perf_counter() - t0
+            lat.append(last - a)
+        m.close()
+        row["fp32_one_at_a_time"] = {"p50_ms": 1e3 * _pct(lat, 0.5), "p99_ms": 1e3 * _pct(lat, 0.99),
+                                     "atom_evals_per_s": float(atoms.sum() / (last - arr[0]))}
+        out["rates"][f"{rate:g}_req_per_s"] = row
+        print(f"[bench] serving at {rate:g} req/s: bf16 server p50 {row['bf16_server']['p50_ms']:.1f} ms, "
+              f"p99 {row['bf16_server']['p99_ms']:.1f} ms; fp32 one-at-a-time p50 "
+              f"{row['fp32_one_at_a_time']['p50_ms']:.1f} ms, p99 {row['fp32_one_at_a_time']['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def time_path(model, X, T, box, F, V, E, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -138,6 +219,8 @@ def main():
     ap.add_argument("--workload", default="chain10k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests of the serving trace to replay (0 = skip the serving run)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -145,6 +228,13 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    trace = systems_trace = None
+    if args.serve_requests > 0 and not args.copy_probe:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+        t0 = time.perf_counter()
+        trace, systems_trace = make_trace(args.serve_requests, workers)
+        print(f"[bench] generated {len(trace)} serving requests in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     import torch
     from paper_2602_02234_amd import Model
     from synth import config_system, default_model_file
@@ -232,6 +322,10 @@ def main():
         out[f"{prec}_ms_per_step"] = 1e3 * o["dt"] / o["steps"]
         out[f"{prec}_force_rmse_sampled"] = o["f_rmse"]
         out[f"{prec}_phase_ms"] = {k: (ms / c if c else 0.0) for k, (ms, c) in o["prof"].items()}
+    if trace is not None:
+        out["serving"] = serving_bench(path, trace, systems_trace, (200.0, 20.0), 16 << 30)
+        r200 = out["serving"]["rates"]["200_req_per_s"]["bf16_server"]
+        out["latency_p50_ms"], out["latency_p99_ms"] = r200["p50_ms"], r200["p99_ms"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))

@@ -17,7 +17,7 @@
 // the two kernels but T); the terms of dG that couple a token to every query row
 // (A^T dH and dS^T U) are gathered in a second pass in which wave w recomputes
 // the score and score-gradient tiles of its own token block against every query
-// block from U and dH kept in LDS.  That pass uses the 16x16x16 MFMA, whose
+// block from U and dH kept in LDS.  That pass uses 16x16x16 products (see mma16), whose
 // A-operand lane layout equals the accumulator layout, so the recomputed tiles
 // feed the transposed product without any data movement.
 #include "dp_env.h"
@@ -38,11 +38,36 @@ __device__ __forceinline__ short bfbits(float x) {
   const bf16_t b = (bf16_t)x;
   return *(const short *)&b;
 }
-// Orders this wave's LDS accesses across a point (the wave reuses its staging buffer).
+// Orders this wave's LDS accesses across a point (the wave reuses its staging buffer):
+// the wave's outstanding memory operations are drained and no instruction is moved
+// across the point.
 __device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// A 16x16x16 product (4 k per lane) through the 16x16x32 instruction.  Lane group q
+// holds k = 4q + i (i < 4) of the short form; both operands place it at k' = 8q + i of
+// the long form with k' = 8q + 4..7 zero, so the sum over k' equals the sum over k.
+// The 16x16x16 bf16 instruction itself is not used: in this kernel its results varied
+// from run to run (up to 1e-1 in pair gradients, depending on the surrounding
+// instruction timing), while this form reproduces the CPU emulation of the kernel and is
+// bitwise stable.
+__device__ __forceinline__ f4 mma16(s4 a, s4 b, f4 c) {
+  bf8 x, y;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const short av = a[i], bv = b[i];
+    x[i] = *(const __bf16 *)&av;
+    y[i] = *(const __bf16 *)&bv;
+    x[i + 4] = (__bf16)0.f;
+    y[i + 4] = (__bf16)0.f;
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
 }
 
 // acc[t] += A(16 x K) . B_t(16 x K)^T for t < nt; A rows at a (stride lda); B_t rows
@@ -66,7 +91,7 @@ __device__ __forceinline__ void mm(f4 (&acc)[NT], const bf16_t *a, int lda, cons
     for (int t = 0; t < NT; ++t)
       if (t < nt) {
         const s4 y = ld4(b + (16 * t + r) * ldb + k0 + 4 * q);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc[t], 0, 0, 0);
+        acc[t] = mma16(x, y, acc[t]);
       }
   }
 }
@@ -264,6 +289,33 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, int l
   }
 }
 
+// The fp32 rows j < n of the wave's block (tiles gv) to dst [NPMAX][M] (one layer input).
+__device__ __forceinline__ void save_rows(float *__restrict__ dst, const f4 (&gv)[7], int jb, int n) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+  const int j0 = jb * 16 + 4 * q;
+  float *p = dst + (size_t)j0 * M + cl;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+    if (j0 + ii < n) {
+#pragma unroll
+      for (int t = 0; t < 7; ++t)
+        if (t < 6 || cl < M - 96) p[ii * M + 16 * t] = gv[t][ii];
+    }
+}
+
+// Reads those rows back (rows j >= n, which never reach a valid token, as zero).
+__device__ __forceinline__ void load_rows(const float *__restrict__ src, f4 (&gv)[7], int jb, int n) {
+  const int l = lane_id(), q = l >> 4, cl = l & 15;
+  const int j0 = jb * 16 + 4 * q;
+  const float *p = src + (size_t)j0 * M + cl;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const bool ok = j0 + ii < n;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) gv[t][ii] = (ok && (t < 6 || cl < M - 96)) ? p[ii * M + 16 * t] : 0.f;
+  }
+}
+
 // ======================================================================== forward
 struct __align__(16) SmemF16 {
   bf16_t Gb[NPMAX * LDK];
@@ -275,7 +327,8 @@ struct __align__(16) SmemF16 {
 __global__ void __launch_bounds__(NWF * 64)
 k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
                const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
-               float rc, float rcs, float ln_eps, float *__restrict__ Tsave, float *__restrict__ D) {
+               float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
+               float *__restrict__ D) {
   __shared__ SmemF16 sm;
   const int i = blockIdx.x;
   const Grid g = grids[sys_of[i]];
@@ -299,6 +352,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   for (int layer = 0; layer < NATTN; ++layer) {
     f4 sv[8], xh[7];
     float isig[4];
+    if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * NPMAX * M, gv, jb, n);
     if (act)
       layer_rows(w, wp, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv, sv, xh, isig, nullptr,
                  nullptr);
@@ -355,16 +409,17 @@ struct __align__(16) SmemB16 {
   float drh[NPMAX * 3];
   float dswa[NPMAX];
   float dRt[NPMAX * 4];
-  float T[M * 4], dT[M * 4];
+  float dT[M * 4];
 };
 
-// Backward of one layer for the wave's blocks.  gin: layer input rows (fp32), dg: on entry
-// the gradient w.r.t. the layer output (ignored for the top layer, whose output gradient
-// is Rt dT^T / sel), on exit w.r.t. the layer input.  colw/colc: per-lane column sums of the
-// softmax-weight gradient W and of dC rhat_j over this wave's rows (token columns 16 ct + lane%16).
-__device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top, SmemB16 &sm, int n,
-                          int nb, int NP, float ln_eps, const f4 (&gin)[2][7], f4 (&dg)[2][7], float (&colw)[8],
-                          float (&colc)[8][3]) {
+// Backward of one layer for the wave's blocks, from the layer input saved by the forward
+// kernel (gs, fp32 rows j < n).  dg: on entry the gradient w.r.t. the layer output
+// (ignored for the top layer, whose output gradient is Rt dT^T / sel), on exit w.r.t.
+// the layer input.  colw/colc: per-lane column sums of the softmax-weight gradient W and
+// of dC rhat_j over this wave's rows (token columns 16 ct + lane%16).
+__device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top,
+                                       SmemB16 &sm, const float *__restrict__ gs, int n, int nb, int NP, float ln_eps,
+                                       f4 (&dg)[2][7], float (&colw)[8], float (&colc)[8][3]) {
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
   bf16_t *stg = sm.stg[wv];
   const float inv_sel = 1.f / (float)SEL;
@@ -374,8 +429,7 @@ __device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int la
     if (jb >= nb) continue;
     f4 gcur[7], sv[8], xh[7];
     float isig[4];
-#pragma unroll
-    for (int t = 0; t < 7; ++t) gcur[t] = gin[b][t];
+    load_rows(gs, gcur, jb, n);
     layer_rows(w, wp, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP, ln_eps, gcur, sv, xh, isig, sm.rmax,
                sm.rz);
     // incoming gradient of the layer output and, for the top layer, dRt = G_out dT / sel
@@ -391,8 +445,8 @@ __device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int la
         if (m < M) {
           if (top) {
             const float *dTm = sm.dT + 4 * m;
-            const float *R = sm.e.Rt + 4 * j;
-            v = (R[0] * dTm[0] + R[1] * dTm[1] + R[2] * dTm[2] + R[3] * dTm[3]) * inv_sel;
+            const float sj = sm.e.s[j], hx = sm.e.rh[3 * j], hy = sm.e.rh[3 * j + 1], hz = sm.e.rh[3 * j + 2];
+            v = sj * (dTm[0] + hx * dTm[1] + hy * dTm[2] + hz * dTm[3]) * inv_sel;
 #pragma unroll
             for (int c = 0; c < 4; ++c) pr[c] += gcur[t][ii] * dTm[c];
           } else {
@@ -543,8 +597,8 @@ __device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int la
           yh[ii] = *(const short *)&vh;
           yu[ii] = *(const short *)&vu;
         }
-        cacc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa, yh, cacc[t], 0, 0, 0);
-        cacc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xs, yu, cacc[t], 0, 0, 0);
+        cacc[t] = mma16(xa, yh, cacc[t]);
+        cacc[t] = mma16(xs, yu, cacc[t]);
       }
     }
 #pragma unroll
@@ -553,11 +607,24 @@ __device__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int la
   __syncthreads();
 }
 
+// Puts the saved layer input rows (fp32 -> bf16) of the wave's blocks into Gb / GbT.
+__device__ __forceinline__ void stage_layer_input(SmemB16 &sm, const float *__restrict__ gs, int n, int nb) {
+  const int wv = wave_id();
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int jb = wv + NWB * b;
+    if (jb >= nb) continue;
+    f4 gv[7];
+    load_rows(gs, gv, jb, n);
+    put_rows(sm.Gb, sm.GbT, gv, jb);
+  }
+}
+
 __global__ void __launch_bounds__(NWB * 64)
 k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
-               const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
-               float rc, float rcs, float ln_eps, const float *__restrict__ Tsave, const float *__restrict__ dD,
-               float4 *__restrict__ gout) {
+               const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids,
+               const int *__restrict__ sys_of, float rc, float rcs, float ln_eps, const float *__restrict__ Gsave,
+               const float *__restrict__ Tsave, const float *__restrict__ dD, float4 *__restrict__ gout) {
   __shared__ SmemB16 sm;
   const int i = blockIdx.x;
   const Grid g = grids[sys_of[i]];
@@ -572,56 +639,35 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     for (int a = 0; a < 3; ++a) sm.drh[3 * x + a] = 0.f;
     for (int a = 0; a < 4; ++a) sm.dRt[4 * x + a] = 0.f;
   }
-  for (int x = threadIdx.x; x < M * 4; x += NWB * 64) sm.T[x] = Tsave[(size_t)i * M * 4 + x];
+  // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m']
+  float *T = (float *)sm.stg[0];  // staging is free until the first layer
+  for (int x = threadIdx.x; x < M * 4; x += NWB * 64) T[x] = Tsave[(size_t)i * M * 4 + x];
   __syncthreads();
   const float *dDi = dD + (size_t)i * ND;
   for (int x = threadIdx.x; x < M * 4; x += NWB * 64) {
     const int m = x >> 2, c = x & 3;
     float acc = 0.f;
-    for (int a = 0; a < M2; ++a) acc += dDi[m * M2 + a] * sm.T[4 * a + c];
+    for (int a = 0; a < M2; ++a) acc += dDi[m * M2 + a] * T[4 * a + c];
     if (m < M2)
-      for (int mm2 = 0; mm2 < M; ++mm2) acc += dDi[mm2 * M2 + m] * sm.T[4 * mm2 + c];
+      for (int mm2 = 0; mm2 < M; ++mm2) acc += dDi[mm2 * M2 + m] * T[4 * mm2 + c];
     sm.dT[x] = acc;
   }
-  // G0 = embedding of the wave's rows (fp32 in registers, bf16 in LDS)
-  f4 g0[2][7], g1[2][7], dg[2][7];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int jb = wv + NWB * b;
-#pragma unroll
-    for (int t = 0; t < 7; ++t) g0[b][t] = g1[b][t] = dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-    if (jb < nb) {
-      embed_rows(w, wp, sm.e, ti, jb, (float *)(sm.Uall + jb * 16 * LDK), (float *)sm.stg[wv], g0[b]);
-      put_rows(sm.Gb, sm.GbT, g0[b], jb);
-    }
-  }
+  const float *gs0 = Gsave + (size_t)i * NATTN * NPMAX * M;
+  const float *gs1 = gs0 + (size_t)NPMAX * M;
+  stage_layer_input(sm, gs1, n, nb);
   __syncthreads();
-  // G1 = first layer applied to G0
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int jb = wv + NWB * b;
-    if (jb >= nb) continue;
-    f4 sv[8], xh[7];
-    float isig[4];
-#pragma unroll
-    for (int t = 0; t < 7; ++t) g1[b][t] = g0[b][t];
-    layer_rows(w, wp, 0, sm.e, sm.Gb, sm.GbT, sm.stg[wv], nullptr, jb, n, nb, NP, ln_eps, g1[b], sv, xh, isig, nullptr,
-               nullptr);
-  }
-  __syncthreads();
+  f4 dg[2][7];
 #pragma unroll
   for (int b = 0; b < 2; ++b)
-    if (wv + NWB * b < nb) put_rows(sm.Gb, sm.GbT, g1[b], wv + NWB * b);
-  __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 7; ++t) dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
   float colw[8], colc[8][3];
 #pragma unroll
   for (int ct = 0; ct < 8; ++ct) colw[ct] = colc[ct][0] = colc[ct][1] = colc[ct][2] = 0.f;
-  layer_bwd(w, wp, 1, true, sm, n, nb, NP, ln_eps, g1, dg, colw, colc);
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-    if (wv + NWB * b < nb) put_rows(sm.Gb, sm.GbT, g0[b], wv + NWB * b);
+  layer_bwd(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg, colw, colc);
+  stage_layer_input(sm, gs0, n, nb);
   __syncthreads();
-  layer_bwd(w, wp, 0, false, sm, n, nb, NP, ln_eps, g0, dg, colw, colc);
+  layer_bwd(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg, colw, colc);
   // column sums of the softmax-weight and gate gradients: lanes -> per-wave -> fixed-order total
   float *cp = (float *)sm.Uall;  // [NWB][NPMAX][4]
 #pragma unroll
@@ -768,14 +814,14 @@ void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, c
                                const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
-                     ws.sys_of, rc, rcs, ln_eps, ws.Tsave, ws.D);
+                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
 }
 
 void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_desc_bwd_b16, dim3(n), dim3(NWB * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
-                     ws.sys_of, rc, rcs, ln_eps, ws.Tsave, ws.D, ws.g);
+                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
 }
 
 }  // namespace dp
