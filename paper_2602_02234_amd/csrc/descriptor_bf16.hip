@@ -137,8 +137,8 @@ __device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)
 
 // Embedding net for the wave's rows (block jb) -> G (fp32 tiles).  h1 is staged (fp32) in
 // scr1 (>= 512 floats), h2 in scr2 (>= 1024 floats); both wave-private.
-__device__ void embed_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, const Env &e, int ti, int jb, float *scr1,
-                           float *scr2, f4 (&gv)[7]) {
+__device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2, const bf16_t *w3T, int ld3,
+                           const Env &e, int ti, int jb, float *scr1, float *scr2, f4 (&gv)[7]) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
   for (int x = l; x < 16 * 32; x += 64) {
     const int r = x >> 5, c = x & 31, j = jb * 16 + r;
@@ -147,7 +147,7 @@ __device__ void embed_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, const
   wave_fence();
   f4 a2[4];
   zero(a2);
-  mm_a32<4>(a2, scr1, 32, wp.W2T, 32, 32);
+  mm_a32<4>(a2, scr1, 32, w2T, ld2, 32);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int c = 16 * t + cl;
@@ -160,7 +160,7 @@ __device__ void embed_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, const
   wave_fence();
   f4 a3[7];
   zero(a3);
-  mm_a32<7>(a3, scr2, 64, wp.W3T, 64, 64);
+  mm_a32<7>(a3, scr2, 64, w3T, ld3, 64);
 #pragma unroll
   for (int t = 0; t < 7; ++t) {
     const int m = 16 * t + cl;
@@ -226,13 +226,14 @@ __device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
 // One attention layer forward for the wave's rows: gv (G_in, fp32) -> gv (G_out).
 // Also returns xh (normalised residual) and isig (1/sigma per accumulator row).
 // If Uall is given, U rows are written there (and read from there for S).
-__device__ void layer_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, const Env &e, const bf16_t *Gb,
+__device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq, const bf16_t *wvoT, int ldv, int layer,
+                           const Env &e, const bf16_t *Gb,
                            const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
                            f4 (&gv)[7], f4 (&sv)[8], f4 (&xh)[7], float (&isig)[4], float *rmax, float *rz) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
   f4 acc[7];
   zero(acc);
-  mm<7>(acc, Gb + jb * 16 * LDK, LDK, wp.WqkT[layer], KM, KM, 7);  // U = G Wqk
+  mm<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq, KM, 7);  // U = G Wqk
   const bf16_t *ua;
   int lda;
   if (Uall) {
@@ -259,7 +260,7 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const WeightsB16 &wp, int l
   stage7(stg, acc);
   wave_fence();
   zero(acc);
-  mm<7>(acc, stg, LDT, wp.WvoT[layer], KM, KM, 7);  // Y = H Wvo
+  mm<7>(acc, stg, LDT, wvoT, ldv, KM, 7);  // Y = H Wvo
   wave_fence();
   // X = G + Y;  G <- gamma (X - mu) / sigma + beta
 #pragma unroll
@@ -317,12 +318,28 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ src, f4 (&gv
 }
 
 // ======================================================================== forward
+constexpr int LDW = 120;  // LDS row stride of the staged weights (k contiguous)
+constexpr int LD2 = 40;   // ... of the staged W2^T [64][32]
+constexpr int LD3 = 72;   // ... of the staged W3^T [112][64]
+
 struct __align__(16) SmemF16 {
   bf16_t Gb[NPMAX * LDK];
   bf16_t GbT[KM * LDT];
   bf16_t stg[NWF][16 * LDT];
+  bf16_t W[2][KM * LDW];  // the current stage's weights: W2^T and W3^T, then Wqk^T and Wvo^T of a layer
   Env e;
 };
+
+// Workgroup copy of a [rows][cols] bf16 matrix (cols a multiple of 8, row stride gld in
+// global memory) into LDS with row stride lld, in 16-byte pieces.
+__device__ __forceinline__ void stage_weights(bf16_t *dst, int lld, const bf16_t *__restrict__ src, int gld, int rows,
+                                              int cols) {
+  const int per = cols / 8;
+  for (int x = threadIdx.x; x < rows * per; x += blockDim.x) {
+    const int r = x / per, c = 8 * (x % per);
+    *(bf8 *)(dst + r * lld + c) = *(const bf8 *)(src + (size_t)r * gld + c);
+  }
+}
 
 __global__ void __launch_bounds__(NWF * 64)
 k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
@@ -338,6 +355,9 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
   build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
+  bf16_t *w2s = sm.W[0], *w3s = sm.W[0] + 64 * LD2;
+  stage_weights(w2s, LD2, wp.W2T, 32, 64, 32);
+  stage_weights(w3s, LD3, wp.W3T, 64, KM, 64);
   __syncthreads();
   const bool act = wv < nb;
   const int jb = wv;
@@ -345,21 +365,24 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   f4 gv[7];
   if (act) {
     // h1 scratch in this wave's own (not yet written) rows of Gb, h2 in its staging buffer
-    embed_rows(w, wp, sm.e, ti, jb, (float *)(sm.Gb + jb * 16 * LDK), (float *)stg, gv);
+    embed_rows(w, w2s, LD2, w3s, LD3, sm.e, ti, jb, (float *)(sm.Gb + jb * 16 * LDK), (float *)stg, gv);
     put_rows(sm.Gb, sm.GbT, gv, jb);
   }
-  __syncthreads();
   for (int layer = 0; layer < NATTN; ++layer) {
+    __syncthreads();
+    stage_weights(sm.W[0], LDW, wp.WqkT[layer], KM, KM, KM);
+    stage_weights(sm.W[1], LDW, wp.WvoT[layer], KM, KM, KM);
     f4 sv[8], xh[7];
     float isig[4];
     if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * NPMAX * M, gv, jb, n);
+    __syncthreads();
     if (act)
-      layer_rows(w, wp, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv, sv, xh, isig, nullptr,
-                 nullptr);
+      layer_rows(w, sm.W[0], LDW, sm.W[1], LDW, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv,
+                 sv, xh, isig, nullptr, nullptr);
     __syncthreads();
     if (act) put_rows(sm.Gb, sm.GbT, gv, jb);
-    __syncthreads();
   }
+  __syncthreads();
   // T = G^T Rt / sel: per-wave partial over its rows, then a fixed-order sum over waves
   float *tp = (float *)sm.stg[wv];
   if (act) {
@@ -430,8 +453,8 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     f4 gcur[7], sv[8], xh[7];
     float isig[4];
     load_rows(gs, gcur, jb, n);
-    layer_rows(w, wp, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP, ln_eps, gcur, sv, xh, isig, sm.rmax,
-               sm.rz);
+    layer_rows(w, wp.WqkT[layer], KM, wp.WvoT[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
+               ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
     // incoming gradient of the layer output and, for the top layer, dRt = G_out dT / sel
     f4 go[7];
 #pragma unroll
