@@ -38,6 +38,14 @@ __device__ __forceinline__ short bfbits(float x) {
   const bf16_t b = (bf16_t)x;
   return *(const short *)&b;
 }
+// Exponential and tanh from the hardware base-2 exponential (v_exp_f32) and reciprocal:
+// relative error a few 1e-7, far below the bfloat16 rounding of the products they feed.
+__device__ __forceinline__ float fexp(float x) { return __expf(x); }
+__device__ __forceinline__ float ftanh(float x) {
+  const float t = __expf(-2.f * fabsf(x));
+  return copysignf((1.f - t) * __builtin_amdgcn_rcpf(1.f + t), x);
+}
+
 // Orders this wave's LDS accesses across a point (the wave reuses its staging buffer):
 // the wave's outstanding memory operations are drained and no instruction is moved
 // across the point.
@@ -140,9 +148,27 @@ __device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)
 __device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2, const bf16_t *w3T, int ld3,
                            const Env &e, int ti, int jb, float *scr1, float *scr2, f4 (&gv)[7]) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
-  for (int x = l; x < 16 * 32; x += 64) {
-    const int r = x >> 5, c = x & 31, j = jb * 16 + r;
-    scr1[r * 32 + c] = c < E1 ? tanhf(e.s[j] * w.w1s[c] + w.Bt[(ti * NTYPES + e.tj[j]) * E1 + c]) : 0.f;
+  // per-lane weights: first layer column c1 = lane % 32 (type part for every neighbour
+  // type), second-layer bias columns 16 t + lane%16, third-layer bias columns
+  const int c1 = l & 31;
+  const bool c1v = c1 < E1;
+  const float w1c = c1v ? w.w1s[c1] : 0.f;
+  float bt[NTYPES];
+#pragma unroll
+  for (int u = 0; u < NTYPES; ++u) bt[u] = c1v ? w.Bt[(ti * NTYPES + u) * E1 + c1] : 0.f;
+  float b2v[4], b3v[7];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) b2v[t] = (16 * t + cl < E2) ? w.b2[16 * t + cl] : 0.f;
+#pragma unroll
+  for (int t = 0; t < 7; ++t) b3v[t] = (16 * t + cl < M) ? w.b3[16 * t + cl] : 0.f;
+#pragma unroll
+  for (int x = 0; x < 8; ++x) {
+    const int r = (l >> 5) + 2 * x, j = jb * 16 + r;
+    const int tj = e.tj[j];
+    float b = bt[0];
+#pragma unroll
+    for (int u = 1; u < NTYPES; ++u) b = (tj == u) ? bt[u] : b;
+    scr1[r * 32 + c1] = c1v ? ftanh(e.s[j] * w1c + b) : 0.f;
   }
   wave_fence();
   f4 a2[4];
@@ -154,7 +180,7 @@ __device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2,
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int r = 4 * q + ii;
-      scr2[r * 64 + c] = c < E2 ? tanhf(a2[t][ii] + w.b2[c]) + scr1[r * 32 + (c % E1)] : 0.f;
+      scr2[r * 64 + c] = c < E2 ? ftanh(a2[t][ii] + b2v[t]) + scr1[r * 32 + (c % E1)] : 0.f;
     }
   }
   wave_fence();
@@ -167,7 +193,7 @@ __device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2,
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int r = 4 * q + ii;
-      gv[t][ii] = m < M ? tanhf(a3[t][ii] + w.b3[m]) + scr2[r * 64 + (m % E2)] : 0.f;
+      gv[t][ii] = m < M ? ftanh(a3[t][ii] + b3v[t]) + scr2[r * 64 + (m % E2)] : 0.f;
     }
   }
   wave_fence();
@@ -180,38 +206,63 @@ __device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2,
 __device__ __forceinline__ void softmax_rows(f4 (&sv)[8], const Env &e, int jb, int n, int nb, bf16_t *stg,
                                              float *rmax, float *rz) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
+  float mx[4], z[4], iz[4], hj[4][3];
 #pragma unroll
   for (int ii = 0; ii < 4; ++ii) {
-    const int r = 4 * q + ii, j = jb * 16 + r;
-    float mx = -INFINITY;
+    const int j = jb * 16 + 4 * q + ii;
+    hj[ii][0] = e.rh[3 * j];
+    hj[ii][1] = e.rh[3 * j + 1];
+    hj[ii][2] = e.rh[3 * j + 2];
+    mx[ii] = -INFINITY;
+    z[ii] = 0.f;
+  }
 #pragma unroll
-    for (int ct = 0; ct < 8; ++ct)
-      if (ct < nb && 16 * ct + cl < n) mx = fmaxf(mx, sv[ct][ii]);
-    mx = max16(mx);
-    if (mx == -INFINITY) mx = 0.f;
-    float z = 0.f;
+  for (int ct = 0; ct < 8; ++ct)
+    if (ct < nb && 16 * ct + cl < n)
 #pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      const int k = 16 * ct + cl;
-      const float ex = (ct < nb && k < n) ? expf(sv[ct][ii] - mx) : 0.f;
+      for (int ii = 0; ii < 4; ++ii) mx[ii] = fmaxf(mx[ii], sv[ct][ii]);
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    mx[ii] = max16(mx[ii]);
+    if (mx[ii] == -INFINITY) mx[ii] = 0.f;
+  }
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct) {
+    const int k = 16 * ct + cl;
+    const bool kv = ct < nb && k < n;
+    const float swk = ct < nb ? e.sw[k] : 0.f;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const float ex = kv ? fexp(sv[ct][ii] - mx[ii]) : 0.f;
       sv[ct][ii] = ex;
-      z += (ct < nb) ? e.sw[k] * ex : 0.f;
-    }
-    z = sum16(z);
-    const float iz = z > 0.f ? 1.f / z : 0.f;
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct)
-      if (ct < nb) {
-        const int k = 16 * ct + cl;
-        const float E = sv[ct][ii] * iz;
-        sv[ct][ii] = E;
-        stg[r * LDT + k] = (bf16_t)(e.sw[k] * E * gate(e, j, k));
-      }
-    if (rmax && cl == 0) {
-      rmax[j] = mx;
-      rz[j] = iz;
+      z[ii] += swk * ex;
     }
   }
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    z[ii] = sum16(z[ii]);
+    iz[ii] = z[ii] > 0.f ? 1.f / z[ii] : 0.f;
+  }
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct)
+    if (ct < nb) {
+      const int k = 16 * ct + cl;
+      const float swk = e.sw[k], hx = e.rh[3 * k], hy = e.rh[3 * k + 1], hz = e.rh[3 * k + 2];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const float E = sv[ct][ii] * iz[ii];
+        sv[ct][ii] = E;
+        const float gt = hj[ii][0] * hx + hj[ii][1] * hy + hj[ii][2] * hz;
+        stg[(4 * q + ii) * LDT + k] = (bf16_t)(swk * E * gt);
+      }
+    }
+  if (rmax && cl == 0)
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = jb * 16 + 4 * q + ii;
+      rmax[j] = mx[ii];
+      rz[j] = iz[ii];
+    }
 }
 
 // Stages fp32 tiles (columns 16 t + lane%16, t < 7) into stg [16][LDT] as bf16.
@@ -386,6 +437,13 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   // T = G^T Rt / sel: per-wave partial over its rows, then a fixed-order sum over waves
   float *tp = (float *)sm.stg[wv];
   if (act) {
+    float rt[4][4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = jb * 16 + 4 * q + ii;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rt[ii][c] = (j < n) ? sm.e.Rt[4 * j + c] : 0.f;
+    }
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
       const int m = 16 * t + cl;
@@ -393,10 +451,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
       for (int c = 0; c < 4; ++c) {
         float p = 0.f;
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          const int j = jb * 16 + 4 * q + ii;
-          p += (j < n) ? gv[t][ii] * sm.e.Rt[4 * j + c] : 0.f;
-        }
+        for (int ii = 0; ii < 4; ++ii) p += gv[t][ii] * rt[ii][c];
         p += __shfl_xor(p, 16);
         p += __shfl_xor(p, 32);
         if (q == 0 && m < M) tp[m * 4 + c] = p;
@@ -522,50 +577,71 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     mm<8>(da, sm.dHall + jb * 16 * LDK, LDK, sm.Gb, LDK, KM, nb);  // dA = dH G^T
     wave_fence();
     // weighted-softmax and gate backward
+    float hj[4][3], rho[4], hxa[4], hya[4], hza[4];
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
-      const int r = 4 * q + ii, j = jb * 16 + r;
-      const bool jv = j < n;
-      float rho = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+      const int j = jb * 16 + 4 * q + ii;
+      hj[ii][0] = sm.e.rh[3 * j];
+      hj[ii][1] = sm.e.rh[3 * j + 1];
+      hj[ii][2] = sm.e.rh[3 * j + 2];
+      rho[ii] = hxa[ii] = hya[ii] = hza[ii] = 0.f;
+    }
 #pragma unroll
-      for (int ct = 0; ct < 8; ++ct) {
-        const int k = 16 * ct + cl;
-        if (ct < nb && jv && k < n) {
-          const float P = sm.e.sw[k] * sv[ct][ii];
-          const float gt = gate(sm.e, j, k);
+    for (int ct = 0; ct < 8; ++ct) {
+      const int k = 16 * ct + cl;
+      const bool kv = ct < nb && k < n;
+      float swk = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+      if (ct < nb) {
+        swk = sm.e.sw[k];
+        hx = sm.e.rh[3 * k];
+        hy = sm.e.rh[3 * k + 1];
+        hz = sm.e.rh[3 * k + 2];
+      }
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        if (kv && jb * 16 + 4 * q + ii < n) {
+          const float P = swk * sv[ct][ii];
+          const float gt = hj[ii][0] * hx + hj[ii][1] * hy + hj[ii][2] * hz;
           const float dP = da[ct][ii] * gt;
           const float dC = da[ct][ii] * P;
-          rho += P * dP;
-          hx += dC * sm.e.rh[3 * k];
-          hy += dC * sm.e.rh[3 * k + 1];
-          hz += dC * sm.e.rh[3 * k + 2];
-          colc[ct][0] += dC * sm.e.rh[3 * j];
-          colc[ct][1] += dC * sm.e.rh[3 * j + 1];
-          colc[ct][2] += dC * sm.e.rh[3 * j + 2];
+          rho[ii] += P * dP;
+          hxa[ii] += dC * hx;
+          hya[ii] += dC * hy;
+          hza[ii] += dC * hz;
+          colc[ct][0] += dC * hj[ii][0];
+          colc[ct][1] += dC * hj[ii][1];
+          colc[ct][2] += dC * hj[ii][2];
           da[ct][ii] = dP;
         } else {
           da[ct][ii] = 0.f;
         }
       }
-      rho = sum16(rho);
-      hx = sum16(hx);
-      hy = sum16(hy);
-      hz = sum16(hz);
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = jb * 16 + 4 * q + ii;
+      rho[ii] = sum16(rho[ii]);
+      const float hx = sum16(hxa[ii]), hy = sum16(hya[ii]), hz = sum16(hza[ii]);
       if (cl == 0) {
-        sm.rrho[j] = rho;
+        sm.rrho[j] = rho[ii];
         sm.drh[3 * j] += hx;
         sm.drh[3 * j + 1] += hy;
         sm.drh[3 * j + 2] += hz;
       }
-#pragma unroll
-      for (int ct = 0; ct < 8; ++ct)
-        if (ct < nb) {
-          const int k = 16 * ct + cl;
-          const float W = (jv && k < n) ? sv[ct][ii] * (da[ct][ii] - rho) : 0.f;
-          colw[ct] += W;
-          stg[r * LDT + k] = (bf16_t)(sm.e.sw[k] * W);  // dS
-        }
     }
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct)
+      if (ct < nb) {
+        const int k = 16 * ct + cl;
+        const float swk = sm.e.sw[k];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const bool v = k < n && jb * 16 + 4 * q + ii < n;
+          const float W = v ? sv[ct][ii] * (da[ct][ii] - rho[ii]) : 0.f;
+          colw[ct] += W;
+          stg[(4 * q + ii) * LDT + k] = (bf16_t)(swk * W);  // dS
+        }
+      }
     wave_fence();
     zero(acc);
     mm<7>(acc, stg, LDT, sm.GbT, LDT, NP, 7);  // dU = dS G
@@ -586,6 +662,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     if (kb >= nb) continue;
     const int k = kb * 16 + cl;
     const bool kv = k < n;
+    const float swk = sm.e.sw[k], hkx = sm.e.rh[3 * k], hky = sm.e.rh[3 * k + 1], hkz = sm.e.rh[3 * k + 2];
     f4 cacc[7];
     zero(cacc);
     for (int jb = 0; jb < nb; ++jb) {
@@ -600,11 +677,11 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
         const int j = jb * 16 + 4 * q + ii;
         float A = 0.f, dS = 0.f;
         if (kv && j < n) {
-          const float E = expf(st[0][ii] - sm.rmax[j]) * sm.rz[j];
-          const float P = sm.e.sw[k] * E;
-          const float gt = gate(sm.e, j, k);
+          const float E = fexp(st[0][ii] - sm.rmax[j]) * sm.rz[j];
+          const float P = swk * E;
+          const float gt = sm.e.rh[3 * j] * hkx + sm.e.rh[3 * j + 1] * hky + sm.e.rh[3 * j + 2] * hkz;
           A = P * gt;
-          dS = sm.e.sw[k] * E * (dt[0][ii] * gt - sm.rrho[j]);
+          dS = P * (dt[0][ii] * gt - sm.rrho[j]);
         }
         xa[ii] = bfbits(A);
         xs[ii] = bfbits(dS);
@@ -726,10 +803,17 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     float *h1 = (float *)(sm.dHall + jb * 16 * LDK);  // [16][32]
     float *h2 = (float *)sm.stg[wv];                  // [16][64]
     float *sc = (float *)sm.GbT + wv * 16 * 104;      // [16][104] fp32: dG0 rows, then dh2 (GbT is free now)
-    // recompute h1, t2, h2 (fp32) for these rows
-    for (int x = l; x < 16 * 32; x += 64) {
-      const int r = x >> 5, c = x & 31, j = jb * 16 + r;
-      h1[r * 32 + c] = c < E1 ? tanhf(sm.e.s[j] * w.w1s[c] + w.Bt[(ti * NTYPES + sm.e.tj[j]) * E1 + c]) : 0.f;
+    // recompute h1, t2, h2 (fp32) for these rows, as the forward kernel made them
+    {
+      const int c1 = l & 31;
+      const bool c1v = c1 < E1;
+      const float w1c = c1v ? w.w1s[c1] : 0.f;
+#pragma unroll
+      for (int x = 0; x < 8; ++x) {
+        const int r = (l >> 5) + 2 * x, j = jb * 16 + r;
+        const float bt = c1v ? w.Bt[(ti * NTYPES + sm.e.tj[j]) * E1 + c1] : 0.f;
+        h1[r * 32 + c1] = c1v ? ftanh(sm.e.s[j] * w1c + bt) : 0.f;
+      }
     }
     wave_fence();
     f4 a2[4];
@@ -742,7 +826,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int r = 4 * q + ii;
-        const float tt = c < E2 ? tanhf(a2[t][ii] + w.b2[c]) : 0.f;
+        const float tt = c < E2 ? ftanh(a2[t][ii] + w.b2[c]) : 0.f;
         t2v[t][ii] = tt;
         h2[r * 64 + c] = c < E2 ? tt + h1[r * 32 + (c % E1)] : 0.f;
       }
@@ -760,7 +844,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int r = 4 * q + ii;
-        const float t3 = m < M ? tanhf(a3[t][ii] + w.b3[m]) : 0.f;
+        const float t3 = m < M ? ftanh(a3[t][ii] + w.b3[m]) : 0.f;
         a3[t][ii] = m < M ? dg[b][t][ii] * (1.f - t3 * t3) : 0.f;
         if (m < M) sc[r * 104 + m] = dg[b][t][ii];
       }
