@@ -656,53 +656,86 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
   }
   __syncthreads();
   // column pass: dG[k] += sum_j A_jk dH_j + dS_jk U_j for the wave's own token blocks
+  // (kb = wave and wave + NWB); the U / dH rows of each block jb are gathered once for both
+  {
+    bool has[2];
+    float swk[2], hk[2][3];
+    f4 cacc[2][7];
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int kb = wv + NWB * b;
-    if (kb >= nb) continue;
-    const int k = kb * 16 + cl;
-    const bool kv = k < n;
-    const float swk = sm.e.sw[k], hkx = sm.e.rh[3 * k], hky = sm.e.rh[3 * k + 1], hkz = sm.e.rh[3 * k + 2];
-    f4 cacc[7];
-    zero(cacc);
-    for (int jb = 0; jb < nb; ++jb) {
-      f4 st[1], dt[1];
-      zero(st);
-      zero(dt);
-      mm<1>(st, sm.Uall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
-      mm<1>(dt, sm.dHall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
-      s4 xa, xs;
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int j = jb * 16 + 4 * q + ii;
-        float A = 0.f, dS = 0.f;
-        if (kv && j < n) {
-          const float E = fexp(st[0][ii] - sm.rmax[j]) * sm.rz[j];
-          const float P = swk * E;
-          const float gt = sm.e.rh[3 * j] * hkx + sm.e.rh[3 * j + 1] * hky + sm.e.rh[3 * j + 2] * hkz;
-          A = P * gt;
-          dS = P * (dt[0][ii] * gt - sm.rrho[j]);
-        }
-        xa[ii] = bfbits(A);
-        xs[ii] = bfbits(dS);
-      }
-#pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const int m = 16 * t + cl;
-        s4 yh, yu;
+    for (int b = 0; b < 2; ++b) {
+      const int kb = wv + NWB * b;
+      has[b] = kb < nb;
+      const int k = min(kb, 7) * 16 + cl;
+      swk[b] = sm.e.sw[k];
+      hk[b][0] = sm.e.rh[3 * k];
+      hk[b][1] = sm.e.rh[3 * k + 1];
+      hk[b][2] = sm.e.rh[3 * k + 2];
+      zero(cacc[b]);
+    }
+    if (has[0]) {
+      for (int jb = 0; jb < nb; ++jb) {
+        float rmx[4], rzz[4], rro[4], hj[4][3];
+        bool jv[4];
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
           const int j = jb * 16 + 4 * q + ii;
-          const bf16_t vh = sm.dHall[j * LDK + m], vu = sm.Uall[j * LDK + m];
-          yh[ii] = *(const short *)&vh;
-          yu[ii] = *(const short *)&vu;
+          jv[ii] = j < n;
+          rmx[ii] = sm.rmax[j];
+          rzz[ii] = sm.rz[j];
+          rro[ii] = sm.rrho[j];
+          hj[ii][0] = sm.e.rh[3 * j];
+          hj[ii][1] = sm.e.rh[3 * j + 1];
+          hj[ii][2] = sm.e.rh[3 * j + 2];
         }
-        cacc[t] = mma16(xa, yh, cacc[t]);
-        cacc[t] = mma16(xs, yu, cacc[t]);
+        s4 yh[7], yu[7];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+          const int m = 16 * t + cl;
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int j = jb * 16 + 4 * q + ii;
+            const bf16_t vh = sm.dHall[j * LDK + m], vu = sm.Uall[j * LDK + m];
+            yh[t][ii] = *(const short *)&vh;
+            yu[t][ii] = *(const short *)&vu;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if (!has[b]) continue;
+          const int kb = wv + NWB * b;
+          const bool kv = kb * 16 + cl < n;
+          f4 st[1], dt[1];
+          zero(st);
+          zero(dt);
+          mm<1>(st, sm.Uall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
+          mm<1>(dt, sm.dHall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
+          s4 xa, xs;
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            float A = 0.f, dS = 0.f;
+            if (kv && jv[ii]) {
+              const float E = fexp(st[0][ii] - rmx[ii]) * rzz[ii];
+              const float P = swk[b] * E;
+              const float gt = hj[ii][0] * hk[b][0] + hj[ii][1] * hk[b][1] + hj[ii][2] * hk[b][2];
+              A = P * gt;
+              dS = P * (dt[0][ii] * gt - rro[ii]);
+            }
+            xa[ii] = bfbits(A);
+            xs[ii] = bfbits(dS);
+          }
+#pragma unroll
+          for (int t = 0; t < 7; ++t) {
+            cacc[b][t] = mma16(xa, yh[t], cacc[b][t]);
+            cacc[b][t] = mma16(xs, yu[t], cacc[b][t]);
+          }
+        }
       }
     }
 #pragma unroll
-    for (int t = 0; t < 7; ++t) dg[b][t] += cacc[t];
+    for (int b = 0; b < 2; ++b)
+      if (has[b])
+#pragma unroll
+        for (int t = 0; t < 7; ++t) dg[b][t] += cacc[b][t];
   }
   __syncthreads();
 }
@@ -795,6 +828,11 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     sm.drh[3 * x + 2] += a3;
   }
   __syncthreads();
+  // the embedding weights of the larger products into LDS (Uall is free now)
+  bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
+  stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
+  stage_weights(w3s, KM, wp.W3, KM, 64, KM);
+  __syncthreads();
   // embedding backward and the pair gradients of the wave's rows
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
@@ -834,7 +872,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     wave_fence();
     f4 a3[7];
     zero(a3);
-    mm_a32<7>(a3, h2, 64, wp.W3T, 64, 64);
+    mm_a32<7>(a3, h2, 64, w3Ts, LD3, 64);
     // dpre3 = dG0 (1 - t3^2) staged as bf16; dG0 half sums (cols c and c + 50) into sc
     wave_fence();
     bf16_t *stg = sm.stg[wv];  // aliases h2, which is no longer needed
@@ -855,7 +893,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     // dh2 = dpre3 W3^T + (dG0[:, :50] + dG0[:, 50:]);  dpre2 = dh2 (1 - t2^2)
     f4 d2[4];
     zero(d2);
-    mm<4>(d2, stg, LDT, wp.W3, KM, KM, 4);
+    mm<4>(d2, stg, LDT, w3s, KM, KM, 4);
     wave_fence();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
