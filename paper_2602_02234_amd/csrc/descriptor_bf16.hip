@@ -104,6 +104,52 @@ __device__ __forceinline__ void mm(f4 (&acc)[NT], const bf16_t *a, int lda, cons
   }
 }
 
+// acc[t] += A(16 x 112) . B_t(16 x 112)^T for t < NT with B in global memory (weights, L2
+// resident).  The fragments of the next k step are loaded before the products of the
+// current one are issued, so a product waits for one L2 round trip, not for one per tile.
+template <int NT>
+__device__ __forceinline__ void mm_g(f4 (&acc)[NT], const bf16_t *a, int lda, const bf16_t *__restrict__ b,
+                                     int ldb) {
+  const int l = lane_id(), r = l & 15, q = l >> 4;
+  bf8 y[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) y[t] = *(const bf8 *)(b + (16 * t + r) * ldb + 8 * q);
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const bf8 x = ld8(a + r * lda + 32 * st + 8 * q);
+    bf8 yn[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (st < 2) {
+        yn[t] = *(const bf8 *)(b + (16 * t + r) * ldb + 32 * (st + 1) + 8 * q);
+      } else {  // the k = 96..111 tail, four per lane, placed as in mma16
+        const s4 v = *(const s4 *)(b + (16 * t + r) * ldb + 96 + 4 * q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const short e = v[i];
+          yn[t][i] = *(const __bf16 *)&e;
+          yn[t][i + 4] = (__bf16)0.f;
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y[t], acc[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) y[t] = yn[t];
+  }
+  const s4 xt = ld4(a + r * lda + 96 + 4 * q);
+  bf8 x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const short e = xt[i];
+    x[i] = *(const __bf16 *)&e;
+    x[i + 4] = (__bf16)0.f;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y[t], acc[t], 0, 0, 0);
+}
+
 // Same with the A operand held as fp32 in LDS (rounded to bf16 when loaded); K multiple of 32.
 template <int NT>
 __device__ __forceinline__ void mm_a32(f4 (&acc)[NT], const float *a, int lda, const bf16_t *b, int ldb, int K) {
@@ -277,6 +323,7 @@ __device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
 // One attention layer forward for the wave's rows: gv (G_in, fp32) -> gv (G_out).
 // Also returns xh (normalised residual) and isig (1/sigma per accumulator row).
 // If Uall is given, U rows are written there (and read from there for S).
+template <bool GW>
 __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq, const bf16_t *wvoT, int ldv, int layer,
                            const Env &e, const bf16_t *Gb,
                            const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
@@ -284,7 +331,10 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
   const int l = lane_id(), q = l >> 4, cl = l & 15;
   f4 acc[7];
   zero(acc);
-  mm<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq, KM, 7);  // U = G Wqk
+  if (GW)
+    mm_g<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq);  // U = G Wqk
+  else
+    mm<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq, KM, 7);
   const bf16_t *ua;
   int lda;
   if (Uall) {
@@ -311,7 +361,10 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
   stage7(stg, acc);
   wave_fence();
   zero(acc);
-  mm<7>(acc, stg, LDT, wvoT, ldv, KM, 7);  // Y = H Wvo
+  if (GW)
+    mm_g<7>(acc, stg, LDT, wvoT, ldv);  // Y = H Wvo
+  else
+    mm<7>(acc, stg, LDT, wvoT, ldv, KM, 7);
   wave_fence();
   // X = G + Y;  G <- gamma (X - mu) / sigma + beta
 #pragma unroll
@@ -428,7 +481,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * NPMAX * M, gv, jb, n);
     __syncthreads();
     if (act)
-      layer_rows(w, sm.W[0], LDW, sm.W[1], LDW, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv,
+      layer_rows<false>(w, sm.W[0], LDW, sm.W[1], LDW, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv,
                  sv, xh, isig, nullptr, nullptr);
     __syncthreads();
     if (act) put_rows(sm.Gb, sm.GbT, gv, jb);
@@ -493,11 +546,12 @@ struct __align__(16) SmemB16 {
 // Backward of one layer for the wave's blocks, from the layer input saved by the forward
 // kernel (gs, fp32 rows j < n).  dg: on entry the gradient w.r.t. the layer output
 // (ignored for the top layer, whose output gradient is Rt dT^T / sel), on exit w.r.t.
-// the layer input.  colw/colc: per-lane column sums of the softmax-weight gradient W and
-// of dC rhat_j over this wave's rows (token columns 16 ct + lane%16).
+// the layer input.  The column pass also adds, for the wave's own token columns k, the
+// column sums over every query row of the softmax-weight gradient W_jk (to dswa[k]) and
+// of the gate gradient dC_jk rhat_j (to drh[k]).
 __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top,
                                        SmemB16 &sm, const float *__restrict__ gs, int n, int nb, int NP, float ln_eps,
-                                       f4 (&dg)[2][7], float (&colw)[8], float (&colc)[8][3]) {
+                                       f4 (&dg)[2][7]) {
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
   bf16_t *stg = sm.stg[wv];
   const float inv_sel = 1.f / (float)SEL;
@@ -508,7 +562,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     f4 gcur[7], sv[8], xh[7];
     float isig[4];
     load_rows(gs, gcur, jb, n);
-    layer_rows(w, wp.WqkT[layer], KM, wp.WvoT[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
+    layer_rows<true>(w, wp.WqkT[layer], KM, wp.WvoT[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
                ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
     // incoming gradient of the layer output and, for the top layer, dRt = G_out dT / sel
     f4 go[7];
@@ -566,7 +620,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     wave_fence();
     f4 acc[7];
     zero(acc);
-    mm<7>(acc, stg, LDT, wp.Wvo[layer], KM, KM, 7);  // dH = dY Wvo^T
+    mm_g<7>(acc, stg, LDT, wp.Wvo[layer], KM);  // dH = dY Wvo^T
 #pragma unroll
     for (int t = 0; t < 7; ++t)
 #pragma unroll
@@ -608,9 +662,6 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
           hxa[ii] += dC * hx;
           hya[ii] += dC * hy;
           hza[ii] += dC * hz;
-          colc[ct][0] += dC * hj[ii][0];
-          colc[ct][1] += dC * hj[ii][1];
-          colc[ct][2] += dC * hj[ii][2];
           da[ct][ii] = dP;
         } else {
           da[ct][ii] = 0.f;
@@ -638,7 +689,6 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
         for (int ii = 0; ii < 4; ++ii) {
           const bool v = k < n && jb * 16 + 4 * q + ii < n;
           const float W = v ? sv[ct][ii] * (da[ct][ii] - rho[ii]) : 0.f;
-          colw[ct] += W;
           stg[(4 * q + ii) * LDT + k] = (bf16_t)(swk * W);  // dS
         }
       }
@@ -649,7 +699,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     stage7(stg, acc);
     wave_fence();
     zero(acc);
-    mm<7>(acc, stg, LDT, wp.Wqk[layer], KM, KM, 7);  // dG += dU Wqk^T
+    mm_g<7>(acc, stg, LDT, wp.Wqk[layer], KM);  // dG += dU Wqk^T
 #pragma unroll
     for (int t = 0; t < 7; ++t) dg[b][t] += acc[t];
     wave_fence();
@@ -660,6 +710,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
   {
     bool has[2];
     float swk[2], hk[2][3];
+    float cw[2][4];  // per-lane partial column sums: W, dC rhat_j (x, y, z)
     f4 cacc[2][7];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -670,6 +721,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
       hk[b][0] = sm.e.rh[3 * k];
       hk[b][1] = sm.e.rh[3 * k + 1];
       hk[b][2] = sm.e.rh[3 * k + 2];
+      cw[b][0] = cw[b][1] = cw[b][2] = cw[b][3] = 0.f;
       zero(cacc[b]);
     }
     if (has[0]) {
@@ -717,8 +769,14 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
               const float E = fexp(st[0][ii] - rmx[ii]) * rzz[ii];
               const float P = swk[b] * E;
               const float gt = hj[ii][0] * hk[b][0] + hj[ii][1] * hk[b][1] + hj[ii][2] * hk[b][2];
+              const float W = E * (dt[0][ii] * gt - rro[ii]);  // softmax-weight gradient
+              const float dC = dt[0][ii] * P;                   // gate gradient
               A = P * gt;
-              dS = P * (dt[0][ii] * gt - rro[ii]);
+              dS = swk[b] * W;
+              cw[b][0] += W;
+              cw[b][1] += dC * hj[ii][0];
+              cw[b][2] += dC * hj[ii][1];
+              cw[b][3] += dC * hj[ii][2];
             }
             xa[ii] = bfbits(A);
             xs[ii] = bfbits(dS);
@@ -732,10 +790,22 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
       }
     }
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-      if (has[b])
+    for (int b = 0; b < 2; ++b) {
+      // column sums over the 4 row groups; column k is owned by this wave alone
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cw[b][c] = sum_cols4(cw[b][c]);
+      if (has[b]) {
 #pragma unroll
         for (int t = 0; t < 7; ++t) dg[b][t] += cacc[b][t];
+        if (q == 0) {
+          const int k = (wv + NWB * b) * 16 + cl;
+          sm.dswa[k] += cw[b][0];
+          sm.drh[3 * k] += cw[b][1];
+          sm.drh[3 * k + 1] += cw[b][2];
+          sm.drh[3 * k + 2] += cw[b][3];
+        }
+      }
+    }
   }
   __syncthreads();
 }
@@ -794,40 +864,10 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int t = 0; t < 7; ++t) dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-  float colw[8], colc[8][3];
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct) colw[ct] = colc[ct][0] = colc[ct][1] = colc[ct][2] = 0.f;
-  layer_bwd(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg, colw, colc);
+  layer_bwd(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg);
   stage_layer_input(sm, gs0, n, nb);
   __syncthreads();
-  layer_bwd(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg, colw, colc);
-  // column sums of the softmax-weight and gate gradients: lanes -> per-wave -> fixed-order total
-  float *cp = (float *)sm.Uall;  // [NWB][NPMAX][4]
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct) {
-    float v0 = colw[ct], v1 = colc[ct][0], v2 = colc[ct][1], v3 = colc[ct][2];
-    v0 = sum_cols4(v0);
-    v1 = sum_cols4(v1);
-    v2 = sum_cols4(v2);
-    v3 = sum_cols4(v3);
-    if (q == 0) {
-      float *o = cp + (wv * NPMAX + 16 * ct + cl) * 4;
-      o[0] = v0; o[1] = v1; o[2] = v2; o[3] = v3;
-    }
-  }
-  __syncthreads();
-  for (int x = threadIdx.x; x < NP; x += NWB * 64) {
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    for (int v = 0; v < NWB; ++v) {
-      const float *o = cp + (v * NPMAX + x) * 4;
-      a0 += o[0]; a1 += o[1]; a2 += o[2]; a3 += o[3];
-    }
-    sm.dswa[x] += a0;
-    sm.drh[3 * x] += a1;
-    sm.drh[3 * x + 1] += a2;
-    sm.drh[3 * x + 2] += a3;
-  }
-  __syncthreads();
+  layer_bwd(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg);
   // the embedding weights of the larger products into LDS (Uall is free now)
   bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
   stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
