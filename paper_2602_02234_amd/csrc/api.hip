@@ -282,7 +282,7 @@ int build_weights(dp_model *m, const HostModel &h) {
 void free_ws(Workspace &ws) {
   void *ps[] = {ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev,
                 ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart, ws.red, ws.grids, ws.sys_off, ws.sys_of, ws.slist,
-                ws.snnei, ws.xref, ws.flags, ws.gE};
+                ws.snnei, ws.xref, ws.flags, ws.gE, ws.bidx, ws.bcnt};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   void *hs[] = {ws.flags_host, ws.grids_host, ws.off_host};
@@ -299,7 +299,8 @@ size_t ws_bytes_per_atom(int prec) {
              + (size_t)ND * sizeof(float)                 // D
              + sizeof(double)                             // Ei
              + (size_t)SEL * sizeof(float4)               // g
-             + 9 * sizeof(double);                        // vpart
+             + 9 * sizeof(double)                         // vpart
+             + 2 * sizeof(int);                           // backward atom lists
   b += (size_t)NATTN * NPMAX * M * sizeof(float);  // Gsave
   return b;
 }
@@ -313,6 +314,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.cell_cursor, MAX_CELLS * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.red, 64 * sizeof(double)));
     HIP_TRY(hipMalloc(&ws.gE, sizeof(double)));
+    HIP_TRY(hipMalloc(&ws.bcnt, 2 * sizeof(int)));
   }
   if (nsys > ws.cap_sys) {
     const int cs = std::max(nsys, 8);
@@ -331,10 +333,10 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
   if (n > ws.cap) {
     const int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
     void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g,
-                  ws.vpart, ws.sys_of, ws.slist, ws.snnei, ws.xref};
+                  ws.vpart, ws.sys_of, ws.slist, ws.snnei, ws.xref, ws.bidx};
     for (void *p : ps)
       if (p) (void)hipFree(p);
-    ws.cell_of = ws.cell_atoms = ws.nlist = ws.nnei = ws.rev = ws.sys_of = ws.slist = ws.snnei = nullptr;
+    ws.cell_of = ws.cell_atoms = ws.nlist = ws.nnei = ws.rev = ws.sys_of = ws.slist = ws.snnei = ws.bidx = nullptr;
     ws.Gsave = ws.Tsave = ws.D = nullptr;
     ws.Ei = ws.vpart = ws.xref = nullptr;
     ws.g = nullptr;
@@ -347,6 +349,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
+    HIP_TRY(hipMalloc(&ws.bidx, 2 * cap * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
     HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));

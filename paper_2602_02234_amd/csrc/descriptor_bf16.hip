@@ -29,7 +29,6 @@ constexpr int KM = 112;   // padded feature width
 constexpr int LDK = 120;  // stride (elements) of [token][feature] bf16 arrays
 constexpr int LDT = 136;  // stride of [feature or row][token] bf16 arrays (tokens padded to 128)
 constexpr int NWF = 8;    // waves per workgroup, forward
-constexpr int NWB = 4;    // waves per workgroup, backward
 typedef short s4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf8 ld8(const bf16_t *p) { return *(const bf8 *)p; }
@@ -529,12 +528,12 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 }
 
 // ======================================================================== backward
-struct __align__(16) SmemB16 {
+template <int NW> struct __align__(16) SmemB16 {
   bf16_t Gb[NPMAX * LDK];
   bf16_t GbT[KM * LDT];
   bf16_t Uall[NPMAX * LDK];
   bf16_t dHall[NPMAX * LDK];
-  bf16_t stg[NWB][16 * LDT];
+  bf16_t stg[NW][16 * LDT];
   Env e;
   float rmax[NPMAX], rz[NPMAX], rrho[NPMAX];
   float drh[NPMAX * 3];
@@ -549,15 +548,16 @@ struct __align__(16) SmemB16 {
 // the layer input.  The column pass also adds, for the wave's own token columns k, the
 // column sums over every query row of the softmax-weight gradient W_jk (to dswa[k]) and
 // of the gate gradient dC_jk rhat_j (to drh[k]).
+template <int NW, int BPW>
 __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top,
-                                       SmemB16 &sm, const float *__restrict__ gs, int n, int nb, int NP, float ln_eps,
-                                       f4 (&dg)[2][7]) {
+                                       SmemB16<NW> &sm, const float *__restrict__ gs, int n, int nb, int NP, float ln_eps,
+                                       f4 (&dg)[BPW][7]) {
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
   bf16_t *stg = sm.stg[wv];
   const float inv_sel = 1.f / (float)SEL;
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int jb = wv + NWB * b;
+  for (int b = 0; b < BPW; ++b) {
+    const int jb = wv + NW * b;
     if (jb >= nb) continue;
     f4 gcur[7], sv[8], xh[7];
     float isig[4];
@@ -706,15 +706,15 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
   }
   __syncthreads();
   // column pass: dG[k] += sum_j A_jk dH_j + dS_jk U_j for the wave's own token blocks
-  // (kb = wave and wave + NWB); the U / dH rows of each block jb are gathered once for both
+  // (kb = wave and wave + NW); the U / dH rows of each block jb are gathered once for both
   {
-    bool has[2];
-    float swk[2], hk[2][3];
-    float cw[2][4];  // per-lane partial column sums: W, dC rhat_j (x, y, z)
-    f4 cacc[2][7];
+    bool has[BPW];
+    float swk[BPW], hk[BPW][3];
+    float cw[BPW][4];  // per-lane partial column sums: W, dC rhat_j (x, y, z)
+    f4 cacc[BPW][7];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int kb = wv + NWB * b;
+    for (int b = 0; b < BPW; ++b) {
+      const int kb = wv + NW * b;
       has[b] = kb < nb;
       const int k = min(kb, 7) * 16 + cl;
       swk[b] = sm.e.sw[k];
@@ -752,9 +752,9 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
           }
         }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BPW; ++b) {
           if (!has[b]) continue;
-          const int kb = wv + NWB * b;
+          const int kb = wv + NW * b;
           const bool kv = kb * 16 + cl < n;
           f4 st[1], dt[1];
           zero(st);
@@ -790,7 +790,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
       }
     }
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < BPW; ++b) {
       // column sums over the 4 row groups; column k is owned by this wave alone
 #pragma unroll
       for (int c = 0; c < 4; ++c) cw[b][c] = sum_cols4(cw[b][c]);
@@ -798,7 +798,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
 #pragma unroll
         for (int t = 0; t < 7; ++t) dg[b][t] += cacc[b][t];
         if (q == 0) {
-          const int k = (wv + NWB * b) * 16 + cl;
+          const int k = (wv + NW * b) * 16 + cl;
           sm.dswa[k] += cw[b][0];
           sm.drh[3 * k] += cw[b][1];
           sm.drh[3 * k + 1] += cw[b][2];
@@ -811,11 +811,12 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
 }
 
 // Puts the saved layer input rows (fp32 -> bf16) of the wave's blocks into Gb / GbT.
-__device__ __forceinline__ void stage_layer_input(SmemB16 &sm, const float *__restrict__ gs, int n, int nb) {
+template <int NW, int BPW>
+__device__ __forceinline__ void stage_layer_input(SmemB16<NW> &sm, const float *__restrict__ gs, int n, int nb) {
   const int wv = wave_id();
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int jb = wv + NWB * b;
+  for (int b = 0; b < BPW; ++b) {
+    const int jb = wv + NW * b;
     if (jb >= nb) continue;
     f4 gv[7];
     load_rows(gs, gv, jb, n);
@@ -823,13 +824,19 @@ __device__ __forceinline__ void stage_layer_input(SmemB16 &sm, const float *__re
   }
 }
 
-__global__ void __launch_bounds__(NWB * 64)
+// NW waves per workgroup, each owning BPW row blocks (wave w owns blocks w, w + NW, ...);
+// the workgroup takes atom idx[blockIdx.x] for blockIdx.x < *count, so atoms can be sent
+// to the instance whose block count fits their neighbour count.
+template <int NW, int BPW>
+__global__ void __launch_bounds__(NW * 64)
 k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
                const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids,
                const int *__restrict__ sys_of, float rc, float rcs, float ln_eps, const float *__restrict__ Gsave,
-               const float *__restrict__ Tsave, const float *__restrict__ dD, float4 *__restrict__ gout) {
-  __shared__ SmemB16 sm;
-  const int i = blockIdx.x;
+               const float *__restrict__ Tsave, const float *__restrict__ dD, float4 *__restrict__ gout,
+               const int *__restrict__ idx, const int *__restrict__ count) {
+  __shared__ SmemB16<NW> sm;
+  if ((int)blockIdx.x >= *count) return;
+  const int i = idx[blockIdx.x];
   const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
@@ -837,17 +844,17 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
   build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
-  for (int x = threadIdx.x; x < NPMAX; x += NWB * 64) {
+  for (int x = threadIdx.x; x < NPMAX; x += NW * 64) {
     sm.dswa[x] = 0.f;
     for (int a = 0; a < 3; ++a) sm.drh[3 * x + a] = 0.f;
     for (int a = 0; a < 4; ++a) sm.dRt[4 * x + a] = 0.f;
   }
   // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m']
   float *T = (float *)sm.stg[0];  // staging is free until the first layer
-  for (int x = threadIdx.x; x < M * 4; x += NWB * 64) T[x] = Tsave[(size_t)i * M * 4 + x];
+  for (int x = threadIdx.x; x < M * 4; x += NW * 64) T[x] = Tsave[(size_t)i * M * 4 + x];
   __syncthreads();
   const float *dDi = dD + (size_t)i * ND;
-  for (int x = threadIdx.x; x < M * 4; x += NWB * 64) {
+  for (int x = threadIdx.x; x < M * 4; x += NW * 64) {
     const int m = x >> 2, c = x & 3;
     float acc = 0.f;
     for (int a = 0; a < M2; ++a) acc += dDi[m * M2 + a] * T[4 * a + c];
@@ -857,17 +864,17 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   }
   const float *gs0 = Gsave + (size_t)i * NATTN * NPMAX * M;
   const float *gs1 = gs0 + (size_t)NPMAX * M;
-  stage_layer_input(sm, gs1, n, nb);
+  stage_layer_input<NW, BPW>(sm, gs1, n, nb);
   __syncthreads();
-  f4 dg[2][7];
+  f4 dg[BPW][7];
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < BPW; ++b)
 #pragma unroll
     for (int t = 0; t < 7; ++t) dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-  layer_bwd(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg);
-  stage_layer_input(sm, gs0, n, nb);
+  layer_bwd<NW, BPW>(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg);
+  stage_layer_input<NW, BPW>(sm, gs0, n, nb);
   __syncthreads();
-  layer_bwd(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg);
+  layer_bwd<NW, BPW>(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg);
   // the embedding weights of the larger products into LDS (Uall is free now)
   bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
   stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
@@ -875,8 +882,8 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   __syncthreads();
   // embedding backward and the pair gradients of the wave's rows
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int jb = wv + NWB * b;
+  for (int b = 0; b < BPW; ++b) {
+    const int jb = wv + NW * b;
     if (jb >= nb) continue;
     float *h1 = (float *)(sm.dHall + jb * 16 * LDK);  // [16][32]
     float *h2 = (float *)sm.stg[wv];                  // [16][64]
@@ -990,7 +997,52 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     }
     wave_fence();
   }
-  for (int j = NP + threadIdx.x; j < SEL; j += NWB * 64) gout[(size_t)i * SEL + j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int j = NP + threadIdx.x; j < SEL; j += NW * 64) gout[(size_t)i * SEL + j] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Stable partition of the atoms by row-block count: idx[0..c0) the atoms with at most
+// SPLIT_NB blocks of 16 neighbours, idx[cap..cap+c1) the others; count[0] = c0, count[1] = c1.
+constexpr int SPLIT_NB = 6;
+__global__ void __launch_bounds__(1024) k_partition(const int *__restrict__ nnei, int n, int cap, int *__restrict__ idx,
+                                                    int *__restrict__ count) {
+  __shared__ int sc[1024];
+  __shared__ int base[2];
+  if (threadIdx.x == 0) base[0] = base[1] = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += 1024) {
+    const int a = c0 + threadIdx.x;
+    int f = 0;  // 1: small, 2: large, 0: none
+    if (a < n) {
+      const int na = min(max(nnei[a], 0), SEL);
+      f = ((max(na, 1) + 15) / 16 <= SPLIT_NB) ? 1 : 2;
+    }
+    // inclusive scan of the small flags (Hillis-Steele)
+    sc[threadIdx.x] = (f == 1);
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+      __syncthreads();
+      sc[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int small_incl = sc[threadIdx.x];
+    const int small_tot = sc[1023];
+    const int valid = min(1024, n - c0);
+    const int pos_small = base[0] + small_incl - 1;
+    const int pos_large = base[1] + ((int)threadIdx.x - small_incl + (f == 1 ? 1 : 0));
+    if (f == 1) idx[pos_small] = a;
+    if (f == 2) idx[cap + pos_large] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      base[0] += small_tot;
+      base[1] += valid - small_tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    count[0] = base[0];
+    count[1] = base[1];
+  }
 }
 
 }  // namespace
@@ -1005,8 +1057,13 @@ void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, c
 void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_bwd_b16, dim3(n), dim3(NWB * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
-                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
+  hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, n, (int)ws.cap, ws.bidx, ws.bcnt);
+  // atoms with up to 6 row blocks: 6 waves, one block each; the rest: 4 waves, two blocks each
+  hipLaunchKernelGGL((k_desc_bwd_b16<6, 1>), dim3(n), dim3(6 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
+                     ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx, ws.bcnt);
+  hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(n), dim3(4 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
+                     ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx + ws.cap,
+                     ws.bcnt + 1);
 }
 
 }  // namespace dp

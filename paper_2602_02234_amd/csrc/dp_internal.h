@@ -108,6 +108,8 @@ struct Workspace {
   int *rev = nullptr;         // [cap][SEL]
   float *Gsave = nullptr;     // [cap][NATTN][NPMAX][M]  inputs of each attention layer
   float *Tsave = nullptr;     // [cap][M][4]
+  int *bidx = nullptr;        // [2][cap]  atoms of each backward kernel instance (bf16 path)
+  int *bcnt = nullptr;        // [2]
   float *D = nullptr;         // [cap][ND]  descriptor, then dE/dD
   double *Ei = nullptr;       // [cap] atomic energies
   float4 *g = nullptr;        // [cap][SEL]  dE_i/dDelta_ij
