@@ -724,6 +724,16 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
       cw[b][0] = cw[b][1] = cw[b][2] = cw[b][3] = 0.f;
       zero(cacc[b]);
     }
+    // the key-side fragments (Gb rows of the wave's column blocks) are the same for every jb
+    bf8 gk[BPW][3];
+    s4 gkt[BPW];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      const bf16_t *gr = sm.Gb + (min(wv + NW * b, 7) * 16 + (l & 15)) * LDK;
+#pragma unroll
+      for (int st = 0; st < 3; ++st) gk[b][st] = ld8(gr + 32 * st + 8 * q);
+      gkt[b] = ld4(gr + 96 + 4 * q);
+    }
     if (has[0]) {
       for (int jb = 0; jb < nb; ++jb) {
         float rmx[4], rzz[4], rro[4], hj[4][3];
@@ -759,8 +769,16 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
           f4 st[1], dt[1];
           zero(st);
           zero(dt);
-          mm<1>(st, sm.Uall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
-          mm<1>(dt, sm.dHall + jb * 16 * LDK, LDK, sm.Gb + kb * 16 * LDK, LDK, KM, 1);
+          {
+            const bf16_t *ur = sm.Uall + (jb * 16 + (l & 15)) * LDK, *hr = sm.dHall + (jb * 16 + (l & 15)) * LDK;
+#pragma unroll
+            for (int s3 = 0; s3 < 3; ++s3) {
+              st[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(ur + 32 * s3 + 8 * q), gk[b][s3], st[0], 0, 0, 0);
+              dt[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(hr + 32 * s3 + 8 * q), gk[b][s3], dt[0], 0, 0, 0);
+            }
+            st[0] = mma16(ld4(ur + 96 + 4 * q), gkt[b], st[0]);
+            dt[0] = mma16(ld4(hr + 96 + 4 * q), gkt[b], dt[0]);
+          }
           s4 xa, xs;
 #pragma unroll
           for (int ii = 0; ii < 4; ++ii) {
@@ -850,10 +868,13 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     for (int a = 0; a < 4; ++a) sm.dRt[4 * x + a] = 0.f;
   }
   // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m']
-  float *T = (float *)sm.stg[0];  // staging is free until the first layer
-  for (int x = threadIdx.x; x < M * 4; x += NW * 64) T[x] = Tsave[(size_t)i * M * 4 + x];
+  float *T = (float *)sm.stg[0];  // staging is free until the first layer: T [100][4], dE/dD [1600]
+  float *dDi = T + M * 4;
+  for (int x = threadIdx.x; x < M; x += NW * 64)
+    *(float4 *)(T + 4 * x) = *(const float4 *)(Tsave + ((size_t)i * M + x) * 4);
+  for (int x = threadIdx.x; x < ND / 4; x += NW * 64)
+    *(float4 *)(dDi + 4 * x) = *(const float4 *)(dD + (size_t)i * ND + 4 * x);
   __syncthreads();
-  const float *dDi = dD + (size_t)i * ND;
   for (int x = threadIdx.x; x < M * 4; x += NW * 64) {
     const int m = x >> 2, c = x & 3;
     float acc = 0.f;
@@ -879,6 +900,9 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
   stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
   stage_weights(w3s, KM, wp.W3, KM, 64, KM);
+  bf16_t *w2Ts = sm.Gb, *w2s = sm.Gb + 64 * LD2;  // Gb is free as well
+  stage_weights(w2Ts, LD2, wp.W2T, 32, 64, 32);
+  stage_weights(w2s, LD3, wp.W2, 64, 32, 64);
   __syncthreads();
   // embedding backward and the pair gradients of the wave's rows
 #pragma unroll
@@ -903,7 +927,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     wave_fence();
     f4 a2[4];
     zero(a2);
-    mm_a32<4>(a2, h1, 32, wp.W2T, 32, 32);
+    mm_a32<4>(a2, h1, 32, w2Ts, LD2, 32);
     float t2v[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -968,7 +992,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     // dh1 = dpre2 W2^T + (dh2[:, :25] + dh2[:, 25:]);  ds_emb = sum_c dh1 (1 - h1^2) w1s
     f4 d1[2];
     zero(d1);
-    mm<2>(d1, stg, LDT, wp.W2, 64, 64, 2);
+    mm<2>(d1, stg, LDT, w2s, LD3, 64, 2);
     float dse[4];
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
