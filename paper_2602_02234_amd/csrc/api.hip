@@ -288,6 +288,9 @@ void free_ws(Workspace &ws) {
   void *hs[] = {ws.flags_host, ws.grids_host, ws.off_host};
   for (void *p : hs)
     if (p) (void)hipHostFree(p);
+  if (ws.side) (void)hipStreamDestroy(ws.side);
+  if (ws.fork_ev) (void)hipEventDestroy(ws.fork_ev);
+  if (ws.join_ev) (void)hipEventDestroy(ws.join_ev);
   ws = Workspace{};
 }
 
@@ -315,6 +318,9 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.red, 64 * sizeof(double)));
     HIP_TRY(hipMalloc(&ws.gE, sizeof(double)));
     HIP_TRY(hipMalloc(&ws.bcnt, 2 * sizeof(int)));
+    HIP_TRY(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ws.fork_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ws.join_ev, hipEventDisableTiming));
   }
   if (nsys > ws.cap_sys) {
     const int cs = std::max(nsys, 8);

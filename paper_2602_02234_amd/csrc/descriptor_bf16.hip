@@ -25,6 +25,65 @@
 namespace dp {
 namespace {
 
+// Per-atom environment of the bfloat16 kernels (as Env, trimmed to what they read, so
+// that a 7-wave backward workgroup fits in LDS): s = sw/r, sw, r, rhat; the neighbour's
+// type as a byte.  Padded tokens (j >= n) have s = sw = 0, r = 1, rhat = 0.
+struct EnvB {
+  float s[NPMAX], sw[NPMAX], r[NPMAX];
+  float rh[NPMAX * 3];
+  unsigned char tj[NPMAX];
+};
+
+__device__ inline void build_envb(EnvB &e, const double *__restrict__ X, const int *__restrict__ types,
+                                  const int *__restrict__ nlist, int i, int n, int natoms, const Grid &g, float rc,
+                                  float rcs) {
+  for (int j = threadIdx.x; j < NPMAX; j += blockDim.x) {
+    float s = 0.f, sw = 0.f, r = 1.f, hx = 0.f, hy = 0.f, hz = 0.f;
+    int tj = 0;
+    if (j < n) {
+      int nj = nlist[(size_t)i * SEL + j];
+      if (nj < 0 || nj >= natoms) nj = i;  // never read outside the coordinate array
+      tj = clamp_type(types[nj]);
+      double d[3];
+      for (int a = 0; a < 3; ++a) {
+        double v = X[3 * nj + a] - X[3 * i + a];
+        if (g.periodic) v -= g.L[a] * rint(v * g.invL[a]);
+        d[a] = v;
+      }
+      const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+      r = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float u = (r - rcs) / (rc - rcs);
+      if (r < rcs) sw = 1.f;
+      else if (r < rc) sw = u * u * u * (-6.f * u * u + 15.f * u - 10.f) + 1.f;
+      s = sw / r;
+      hx = dx / r; hy = dy / r; hz = dz / r;
+    }
+    e.s[j] = s; e.sw[j] = sw; e.r[j] = r;
+    e.rh[3 * j] = hx; e.rh[3 * j + 1] = hy; e.rh[3 * j + 2] = hz;
+    e.tj[j] = (unsigned char)tj;
+  }
+}
+
+// g = dE_i/dDelta_ij of token j from the gradients reaching s (ds_emb, through Rt),
+// rhat (drh, through Rt and the gate) and sw (dswa, through the softmax weights); the
+// switch derivative is formed here from r.
+__device__ __forceinline__ float4 pair_gradient_b(const EnvB &e, int j, float ds_emb, const float *dRt,
+                                                  const float *drh, float dswa, float rc, float rcs) {
+  const float s = e.s[j], sw = e.sw[j], rr = e.r[j];
+  const float hx = e.rh[3 * j], hy = e.rh[3 * j + 1], hz = e.rh[3 * j + 2];
+  const float u = (rr - rcs) / (rc - rcs);
+  const float dsw = (rr >= rcs && rr < rc) ? -30.f * u * u * (1.f - u) * (1.f - u) / (rc - rcs) : 0.f;
+  const float ds = ds_emb + dRt[0] + dRt[1] * hx + dRt[2] * hy + dRt[3] * hz;
+  const float gx = drh[0] + s * dRt[1];
+  const float gy = drh[1] + s * dRt[2];
+  const float gz = drh[2] + s * dRt[3];
+  const float dswt = dswa + ds / rr;
+  const float dr = -ds * sw / (rr * rr) + dswt * dsw;
+  const float proj = gx * hx + gy * hy + gz * hz;
+  return make_float4((gx - proj * hx) / rr + dr * hx, (gy - proj * hy) / rr + dr * hy, (gz - proj * hz) / rr + dr * hz,
+                     0.f);
+}
+
 constexpr int KM = 112;   // padded feature width
 constexpr int LDK = 120;  // stride (elements) of [token][feature] bf16 arrays
 constexpr int LDT = 136;  // stride of [feature or row][token] bf16 arrays (tokens padded to 128)
@@ -191,7 +250,7 @@ __device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)
 // Embedding net for the wave's rows (block jb) -> G (fp32 tiles).  h1 is staged (fp32) in
 // scr1 (>= 512 floats), h2 in scr2 (>= 1024 floats); both wave-private.
 __device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2, const bf16_t *w3T, int ld3,
-                           const Env &e, int ti, int jb, float *scr1, float *scr2, f4 (&gv)[7]) {
+                           const EnvB &e, int ti, int jb, float *scr1, float *scr2, f4 (&gv)[7]) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
   // per-lane weights: first layer column c1 = lane % 32 (type part for every neighbour
   // type), second-layer bias columns 16 t + lane%16, third-layer bias columns
@@ -248,7 +307,7 @@ __device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2,
 // sv holds S on entry and E = exp(S - m)/Z on exit (0 for invalid tokens); the
 // attention weights A = sw_k E gate_jk are written (bf16) to stg [16][LDT].
 // Optionally records the row max and 1/Z (rmax, rz) for a later recomputation.
-__device__ __forceinline__ void softmax_rows(f4 (&sv)[8], const Env &e, int jb, int n, int nb, bf16_t *stg,
+__device__ __forceinline__ void softmax_rows(f4 (&sv)[8], const EnvB &e, int jb, int n, int nb, bf16_t *stg,
                                              float *rmax, float *rz) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
   float mx[4], z[4], iz[4], hj[4][3];
@@ -324,7 +383,7 @@ __device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
 // If Uall is given, U rows are written there (and read from there for S).
 template <bool GW>
 __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq, const bf16_t *wvoT, int ldv, int layer,
-                           const Env &e, const bf16_t *Gb,
+                           const EnvB &e, const bf16_t *Gb,
                            const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
                            f4 (&gv)[7], f4 (&sv)[8], f4 (&xh)[7], float (&isig)[4], float *rmax, float *rz) {
   const int l = lane_id(), q = l >> 4, cl = l & 15;
@@ -430,7 +489,7 @@ struct __align__(16) SmemF16 {
   bf16_t GbT[KM * LDT];
   bf16_t stg[NWF][16 * LDT];
   bf16_t W[2][KM * LDW];  // the current stage's weights: W2^T and W3^T, then Wqk^T and Wvo^T of a layer
-  Env e;
+  EnvB e;
 };
 
 // Workgroup copy of a [rows][cols] bf16 matrix (cols a multiple of 8, row stride gld in
@@ -457,7 +516,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
-  build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
+  build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   bf16_t *w2s = sm.W[0], *w3s = sm.W[0] + 64 * LD2;
   stage_weights(w2s, LD2, wp.W2T, 32, 64, 32);
   stage_weights(w3s, LD3, wp.W3T, 64, KM, 64);
@@ -493,8 +552,10 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int j = jb * 16 + 4 * q + ii;
+      const float sj = (j < n) ? sm.e.s[j] : 0.f;
+      rt[ii][0] = sj;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) rt[ii][c] = (j < n) ? sm.e.Rt[4 * j + c] : 0.f;
+      for (int c = 1; c < 4; ++c) rt[ii][c] = sj * sm.e.rh[3 * j + c - 1];
     }
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
@@ -534,7 +595,7 @@ template <int NW> struct __align__(16) SmemB16 {
   bf16_t Uall[NPMAX * LDK];
   bf16_t dHall[NPMAX * LDK];
   bf16_t stg[NW][16 * LDT];
-  Env e;
+  EnvB e;
   float rmax[NPMAX], rz[NPMAX], rrho[NPMAX];
   float drh[NPMAX * 3];
   float dswa[NPMAX];
@@ -861,7 +922,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
-  build_env(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
+  build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   for (int x = threadIdx.x; x < NPMAX; x += NW * 64) {
     sm.dswa[x] = 0.f;
     for (int a = 0; a < 3; ++a) sm.drh[3 * x + a] = 0.f;
@@ -901,6 +962,9 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
   stage_weights(w3s, KM, wp.W3, KM, 64, KM);
   bf16_t *w2Ts = sm.Gb, *w2s = sm.Gb + 64 * LD2;  // Gb is free as well
+  static_assert(NW <= 7 && 4 * 16 * 104 * 4 <= KM * LDT * 2 &&
+                    (64 * LD2 + 32 * LD3) * 2 + (NW > 4 ? NW - 4 : 0) * 16 * 104 * 4 <= NPMAX * LDK * 2,
+                "per-wave fp32 scratch of the embedding backward must fit in GbT and the rest of Gb");
   stage_weights(w2Ts, LD2, wp.W2T, 32, 64, 32);
   stage_weights(w2s, LD3, wp.W2, 64, 32, 64);
   __syncthreads();
@@ -911,7 +975,8 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     if (jb >= nb) continue;
     float *h1 = (float *)(sm.dHall + jb * 16 * LDK);  // [16][32]
     float *h2 = (float *)sm.stg[wv];                  // [16][64]
-    float *sc = (float *)sm.GbT + wv * 16 * 104;      // [16][104] fp32: dG0 rows, then dh2 (GbT is free now)
+    // [16][104] fp32: dG0 rows, then dh2; waves 0-3 in GbT, waves 4-6 in Gb after the W2 copies
+    float *sc = wv < 4 ? (float *)sm.GbT + wv * 16 * 104 : (float *)(w2s + 32 * LD3) + (wv - 4) * 16 * 104;
     // recompute h1, t2, h2 (fp32) for these rows, as the forward kernel made them
     {
       const int c1 = l & 31;
@@ -1015,7 +1080,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
       const int j = jb * 16 + 4 * q + ii;
       if (cl == ii && j < SEL) {
         float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < n) out = pair_gradient(sm.e, j, dse[ii], sm.dRt + 4 * j, sm.drh + 3 * j, sm.dswa[j]);
+        if (j < n) out = pair_gradient_b(sm.e, j, dse[ii], sm.dRt + 4 * j, sm.drh + 3 * j, sm.dswa[j], rc, rcs);
         gout[(size_t)i * SEL + j] = out;
       }
     }
@@ -1026,7 +1091,7 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 
 // Stable partition of the atoms by row-block count: idx[0..c0) the atoms with at most
 // SPLIT_NB blocks of 16 neighbours, idx[cap..cap+c1) the others; count[0] = c0, count[1] = c1.
-constexpr int SPLIT_NB = 6;
+constexpr int SPLIT_NB = 7;
 __global__ void __launch_bounds__(1024) k_partition(const int *__restrict__ nnei, int n, int cap, int *__restrict__ idx,
                                                     int *__restrict__ count) {
   __shared__ int sc[1024];
@@ -1082,12 +1147,17 @@ void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, c
                                const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, n, (int)ws.cap, ws.bidx, ws.bcnt);
-  // atoms with up to 6 row blocks: 6 waves, one block each; the rest: 4 waves, two blocks each
-  hipLaunchKernelGGL((k_desc_bwd_b16<6, 1>), dim3(n), dim3(6 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
-                     ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx, ws.bcnt);
-  hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(n), dim3(4 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
-                     ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx + ws.cap,
+  // atoms with up to 7 row blocks: 7 waves, one block each (on st); the rest: 4 waves,
+  // two blocks each, on the side stream, so that a few dense atoms overlap the bulk
+  (void)hipEventRecord(ws.fork_ev, st);
+  (void)hipStreamWaitEvent(ws.side, ws.fork_ev, 0);
+  hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(n), dim3(4 * 64), 0, ws.side, w, wp, coords, types, n, ws.nlist,
+                     ws.nnei, ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx + ws.cap,
                      ws.bcnt + 1);
+  hipLaunchKernelGGL((k_desc_bwd_b16<7, 1>), dim3(n), dim3(7 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
+                     ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx, ws.bcnt);
+  (void)hipEventRecord(ws.join_ev, ws.side);
+  (void)hipStreamWaitEvent(st, ws.join_ev, 0);
 }
 
 }  // namespace dp

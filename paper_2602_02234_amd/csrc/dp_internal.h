@@ -118,6 +118,8 @@ struct Workspace {
   unsigned *flags = nullptr;  // [4] status words: flags, overflow count, rev misses, spare
   unsigned *flags_host = nullptr;  // pinned mirror
   double *gE = nullptr;       // [1] scale of the backward pass
+  hipStream_t side = nullptr;  // second stream of the bf16 backward (its instances run side by side)
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 // How the neighbour lists of a step are made.
