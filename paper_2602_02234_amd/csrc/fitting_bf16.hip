@@ -3,8 +3,8 @@
 // carry the path's largest rounding sensitivity; each one runs on bf16 MFMA with
 // both operands split into two bf16 terms, x = x_hi + x_lo, and three products
 // x_hi w_hi + x_hi w_lo + x_lo w_hi accumulated in fp32 (the dropped lo*lo term is
-// 2^-16 relative).  16 atoms per workgroup; the hidden width 240 is padded to 256
-// along k.  dE/dD overwrites D in place.
+// 2^-16 relative).  16 atoms per workgroup, two workgroups per CU; the hidden width
+// 240 is padded to 256 along k.  dE/dD overwrites D in place.
 #include "dp_internal.h"
 
 namespace dp {
@@ -13,12 +13,12 @@ namespace {
 constexpr int KH = 256;       // padded hidden width along k
 constexpr int LDA = KH + 8;   // LDS row stride (floats) of the hidden activations
 constexpr int NWT = 8;        // waves
+constexpr int NT = FH / 16;   // 15 hidden column tiles
 
 __device__ __forceinline__ bf8 ld8g(const bf16_t *p) { return *(const bf8 *)p; }
 
 // Splits 8 fp32 values into bf16 hi and lo parts.
-__device__ __forceinline__ void split8(const float *p, bf8 &hi, bf8 &lo) {
-  const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+__device__ __forceinline__ void split8(const float4 a, const float4 b, bf8 &hi, bf8 &lo) {
   const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -34,45 +34,76 @@ __device__ __forceinline__ f4 mma3(const bf8 &xh, const bf8 &xl, const bf8 &yh, 
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh, acc, 0, 0, 0);
 }
 
-// acc = A(16 x K) . B_t^T for the column tiles t = wave, wave + NWT, ... (< ntiles);
-// A fp32 rows at a (stride lda, K multiple of 32), B split bf16 [col][k] at bh/bl (stride ldb).
-template <int MAXT>
-__device__ __forceinline__ void mm_split(f4 (&acc)[MAXT], const float *a, int lda, const bf16_t *bh,
-                                         const bf16_t *bl, int ldb, int K, int ntiles) {
+// acc = A(16 x K) . B_t^T for the column tiles t = wave + NWT u (< NT), u < 2; A fp32
+// rows at a (stride lda, K a multiple of 32), B split bf16 [col][k] at bh/bl (stride
+// ldb).  The operands of step k + 32 are loaded before the products of step k.
+__device__ __forceinline__ void mm_split2(f4 (&acc)[2], const float *a, int lda, const bf16_t *bh, const bf16_t *bl,
+                                          int ldb, int K) {
+  const int l = lane_id(), r = l & 15, q = l >> 4, wv = wave_id();
+  const bool t1 = wv + NWT < NT;
+  acc[0] = acc[1] = f4{0.f, 0.f, 0.f, 0.f};
+  const float *ar = a + r * lda + 8 * q;
+  const size_t o0 = (size_t)(16 * wv + r) * ldb + 8 * q, o1 = (size_t)(16 * min(wv + NWT, NT - 1) + r) * ldb + 8 * q;
+  float4 pa0 = *(const float4 *)ar, pa1 = *(const float4 *)(ar + 4);
+  bf8 ph0 = ld8g(bh + o0), pl0 = ld8g(bl + o0), ph1 = ld8g(bh + o1), pl1 = ld8g(bl + o1);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const float4 a0 = pa0, a1 = pa1;
+    const bf8 h0 = ph0, l0 = pl0, h1 = ph1, l1 = pl1;
+    if (k0 + 32 < K) {
+      const int k = k0 + 32;
+      pa0 = *(const float4 *)(ar + k);
+      pa1 = *(const float4 *)(ar + k + 4);
+      ph0 = ld8g(bh + o0 + k); pl0 = ld8g(bl + o0 + k);
+      ph1 = ld8g(bh + o1 + k); pl1 = ld8g(bl + o1 + k);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    bf8 xh, xl;
+    split8(a0, a1, xh, xl);
+    acc[0] = mma3(xh, xl, h0, l0, acc[0]);
+    if (t1) acc[1] = mma3(xh, xl, h1, l1, acc[1]);
+  }
+}
+
+// The dE/dD product for the column tiles t = wave + NWT u, U0 <= u < U1 (< ND / 16),
+// A from LDS (K = 256).
+template <int U0, int U1>
+__device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, int lda, const bf16_t *bh,
+                                            const bf16_t *bl, int ldb) {
   const int l = lane_id(), r = l & 15, q = l >> 4, wv = wave_id();
 #pragma unroll
-  for (int u = 0; u < MAXT; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int u = 0; u < U1 - U0; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < KH; k0 += 32) {
     bf8 xh, xl;
-    split8(a + r * lda + k0 + 8 * q, xh, xl);
+    const float *ar = a + r * lda + k0 + 8 * q;
+    split8(*(const float4 *)ar, *(const float4 *)(ar + 4), xh, xl);
 #pragma unroll
-    for (int u = 0; u < MAXT; ++u) {
+    for (int u = U0; u < U1; ++u) {
       const int t = wv + NWT * u;
-      if (t < ntiles) {
+      if (t < ND / 16) {
         const size_t o = (size_t)(16 * t + r) * ldb + k0 + 8 * q;
-        acc[u] = mma3(xh, xl, ld8g(bh + o), ld8g(bl + o), acc[u]);
+        acc[u - U0] = mma3(xh, xl, ld8g(bh + o), ld8g(bl + o), acc[u - U0]);
       }
     }
   }
 }
 
-__global__ void __launch_bounds__(NWT * 64)
+__global__ void __launch_bounds__(NWT * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n, float *__restrict__ D,
           double *__restrict__ Ei, int backward) {
-  __shared__ __align__(16) float y1[16 * LDA], t2[16 * LDA], y2[16 * LDA], t3[16 * LDA], bA[16 * LDA],
-      bB[16 * LDA];
+  // y1, t2: the first two layers' outputs; y2: the third layer's input, later dE/dy2;
+  // X: dE/dpre3, dE/dpre2, dE/dpre1 in turn.  Columns 240..255 stay zero.
+  __shared__ __align__(16) float y1[16 * LDA], t2[16 * LDA], y2[16 * LDA], X[16 * LDA];
+  __shared__ double ep[16][16];  // per-row energy partials, one per column tile
   const int a0 = blockIdx.x * 16;
   const int l = lane_id(), q = l >> 4, cl = l & 15, wv = wave_id();
-  constexpr int NT = FH / 16;  // 15 hidden column tiles
   for (int x = threadIdx.x; x < 16 * (KH - FH); x += NWT * 64) {
     const int r = x / (KH - FH), c = FH + x % (KH - FH);
-    y1[r * LDA + c] = t2[r * LDA + c] = y2[r * LDA + c] = t3[r * LDA + c] = bA[r * LDA + c] = bB[r * LDA + c] = 0.f;
+    y1[r * LDA + c] = t2[r * LDA + c] = y2[r * LDA + c] = X[r * LDA + c] = 0.f;
   }
-  __syncthreads();
   f4 acc[2];
   // y1 = tanh(D F1 + c1); the D allocation has 16 spare rows, so rows >= n of the
   // last batch are read in bounds (their results are discarded)
-  mm_split<2>(acc, D + (size_t)a0 * ND, ND, wp.F1T[0], wp.F1T[1], ND, ND, NT);
+  mm_split2(acc, D + (size_t)a0 * ND, ND, wp.F1T[0], wp.F1T[1], ND, ND);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -80,7 +111,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
       for (int ii = 0; ii < 4; ++ii) y1[(4 * q + ii) * LDA + 16 * t + cl] = tanhf(acc[u][ii] + w.c1[16 * t + cl]);
   }
   __syncthreads();
-  mm_split<2>(acc, y1, LDA, wp.F2T[0], wp.F2T[1], KH, KH, NT);
+  mm_split2(acc, y1, LDA, wp.F2T[0], wp.F2T[1], KH, KH);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -93,7 +124,9 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
       }
   }
   __syncthreads();
-  mm_split<2>(acc, y2, LDA, wp.F3T[0], wp.F3T[1], KH, KH, NT);
+  // y3 = tanh(y2 F3 + c3) + y2 stays in registers: E_i = y3 . F4 + c4 + ebias(t_i) as
+  // per-tile partials, and dE/dpre3 = F4 (1 - t3^2) goes to X
+  mm_split2(acc, y2, LDA, wp.F3T[0], wp.F3T[1], KH, KH);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -101,8 +134,13 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
       for (int ii = 0; ii < 4; ++ii) {
         const int r = 4 * q + ii, c = 16 * t + cl;
         const float tt = tanhf(acc[u][ii] + w.c3[c]);
-        t3[r * LDA + c] = tt;
-        bA[r * LDA + c] = tt + y2[r * LDA + c];
+        X[r * LDA + c] = w.F4[c] * (1.f - tt * tt);
+        double p = (double)(tt + y2[r * LDA + c]) * (double)w.F4[c];
+        p += __shfl_xor(p, 1);
+        p += __shfl_xor(p, 2);
+        p += __shfl_xor(p, 4);
+        p += __shfl_xor(p, 8);
+        if (cl == 0) ep[r][t] = p;
       }
   }
   __syncthreads();
@@ -111,19 +149,13 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
     int ty = types[a0 + r];
     ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
     double e = 0.0;
-    for (int o = 0; o < FH; ++o) e += (double)bA[r * LDA + o] * (double)w.F4[o];
+    for (int t = 0; t < NT; ++t) e += ep[r][t];
     Ei[a0 + r] = e + (double)w.c4 + (double)w.ebias[ty];
   }
   if (!backward) return;
-  __syncthreads();
-  for (int x = threadIdx.x; x < 16 * FH; x += NWT * 64) {
-    const int r = x / FH, o = x % FH;
-    const float tt = t3[r * LDA + o];
-    bB[r * LDA + o] = w.F4[o] * (1.f - tt * tt);  // dpre3
-  }
-  __syncthreads();
-  // dy2 = dpre3 F3^T + F4;  dpre2 = dy2 (1 - t2^2)
-  mm_split<2>(acc, bB, LDA, wp.F3[0], wp.F3[1], KH, KH, NT);
+  // dy2 = dpre3 F3^T + F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
+  mm_split2(acc, X, LDA, wp.F3[0], wp.F3[1], KH, KH);
+  __syncthreads();  // every wave has read X
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -132,36 +164,51 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
         const int r = 4 * q + ii, c = 16 * t + cl;
         const float dy2 = acc[u][ii] + w.F4[c];
         const float tt = t2[r * LDA + c];
-        bA[r * LDA + c] = dy2;
-        t3[r * LDA + c] = dy2 * (1.f - tt * tt);
+        y2[r * LDA + c] = dy2;
+        X[r * LDA + c] = dy2 * (1.f - tt * tt);
       }
   }
   __syncthreads();
   // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
-  mm_split<2>(acc, t3, LDA, wp.F2[0], wp.F2[1], KH, KH, NT);
+  mm_split2(acc, X, LDA, wp.F2[0], wp.F2[1], KH, KH);
+  __syncthreads();
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
     if (t < NT)
       for (int ii = 0; ii < 4; ++ii) {
         const int r = 4 * q + ii, c = 16 * t + cl;
-        const float dy1 = acc[u][ii] + bA[r * LDA + c];
+        const float dy1 = acc[u][ii] + y2[r * LDA + c];
         const float yy = y1[r * LDA + c];
-        bB[r * LDA + c] = dy1 * (1.f - yy * yy);
+        X[r * LDA + c] = dy1 * (1.f - yy * yy);
       }
   }
   __syncthreads();
-  // dE/dD = dpre1 F1^T  (100 column tiles)
-  f4 dacc[13];
-  mm_split<13>(dacc, bB, LDA, wp.F1[0], wp.F1[1], KH, KH, ND / 16);
+  // dE/dD = dpre1 F1^T  (100 column tiles, in two passes over k)
+  {
+    f4 dacc[7];
+    mm_split_dd<0, 7>(dacc, X, LDA, wp.F1[0], wp.F1[1], KH);
 #pragma unroll
-  for (int u = 0; u < 13; ++u) {
-    const int t = wv + NWT * u;
-    if (t < ND / 16)
+    for (int u = 0; u < 7; ++u) {
+      const int t = wv + NWT * u;
       for (int ii = 0; ii < 4; ++ii) {
         const int r = 4 * q + ii;
         if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
       }
+    }
+  }
+  {
+    f4 dacc[6];
+    mm_split_dd<7, 13>(dacc, X, LDA, wp.F1[0], wp.F1[1], KH);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int t = wv + NWT * (u + 7);
+      if (t < ND / 16)
+        for (int ii = 0; ii < 4; ++ii) {
+          const int r = 4 * q + ii;
+          if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
+        }
+    }
   }
 }
 
