@@ -1,488 +1,11 @@
-// Per-atom descriptor kernels of the bfloat16 path (gfx950 MFMA, fp32 accumulation).
-//
-// Same model as descriptor.hip (environment, type-embedded embedding net, two
-// switch-weighted gated self-attention layers with a residual LayerNorm update,
-// descriptor T = G^T Rt / sel, D = T T_<16^T), organised for throughput:
-//
-//  * every wave owns whole 16-token row blocks and carries them through a layer
-//    (U = G Wqk, S = U G^T, softmax, H = A G, Y = H Wvo, LayerNorm) in registers,
-//    so a layer needs two workgroup barriers instead of one per product;
-//  * the representation G lives in LDS twice as bf16, token-major (Gb) and
-//    feature-major (GbT), so that every MFMA fragment -- whichever index is the
-//    reduction index -- is one 16-byte load; the fp32 master copy of the wave's
-//    own rows stays in registers (residual and LayerNorm in fp32);
-//  * weights come pre-padded and k-contiguous from global memory (L2-resident);
-//  * feature width 100 is padded to 112 and contracted as 3 x 32 + 16 along k.
-// Backward: the forward is recomputed in the kernel (nothing is stored between
-// the two kernels but T); the terms of dG that couple a token to every query row
-// (A^T dH and dS^T U) are gathered in a second pass in which wave w recomputes
-// the score and score-gradient tiles of its own token block against every query
-// block from U and dH kept in LDS.  That pass uses 16x16x16 products (see mma16), whose
-// A-operand lane layout equals the accumulator layout, so the recomputed tiles
-// feed the transposed product without any data movement.
-#include "dp_env.h"
+// Forward descriptor kernel of the bfloat16 path: one workgroup (8 waves) per atom.
+// Environment, type-embedded embedding net, two attention layers (each layer's
+// weights staged in LDS), T = G^T Rt / sel and D = T T_<16^T; the input rows of each
+// attention layer are saved (fp32, rows < n) for the backward kernel.
+#include "descriptor_bf16.h"
 
 namespace dp {
 namespace {
-
-// Per-atom environment of the bfloat16 kernels (as Env, trimmed to what they read, so
-// that a 7-wave backward workgroup fits in LDS): s = sw/r, sw, r, rhat; the neighbour's
-// type as a byte.  Padded tokens (j >= n) have s = sw = 0, r = 1, rhat = 0.
-struct EnvB {
-  float s[NPMAX], sw[NPMAX], r[NPMAX];
-  float rh[NPMAX * 3];
-  unsigned char tj[NPMAX];
-};
-
-__device__ inline void build_envb(EnvB &e, const double *__restrict__ X, const int *__restrict__ types,
-                                  const int *__restrict__ nlist, int i, int n, int natoms, const Grid &g, float rc,
-                                  float rcs) {
-  for (int j = threadIdx.x; j < NPMAX; j += blockDim.x) {
-    float s = 0.f, sw = 0.f, r = 1.f, hx = 0.f, hy = 0.f, hz = 0.f;
-    int tj = 0;
-    if (j < n) {
-      int nj = nlist[(size_t)i * SEL + j];
-      if (nj < 0 || nj >= natoms) nj = i;  // never read outside the coordinate array
-      tj = clamp_type(types[nj]);
-      double d[3];
-      for (int a = 0; a < 3; ++a) {
-        double v = X[3 * nj + a] - X[3 * i + a];
-        if (g.periodic) v -= g.L[a] * rint(v * g.invL[a]);
-        d[a] = v;
-      }
-      const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
-      r = sqrtf(dx * dx + dy * dy + dz * dz);
-      const float u = (r - rcs) / (rc - rcs);
-      if (r < rcs) sw = 1.f;
-      else if (r < rc) sw = u * u * u * (-6.f * u * u + 15.f * u - 10.f) + 1.f;
-      s = sw / r;
-      hx = dx / r; hy = dy / r; hz = dz / r;
-    }
-    e.s[j] = s; e.sw[j] = sw; e.r[j] = r;
-    e.rh[3 * j] = hx; e.rh[3 * j + 1] = hy; e.rh[3 * j + 2] = hz;
-    e.tj[j] = (unsigned char)tj;
-  }
-}
-
-// g = dE_i/dDelta_ij of token j from the gradients reaching s (ds_emb, through Rt),
-// rhat (drh, through Rt and the gate) and sw (dswa, through the softmax weights); the
-// switch derivative is formed here from r.
-__device__ __forceinline__ float4 pair_gradient_b(const EnvB &e, int j, float ds_emb, const float *dRt,
-                                                  const float *drh, float dswa, float rc, float rcs) {
-  const float s = e.s[j], sw = e.sw[j], rr = e.r[j];
-  const float hx = e.rh[3 * j], hy = e.rh[3 * j + 1], hz = e.rh[3 * j + 2];
-  const float u = (rr - rcs) / (rc - rcs);
-  const float dsw = (rr >= rcs && rr < rc) ? -30.f * u * u * (1.f - u) * (1.f - u) / (rc - rcs) : 0.f;
-  const float ds = ds_emb + dRt[0] + dRt[1] * hx + dRt[2] * hy + dRt[3] * hz;
-  const float gx = drh[0] + s * dRt[1];
-  const float gy = drh[1] + s * dRt[2];
-  const float gz = drh[2] + s * dRt[3];
-  const float dswt = dswa + ds / rr;
-  const float dr = -ds * sw / (rr * rr) + dswt * dsw;
-  const float proj = gx * hx + gy * hy + gz * hz;
-  return make_float4((gx - proj * hx) / rr + dr * hx, (gy - proj * hy) / rr + dr * hy, (gz - proj * hz) / rr + dr * hz,
-                     0.f);
-}
-
-constexpr int KM = 112;   // padded feature width
-constexpr int LDK = 120;  // stride (elements) of [token][feature] bf16 arrays
-constexpr int LDT = 136;  // stride of [feature or row][token] bf16 arrays (tokens padded to 128)
-constexpr int NWF = 8;    // waves per workgroup, forward
-typedef short s4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ bf8 ld8(const bf16_t *p) { return *(const bf8 *)p; }
-__device__ __forceinline__ s4 ld4(const bf16_t *p) { return *(const s4 *)p; }
-__device__ __forceinline__ short bfbits(float x) {
-  const bf16_t b = (bf16_t)x;
-  return *(const short *)&b;
-}
-// Exponential and tanh from the hardware base-2 exponential (v_exp_f32) and reciprocal:
-// relative error a few 1e-7, far below the bfloat16 rounding of the products they feed.
-__device__ __forceinline__ float fexp(float x) { return __expf(x); }
-__device__ __forceinline__ float ftanh(float x) {
-  const float t = __expf(-2.f * fabsf(x));
-  return copysignf((1.f - t) * __builtin_amdgcn_rcpf(1.f + t), x);
-}
-
-// Orders this wave's LDS accesses across a point (the wave reuses its staging buffer):
-// the wave's outstanding memory operations are drained and no instruction is moved
-// across the point.
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_sched_barrier(0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_sched_barrier(0);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// A 16x16x16 product (4 k per lane) through the 16x16x32 instruction.  Lane group q
-// holds k = 4q + i (i < 4) of the short form; both operands place it at k' = 8q + i of
-// the long form with k' = 8q + 4..7 zero, so the sum over k' equals the sum over k.
-// The 16x16x16 bf16 instruction itself is not used: in this kernel its results varied
-// from run to run (up to 1e-1 in pair gradients, depending on the surrounding
-// instruction timing), while this form reproduces the CPU emulation of the kernel and is
-// bitwise stable.
-__device__ __forceinline__ f4 mma16(s4 a, s4 b, f4 c) {
-  bf8 x, y;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const short av = a[i], bv = b[i];
-    x[i] = *(const __bf16 *)&av;
-    y[i] = *(const __bf16 *)&bv;
-    x[i + 4] = (__bf16)0.f;
-    y[i + 4] = (__bf16)0.f;
-  }
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
-}
-
-// acc[t] += A(16 x K) . B_t(16 x K)^T for t < nt; A rows at a (stride lda); B_t rows
-// at b + 16 t ldb (stride ldb); K a multiple of 16; operands bf16, k contiguous.
-template <int NT>
-__device__ __forceinline__ void mm(f4 (&acc)[NT], const bf16_t *a, int lda, const bf16_t *b, int ldb, int K, int nt) {
-  const int l = lane_id(), r = l & 15, q = l >> 4;
-  int k0 = 0;
-  for (; k0 + 32 <= K; k0 += 32) {
-    const bf8 x = ld8(a + r * lda + k0 + 8 * q);
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      if (t < nt) {
-        const bf8 y = ld8(b + (16 * t + r) * ldb + k0 + 8 * q);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[t], 0, 0, 0);
-      }
-  }
-  if (k0 < K) {
-    const s4 x = ld4(a + r * lda + k0 + 4 * q);
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      if (t < nt) {
-        const s4 y = ld4(b + (16 * t + r) * ldb + k0 + 4 * q);
-        acc[t] = mma16(x, y, acc[t]);
-      }
-  }
-}
-
-// acc[t] += A(16 x 112) . B_t(16 x 112)^T for t < NT with B in global memory (weights, L2
-// resident).  The fragments of the next k step are loaded before the products of the
-// current one are issued, so a product waits for one L2 round trip, not for one per tile.
-template <int NT>
-__device__ __forceinline__ void mm_g(f4 (&acc)[NT], const bf16_t *a, int lda, const bf16_t *__restrict__ b,
-                                     int ldb) {
-  const int l = lane_id(), r = l & 15, q = l >> 4;
-  bf8 y[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) y[t] = *(const bf8 *)(b + (16 * t + r) * ldb + 8 * q);
-#pragma unroll
-  for (int st = 0; st < 3; ++st) {
-    const bf8 x = ld8(a + r * lda + 32 * st + 8 * q);
-    bf8 yn[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (st < 2) {
-        yn[t] = *(const bf8 *)(b + (16 * t + r) * ldb + 32 * (st + 1) + 8 * q);
-      } else {  // the k = 96..111 tail, four per lane, placed as in mma16
-        const s4 v = *(const s4 *)(b + (16 * t + r) * ldb + 96 + 4 * q);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const short e = v[i];
-          yn[t][i] = *(const __bf16 *)&e;
-          yn[t][i + 4] = (__bf16)0.f;
-        }
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y[t], acc[t], 0, 0, 0);
-#pragma unroll
-    for (int t = 0; t < NT; ++t) y[t] = yn[t];
-  }
-  const s4 xt = ld4(a + r * lda + 96 + 4 * q);
-  bf8 x;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const short e = xt[i];
-    x[i] = *(const __bf16 *)&e;
-    x[i + 4] = (__bf16)0.f;
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y[t], acc[t], 0, 0, 0);
-}
-
-// Same with the A operand held as fp32 in LDS (rounded to bf16 when loaded); K multiple of 32.
-template <int NT>
-__device__ __forceinline__ void mm_a32(f4 (&acc)[NT], const float *a, int lda, const bf16_t *b, int ldb, int K) {
-  const int l = lane_id(), r = l & 15, q = l >> 4;
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    bf8 x;
-    const float *ap = a + r * lda + k0 + 8 * q;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = (__bf16)ap[e];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const bf8 y = ld8(b + (16 * t + r) * ldb + k0 + 8 * q);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[t], 0, 0, 0);
-    }
-  }
-}
-
-template <int NT> __device__ __forceinline__ void zero(f4 (&a)[NT]) {
-#pragma unroll
-  for (int t = 0; t < NT; ++t) a[t] = f4{0.f, 0.f, 0.f, 0.f};
-}
-
-// Writes the wave's 16 rows (block jb; fp32 tiles gv, columns 16 t + lane%16) into
-// Gb (token-major) and GbT (feature-major) as bf16; columns >= M are written as zero.
-__device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)[7], int jb) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-#pragma unroll
-  for (int t = 0; t < 7; ++t) {
-    const int m = 16 * t + cl;
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      const bf16_t v = (bf16_t)(m < M ? gv[t][ii] : 0.f);
-      Gb[j * LDK + m] = v;
-      GbT[m * LDT + j] = v;
-    }
-  }
-}
-
-// Embedding net for the wave's rows (block jb) -> G (fp32 tiles).  h1 is staged (fp32) in
-// scr1 (>= 512 floats), h2 in scr2 (>= 1024 floats); both wave-private.
-__device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2, const bf16_t *w3T, int ld3,
-                           const EnvB &e, int ti, int jb, float *scr1, float *scr2, f4 (&gv)[7]) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-  // per-lane weights: first layer column c1 = lane % 32 (type part for every neighbour
-  // type), second-layer bias columns 16 t + lane%16, third-layer bias columns
-  const int c1 = l & 31;
-  const bool c1v = c1 < E1;
-  const float w1c = c1v ? w.w1s[c1] : 0.f;
-  float bt[NTYPES];
-#pragma unroll
-  for (int u = 0; u < NTYPES; ++u) bt[u] = c1v ? w.Bt[(ti * NTYPES + u) * E1 + c1] : 0.f;
-  float b2v[4], b3v[7];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) b2v[t] = (16 * t + cl < E2) ? w.b2[16 * t + cl] : 0.f;
-#pragma unroll
-  for (int t = 0; t < 7; ++t) b3v[t] = (16 * t + cl < M) ? w.b3[16 * t + cl] : 0.f;
-#pragma unroll
-  for (int x = 0; x < 8; ++x) {
-    const int r = (l >> 5) + 2 * x, j = jb * 16 + r;
-    const int tj = e.tj[j];
-    float b = bt[0];
-#pragma unroll
-    for (int u = 1; u < NTYPES; ++u) b = (tj == u) ? bt[u] : b;
-    scr1[r * 32 + c1] = c1v ? ftanh(e.s[j] * w1c + b) : 0.f;
-  }
-  wave_fence();
-  f4 a2[4];
-  zero(a2);
-  mm_a32<4>(a2, scr1, 32, w2T, ld2, 32);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int c = 16 * t + cl;
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int r = 4 * q + ii;
-      scr2[r * 64 + c] = c < E2 ? ftanh(a2[t][ii] + b2v[t]) + scr1[r * 32 + (c % E1)] : 0.f;
-    }
-  }
-  wave_fence();
-  f4 a3[7];
-  zero(a3);
-  mm_a32<7>(a3, scr2, 64, w3T, ld3, 64);
-#pragma unroll
-  for (int t = 0; t < 7; ++t) {
-    const int m = 16 * t + cl;
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int r = 4 * q + ii;
-      gv[t][ii] = m < M ? ftanh(a3[t][ii] + b3v[t]) + scr2[r * 64 + (m % E2)] : 0.f;
-    }
-  }
-  wave_fence();
-}
-
-// Scores of the wave's rows (block jb) against every token -> row softmax weights.
-// sv holds S on entry and E = exp(S - m)/Z on exit (0 for invalid tokens); the
-// attention weights A = sw_k E gate_jk are written (bf16) to stg [16][LDT].
-// Optionally records the row max and 1/Z (rmax, rz) for a later recomputation.
-__device__ __forceinline__ void softmax_rows(f4 (&sv)[8], const EnvB &e, int jb, int n, int nb, bf16_t *stg,
-                                             float *rmax, float *rz) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-  float mx[4], z[4], iz[4], hj[4][3];
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const int j = jb * 16 + 4 * q + ii;
-    hj[ii][0] = e.rh[3 * j];
-    hj[ii][1] = e.rh[3 * j + 1];
-    hj[ii][2] = e.rh[3 * j + 2];
-    mx[ii] = -INFINITY;
-    z[ii] = 0.f;
-  }
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct)
-    if (ct < nb && 16 * ct + cl < n)
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) mx[ii] = fmaxf(mx[ii], sv[ct][ii]);
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    mx[ii] = max16(mx[ii]);
-    if (mx[ii] == -INFINITY) mx[ii] = 0.f;
-  }
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct) {
-    const int k = 16 * ct + cl;
-    const bool kv = ct < nb && k < n;
-    const float swk = ct < nb ? e.sw[k] : 0.f;
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const float ex = kv ? fexp(sv[ct][ii] - mx[ii]) : 0.f;
-      sv[ct][ii] = ex;
-      z[ii] += swk * ex;
-    }
-  }
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    z[ii] = sum16(z[ii]);
-    iz[ii] = z[ii] > 0.f ? 1.f / z[ii] : 0.f;
-  }
-#pragma unroll
-  for (int ct = 0; ct < 8; ++ct)
-    if (ct < nb) {
-      const int k = 16 * ct + cl;
-      const float swk = e.sw[k], hx = e.rh[3 * k], hy = e.rh[3 * k + 1], hz = e.rh[3 * k + 2];
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const float E = sv[ct][ii] * iz[ii];
-        sv[ct][ii] = E;
-        const float gt = hj[ii][0] * hx + hj[ii][1] * hy + hj[ii][2] * hz;
-        stg[(4 * q + ii) * LDT + k] = (bf16_t)(swk * E * gt);
-      }
-    }
-  if (rmax && cl == 0)
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      rmax[j] = mx[ii];
-      rz[j] = iz[ii];
-    }
-}
-
-// Stages fp32 tiles (columns 16 t + lane%16, t < 7) into stg [16][LDT] as bf16.
-__device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-#pragma unroll
-  for (int t = 0; t < 7; ++t)
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) stg[(4 * q + ii) * LDT + 16 * t + cl] = (bf16_t)v[t][ii];
-}
-
-// One attention layer forward for the wave's rows: gv (G_in, fp32) -> gv (G_out).
-// Also returns xh (normalised residual) and isig (1/sigma per accumulator row).
-// If Uall is given, U rows are written there (and read from there for S).
-template <bool GW>
-__device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq, const bf16_t *wvoT, int ldv, int layer,
-                           const EnvB &e, const bf16_t *Gb,
-                           const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
-                           f4 (&gv)[7], f4 (&sv)[8], f4 (&xh)[7], float (&isig)[4], float *rmax, float *rz) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-  f4 acc[7];
-  zero(acc);
-  if (GW)
-    mm_g<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq);  // U = G Wqk
-  else
-    mm<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq, KM, 7);
-  const bf16_t *ua;
-  int lda;
-  if (Uall) {
-#pragma unroll
-    for (int t = 0; t < 7; ++t)
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) Uall[(jb * 16 + 4 * q + ii) * LDK + 16 * t + cl] = (bf16_t)acc[t][ii];
-    ua = Uall + jb * 16 * LDK;
-    lda = LDK;
-  } else {
-    stage7(stg, acc);
-    ua = stg;
-    lda = LDT;
-  }
-  wave_fence();
-  zero(sv);
-  mm<8>(sv, ua, lda, Gb, LDK, KM, nb);  // S = U G^T
-  wave_fence();
-  softmax_rows(sv, e, jb, n, nb, stg, rmax, rz);
-  wave_fence();
-  zero(acc);
-  mm<7>(acc, stg, LDT, GbT, LDT, NP, 7);  // H = A G
-  wave_fence();
-  stage7(stg, acc);
-  wave_fence();
-  zero(acc);
-  if (GW)
-    mm_g<7>(acc, stg, LDT, wvoT, ldv);  // Y = H Wvo
-  else
-    mm<7>(acc, stg, LDT, wvoT, ldv, KM, 7);
-  wave_fence();
-  // X = G + Y;  G <- gamma (X - mu) / sigma + beta
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    float s1 = 0.f;
-#pragma unroll
-    for (int t = 0; t < 7; ++t) {
-      const float x = (16 * t + cl < M) ? gv[t][ii] + acc[t][ii] : 0.f;
-      xh[t][ii] = x;
-      s1 += x;
-    }
-    const float mu = sum16(s1) * (1.f / M);
-    float s2 = 0.f;
-#pragma unroll
-    for (int t = 0; t < 7; ++t) {
-      const float d = (16 * t + cl < M) ? xh[t][ii] - mu : 0.f;
-      s2 += d * d;
-    }
-    isig[ii] = 1.f / sqrtf(sum16(s2) * (1.f / M) + ln_eps);
-#pragma unroll
-    for (int t = 0; t < 7; ++t) {
-      const int m = 16 * t + cl;
-      const float xn = (m < M) ? (xh[t][ii] - mu) * isig[ii] : 0.f;
-      xh[t][ii] = xn;
-      gv[t][ii] = (m < M) ? w.gamma[layer][m] * xn + w.beta[layer][m] : 0.f;
-    }
-  }
-}
-
-// The fp32 rows j < n of the wave's block (tiles gv) to dst [NPMAX][M] (one layer input).
-__device__ __forceinline__ void save_rows(float *__restrict__ dst, const f4 (&gv)[7], int jb, int n) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-  const int j0 = jb * 16 + 4 * q;
-  float *p = dst + (size_t)j0 * M + cl;
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
-    if (j0 + ii < n) {
-#pragma unroll
-      for (int t = 0; t < 7; ++t)
-        if (t < 6 || cl < M - 96) p[ii * M + 16 * t] = gv[t][ii];
-    }
-}
-
-// Reads those rows back (rows j >= n, which never reach a valid token, as zero).
-__device__ __forceinline__ void load_rows(const float *__restrict__ src, f4 (&gv)[7], int jb, int n) {
-  const int l = lane_id(), q = l >> 4, cl = l & 15;
-  const int j0 = jb * 16 + 4 * q;
-  const float *p = src + (size_t)j0 * M + cl;
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const bool ok = j0 + ii < n;
-#pragma unroll
-    for (int t = 0; t < 7; ++t) gv[t][ii] = (ok && (t < 6 || cl < M - 96)) ? p[ii * M + 16 * t] : 0.f;
-  }
-}
-
-// ======================================================================== forward
-constexpr int LDW = 120;  // LDS row stride of the staged weights (k contiguous)
-constexpr int LD2 = 40;   // ... of the staged W2^T [64][32]
-constexpr int LD3 = 72;   // ... of the staged W3^T [112][64]
 
 struct __align__(16) SmemF16 {
   bf16_t Gb[NPMAX * LDK];
@@ -491,17 +14,6 @@ struct __align__(16) SmemF16 {
   bf16_t W[2][KM * LDW];  // the current stage's weights: W2^T and W3^T, then Wqk^T and Wvo^T of a layer
   EnvB e;
 };
-
-// Workgroup copy of a [rows][cols] bf16 matrix (cols a multiple of 8, row stride gld in
-// global memory) into LDS with row stride lld, in 16-byte pieces.
-__device__ __forceinline__ void stage_weights(bf16_t *dst, int lld, const bf16_t *__restrict__ src, int gld, int rows,
-                                              int cols) {
-  const int per = cols / 8;
-  for (int x = threadIdx.x; x < rows * per; x += blockDim.x) {
-    const int r = x / per, c = 8 * (x % per);
-    *(bf8 *)(dst + r * lld + c) = *(const bf8 *)(src + (size_t)r * gld + c);
-  }
-}
 
 __global__ void __launch_bounds__(NWF * 64)
 k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
@@ -515,7 +27,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
-  const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
+  const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
   build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   bf16_t *w2s = sm.W[0], *w3s = sm.W[0] + 64 * LD2;
   stage_weights(w2s, LD2, wp.W2T, 32, 64, 32);
@@ -588,552 +100,6 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   }
 }
 
-// ======================================================================== backward
-template <int NW> struct __align__(16) SmemB16 {
-  bf16_t Gb[NPMAX * LDK];
-  bf16_t GbT[KM * LDT];
-  bf16_t Uall[NPMAX * LDK];
-  bf16_t dHall[NPMAX * LDK];
-  bf16_t stg[NW][16 * LDT];
-  EnvB e;
-  float rmax[NPMAX], rz[NPMAX], rrho[NPMAX];
-  float drh[NPMAX * 3];
-  float dswa[NPMAX];
-  float dRt[NPMAX * 4];
-  float dT[M * 4];
-};
-
-// Backward of one layer for the wave's blocks, from the layer input saved by the forward
-// kernel (gs, fp32 rows j < n).  dg: on entry the gradient w.r.t. the layer output
-// (ignored for the top layer, whose output gradient is Rt dT^T / sel), on exit w.r.t.
-// the layer input.  The column pass also adds, for the wave's own token columns k, the
-// column sums over every query row of the softmax-weight gradient W_jk (to dswa[k]) and
-// of the gate gradient dC_jk rhat_j (to drh[k]).
-template <int NW, int BPW>
-__device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top,
-                                       SmemB16<NW> &sm, const float *__restrict__ gs, int n, int nb, int NP, float ln_eps,
-                                       f4 (&dg)[BPW][7]) {
-  const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
-  bf16_t *stg = sm.stg[wv];
-  const float inv_sel = 1.f / (float)SEL;
-#pragma unroll
-  for (int b = 0; b < BPW; ++b) {
-    const int jb = wv + NW * b;
-    if (jb >= nb) continue;
-    f4 gcur[7], sv[8], xh[7];
-    float isig[4];
-    load_rows(gs, gcur, jb, n);
-    layer_rows<true>(w, wp.WqkT[layer], KM, wp.WvoT[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
-               ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
-    // incoming gradient of the layer output and, for the top layer, dRt = G_out dT / sel
-    f4 go[7];
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      float pr[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const int m = 16 * t + cl;
-        float v = 0.f;
-        if (m < M) {
-          if (top) {
-            const float *dTm = sm.dT + 4 * m;
-            const float sj = sm.e.s[j], hx = sm.e.rh[3 * j], hy = sm.e.rh[3 * j + 1], hz = sm.e.rh[3 * j + 2];
-            v = sj * (dTm[0] + hx * dTm[1] + hy * dTm[2] + hz * dTm[3]) * inv_sel;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) pr[c] += gcur[t][ii] * dTm[c];
-          } else {
-            v = dg[b][t][ii];
-          }
-        }
-        go[t][ii] = v;
-      }
-      if (top) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const float p = sum16(pr[c]) * inv_sel;
-          if (cl == 0) sm.dRt[4 * j + c] += p;
-        }
-      }
-    }
-    // LayerNorm backward: dX = (dxh - mean(dxh) - xh mean(dxh xh)) / sigma, dxh = gamma dG_out
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const int m = 16 * t + cl;
-        const float d = (m < M) ? w.gamma[layer][m] * go[t][ii] : 0.f;
-        go[t][ii] = d;
-        s0 += d;
-        s1 += d * xh[t][ii];
-      }
-      s0 = sum16(s0) * (1.f / M);
-      s1 = sum16(s1) * (1.f / M);
-#pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const int m = 16 * t + cl;
-        dg[b][t][ii] = (m < M) ? (go[t][ii] - s0 - xh[t][ii] * s1) * isig[ii] : 0.f;  // dG_in starts as dX
-      }
-    }
-    wave_fence();
-    stage7(stg, dg[b]);  // dY = dX
-    wave_fence();
-    f4 acc[7];
-    zero(acc);
-    mm_g<7>(acc, stg, LDT, wp.Wvo[layer], KM);  // dH = dY Wvo^T
-#pragma unroll
-    for (int t = 0; t < 7; ++t)
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) sm.dHall[(jb * 16 + 4 * q + ii) * LDK + 16 * t + cl] = (bf16_t)acc[t][ii];
-    wave_fence();
-    f4 da[8];
-    zero(da);
-    mm<8>(da, sm.dHall + jb * 16 * LDK, LDK, sm.Gb, LDK, KM, nb);  // dA = dH G^T
-    wave_fence();
-    // weighted-softmax and gate backward
-    float hj[4][3], rho[4], hxa[4], hya[4], hza[4];
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      hj[ii][0] = sm.e.rh[3 * j];
-      hj[ii][1] = sm.e.rh[3 * j + 1];
-      hj[ii][2] = sm.e.rh[3 * j + 2];
-      rho[ii] = hxa[ii] = hya[ii] = hza[ii] = 0.f;
-    }
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      const int k = 16 * ct + cl;
-      const bool kv = ct < nb && k < n;
-      float swk = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
-      if (ct < nb) {
-        swk = sm.e.sw[k];
-        hx = sm.e.rh[3 * k];
-        hy = sm.e.rh[3 * k + 1];
-        hz = sm.e.rh[3 * k + 2];
-      }
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        if (kv && jb * 16 + 4 * q + ii < n) {
-          const float P = swk * sv[ct][ii];
-          const float gt = hj[ii][0] * hx + hj[ii][1] * hy + hj[ii][2] * hz;
-          const float dP = da[ct][ii] * gt;
-          const float dC = da[ct][ii] * P;
-          rho[ii] += P * dP;
-          hxa[ii] += dC * hx;
-          hya[ii] += dC * hy;
-          hza[ii] += dC * hz;
-          da[ct][ii] = dP;
-        } else {
-          da[ct][ii] = 0.f;
-        }
-      }
-    }
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      rho[ii] = sum16(rho[ii]);
-      const float hx = sum16(hxa[ii]), hy = sum16(hya[ii]), hz = sum16(hza[ii]);
-      if (cl == 0) {
-        sm.rrho[j] = rho[ii];
-        sm.drh[3 * j] += hx;
-        sm.drh[3 * j + 1] += hy;
-        sm.drh[3 * j + 2] += hz;
-      }
-    }
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct)
-      if (ct < nb) {
-        const int k = 16 * ct + cl;
-        const float swk = sm.e.sw[k];
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          const bool v = k < n && jb * 16 + 4 * q + ii < n;
-          const float W = v ? sv[ct][ii] * (da[ct][ii] - rho[ii]) : 0.f;
-          stg[(4 * q + ii) * LDT + k] = (bf16_t)(swk * W);  // dS
-        }
-      }
-    wave_fence();
-    zero(acc);
-    mm<7>(acc, stg, LDT, sm.GbT, LDT, NP, 7);  // dU = dS G
-    wave_fence();
-    stage7(stg, acc);
-    wave_fence();
-    zero(acc);
-    mm_g<7>(acc, stg, LDT, wp.Wqk[layer], KM);  // dG += dU Wqk^T
-#pragma unroll
-    for (int t = 0; t < 7; ++t) dg[b][t] += acc[t];
-    wave_fence();
-  }
-  __syncthreads();
-  // column pass: dG[k] += sum_j A_jk dH_j + dS_jk U_j for the wave's own token blocks
-  // (kb = wave and wave + NW); the U / dH rows of each block jb are gathered once for both
-  {
-    bool has[BPW];
-    float swk[BPW], hk[BPW][3];
-    float cw[BPW][4];  // per-lane partial column sums: W, dC rhat_j (x, y, z)
-    f4 cacc[BPW][7];
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-      const int kb = wv + NW * b;
-      has[b] = kb < nb;
-      const int k = min(kb, 7) * 16 + cl;
-      swk[b] = sm.e.sw[k];
-      hk[b][0] = sm.e.rh[3 * k];
-      hk[b][1] = sm.e.rh[3 * k + 1];
-      hk[b][2] = sm.e.rh[3 * k + 2];
-      cw[b][0] = cw[b][1] = cw[b][2] = cw[b][3] = 0.f;
-      zero(cacc[b]);
-    }
-    // the key-side fragments (Gb rows of the wave's column blocks) are the same for every jb
-    bf8 gk[BPW][3];
-    s4 gkt[BPW];
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-      const bf16_t *gr = sm.Gb + (min(wv + NW * b, 7) * 16 + (l & 15)) * LDK;
-#pragma unroll
-      for (int st = 0; st < 3; ++st) gk[b][st] = ld8(gr + 32 * st + 8 * q);
-      gkt[b] = ld4(gr + 96 + 4 * q);
-    }
-    if (has[0]) {
-      for (int jb = 0; jb < nb; ++jb) {
-        float rmx[4], rzz[4], rro[4], hj[4][3];
-        bool jv[4];
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          const int j = jb * 16 + 4 * q + ii;
-          jv[ii] = j < n;
-          rmx[ii] = sm.rmax[j];
-          rzz[ii] = sm.rz[j];
-          rro[ii] = sm.rrho[j];
-          hj[ii][0] = sm.e.rh[3 * j];
-          hj[ii][1] = sm.e.rh[3 * j + 1];
-          hj[ii][2] = sm.e.rh[3 * j + 2];
-        }
-        s4 yh[7], yu[7];
-#pragma unroll
-        for (int t = 0; t < 7; ++t) {
-          const int m = 16 * t + cl;
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii) {
-            const int j = jb * 16 + 4 * q + ii;
-            const bf16_t vh = sm.dHall[j * LDK + m], vu = sm.Uall[j * LDK + m];
-            yh[t][ii] = *(const short *)&vh;
-            yu[t][ii] = *(const short *)&vu;
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < BPW; ++b) {
-          if (!has[b]) continue;
-          const int kb = wv + NW * b;
-          const bool kv = kb * 16 + cl < n;
-          f4 st[1], dt[1];
-          zero(st);
-          zero(dt);
-          {
-            const bf16_t *ur = sm.Uall + (jb * 16 + (l & 15)) * LDK, *hr = sm.dHall + (jb * 16 + (l & 15)) * LDK;
-#pragma unroll
-            for (int s3 = 0; s3 < 3; ++s3) {
-              st[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(ur + 32 * s3 + 8 * q), gk[b][s3], st[0], 0, 0, 0);
-              dt[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(hr + 32 * s3 + 8 * q), gk[b][s3], dt[0], 0, 0, 0);
-            }
-            st[0] = mma16(ld4(ur + 96 + 4 * q), gkt[b], st[0]);
-            dt[0] = mma16(ld4(hr + 96 + 4 * q), gkt[b], dt[0]);
-          }
-          s4 xa, xs;
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii) {
-            float A = 0.f, dS = 0.f;
-            if (kv && jv[ii]) {
-              const float E = fexp(st[0][ii] - rmx[ii]) * rzz[ii];
-              const float P = swk[b] * E;
-              const float gt = hj[ii][0] * hk[b][0] + hj[ii][1] * hk[b][1] + hj[ii][2] * hk[b][2];
-              const float W = E * (dt[0][ii] * gt - rro[ii]);  // softmax-weight gradient
-              const float dC = dt[0][ii] * P;                   // gate gradient
-              A = P * gt;
-              dS = swk[b] * W;
-              cw[b][0] += W;
-              cw[b][1] += dC * hj[ii][0];
-              cw[b][2] += dC * hj[ii][1];
-              cw[b][3] += dC * hj[ii][2];
-            }
-            xa[ii] = bfbits(A);
-            xs[ii] = bfbits(dS);
-          }
-#pragma unroll
-          for (int t = 0; t < 7; ++t) {
-            cacc[b][t] = mma16(xa, yh[t], cacc[b][t]);
-            cacc[b][t] = mma16(xs, yu[t], cacc[b][t]);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-      // column sums over the 4 row groups; column k is owned by this wave alone
-#pragma unroll
-      for (int c = 0; c < 4; ++c) cw[b][c] = sum_cols4(cw[b][c]);
-      if (has[b]) {
-#pragma unroll
-        for (int t = 0; t < 7; ++t) dg[b][t] += cacc[b][t];
-        if (q == 0) {
-          const int k = (wv + NW * b) * 16 + cl;
-          sm.dswa[k] += cw[b][0];
-          sm.drh[3 * k] += cw[b][1];
-          sm.drh[3 * k + 1] += cw[b][2];
-          sm.drh[3 * k + 2] += cw[b][3];
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// Puts the saved layer input rows (fp32 -> bf16) of the wave's blocks into Gb / GbT.
-template <int NW, int BPW>
-__device__ __forceinline__ void stage_layer_input(SmemB16<NW> &sm, const float *__restrict__ gs, int n, int nb) {
-  const int wv = wave_id();
-#pragma unroll
-  for (int b = 0; b < BPW; ++b) {
-    const int jb = wv + NW * b;
-    if (jb >= nb) continue;
-    f4 gv[7];
-    load_rows(gs, gv, jb, n);
-    put_rows(sm.Gb, sm.GbT, gv, jb);
-  }
-}
-
-// NW waves per workgroup, each owning BPW row blocks (wave w owns blocks w, w + NW, ...);
-// the workgroup takes atom idx[blockIdx.x] for blockIdx.x < *count, so atoms can be sent
-// to the instance whose block count fits their neighbour count.
-template <int NW, int BPW>
-__global__ void __launch_bounds__(NW * 64)
-k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
-               const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids,
-               const int *__restrict__ sys_of, float rc, float rcs, float ln_eps, const float *__restrict__ Gsave,
-               const float *__restrict__ Tsave, const float *__restrict__ dD, float4 *__restrict__ gout,
-               const int *__restrict__ idx, const int *__restrict__ count) {
-  __shared__ SmemB16<NW> sm;
-  if ((int)blockIdx.x >= *count) return;
-  const int i = idx[blockIdx.x];
-  const Grid g = grids[sys_of[i]];
-  const int n = min(max(nnei[i], 0), SEL);
-  const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
-  const int nb = NP / 16;
-  const int ti = clamp_type(types[i]);
-  const int wv = wave_id(), l = lane_id(), q = l >> 4, cl = l & 15;
-  build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
-  for (int x = threadIdx.x; x < NPMAX; x += NW * 64) {
-    sm.dswa[x] = 0.f;
-    for (int a = 0; a < 3; ++a) sm.drh[3 * x + a] = 0.f;
-    for (int a = 0; a < 4; ++a) sm.dRt[4 * x + a] = 0.f;
-  }
-  // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m']
-  float *T = (float *)sm.stg[0];  // staging is free until the first layer: T [100][4], dE/dD [1600]
-  float *dDi = T + M * 4;
-  for (int x = threadIdx.x; x < M; x += NW * 64)
-    *(float4 *)(T + 4 * x) = *(const float4 *)(Tsave + ((size_t)i * M + x) * 4);
-  for (int x = threadIdx.x; x < ND / 4; x += NW * 64)
-    *(float4 *)(dDi + 4 * x) = *(const float4 *)(dD + (size_t)i * ND + 4 * x);
-  __syncthreads();
-  for (int x = threadIdx.x; x < M * 4; x += NW * 64) {
-    const int m = x >> 2, c = x & 3;
-    float acc = 0.f;
-    for (int a = 0; a < M2; ++a) acc += dDi[m * M2 + a] * T[4 * a + c];
-    if (m < M2)
-      for (int mm2 = 0; mm2 < M; ++mm2) acc += dDi[mm2 * M2 + m] * T[4 * mm2 + c];
-    sm.dT[x] = acc;
-  }
-  const float *gs0 = Gsave + (size_t)i * NATTN * NPMAX * M;
-  const float *gs1 = gs0 + (size_t)NPMAX * M;
-  stage_layer_input<NW, BPW>(sm, gs1, n, nb);
-  __syncthreads();
-  f4 dg[BPW][7];
-#pragma unroll
-  for (int b = 0; b < BPW; ++b)
-#pragma unroll
-    for (int t = 0; t < 7; ++t) dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-  layer_bwd<NW, BPW>(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg);
-  stage_layer_input<NW, BPW>(sm, gs0, n, nb);
-  __syncthreads();
-  layer_bwd<NW, BPW>(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg);
-  // the embedding weights of the larger products into LDS (Uall is free now)
-  bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
-  stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
-  stage_weights(w3s, KM, wp.W3, KM, 64, KM);
-  bf16_t *w2Ts = sm.Gb, *w2s = sm.Gb + 64 * LD2;  // Gb is free as well
-  static_assert(NW <= 7 && 4 * 16 * 104 * 4 <= KM * LDT * 2 &&
-                    (64 * LD2 + 32 * LD3) * 2 + (NW > 4 ? NW - 4 : 0) * 16 * 104 * 4 <= NPMAX * LDK * 2,
-                "per-wave fp32 scratch of the embedding backward must fit in GbT and the rest of Gb");
-  stage_weights(w2Ts, LD2, wp.W2T, 32, 64, 32);
-  stage_weights(w2s, LD3, wp.W2, 64, 32, 64);
-  __syncthreads();
-  // embedding backward and the pair gradients of the wave's rows
-#pragma unroll
-  for (int b = 0; b < BPW; ++b) {
-    const int jb = wv + NW * b;
-    if (jb >= nb) continue;
-    float *h1 = (float *)(sm.dHall + jb * 16 * LDK);  // [16][32]
-    float *h2 = (float *)sm.stg[wv];                  // [16][64]
-    // [16][104] fp32: dG0 rows, then dh2; waves 0-3 in GbT, waves 4-6 in Gb after the W2 copies
-    float *sc = wv < 4 ? (float *)sm.GbT + wv * 16 * 104 : (float *)(w2s + 32 * LD3) + (wv - 4) * 16 * 104;
-    // recompute h1, t2, h2 (fp32) for these rows, as the forward kernel made them
-    {
-      const int c1 = l & 31;
-      const bool c1v = c1 < E1;
-      const float w1c = c1v ? w.w1s[c1] : 0.f;
-#pragma unroll
-      for (int x = 0; x < 8; ++x) {
-        const int r = (l >> 5) + 2 * x, j = jb * 16 + r;
-        const float bt = c1v ? w.Bt[(ti * NTYPES + sm.e.tj[j]) * E1 + c1] : 0.f;
-        h1[r * 32 + c1] = c1v ? ftanh(sm.e.s[j] * w1c + bt) : 0.f;
-      }
-    }
-    wave_fence();
-    f4 a2[4];
-    zero(a2);
-    mm_a32<4>(a2, h1, 32, w2Ts, LD2, 32);
-    float t2v[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = 16 * t + cl;
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii;
-        const float tt = c < E2 ? ftanh(a2[t][ii] + w.b2[c]) : 0.f;
-        t2v[t][ii] = tt;
-        h2[r * 64 + c] = c < E2 ? tt + h1[r * 32 + (c % E1)] : 0.f;
-      }
-    }
-    wave_fence();
-    f4 a3[7];
-    zero(a3);
-    mm_a32<7>(a3, h2, 64, w3Ts, LD3, 64);
-    // dpre3 = dG0 (1 - t3^2) staged as bf16; dG0 half sums (cols c and c + 50) into sc
-    wave_fence();
-    bf16_t *stg = sm.stg[wv];  // aliases h2, which is no longer needed
-#pragma unroll
-    for (int t = 0; t < 7; ++t) {
-      const int m = 16 * t + cl;
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii;
-        const float t3 = m < M ? ftanh(a3[t][ii] + w.b3[m]) : 0.f;
-        a3[t][ii] = m < M ? dg[b][t][ii] * (1.f - t3 * t3) : 0.f;
-        if (m < M) sc[r * 104 + m] = dg[b][t][ii];
-      }
-    }
-    wave_fence();
-    stage7(stg, a3);  // dpre3 (bf16) over h2 (no longer needed)
-    wave_fence();
-    // dh2 = dpre3 W3^T + (dG0[:, :50] + dG0[:, 50:]);  dpre2 = dh2 (1 - t2^2)
-    f4 d2[4];
-    zero(d2);
-    mm<4>(d2, stg, LDT, w3s, KM, KM, 4);
-    wave_fence();
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = 16 * t + cl;
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii;
-        const float v = c < E2 ? d2[t][ii] + sc[r * 104 + c] + sc[r * 104 + c + E2] : 0.f;
-        d2[t][ii] = v;  // dh2
-      }
-    }
-    wave_fence();
-    // stage dpre2 (bf16, [16][64]) and dh2 halves sum (fp32, for dh1) in sc
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = 16 * t + cl;
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii;
-        stg[r * LDT + c] = (bf16_t)(c < E2 ? d2[t][ii] * (1.f - t2v[t][ii] * t2v[t][ii]) : 0.f);
-        if (c < E2) sc[r * 104 + c] = d2[t][ii];
-      }
-    }
-    wave_fence();
-    // dh1 = dpre2 W2^T + (dh2[:, :25] + dh2[:, 25:]);  ds_emb = sum_c dh1 (1 - h1^2) w1s
-    f4 d1[2];
-    zero(d1);
-    mm<2>(d1, stg, LDT, w2s, LD3, 64, 2);
-    float dse[4];
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int r = 4 * q + ii;
-      float p = 0.f;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int c = 16 * t + cl;
-        if (c < E1) {
-          const float dh1 = d1[t][ii] + sc[r * 104 + c] + sc[r * 104 + c + E1];
-          const float hv = h1[r * 32 + c];
-          p += dh1 * (1.f - hv * hv) * w.w1s[c];
-        }
-      }
-      dse[ii] = sum16(p);
-    }
-    // pair gradients (lane cl == ii handles row 4q + ii)
-#pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      if (cl == ii && j < SEL) {
-        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < n) out = pair_gradient_b(sm.e, j, dse[ii], sm.dRt + 4 * j, sm.drh + 3 * j, sm.dswa[j], rc, rcs);
-        gout[(size_t)i * SEL + j] = out;
-      }
-    }
-    wave_fence();
-  }
-  for (int j = NP + threadIdx.x; j < SEL; j += NW * 64) gout[(size_t)i * SEL + j] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
-// Stable partition of the atoms by row-block count: idx[0..c0) the atoms with at most
-// SPLIT_NB blocks of 16 neighbours, idx[cap..cap+c1) the others; count[0] = c0, count[1] = c1.
-constexpr int SPLIT_NB = 7;
-__global__ void __launch_bounds__(1024) k_partition(const int *__restrict__ nnei, int n, int cap, int *__restrict__ idx,
-                                                    int *__restrict__ count) {
-  __shared__ int sc[1024];
-  __shared__ int base[2];
-  if (threadIdx.x == 0) base[0] = base[1] = 0;
-  __syncthreads();
-  for (int c0 = 0; c0 < n; c0 += 1024) {
-    const int a = c0 + threadIdx.x;
-    int f = 0;  // 1: small, 2: large, 0: none
-    if (a < n) {
-      const int na = min(max(nnei[a], 0), SEL);
-      f = ((max(na, 1) + 15) / 16 <= SPLIT_NB) ? 1 : 2;
-    }
-    // inclusive scan of the small flags (Hillis-Steele)
-    sc[threadIdx.x] = (f == 1);
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
-      __syncthreads();
-      sc[threadIdx.x] += v;
-      __syncthreads();
-    }
-    const int small_incl = sc[threadIdx.x];
-    const int small_tot = sc[1023];
-    const int valid = min(1024, n - c0);
-    const int pos_small = base[0] + small_incl - 1;
-    const int pos_large = base[1] + ((int)threadIdx.x - small_incl + (f == 1 ? 1 : 0));
-    if (f == 1) idx[pos_small] = a;
-    if (f == 2) idx[cap + pos_large] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      base[0] += small_tot;
-      base[1] += valid - small_tot;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    count[0] = base[0];
-    count[1] = base[1];
-  }
-}
-
 }  // namespace
 
 void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
@@ -1141,23 +107,6 @@ void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, c
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
-}
-
-void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n,
-                               float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, n, (int)ws.cap, ws.bidx, ws.bcnt);
-  // atoms with up to 7 row blocks: 7 waves, one block each (on st); the rest: 4 waves,
-  // two blocks each, on the side stream, so that a few dense atoms overlap the bulk
-  (void)hipEventRecord(ws.fork_ev, st);
-  (void)hipStreamWaitEvent(ws.side, ws.fork_ev, 0);
-  hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(n), dim3(4 * 64), 0, ws.side, w, wp, coords, types, n, ws.nlist,
-                     ws.nnei, ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx + ws.cap,
-                     ws.bcnt + 1);
-  hipLaunchKernelGGL((k_desc_bwd_b16<7, 1>), dim3(n), dim3(7 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
-                     ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx, ws.bcnt);
-  (void)hipEventRecord(ws.join_ev, ws.side);
-  (void)hipStreamWaitEvent(st, ws.join_ev, 0);
 }
 
 }  // namespace dp
