@@ -47,36 +47,44 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     load_rows(gs, gcur, jb, n);
     layer_rows<true>(w, wp.WqkT[layer], KM, wp.WvoT[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
                ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
-    // incoming gradient of the layer output and, for the top layer, dRt = G_out dT / sel
+    // incoming gradient of the layer output: for the top layer go = Rt dT^T / sel (and
+    // dRt = G_out dT / sel), otherwise the gradient the layer above passed down
     f4 go[7];
+    if (top) {
+      float4 dTv[7];
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
-      float pr[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < 7; ++t)
+        dTv[t] = (16 * t + cl < M) ? *(const float4 *)(sm.dT + 4 * (16 * t + cl)) : make_float4(0.f, 0.f, 0.f, 0.f);
+      float pr[16];  // the lane's partial G_out dT over its feature columns, [row ii][c]
 #pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const int m = 16 * t + cl;
-        float v = 0.f;
-        if (m < M) {
-          if (top) {
-            const float *dTm = sm.dT + 4 * m;
-            const float sj = sm.e.s[j], hx = sm.e.rh[3 * j], hy = sm.e.rh[3 * j + 1], hz = sm.e.rh[3 * j + 2];
-            v = sj * (dTm[0] + hx * dTm[1] + hy * dTm[2] + hz * dTm[3]) * inv_sel;
+      for (int ii = 0; ii < 4; ++ii) {
+        const int j = jb * 16 + 4 * q + ii;
+        const float sj = sm.e.s[j], hx = sm.e.rh[3 * j], hy = sm.e.rh[3 * j + 1], hz = sm.e.rh[3 * j + 2];
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) pr[c] += gcur[t][ii] * dTm[c];
-          } else {
-            v = dg[b][t][ii];
-          }
+        for (int t = 0; t < 7; ++t) {
+          const float4 d = dTv[t];
+          go[t][ii] = sj * (d.x + hx * d.y + hy * d.z + hz * d.w) * inv_sel;  // zero for padded features
+          const float gvv = gcur[t][ii];
+          p0 += gvv * d.x; p1 += gvv * d.y; p2 += gvv * d.z; p3 += gvv * d.w;
         }
-        go[t][ii] = v;
+        pr[4 * ii] = p0; pr[4 * ii + 1] = p1; pr[4 * ii + 2] = p2; pr[4 * ii + 3] = p3;
       }
-      if (top) {
+      // reduce-scatter over the 16 lanes of the row group: afterwards lane cl holds the
+      // total of entry cl = 4 ii + c
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const float p = sum16(pr[c]) * inv_sel;
-          if (cl == 0) sm.dRt[4 * j + c] += p;
+      for (int h = 8; h >= 1; h >>= 1) {
+        const bool upper = (cl & h) != 0;
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+          const float lo = pr[k], hi = pr[k + h];
+          pr[k] = (upper ? hi : lo) + __shfl_xor(upper ? lo : hi, h);
         }
       }
+      sm.dRt[4 * (jb * 16 + 4 * q) + cl] = pr[0] * inv_sel;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 7; ++t) go[t] = (16 * t + cl < M) ? dg[b][t] : f4{0.f, 0.f, 0.f, 0.f};
     }
     // LayerNorm backward: dX = (dxh - mean(dxh) - xh mean(dxh xh)) / sigma, dxh = gamma dG_out
 #pragma unroll
@@ -344,27 +352,42 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
+  // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m'];
+  // staging is free until the first layer: T [100][4], dE/dD [1600], partial sums [NW * 64]
+  float *T = (float *)sm.stg[0];
+  float *dDi = T + M * 4;
+  float *part = dDi + ND;
+  static_assert((M * 4 + ND + NW * 64) * sizeof(float) <= sizeof(sm.stg), "dT staging must fit in stg");
+  for (int x = threadIdx.x; x < M; x += NW * 64)
+    *(float4 *)(T + 4 * x) = *(const float4 *)(Tsave + ((size_t)i * M + x) * 4);
+  for (int x = threadIdx.x; x < ND / 4; x += NW * 64)
+    *(float4 *)(dDi + 4 * x) = *(const float4 *)(dD + (size_t)i * ND + 4 * x);
   build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   for (int x = threadIdx.x; x < NPMAX; x += NW * 64) {
     sm.dswa[x] = 0.f;
     for (int a = 0; a < 3; ++a) sm.drh[3 * x + a] = 0.f;
     for (int a = 0; a < 4; ++a) sm.dRt[4 * x + a] = 0.f;
   }
-  // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m']
-  float *T = (float *)sm.stg[0];  // staging is free until the first layer: T [100][4], dE/dD [1600]
-  float *dDi = T + M * 4;
-  for (int x = threadIdx.x; x < M; x += NW * 64)
-    *(float4 *)(T + 4 * x) = *(const float4 *)(Tsave + ((size_t)i * M + x) * 4);
-  for (int x = threadIdx.x; x < ND / 4; x += NW * 64)
-    *(float4 *)(dDi + 4 * x) = *(const float4 *)(dD + (size_t)i * ND + 4 * x);
   __syncthreads();
   for (int x = threadIdx.x; x < M * 4; x += NW * 64) {
     const int m = x >> 2, c = x & 3;
     float acc = 0.f;
     for (int a = 0; a < M2; ++a) acc += dDi[m * M2 + a] * T[4 * a + c];
-    if (m < M2)
-      for (int mm2 = 0; mm2 < M; ++mm2) acc += dDi[mm2 * M2 + m] * T[4 * mm2 + c];
     sm.dT[x] = acc;
+  }
+  {
+    // the second sum of the 64 entries m < M2 in NW chunks of m', one (chunk, entry) per thread
+    constexpr int CH = (M + NW - 1) / NW;
+    const int e = threadIdx.x & 63, ch = threadIdx.x >> 6, m = e >> 2, c = e & 3;
+    float acc = 0.f;
+    for (int mm2 = ch * CH; mm2 < min(M, (ch + 1) * CH); ++mm2) acc += dDi[mm2 * M2 + m] * T[4 * mm2 + c];
+    part[threadIdx.x] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    float acc = sm.dT[threadIdx.x];
+    for (int ch = 0; ch < NW; ++ch) acc += part[64 * ch + threadIdx.x];
+    sm.dT[threadIdx.x] = acc;
   }
   const float *gs0 = Gsave + (size_t)i * NATTN * NPMAX * M;
   const float *gs1 = gs0 + (size_t)NPMAX * M;
