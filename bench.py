@@ -193,6 +193,26 @@ def serving_bench(model_path, trace, systems, rates, budget_bytes):
     return out
 
 
+def measured_traffic(phase, precision, workload):
+    """HBM bytes per launch of a phase from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading), or None when there
+    is none for this phase and workload or a kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get("phases", {}).get(phase)
+    if rec is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2602_02234_amd", "csrc")
+    for name, digest in rec["sources"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def time_path(model, X, T, box, F, V, E, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -307,7 +327,8 @@ def main():
                                f"{system.box[0, 0]:.2f} A box, rc 6 A, sel 120; energy+forces+virial per step",
                    "precision_path": args.precision, "natoms": N, "mean_neighbors": float(n.mean())},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK[args.precision] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
+                     "traffic": measured_traffic(dom, args.precision, args.workload),
                      "avg_ms": avg[dom], "alg_flop_per_launch": alg[dom],
                      "executed_flop_per_launch": executed[dom]},
         "step_roofline": {"alg_flop_per_step": step_alg,

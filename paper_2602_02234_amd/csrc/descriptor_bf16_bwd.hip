@@ -70,16 +70,31 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
         }
         pr[4 * ii] = p0; pr[4 * ii + 1] = p1; pr[4 * ii + 2] = p2; pr[4 * ii + 3] = p3;
       }
-      // reduce-scatter over the 16 lanes of the row group: afterwards lane cl holds the
-      // total of entry cl = 4 ii + c
+      // reduce-scatter over the 16 lanes of the row group: at the step of bit h each lane
+      // keeps the half of its entries selected by that bit of its lane index and adds the
+      // partner's copy of it (partners differ in bit h and agree in the bits above);
+      // afterwards lane cl holds the total of entry cl = 4 ii + c
 #pragma unroll
-      for (int h = 8; h >= 1; h >>= 1) {
-        const bool upper = (cl & h) != 0;
+      for (int k = 0; k < 8; ++k) {
+        const bool up = (cl & 8) != 0;
+        const float lo = pr[k], hi = pr[k + 8];
+        pr[k] = (up ? hi : lo) + dpp<0x128>(up ? lo : hi);
+      }
 #pragma unroll
-        for (int k = 0; k < h; ++k) {
-          const float lo = pr[k], hi = pr[k + h];
-          pr[k] = (upper ? hi : lo) + __shfl_xor(upper ? lo : hi, h);
-        }
+      for (int k = 0; k < 4; ++k) {
+        const bool up = (cl & 4) != 0;
+        const float lo = pr[k], hi = pr[k + 4];
+        pr[k] = (up ? hi : lo) + dpp<0x141>(up ? lo : hi);
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const bool up = (cl & 2) != 0;
+        const float lo = pr[k], hi = pr[k + 2];
+        pr[k] = (up ? hi : lo) + dpp<0x4E>(up ? lo : hi);
+      }
+      {
+        const bool up = (cl & 1) != 0;
+        pr[0] = (up ? pr[1] : pr[0]) + dpp<0xB1>(up ? pr[0] : pr[1]);
       }
       sm.dRt[4 * (jb * 16 + 4 * q) + cl] = pr[0] * inv_sel;
     } else {

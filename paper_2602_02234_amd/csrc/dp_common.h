@@ -79,19 +79,27 @@ template <> struct Mma<bf16_t> {
 __device__ __forceinline__ int acc_row(int i) { return 4 * (lane_id() >> 4) + i; }
 __device__ __forceinline__ int acc_col() { return lane_id() & 15; }
 
-// Sum over the 16 lanes sharing lane/16 (one tile row group); result in all of them.
+// Cross-lane moves within a row of 16 lanes by DPP (no LDS round trip): the value of
+// the partner lane.  Quad permutations 0xB1 (lane ^ 1) and 0x4E (lane ^ 2), half-row
+// mirror 0x141 (lane ^ 7 within 8), row mirror 0x140 (lane ^ 15 within 16) and row
+// rotation by 8, 0x128 (lane ^ 8 within 16).  Every lane of the wave must be active.
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+// Sum over the 16 lanes sharing lane/16 (one tile row group); the same value in all of
+// them (each step adds a partner's value, and a + b == b + a exactly).
 __device__ __forceinline__ float sum16(float v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
   return v;
 }
 __device__ __forceinline__ float max16(float v) {
-  v = fmaxf(v, __shfl_xor(v, 1));
-  v = fmaxf(v, __shfl_xor(v, 2));
-  v = fmaxf(v, __shfl_xor(v, 4));
-  v = fmaxf(v, __shfl_xor(v, 8));
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x141>(v));
+  v = fmaxf(v, dpp<0x140>(v));
   return v;
 }
 // Sum over the 4 lanes l, l^16, l^32, l^48 (one tile column across row groups).
