@@ -206,7 +206,11 @@ def measured_traffic(phase, precision, workload):
     if rec is None:
         return None
     csrc = os.path.join(ROOT, "paper_2602_02234_amd", "csrc")
+    if not isinstance(rec.get("sources"), dict) or "hbm_bytes_per_launch" not in rec:
+        return None
     for name, digest in rec["sources"].items():
+        if not os.path.exists(os.path.join(csrc, name)):
+            return None
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
