@@ -251,9 +251,24 @@ int build_weights(dp_model *m, const HostModel &h) {
     const auto f2 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, c, k) : 0.0; });
     const auto f3t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, k, c) : 0.0; });
     const auto f3 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, c, k) : 0.0; });
-    for (const auto *v : {&f1t, &f1, &f2t, &f2, &f3t, &f3}) {
-      op.push_back(hi_lo(*v, 0));
-      op.push_back(hi_lo(*v, 1));
+    // the fitting operands in MFMA fragment order: the 16 x 32 fragment (column tile t,
+    // k step s) is 64 lanes x 8 contiguous values, lane l holding row 16 t + l % 16,
+    // k = 32 s + 8 (l / 16) .. + 8; so one wave's fragment load is 1 KB of whole lines
+    auto frag = [](const std::vector<float> &v, int R, int K) {
+      std::vector<float> o(v.size());
+      const int S = K / 32;
+      for (int t = 0; t < R / 16; ++t)
+        for (int st = 0; st < S; ++st)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e)
+              o[(((size_t)t * S + st) * 64 + l) * 8 + e] = v[(size_t)(16 * t + l % 16) * K + 32 * st + 8 * (l / 16) + e];
+      return o;
+    };
+    const std::vector<float> fr[] = {frag(f1t, FH, ND), frag(f1, ND, 256), frag(f2t, FH, 256),
+                                     frag(f2, FH, 256), frag(f3t, FH, 256), frag(f3, FH, 256)};
+    for (const auto &v : fr) {
+      op.push_back(hi_lo(v, 0));
+      op.push_back(hi_lo(v, 1));
     }
   }
   HIP_TRY(hipMalloc(&m->wbuf, pk.bytes.size()));

@@ -78,7 +78,9 @@ struct WeightsB16 {
   const bf16_t *Wqk[NATTN];    // [112][112]
   const bf16_t *WvoT[NATTN];   // [112][112]
   const bf16_t *Wvo[NATTN];    // [112][112]
-  const bf16_t *F1T[2];        // [240][1600] hi, lo
+  // fitting operands, hi and lo parts, in MFMA fragment order (fragment (t, s) of a
+  // [cols][K] matrix at ((t * K / 32 + s) * 64 + lane) * 8)
+  const bf16_t *F1T[2];        // [240][1600]
   const bf16_t *F1[2];         // [1600][256]
   const bf16_t *F2T[2];        // [240][256]
   const bf16_t *F2[2];         // [240][256]

@@ -35,26 +35,28 @@ __device__ __forceinline__ f4 mma3(const bf8 &xh, const bf8 &xl, const bf8 &yh, 
 }
 
 // acc = A(16 x K) . B_t^T for the column tiles t = wave + NWT u (< NT), u < 2; A fp32
-// rows at a (stride lda, K a multiple of 32), B split bf16 [col][k] at bh/bl (stride
-// ldb).  The operands of step k + 32 are loaded before the products of step k.
+// rows at a (stride lda, K a multiple of 32), B split bf16 in fragment order at bh/bl.
+// The operands of step k + 32 are loaded before the products of step k.
 __device__ __forceinline__ void mm_split2(f4 (&acc)[2], const float *a, int lda, const bf16_t *bh, const bf16_t *bl,
-                                          int ldb, int K) {
+                                          int K) {
   const int l = lane_id(), r = l & 15, q = l >> 4, wv = wave_id();
   const bool t1 = wv + NWT < NT;
+  const int S = K / 32;
   acc[0] = acc[1] = f4{0.f, 0.f, 0.f, 0.f};
   const float *ar = a + r * lda + 8 * q;
-  const size_t o0 = (size_t)(16 * wv + r) * ldb + 8 * q, o1 = (size_t)(16 * min(wv + NWT, NT - 1) + r) * ldb + 8 * q;
+  const size_t o0 = (size_t)wv * S * 512 + 8 * l, o1 = (size_t)min(wv + NWT, NT - 1) * S * 512 + 8 * l;
   float4 pa0 = *(const float4 *)ar, pa1 = *(const float4 *)(ar + 4);
   bf8 ph0 = ld8g(bh + o0), pl0 = ld8g(bl + o0), ph1 = ld8g(bh + o1), pl1 = ld8g(bl + o1);
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = 0, st = 0; k0 < K; k0 += 32, ++st) {
     const float4 a0 = pa0, a1 = pa1;
     const bf8 h0 = ph0, l0 = pl0, h1 = ph1, l1 = pl1;
     if (k0 + 32 < K) {
       const int k = k0 + 32;
+      const size_t f = (size_t)(st + 1) * 512;
       pa0 = *(const float4 *)(ar + k);
       pa1 = *(const float4 *)(ar + k + 4);
-      ph0 = ld8g(bh + o0 + k); pl0 = ld8g(bl + o0 + k);
-      ph1 = ld8g(bh + o1 + k); pl1 = ld8g(bl + o1 + k);
+      ph0 = ld8g(bh + o0 + f); pl0 = ld8g(bl + o0 + f);
+      ph1 = ld8g(bh + o1 + f); pl1 = ld8g(bl + o1 + f);
     }
     __builtin_amdgcn_sched_barrier(0);
     bf8 xh, xl;
@@ -65,10 +67,10 @@ __device__ __forceinline__ void mm_split2(f4 (&acc)[2], const float *a, int lda,
 }
 
 // The dE/dD product for the column tiles t = wave + NWT u, U0 <= u < U1 (< ND / 16),
-// A from LDS (K = 256).
+// A from LDS (K = 256), B in fragment order.
 template <int U0, int U1>
 __device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, int lda, const bf16_t *bh,
-                                            const bf16_t *bl, int ldb) {
+                                            const bf16_t *bl) {
   const int l = lane_id(), r = l & 15, q = l >> 4, wv = wave_id();
 #pragma unroll
   for (int u = 0; u < U1 - U0; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
@@ -80,7 +82,7 @@ __device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, 
     for (int u = U0; u < U1; ++u) {
       const int t = wv + NWT * u;
       if (t < ND / 16) {
-        const size_t o = (size_t)(16 * t + r) * ldb + k0 + 8 * q;
+        const size_t o = ((size_t)t * (KH / 32) + k0 / 32) * 512 + 8 * l;
         acc[u - U0] = mma3(xh, xl, ld8g(bh + o), ld8g(bl + o), acc[u - U0]);
       }
     }
@@ -103,7 +105,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
   f4 acc[2];
   // y1 = tanh(D F1 + c1); the D allocation has 16 spare rows, so rows >= n of the
   // last batch are read in bounds (their results are discarded)
-  mm_split2(acc, D + (size_t)a0 * ND, ND, wp.F1T[0], wp.F1T[1], ND, ND);
+  mm_split2(acc, D + (size_t)a0 * ND, ND, wp.F1T[0], wp.F1T[1], ND);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -111,7 +113,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
       for (int ii = 0; ii < 4; ++ii) y1[(4 * q + ii) * LDA + 16 * t + cl] = tanhf(acc[u][ii] + w.c1[16 * t + cl]);
   }
   __syncthreads();
-  mm_split2(acc, y1, LDA, wp.F2T[0], wp.F2T[1], KH, KH);
+  mm_split2(acc, y1, LDA, wp.F2T[0], wp.F2T[1], KH);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -126,7 +128,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
   __syncthreads();
   // y3 = tanh(y2 F3 + c3) + y2 stays in registers: E_i = y3 . F4 + c4 + ebias(t_i) as
   // per-tile partials, and dE/dpre3 = F4 (1 - t3^2) goes to X
-  mm_split2(acc, y2, LDA, wp.F3T[0], wp.F3T[1], KH, KH);
+  mm_split2(acc, y2, LDA, wp.F3T[0], wp.F3T[1], KH);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = wv + NWT * u;
@@ -154,7 +156,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
   }
   if (!backward) return;
   // dy2 = dpre3 F3^T + F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
-  mm_split2(acc, X, LDA, wp.F3[0], wp.F3[1], KH, KH);
+  mm_split2(acc, X, LDA, wp.F3[0], wp.F3[1], KH);
   __syncthreads();  // every wave has read X
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -170,7 +172,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
   }
   __syncthreads();
   // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
-  mm_split2(acc, X, LDA, wp.F2[0], wp.F2[1], KH, KH);
+  mm_split2(acc, X, LDA, wp.F2[0], wp.F2[1], KH);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -187,7 +189,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
   // dE/dD = dpre1 F1^T  (100 column tiles, in two passes over k)
   {
     f4 dacc[7];
-    mm_split_dd<0, 7>(dacc, X, LDA, wp.F1[0], wp.F1[1], KH);
+    mm_split_dd<0, 7>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
 #pragma unroll
     for (int u = 0; u < 7; ++u) {
       const int t = wv + NWT * u;
@@ -199,7 +201,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
   }
   {
     f4 dacc[6];
-    mm_split_dd<7, 13>(dacc, X, LDA, wp.F1[0], wp.F1[1], KH);
+    mm_split_dd<7, 13>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
       const int t = wv + NWT * (u + 7);
