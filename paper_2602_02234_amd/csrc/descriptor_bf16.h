@@ -179,12 +179,13 @@ __device__ __forceinline__ void mm(f4 (&acc)[NT], const bf16_t *a, int lda, cons
 // resident).  The fragments of the next k step are loaded before the products of the
 // current one are issued, so a product waits for one L2 round trip, not for one per tile.
 template <int NT>
-__device__ __forceinline__ void mm_g(f4 (&acc)[NT], const bf16_t *a, int lda, const bf16_t *__restrict__ b,
-                                     int ldb) {
+__device__ __forceinline__ void mm_g(f4 (&acc)[NT], const bf16_t *a, int lda, const bf16_t *__restrict__ bf) {
   const int l = lane(), r = l & 15, q = l >> 4;
+  // B in fragment order: tile t at bf + 1792 t, its k fragments s < 3 at + 512 s + 8 l,
+  // the k = 96..111 tail at + 1536 + 4 l
   bf8 y[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) y[t] = *(const bf8 *)(b + (16 * t + r) * ldb + 8 * q);
+  for (int t = 0; t < NT; ++t) y[t] = *(const bf8 *)(bf + 1792 * t + 8 * l);
 #pragma unroll
   for (int st = 0; st < 3; ++st) {
     const bf8 x = ld8(a + r * lda + 32 * st + 8 * q);
@@ -192,9 +193,9 @@ __device__ __forceinline__ void mm_g(f4 (&acc)[NT], const bf16_t *a, int lda, co
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (st < 2) {
-        yn[t] = *(const bf8 *)(b + (16 * t + r) * ldb + 32 * (st + 1) + 8 * q);
+        yn[t] = *(const bf8 *)(bf + 1792 * t + 512 * (st + 1) + 8 * l);
       } else {  // the k = 96..111 tail, four per lane, placed as in mma16
-        const s4 v = *(const s4 *)(b + (16 * t + r) * ldb + 96 + 4 * q);
+        const s4 v = *(const s4 *)(bf + 1792 * t + 1536 + 4 * l);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const short e = v[i];
@@ -403,7 +404,7 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
   f4 acc[7];
   zero(acc);
   if (GW)
-    mm_g<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq);  // U = G Wqk
+    mm_g<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT);  // U = G Wqk (wqkT in fragment order)
   else
     mm<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq, KM, 7);
   const bf16_t *ua;
@@ -433,7 +434,7 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
   wave_fence();
   zero(acc);
   if (GW)
-    mm_g<7>(acc, stg, LDT, wvoT, ldv);  // Y = H Wvo
+    mm_g<7>(acc, stg, LDT, wvoT);  // Y = H Wvo (wvoT in fragment order)
   else
     mm<7>(acc, stg, LDT, wvoT, ldv, KM, 7);
   wave_fence();

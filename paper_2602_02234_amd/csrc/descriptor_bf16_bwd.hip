@@ -45,7 +45,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     f4 gcur[7], sv[8], xh[7];
     float isig[4];
     load_rows(gs, gcur, jb, n);
-    layer_rows<true>(w, wp.WqkT[layer], KM, wp.WvoT[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
+    layer_rows<true>(w, wp.WqkTf[layer], KM, wp.WvoTf[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
                ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
     // incoming gradient of the layer output: for the top layer go = Rt dT^T / sel (and
     // dRt = G_out dT / sel), otherwise the gradient the layer above passed down
@@ -126,7 +126,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     wave_fence();
     f4 acc[7];
     zero(acc);
-    mm_g<7>(acc, stg, LDT, wp.Wvo[layer], KM);  // dH = dY Wvo^T
+    mm_g<7>(acc, stg, LDT, wp.Wvo[layer]);  // dH = dY Wvo^T
 #pragma unroll
     for (int t = 0; t < 7; ++t)
 #pragma unroll
@@ -205,7 +205,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     stage7(stg, acc);
     wave_fence();
     zero(acc);
-    mm_g<7>(acc, stg, LDT, wp.Wqk[layer], KM);  // dG += dU Wqk^T
+    mm_g<7>(acc, stg, LDT, wp.Wqk[layer]);  // dG += dU Wqk^T
 #pragma unroll
     for (int t = 0; t < 7; ++t) dg[b][t] += acc[t];
     wave_fence();
