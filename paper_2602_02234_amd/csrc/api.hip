@@ -337,7 +337,7 @@ size_t ws_bytes_per_atom(int prec) {
              + (size_t)SEL * sizeof(float4)               // g
              + 9 * sizeof(double)                         // vpart
              + 2 * sizeof(int);                           // backward atom lists
-  b += (size_t)NATTN * NPMAX * M * sizeof(float);  // Gsave
+  b += (size_t)NATTN * GSAVE_LAYER * sizeof(float);  // Gsave
   return b;
 }
 
@@ -386,7 +386,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.nlist, cap * SEL * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.nnei, cap * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
-    HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * NPMAX * M * sizeof(float)));
+    HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * GSAVE_LAYER * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.bidx, 2 * cap * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers

@@ -205,7 +205,7 @@ k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
   for (int layer = 0; layer < NATTN; ++layer) {
     float *Gin = sm.G[layer & 1];
     float *Gout = sm.G[(layer + 1) & 1];
-    float *gs = Gsave + ((size_t)i * NATTN + layer) * NPMAX * M;
+    float *gs = Gsave + ((size_t)i * NATTN + layer) * GSAVE_LAYER;
     for (int q = threadIdx.x; q < NP * M; q += NTHREADS) gs[q] = Gin[(q / M) * LDM + q % M];
     for (int jb = 0; jb < nb; ++jb) {
       attn_block_front(w, layer, sm.e, Gin, jb, n, NP, sm.Ub, nullptr, sm.Ab, sm.Hb, sm.red);
@@ -293,7 +293,7 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
   const float inv_sel = 1.f / (float)SEL;
 
   for (int layer = NATTN - 1; layer >= 0; --layer) {
-    const float *gs = Gsave + ((size_t)i * NATTN + layer) * NPMAX * M;
+    const float *gs = Gsave + ((size_t)i * NATTN + layer) * GSAVE_LAYER;
     for (int q = threadIdx.x; q < NP * M; q += NTHREADS) sm.Gin[(q / M) * LDM + q % M] = gs[q];
     __syncthreads();
     f4 colacc[7];

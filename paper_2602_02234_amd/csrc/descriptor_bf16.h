@@ -466,30 +466,27 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
   }
 }
 
-// The fp32 rows j < n of the wave's block (tiles gv) to dst [NPMAX][M] (one layer input).
-__device__ __forceinline__ void save_rows(float *__restrict__ dst, const f4 (&gv)[7], int jb, int n) {
-  const int l = lane(), q = l >> 4, cl = l & 15;
-  const int j0 = jb * 16 + 4 * q;
-  float *p = dst + (size_t)j0 * M + cl;
+// One layer input, saved for the backward in the accumulator layout of the row blocks:
+// block jb at dst + 1792 jb, its tile t at + 256 t, lane l's four values at + 4 l, so
+// each tile is one 1 KB contiguous access per wave.  Rows j >= n and features m >= M are
+// stored as they are and masked on reading.
+__device__ __forceinline__ void save_rows(float *__restrict__ dst, const f4 (&gv)[7], int jb) {
+  float *p = dst + 1792 * jb + 4 * lane();
 #pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
-    if (j0 + ii < n) {
-#pragma unroll
-      for (int t = 0; t < 7; ++t)
-        if (t < 6 || cl < M - 96) p[ii * M + 16 * t] = gv[t][ii];
-    }
+  for (int t = 0; t < 7; ++t) *(f4 *)(p + 256 * t) = gv[t];
 }
 
-// Reads those rows back (rows j >= n, which never reach a valid token, as zero).
+// Reads those rows back (rows j >= n, which never reach a valid token, and features
+// m >= M as zero).
 __device__ __forceinline__ void load_rows(const float *__restrict__ src, f4 (&gv)[7], int jb, int n) {
   const int l = lane(), q = l >> 4, cl = l & 15;
   const int j0 = jb * 16 + 4 * q;
-  const float *p = src + (size_t)j0 * M + cl;
+  const float *p = src + 1792 * jb + 4 * l;
 #pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const bool ok = j0 + ii < n;
+  for (int t = 0; t < 7; ++t) {
+    const f4 v = *(const f4 *)(p + 256 * t);
 #pragma unroll
-    for (int t = 0; t < 7; ++t) gv[t][ii] = (ok && (t < 6 || cl < M - 96)) ? p[ii * M + 16 * t] : 0.f;
+    for (int ii = 0; ii < 4; ++ii) gv[t][ii] = (j0 + ii < n && (t < 6 || cl < M - 96)) ? v[ii] : 0.f;
   }
 }
 

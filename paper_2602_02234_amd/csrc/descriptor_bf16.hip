@@ -48,7 +48,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     stage_weights(sm.W[1], LDW, wp.WvoT[layer], KM, KM, KM);
     f4 sv[8], xh[7];
     float isig[4];
-    if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * NPMAX * M, gv, jb, n);
+    if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * GSAVE_LAYER, gv, jb);
     __syncthreads();
     if (act)
       layer_rows<false>(w, sm.W[0], LDW, sm.W[1], LDW, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv,

@@ -404,8 +404,8 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     for (int ch = 0; ch < NW; ++ch) acc += part[64 * ch + threadIdx.x];
     sm.dT[threadIdx.x] = acc;
   }
-  const float *gs0 = Gsave + (size_t)i * NATTN * NPMAX * M;
-  const float *gs1 = gs0 + (size_t)NPMAX * M;
+  const float *gs0 = Gsave + (size_t)i * NATTN * GSAVE_LAYER;
+  const float *gs1 = gs0 + GSAVE_LAYER;
   stage_layer_input<NW, BPW>(sm, gs1, n, nb);
   __syncthreads();
   f4 dg[BPW][7];

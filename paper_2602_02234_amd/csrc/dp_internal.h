@@ -110,7 +110,7 @@ struct Workspace {
   int *nlist = nullptr;       // [cap][SEL]
   int *nnei = nullptr;        // [cap]
   int *rev = nullptr;         // [cap][SEL]
-  float *Gsave = nullptr;     // [cap][NATTN][NPMAX][M]  inputs of each attention layer
+  float *Gsave = nullptr;     // [cap][NATTN][GSAVE_LAYER]  inputs of each attention layer
   float *Tsave = nullptr;     // [cap][M][4]
   int *bidx = nullptr;        // [2][cap]  atoms of each backward kernel instance (bf16 path)
   int *bcnt = nullptr;        // [2]
