@@ -494,14 +494,35 @@ constexpr int LDW = 120;  // LDS row stride of the staged weights (k contiguous)
 constexpr int LD2 = 40;   // ... of the staged W2^T [64][32]
 constexpr int LD3 = 72;   // ... of the staged W3^T [112][64]
 
-// Workgroup copy of a [rows][cols] bf16 matrix (cols a multiple of 8, row stride gld in
-// global memory) into LDS with row stride lld, in 16-byte pieces.
-__device__ __forceinline__ void stage_weights(bf16_t *dst, int lld, const bf16_t *__restrict__ src, int gld, int rows,
-                                              int cols) {
-  const int per = cols / 8;
-  for (int x = threadIdx.x; x < rows * per; x += blockDim.x) {
-    const int r = x / per, c = 8 * (x % per);
-    *(bf8 *)(dst + r * lld + c) = *(const bf8 *)(src + (size_t)r * gld + c);
+// Workgroup copy of two bf16 matrices, [R0][C0] and [R1][C1] (columns multiples of 8,
+// row strides g0, g1 in global memory), into LDS with row strides l0, l1, by NTHR
+// threads in 16-byte pieces.  Every load of a thread is issued before its first store,
+// so the copy costs one L2 round trip.
+template <int R0, int C0, int R1, int C1, int NTHR>
+__device__ __forceinline__ void stage_weights2(bf16_t *d0, int l0, const bf16_t *__restrict__ s0, int g0, bf16_t *d1,
+                                               int l1, const bf16_t *__restrict__ s1, int g1) {
+  constexpr int P0 = C0 / 8, T0 = R0 * P0, N0 = (T0 + NTHR - 1) / NTHR;
+  constexpr int P1 = C1 / 8, T1 = R1 * P1, N1 = (T1 + NTHR - 1) / NTHR;
+  bf8 v0[N0], v1[N1];
+#pragma unroll
+  for (int c = 0; c < N0; ++c) {
+    const int x = threadIdx.x + c * NTHR;
+    if (x < T0) v0[c] = *(const bf8 *)(s0 + (size_t)(x / P0) * g0 + 8 * (x % P0));
+  }
+#pragma unroll
+  for (int c = 0; c < N1; ++c) {
+    const int x = threadIdx.x + c * NTHR;
+    if (x < T1) v1[c] = *(const bf8 *)(s1 + (size_t)(x / P1) * g1 + 8 * (x % P1));
+  }
+#pragma unroll
+  for (int c = 0; c < N0; ++c) {
+    const int x = threadIdx.x + c * NTHR;
+    if (x < T0) *(bf8 *)(d0 + (x / P0) * l0 + 8 * (x % P0)) = v0[c];
+  }
+#pragma unroll
+  for (int c = 0; c < N1; ++c) {
+    const int x = threadIdx.x + c * NTHR;
+    if (x < T1) *(bf8 *)(d1 + (x / P1) * l1 + 8 * (x % P1)) = v1[c];
   }
 }
 

@@ -30,8 +30,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
   build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
   bf16_t *w2s = sm.W[0], *w3s = sm.W[0] + 64 * LD2;
-  stage_weights(w2s, LD2, wp.W2T, 32, 64, 32);
-  stage_weights(w3s, LD3, wp.W3T, 64, KM, 64);
+  stage_weights2<64, 32, KM, 64, NWF * 64>(w2s, LD2, wp.W2T, 32, w3s, LD3, wp.W3T, 64);
   __syncthreads();
   const bool act = wv < nb;
   const int jb = wv;
@@ -44,8 +43,11 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   }
   for (int layer = 0; layer < NATTN; ++layer) {
     __syncthreads();
-    stage_weights(sm.W[0], LDW, wp.WqkT[layer], KM, KM, KM);
-    stage_weights(sm.W[1], LDW, wp.WvoT[layer], KM, KM, KM);
+    // each matrix as two column halves (this form needs no scratch registers here)
+    stage_weights2<KM, KM / 2, KM, KM / 2, NWF * 64>(sm.W[0], LDW, wp.WqkT[layer], KM, sm.W[0] + KM / 2, LDW,
+                                                     wp.WqkT[layer] + KM / 2, KM);
+    stage_weights2<KM, KM / 2, KM, KM / 2, NWF * 64>(sm.W[1], LDW, wp.WvoT[layer], KM, sm.W[1] + KM / 2, LDW,
+                                                     wp.WvoT[layer] + KM / 2, KM);
     f4 sv[8], xh[7];
     float isig[4];
     if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * GSAVE_LAYER, gv, jb);

@@ -419,14 +419,12 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   layer_bwd<NW, BPW>(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg);
   // the embedding weights of the larger products into LDS (Uall is free now)
   bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
-  stage_weights(w3Ts, LD3, wp.W3T, 64, KM, 64);
-  stage_weights(w3s, KM, wp.W3, KM, 64, KM);
+  stage_weights2<KM, 64, 64, KM, NW * 64>(w3Ts, LD3, wp.W3T, 64, w3s, KM, wp.W3, KM);
   bf16_t *w2Ts = sm.Gb, *w2s = sm.Gb + 64 * LD2;  // Gb is free as well
   static_assert(NW <= 7 && 4 * 16 * 104 * 4 <= KM * LDT * 2 &&
                     (64 * LD2 + 32 * LD3) * 2 + (NW > 4 ? NW - 4 : 0) * 16 * 104 * 4 <= NPMAX * LDK * 2,
                 "per-wave fp32 scratch of the embedding backward must fit in GbT and the rest of Gb");
-  stage_weights(w2Ts, LD2, wp.W2T, 32, 64, 32);
-  stage_weights(w2s, LD3, wp.W2, 64, 32, 64);
+  stage_weights2<64, 32, 32, 64, NW * 64>(w2Ts, LD2, wp.W2T, 32, w2s, LD3, wp.W2, 64);
   __syncthreads();
   // embedding backward and the pair gradients of the wave's rows
 #pragma unroll
