@@ -467,13 +467,16 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
 }
 
 // One layer input, saved for the backward in the accumulator layout of the row blocks:
-// block jb at dst + 1792 jb, its tile t at + 256 t, lane l's four values at + 4 l, so
-// each tile is one 1 KB contiguous access per wave.  Rows j >= n and features m >= M are
-// stored as they are and masked on reading.
+// block jb at dst + 1600 jb, its tiles t < 6 at + 256 t with lane l's four values at
+// + 4 l, and the four real features of tile 6 (lanes with l % 16 < 4) at
+// + 1536 + 4 (4 (l / 16) + l % 16); each tile is one contiguous access per wave.  Rows
+// j >= n of the block are stored as they are and masked on reading.
 __device__ __forceinline__ void save_rows(float *__restrict__ dst, const f4 (&gv)[7], int jb) {
-  float *p = dst + 1792 * jb + 4 * lane();
+  const int l = lane(), q = l >> 4, cl = l & 15;
+  float *p = dst + 1600 * jb;
 #pragma unroll
-  for (int t = 0; t < 7; ++t) *(f4 *)(p + 256 * t) = gv[t];
+  for (int t = 0; t < 6; ++t) *(f4 *)(p + 256 * t + 4 * l) = gv[t];
+  if (cl < M - 96) *(f4 *)(p + 1536 + 4 * (4 * q + cl)) = gv[6];
 }
 
 // Reads those rows back (rows j >= n, which never reach a valid token, and features
@@ -481,12 +484,14 @@ __device__ __forceinline__ void save_rows(float *__restrict__ dst, const f4 (&gv
 __device__ __forceinline__ void load_rows(const float *__restrict__ src, f4 (&gv)[7], int jb, int n) {
   const int l = lane(), q = l >> 4, cl = l & 15;
   const int j0 = jb * 16 + 4 * q;
-  const float *p = src + 1792 * jb + 4 * l;
+  const float *p = src + 1600 * jb;
 #pragma unroll
   for (int t = 0; t < 7; ++t) {
-    const f4 v = *(const f4 *)(p + 256 * t);
+    f4 v = f4{0.f, 0.f, 0.f, 0.f};
+    if (t < 6) v = *(const f4 *)(p + 256 * t + 4 * l);
+    else if (cl < M - 96) v = *(const f4 *)(p + 1536 + 4 * (4 * q + cl));
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii) gv[t][ii] = (j0 + ii < n && (t < 6 || cl < M - 96)) ? v[ii] : 0.f;
+    for (int ii = 0; ii < 4; ++ii) gv[t][ii] = j0 + ii < n ? v[ii] : 0.f;
   }
 }
 

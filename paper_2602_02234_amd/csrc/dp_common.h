@@ -19,8 +19,7 @@ constexpr int ND = M * M2;   // descriptor length 1600
 constexpr int FH = 240;      // fitting width
 constexpr int SEL = 120;     // neighbour capacity
 constexpr int NPMAX = 128;   // tokens per atom after padding to a multiple of 16
-constexpr int GSAVE_LAYER = (NPMAX / 16) * 7 * 256;  // floats per atom and layer of the saved layer inputs
-static_assert(GSAVE_LAYER >= NPMAX * M, "the saved-input slot holds either layout");
+constexpr int GSAVE_LAYER = NPMAX * M;  // floats per atom and layer of the saved layer inputs
 
 // ---------------------------------------------------------------- LDS strides
 constexpr int LDM = 104;     // row stride (floats) of [token][M] arrays
