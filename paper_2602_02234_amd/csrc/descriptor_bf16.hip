@@ -59,31 +59,29 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     if (act) put_rows(sm.Gb, sm.GbT, gv, jb);
   }
   __syncthreads();
-  // T = G^T Rt / sel: per-wave partial over its rows, then a fixed-order sum over waves
+  // T = G^T Rt / sel: per-wave partial over its rows, then a fixed-order sum over waves.
+  // The partial is four fp32 MFMAs per feature tile: A = the wave's G rows 4q + ii
+  // straight from the accumulator registers (lane (q, c) holds G[4q + ii][16t + c], i.e.
+  // A[c][q]), B[q][c] = Rt[4q + ii][c] for c < 4; lane (q, c) ends with T[16t + 4q + r][c].
   float *tp = (float *)sm.stg[wv];
   if (act) {
-    float rt[4][4];
+    f4 tacc[7];
+    zero(tacc);
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int j = jb * 16 + 4 * q + ii;
       const float sj = (j < n) ? sm.e.s[j] : 0.f;
-      rt[ii][0] = sj;
+      const float rt = cl == 0 ? sj : (cl < 4 ? sj * sm.e.rh[3 * j + cl - 1] : 0.f);
 #pragma unroll
-      for (int c = 1; c < 4; ++c) rt[ii][c] = sj * sm.e.rh[3 * j + c - 1];
+      for (int t = 0; t < 7; ++t) tacc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t][ii], rt, tacc[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < 7; ++t) {
-      const int m = 16 * t + cl;
+    for (int t = 0; t < 7; ++t)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float p = 0.f;
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) p += gv[t][ii] * rt[ii][c];
-        p += __shfl_xor(p, 16);
-        p += __shfl_xor(p, 32);
-        if (q == 0 && m < M) tp[m * 4 + c] = p;
+      for (int r = 0; r < 4; ++r) {
+        const int m = 16 * t + 4 * q + r;
+        if (cl < 4 && m < M) tp[m * 4 + cl] = tacc[t][r];
       }
-    }
   }
   __syncthreads();
   float *T = (float *)sm.GbT;
