@@ -96,6 +96,25 @@ def test_open_cluster_matches_oracle(gpu_models, omodel, prec):
     assert_within(m, prec)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_dense_cluster_matches_oracle(gpu_models, omodel, prec):
+    """130 atoms in an 8 A cube: 3 to 8 blocks of 16 neighbours per atom, so the BF16
+    backward runs both of its instances in one call (up to 7 blocks: 7 waves, one block
+    each; 8 blocks: 4 waves, two blocks each).  Forces here have RMS ~3 eV/A; the force
+    bounds, stated for forces of RMS 1 eV/A, are applied to F / RMS(F_oracle)."""
+    gpu = gpu_models[prec]
+    X, t = _cluster(130, 11, spread=4.0)
+    _, nn, _ = neighbor_list_bruteforce(X, None, gpu.rc, gpu.sel)
+    nb = (np.maximum(nn, 1) + 15) // 16
+    assert (nb == 8).sum() >= 5 and (nb <= 7).sum() >= 50
+    ref = evaluate(omodel, X, t, None)
+    out = gpu.compute(X, t, None, atom_energy=True)
+    s = float(np.sqrt(np.mean(ref["F"] ** 2)))
+    m = compare(dict(out, F=out["F"] / s), dict(ref, F=ref["F"] / s), len(t))
+    print(prec, "force rms", s, m)
+    assert_within(m, prec)
+
+
 def test_sparse_atoms_and_isolated_atom(gpu_fp32, omodel):
     """Atoms with 0, 1 and 2 neighbours (single-token attention, empty descriptor)."""
     X = np.array([[0.0, 0.0, 0.0], [1.2, 0.3, -0.4], [30.0, 0.0, 0.0], [33.5, 1.0, 0.0], [31.0, 2.5, 1.0],
