@@ -123,7 +123,7 @@ __device__ __forceinline__ float ftanh(float x) {
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_sched_barrier(0);
-  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): LDS done; global loads may stay in flight
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_sched_barrier(0);
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");

@@ -26,15 +26,17 @@ template <int NW> struct __align__(16) SmemB16 {
 };
 
 // Backward of one layer for the wave's blocks, from the layer input saved by the forward
-// kernel (gs, fp32 rows j < n).  dg: on entry the gradient w.r.t. the layer output
+// kernel (gin: the wave's fp32 rows, j >= n zero).  If gs_next is given, the next
+// layer's saved input rows are loaded into gin before the column pass, so that their
+// latency overlaps it.  dg: on entry the gradient w.r.t. the layer output
 // (ignored for the top layer, whose output gradient is Rt dT^T / sel), on exit w.r.t.
 // the layer input.  The column pass also adds, for the wave's own token columns k, the
 // column sums over every query row of the softmax-weight gradient W_jk (to dswa[k]) and
 // of the gate gradient dC_jk rhat_j (to drh[k]).
 template <int NW, int BPW>
 __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top,
-                                       SmemB16<NW> &sm, const float *__restrict__ gs, int n, int nb, int NP, float ln_eps,
-                                       f4 (&dg)[BPW][7]) {
+                                       SmemB16<NW> &sm, f4 (&gin)[BPW][7], const float *__restrict__ gs_next, int n,
+                                       int nb, int NP, float ln_eps, f4 (&dg)[BPW][7]) {
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
   bf16_t *stg = sm.stg[wv];
   const float inv_sel = 1.f / (float)SEL;
@@ -44,7 +46,8 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     if (jb >= nb) continue;
     f4 gcur[7], sv[8], xh[7];
     float isig[4];
-    load_rows(gs, gcur, jb, n);
+#pragma unroll
+    for (int t = 0; t < 7; ++t) gcur[t] = gin[b][t];
     layer_rows<true>(w, wp.WqkTf[layer], KM, wp.WvoTf[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
                ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
     // incoming gradient of the layer output: for the top layer go = Rt dT^T / sel (and
@@ -210,6 +213,11 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     for (int t = 0; t < 7; ++t) dg[b][t] += acc[t];
     wave_fence();
   }
+  if (gs_next) {
+#pragma unroll
+    for (int b = 0; b < BPW; ++b)
+      if (wv + NW * b < nb) load_rows(gs_next, gin[b], wv + NW * b, n);
+  }
   __syncthreads();
   // column pass: dG[k] += sum_j A_jk dH_j + dS_jk U_j for the wave's own token blocks
   // (kb = wave and wave + NW); the U / dH rows of each block jb are gathered once for both
@@ -335,17 +343,13 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
 }
 
 // Puts the saved layer input rows (fp32 -> bf16) of the wave's blocks into Gb / GbT.
+// The wave's layer input rows (bf16) into Gb and GbT.
 template <int NW, int BPW>
-__device__ __forceinline__ void stage_layer_input(SmemB16<NW> &sm, const float *__restrict__ gs, int n, int nb) {
+__device__ __forceinline__ void put_layer_input(SmemB16<NW> &sm, const f4 (&gin)[BPW][7], int nb) {
   const int wv = wave_id();
 #pragma unroll
-  for (int b = 0; b < BPW; ++b) {
-    const int jb = wv + NW * b;
-    if (jb >= nb) continue;
-    f4 gv[7];
-    load_rows(gs, gv, jb, n);
-    put_rows(sm.Gb, sm.GbT, gv, jb);
-  }
+  for (int b = 0; b < BPW; ++b)
+    if (wv + NW * b < nb) put_rows(sm.Gb, sm.GbT, gin[b], wv + NW * b);
 }
 
 // NW waves per workgroup, each owning BPW row blocks (wave w owns blocks w, w + NW, ...);
@@ -367,6 +371,14 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int nb = NP / 16;
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
+  // the top layer's saved input rows of the wave's blocks, loaded first so that their
+  // latency overlaps the environment and dT work
+  const float *gs0 = Gsave + (size_t)i * NATTN * GSAVE_LAYER;
+  const float *gs1 = gs0 + GSAVE_LAYER;
+  f4 gin[BPW][7];
+#pragma unroll
+  for (int b = 0; b < BPW; ++b)
+    if (wv + NW * b < nb) load_rows(gs1, gin[b], wv + NW * b, n);
   // dT = dE/dT from dE/dD (D = T T<^T): dT[m] = sum_a dD[m][a] T[a] + [m < M2] sum_m' dD[m'][m] T[m'];
   // staging is free until the first layer: T [100][4], dE/dD [1600], partial sums [NW * 64]
   float *T = (float *)sm.stg[0];
@@ -404,19 +416,17 @@ k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     for (int ch = 0; ch < NW; ++ch) acc += part[64 * ch + threadIdx.x];
     sm.dT[threadIdx.x] = acc;
   }
-  const float *gs0 = Gsave + (size_t)i * NATTN * GSAVE_LAYER;
-  const float *gs1 = gs0 + GSAVE_LAYER;
-  stage_layer_input<NW, BPW>(sm, gs1, n, nb);
+  put_layer_input<NW, BPW>(sm, gin, nb);
   __syncthreads();
   f4 dg[BPW][7];
 #pragma unroll
   for (int b = 0; b < BPW; ++b)
 #pragma unroll
     for (int t = 0; t < 7; ++t) dg[b][t] = f4{0.f, 0.f, 0.f, 0.f};
-  layer_bwd<NW, BPW>(w, wp, 1, true, sm, gs1, n, nb, NP, ln_eps, dg);
-  stage_layer_input<NW, BPW>(sm, gs0, n, nb);
+  layer_bwd<NW, BPW>(w, wp, 1, true, sm, gin, gs0, n, nb, NP, ln_eps, dg);
+  put_layer_input<NW, BPW>(sm, gin, nb);
   __syncthreads();
-  layer_bwd<NW, BPW>(w, wp, 0, false, sm, gs0, n, nb, NP, ln_eps, dg);
+  layer_bwd<NW, BPW>(w, wp, 0, false, sm, gin, nullptr, n, nb, NP, ln_eps, dg);
   // the embedding weights of the larger products into LDS (Uall is free now)
   bf16_t *w3Ts = sm.Uall, *w3s = sm.Uall + KM * LD3;
   stage_weights2<KM, 64, 64, KM, NW * 64>(w3Ts, LD3, wp.W3T, 64, w3s, KM, wp.W3, KM);
