@@ -239,8 +239,7 @@ int build_weights(dp_model *m, const HostModel &h) {
           vo[(size_t)r * M + c] = s2;
         }
       auto at = [](const std::vector<double> &v, int r, int c) { return (r < M && c < M) ? v[(size_t)r * M + c] : 0.0; };
-      // the products that read these from global memory take them in MFMA fragment
-      // order: per 16-column tile, three 32-k fragments of 64 lanes x 8 values (lane l:
+      // the attention products read these from global memory, in MFMA fragment order: per 16-column tile, three 32-k fragments of 64 lanes x 8 values (lane l:
       // row l % 16, k = 32 s + 8 (l / 16) ..), then the k = 96..111 tail as 64 lanes x 4
       auto frag112 = [](const std::vector<float> &v) {
         std::vector<float> o(v.size());
@@ -255,12 +254,10 @@ int build_weights(dp_model *m, const HostModel &h) {
       };
       const auto qkT = mat(112, 112, [&](int c, int k) { return at(qk, k, c); });
       const auto voT = mat(112, 112, [&](int c, int k) { return at(vo, k, c); });
-      op.push_back(hi_lo(qkT, 0));
-      op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(qk, c, k); })), 0));
-      op.push_back(hi_lo(voT, 0));
-      op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(vo, c, k); })), 0));
       op.push_back(hi_lo(frag112(qkT), 0));
+      op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(qk, c, k); })), 0));
       op.push_back(hi_lo(frag112(voT), 0));
+      op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(vo, c, k); })), 0));
     }
     auto F = [&](const std::vector<double> &v, int ld, int r, int c) { return v[(size_t)r * ld + c]; };
     const auto f1t = mat(FH, ND, [&](int c, int k) { return F(h.F1, FH, k, c); });
@@ -301,7 +298,7 @@ int build_weights(dp_model *m, const HostModel &h) {
     WeightsB16 &w = m->wp;
     w.W2T = P(); w.W3T = P(); w.W3 = P(); w.W2 = P();
     for (int a = 0; a < NATTN; ++a) {
-      w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P(); w.WqkTf[a] = P(); w.WvoTf[a] = P();
+      w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P();
     }
     w.F1T[0] = P(); w.F1T[1] = P(); w.F1[0] = P(); w.F1[1] = P();
     w.F2T[0] = P(); w.F2T[1] = P(); w.F2[0] = P(); w.F2[1] = P();

@@ -394,19 +394,16 @@ __device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
 
 // One attention layer forward for the wave's rows: gv (G_in, fp32) -> gv (G_out).
 // Also returns xh (normalised residual) and isig (1/sigma per accumulator row).
-// If Uall is given, U rows are written there (and read from there for S).
-template <bool GW>
-__device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq, const bf16_t *wvoT, int ldv, int layer,
+// If Uall is given, U rows are written there (and read from there for S).  The weight
+// operands wqkT and wvoT are read from global memory in MFMA fragment order.
+__device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, const bf16_t *wvoT, int layer,
                            const EnvB &e, const bf16_t *Gb,
                            const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
                            f4 (&gv)[7], f4 (&sv)[8], f4 (&xh)[7], float (&isig)[4], float *rmax, float *rz) {
   const int l = lane(), q = l >> 4, cl = l & 15;
   f4 acc[7];
   zero(acc);
-  if (GW)
-    mm_g<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT);  // U = G Wqk (wqkT in fragment order)
-  else
-    mm<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT, ldq, KM, 7);
+  mm_g<7>(acc, Gb + jb * 16 * LDK, LDK, wqkT);  // U = G Wqk
   const bf16_t *ua;
   int lda;
   if (Uall) {
@@ -433,10 +430,7 @@ __device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, int ldq
   stage7(stg, acc);
   wave_fence();
   zero(acc);
-  if (GW)
-    mm_g<7>(acc, stg, LDT, wvoT);  // Y = H Wvo (wvoT in fragment order)
-  else
-    mm<7>(acc, stg, LDT, wvoT, ldv, KM, 7);
+  mm_g<7>(acc, stg, LDT, wvoT);  // Y = H Wvo
   wave_fence();
   // X = G + Y;  G <- gamma (X - mu) / sigma + beta
 #pragma unroll
@@ -495,7 +489,6 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ src, f4 (&gv
   }
 }
 
-constexpr int LDW = 120;  // LDS row stride of the staged weights (k contiguous)
 constexpr int LD2 = 40;   // ... of the staged W2^T [64][32]
 constexpr int LD3 = 72;   // ... of the staged W3^T [112][64]
 

@@ -1,7 +1,7 @@
 // Forward descriptor kernel of the bfloat16 path: one workgroup (8 waves) per atom.
-// Environment, type-embedded embedding net, two attention layers (each layer's
-// weights staged in LDS), T = G^T Rt / sel and D = T T_<16^T; the input rows of each
-// attention layer are saved (fp32, rows < n) for the backward kernel.
+// Environment, type-embedded embedding net (its weights staged in LDS), two attention
+// layers (their weights read from L2 in MFMA fragment order), T = G^T Rt / sel and
+// D = T T_<16^T; the input rows of each attention layer are saved for the backward.
 #include "descriptor_bf16.h"
 
 namespace dp {
@@ -11,7 +11,7 @@ struct __align__(16) SmemF16 {
   bf16_t Gb[NPMAX * LDK];
   bf16_t GbT[KM * LDT];
   bf16_t stg[NWF][16 * LDT];
-  bf16_t W[2][KM * LDW];  // the current stage's weights: W2^T and W3^T, then Wqk^T and Wvo^T of a layer
+  bf16_t Wemb[64 * LD2 + KM * LD3];  // the embedding's W2^T and W3^T
   EnvB e;
 };
 
@@ -29,7 +29,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
   build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
-  bf16_t *w2s = sm.W[0], *w3s = sm.W[0] + 64 * LD2;
+  bf16_t *w2s = sm.Wemb, *w3s = sm.Wemb + 64 * LD2;
   stage_weights2<64, 32, KM, 64, NWF * 64>(w2s, LD2, wp.W2T, 32, w3s, LD3, wp.W3T, 64);
   __syncthreads();
   const bool act = wv < nb;
@@ -42,20 +42,15 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
     put_rows(sm.Gb, sm.GbT, gv, jb);
   }
   for (int layer = 0; layer < NATTN; ++layer) {
-    __syncthreads();
-    // each matrix as two column halves (this form needs no scratch registers here)
-    stage_weights2<KM, KM / 2, KM, KM / 2, NWF * 64>(sm.W[0], LDW, wp.WqkT[layer], KM, sm.W[0] + KM / 2, LDW,
-                                                     wp.WqkT[layer] + KM / 2, KM);
-    stage_weights2<KM, KM / 2, KM, KM / 2, NWF * 64>(sm.W[1], LDW, wp.WvoT[layer], KM, sm.W[1] + KM / 2, LDW,
-                                                     wp.WvoT[layer] + KM / 2, KM);
+    __syncthreads();  // Gb and GbT hold the layer input
     f4 sv[8], xh[7];
     float isig[4];
-    if (act) save_rows(Gsave + ((size_t)i * NATTN + layer) * GSAVE_LAYER, gv, jb);
-    __syncthreads();
-    if (act)
-      layer_rows<false>(w, sm.W[0], LDW, sm.W[1], LDW, layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv,
+    if (act) {
+      save_rows(Gsave + ((size_t)i * NATTN + layer) * GSAVE_LAYER, gv, jb);
+      layer_rows(w, wp.WqkT[layer], wp.WvoT[layer], layer, sm.e, sm.Gb, sm.GbT, stg, nullptr, jb, n, nb, NP, ln_eps, gv,
                  sv, xh, isig, nullptr, nullptr);
-    __syncthreads();
+    }
+    __syncthreads();  // every wave is done reading them
     if (act) put_rows(sm.Gb, sm.GbT, gv, jb);
   }
   __syncthreads();

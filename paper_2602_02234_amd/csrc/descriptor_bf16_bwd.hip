@@ -48,7 +48,7 @@ __device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const Weight
     float isig[4];
 #pragma unroll
     for (int t = 0; t < 7; ++t) gcur[t] = gin[b][t];
-    layer_rows<true>(w, wp.WqkTf[layer], KM, wp.WvoTf[layer], KM, layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
+    layer_rows(w, wp.WqkT[layer], wp.WvoT[layer], layer, sm.e, sm.Gb, sm.GbT, stg, sm.Uall, jb, n, nb, NP,
                ln_eps, gcur, sv, xh, isig, sm.rmax, sm.rz);
     // incoming gradient of the layer output: for the top layer go = Rt dT^T / sel (and
     // dRt = G_out dT / sel), otherwise the gradient the layer above passed down

@@ -74,12 +74,11 @@ struct WeightsB16 {
   const bf16_t *W3T;           // [112][64]   W3T[m][k] = W3[k][m]
   const bf16_t *W3;            // [64][112]   W3[c][m]
   const bf16_t *W2;            // [32][64]    W2[e1][e2]
-  const bf16_t *WqkT[NATTN];   // [112][112]  WqkT[c][k] = Wqk[k][c]
-  const bf16_t *Wqk[NATTN];    // [112][112]  in MFMA fragment order (see mm_g)
-  const bf16_t *WvoT[NATTN];   // [112][112]
-  const bf16_t *Wvo[NATTN];    // [112][112]  fragment order
-  const bf16_t *WqkTf[NATTN];  // WqkT in fragment order
-  const bf16_t *WvoTf[NATTN];  // WvoT in fragment order
+  // attention weights, [112][112] each, in MFMA fragment order (see mm_g)
+  const bf16_t *WqkT[NATTN];   // WqkT[c][k] = Wqk[k][c]
+  const bf16_t *Wqk[NATTN];
+  const bf16_t *WvoT[NATTN];
+  const bf16_t *Wvo[NATTN];
   // fitting operands, hi and lo parts, in MFMA fragment order (fragment (t, s) of a
   // [cols][K] matrix at ((t * K / 32 + s) * 64 + lane) * 8)
   const bf16_t *F1T[2];        // [240][1600]
