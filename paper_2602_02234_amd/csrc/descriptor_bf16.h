@@ -14,8 +14,9 @@
 //    feature-major (GbT), so that every MFMA fragment -- whichever index is the
 //    reduction index -- is one 16-byte load; the fp32 master copy of the wave's
 //    own rows stays in registers (residual and LayerNorm in fp32);
-//  * weights come pre-padded and k-contiguous from global memory (L2-resident) or
-//    are staged in LDS;
+//  * the attention weights are read from global memory (L2-resident), pre-padded and
+//    in MFMA fragment order, so a wave's fragment load is 1 KB of whole cache lines;
+//    the small embedding weights are staged in LDS;
 //  * feature width 100 is padded to 112 and contracted as 3 x 32 + 16 along k.
 //
 // lane() is the lane index.  A translation unit that defines DP_BF16_OPAQUE_LANE
@@ -118,8 +119,8 @@ __device__ __forceinline__ float ftanh(float x) {
 }
 
 // Orders this wave's LDS accesses across a point (the wave reuses its staging buffer):
-// the wave's outstanding memory operations are drained and no instruction is moved
-// across the point.
+// the wave's outstanding LDS operations are drained and no instruction is moved across
+// the point; global loads may stay in flight (their users wait for them as usual).
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_sched_barrier(0);
