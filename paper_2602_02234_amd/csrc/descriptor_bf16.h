@@ -252,13 +252,14 @@ __device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)
 #pragma unroll
   for (int t = 0; t < 7; ++t) {
     const int m = 16 * t + cl;
+    s4 col;  // the lane's four rows of feature m, consecutive in GbT: one 8-byte store
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
-      const int j = jb * 16 + 4 * q + ii;
       const bf16_t v = (bf16_t)(m < M ? gv[t][ii] : 0.f);
-      Gb[j * LDK + m] = v;
-      GbT[m * LDT + j] = v;
+      Gb[(jb * 16 + 4 * q + ii) * LDK + m] = v;
+      col[ii] = __builtin_bit_cast(short, v);
     }
+    *(s4 *)(GbT + m * LDT + jb * 16 + 4 * q) = col;
   }
 }
 
