@@ -71,6 +71,15 @@ enum {
 int dp_model_load(const char *path, int precision, int device, dp_model **out);
 void dp_model_free(dp_model *m);
 
+/* Host-only check of a model file; makes no HIP call, so it runs without a GPU.
+ * Reads the file, builds the weight image dp_model_load would upload for
+ * `precision`, points the kernels' weight structures into it and checks that
+ * every pointer the kernels of that precision read is set and lies inside the
+ * image (DP_ERR_MODEL_FILE naming the member otherwise).  unbind, when not NULL,
+ * names one member to clear before the check (a self-test of the check itself).
+ * *image_bytes (may be NULL) receives the size of the device weight image. */
+int dp_check_model_file(const char *path, int precision, const char *unbind, size_t *image_bytes);
+
 /* Cutoff rc (Angstrom), neighbour capacity sel, number of atom types. Any
  * output pointer may be NULL. */
 int dp_model_info(const dp_model *m, double *rc, int *sel, int *ntypes);

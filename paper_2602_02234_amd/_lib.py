@@ -26,6 +26,7 @@ _I64 = C.c_int64
 SIGNATURES = {
     "dp_model_load": (C.c_int, [C.c_char_p, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
     "dp_model_free": (None, [_P]),
+    "dp_check_model_file": (C.c_int, [C.c_char_p, C.c_int, C.c_char_p, C.POINTER(C.c_size_t)]),
     "dp_model_info": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "dp_compute": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "dp_compute_device": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),

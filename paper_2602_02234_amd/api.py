@@ -41,6 +41,9 @@ class Model:
         check(lib.dp_model_info(h, C.byref(rc), C.byref(sel), C.byref(nt)), "dp_model_info")
         self.rc, self.sel, self.ntypes = rc.value, sel.value, nt.value
         self.last_status = 0
+        # counts calls that replace the model's saved forward state; an autograd
+        # backward compares it with the count its own forward left
+        self.calls = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -56,6 +59,7 @@ class Model:
     # ---------------------------------------------------------------- host buffers
     def compute(self, coords, types, box=None, forces: bool = True, atom_energy: bool = False):
         """E (eV), F [N][3] (eV/A), virial [3][3] (eV) and optionally E_i, from host arrays."""
+        self.calls += 1
         X = np.ascontiguousarray(coords, dtype=np.float64)
         T = np.ascontiguousarray(types, dtype=np.int32)
         n = X.shape[0]
@@ -74,6 +78,7 @@ class Model:
         return out
 
     def neighbors(self, coords, box=None):
+        self.calls += 1
         X = np.ascontiguousarray(coords, dtype=np.float64)
         n = X.shape[0]
         nl = np.zeros((n, self.sel), dtype=np.int32)
@@ -124,6 +129,7 @@ class Model:
 
         Returns the energy tensor [1].  ``forces``/``virial`` None (both) runs the energy pass only.
         """
+        self.calls += 1
         import torch
         n = coords.shape[0]
         assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
@@ -144,6 +150,7 @@ class Model:
     def compute_batch(self, systems, forces: bool = True):
         """Several periodic systems [(coords, types, box), ...] in one batched step (through
         device buffers).  Returns one dict per system (E, F, virial)."""
+        self.calls += 1
         import torch
         dev = torch.device("cuda", self.device)
         ns = np.array([len(t) for _, t, _ in systems], dtype=np.int64)
@@ -178,6 +185,7 @@ class Model:
     def nve(self, coords, velocities, types, masses, box, dt_fs: float, steps: int):
         """Velocity-Verlet NVE on the device (torch float64 coords/velocities advanced in place).
         Returns (epot, ekin), arrays of steps + 1 energies in eV."""
+        self.calls += 1
         import torch
         assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
         assert velocities.is_cuda and velocities.dtype == torch.float64 and velocities.is_contiguous()
@@ -192,6 +200,7 @@ class Model:
         return ep, ek
 
     def backward_device(self, grad_energy, grad_coords, virial=None, stream=None):
+        self.calls += 1
         import torch
         s = stream if stream is not None else torch.cuda.current_stream(grad_coords.device).cuda_stream
         st = _lib.load().dp_backward_device(self._h, C.c_void_p(grad_energy.data_ptr()),
@@ -262,18 +271,25 @@ def _autograd_function():
         @staticmethod
         def forward(ctx, coords, types, model, box):
             x = coords.detach().contiguous()
-            E = model.compute_device(x, types.contiguous(), box)
+            t = types.contiguous()
+            E = model.compute_device(x, t, box)
             ctx.model = model
-            ctx.shape = x.shape
-            ctx.save_for_backward(x, types)
+            ctx.box = box
+            ctx.token = model.calls
+            ctx.save_for_backward(x, t)
             return E.reshape(())
 
         @staticmethod
         def backward(ctx, gE):
             x, types = ctx.saved_tensors
-            g = torch.empty(ctx.shape, dtype=torch.float64, device=x.device)
+            model = ctx.model
+            if model.calls != ctx.token:
+                # another call ran on the model since this forward: its saved state is
+                # not this graph's, so the energy pass is redone at this forward's inputs
+                model.compute_device(x, types, ctx.box)
+            g = torch.empty(x.shape, dtype=torch.float64, device=x.device)
             gE = gE.detach().reshape(1).to(torch.float64).contiguous()
-            ctx.model.backward_device(gE, g)
+            model.backward_device(gE, g)
             return g, None, None, None
 
     return DPEnergy

@@ -110,12 +110,7 @@ struct Packer {
     return o;
   }
   size_t addf(const std::vector<float> &v) { return add(v.data(), v.size() * 4); }
-  size_t addT(const std::vector<float> &v, int prec) {
-    if (prec == DP_FP32) return addf(v);
-    std::vector<uint16_t> b(v.size());
-    for (size_t i = 0; i < v.size(); ++i) b[i] = to_bf16(v[i]);
-    return add(b.data(), b.size() * 2);
-  }
+  size_t addd(const std::vector<double> &v) { return add(v.data(), v.size() * 8); }
 };
 
 std::vector<float> tof(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
@@ -127,27 +122,18 @@ std::vector<float> transpose(const std::vector<double> &v, int rows, int cols) {
   return o;
 }
 
-template <typename T>
-void bind_weights(Weights<T> &w, const unsigned char *base, const std::vector<size_t> &o, float c4) {
-  int k = 0;
-  auto F = [&]() { return (const float *)(base + o[k++]); };
-  auto P = [&]() { return (const T *)(base + o[k++]); };
-  w.w1s = F(); w.Bt = F();
-  w.W2T = P(); w.W2 = P(); w.b2 = F();
-  w.W3T = P(); w.W3 = P(); w.b3 = F();
-  for (int a = 0; a < NATTN; ++a) {
-    w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P(); w.gamma[a] = F(); w.beta[a] = F();
-  }
-  w.F1T = P(); w.F1 = P(); w.F2T = P(); w.F2 = P(); w.F3T = P(); w.F3 = P();
-  w.c1 = F(); w.c2 = F(); w.c3 = F(); w.F4 = F();
-  w.c4 = c4;
-  w.ebias = F();
-}
-
-int build_weights(dp_model *m, const HostModel &h) {
-  const int pr = m->prec;
+// Offsets of the pieces of the weight image, in the order the binders take them.
+struct Image {
   Packer pk;
-  std::vector<size_t> o;
+  std::vector<size_t> tab, f32, b16;
+  double c4 = 0.0;
+};
+
+// The whole device weight image on the host (no HIP call): the tables both paths read,
+// then the GEMM operands of the model's precision only.
+void pack_weights(const HostModel &h, int pr, Image &im) {
+  Packer &pk = im.pk;
+  std::vector<size_t> &o = im.tab;
   // first embedding layer: s column, and the type part folded with the bias
   std::vector<float> w1s(E1), Bt(NTYPES * NTYPES * E1);
   for (int e = 0; e < E1; ++e) w1s[e] = (float)h.W1[e];
@@ -163,15 +149,25 @@ int build_weights(dp_model *m, const HostModel &h) {
       }
   o.push_back(pk.addf(w1s));
   o.push_back(pk.addf(Bt));
-  o.push_back(pk.addT(transpose(h.W2, E1, E2), pr));
-  o.push_back(pk.addT(tof(h.W2), pr));
   o.push_back(pk.addf(tof(h.b2)));
-  o.push_back(pk.addT(transpose(h.W3, E2, M), pr));
-  o.push_back(pk.addT(tof(h.W3), pr));
   o.push_back(pk.addf(tof(h.b3)));
-  const double isd = 1.0 / std::sqrt((double)DATTN);
   for (int a = 0; a < NATTN; ++a) {
-    std::vector<double> qk((size_t)M * M), vo((size_t)M * M);
+    o.push_back(pk.addf(tof(h.gam[a])));
+    o.push_back(pk.addf(tof(h.bet[a])));
+  }
+  o.push_back(pk.addf(tof(h.c1)));
+  o.push_back(pk.addf(tof(h.c2)));
+  o.push_back(pk.addf(tof(h.c3)));
+  o.push_back(pk.addf(tof(h.F4)));
+  o.push_back(pk.addd(h.F4));
+  o.push_back(pk.addd(h.ebias));
+  im.c4 = h.c4[0];
+  // the fused single-head attention operands, formed in float64
+  const double isd = 1.0 / std::sqrt((double)DATTN);
+  std::vector<double> QK[NATTN], VO[NATTN];
+  for (int a = 0; a < NATTN; ++a) {
+    QK[a].assign((size_t)M * M, 0.0);
+    VO[a].assign((size_t)M * M, 0.0);
     for (int r = 0; r < M; ++r)
       for (int c = 0; c < M; ++c) {
         double s1 = 0, s2 = 0;
@@ -179,130 +175,202 @@ int build_weights(dp_model *m, const HostModel &h) {
           s1 += h.WQ[a][(size_t)r * DATTN + q] * h.WK[a][(size_t)c * DATTN + q];
           s2 += h.WV[a][(size_t)r * DATTN + q] * h.WO[a][(size_t)q * M + c];
         }
-        qk[(size_t)r * M + c] = s1 * isd;
-        vo[(size_t)r * M + c] = s2;
+        QK[a][(size_t)r * M + c] = s1 * isd;
+        VO[a][(size_t)r * M + c] = s2;
       }
-    o.push_back(pk.addT(transpose(qk, M, M), pr));
-    o.push_back(pk.addT(tof(qk), pr));
-    o.push_back(pk.addT(transpose(vo, M, M), pr));
-    o.push_back(pk.addT(tof(vo), pr));
-    o.push_back(pk.addf(tof(h.gam[a])));
-    o.push_back(pk.addf(tof(h.bet[a])));
   }
-  o.push_back(pk.addT(transpose(h.F1, ND, FH), pr));
-  o.push_back(pk.addT(tof(h.F1), pr));
-  o.push_back(pk.addT(transpose(h.F2, FH, FH), pr));
-  o.push_back(pk.addT(tof(h.F2), pr));
-  o.push_back(pk.addT(transpose(h.F3, FH, FH), pr));
-  o.push_back(pk.addT(tof(h.F3), pr));
-  o.push_back(pk.addf(tof(h.c1)));
-  o.push_back(pk.addf(tof(h.c2)));
-  o.push_back(pk.addf(tof(h.c3)));
-  o.push_back(pk.addf(tof(h.F4)));
-  o.push_back(pk.addf(tof(h.ebias)));
-  // padded [rows][k] bf16 operands of the bfloat16 kernels (zero outside the real extent)
-  std::vector<size_t> op;
-  if (pr == DP_BF16) {
-    auto mat = [](int R, int K, auto f) {
-      std::vector<float> v((size_t)R * K, 0.f);
-      for (int r = 0; r < R; ++r)
-        for (int k = 0; k < K; ++k) v[(size_t)r * K + k] = (float)f(r, k);
-      return v;
-    };
-    auto hi_lo = [&](const std::vector<float> &v, int part) {
-      std::vector<uint16_t> b(v.size());
-      for (size_t i = 0; i < v.size(); ++i) {
-        const uint16_t hb = to_bf16(v[i]);
-        uint32_t hu = (uint32_t)hb << 16;
-        float hf;
-        std::memcpy(&hf, &hu, 4);
-        b[i] = part == 0 ? hb : to_bf16(v[i] - hf);
-      }
-      return pk.add(b.data(), b.size() * 2);
-    };
-    auto W2 = [&](int a, int b) { return h.W2[(size_t)a * E2 + b]; };
-    auto W3 = [&](int a, int b) { return h.W3[(size_t)a * M + b]; };
-    op.push_back(hi_lo(mat(64, 32, [&](int c, int k) { return (c < E2 && k < E1) ? W2(k, c) : 0.0; }), 0));
-    op.push_back(hi_lo(mat(112, 64, [&](int c, int k) { return (c < M && k < E2) ? W3(k, c) : 0.0; }), 0));
-    op.push_back(hi_lo(mat(64, 112, [&](int c, int k) { return (c < E2 && k < M) ? W3(c, k) : 0.0; }), 0));
-    op.push_back(hi_lo(mat(32, 64, [&](int c, int k) { return (c < E1 && k < E2) ? W2(c, k) : 0.0; }), 0));
+  if (pr == DP_FP32) {
+    std::vector<size_t> &f = im.f32;
+    f.push_back(pk.addf(transpose(h.W2, E1, E2)));
+    f.push_back(pk.addf(tof(h.W2)));
+    f.push_back(pk.addf(transpose(h.W3, E2, M)));
+    f.push_back(pk.addf(tof(h.W3)));
     for (int a = 0; a < NATTN; ++a) {
-      std::vector<double> qk((size_t)M * M), vo((size_t)M * M);
-      for (int r = 0; r < M; ++r)
-        for (int c = 0; c < M; ++c) {
-          double s1 = 0, s2 = 0;
-          for (int q = 0; q < DATTN; ++q) {
-            s1 += h.WQ[a][(size_t)r * DATTN + q] * h.WK[a][(size_t)c * DATTN + q];
-            s2 += h.WV[a][(size_t)r * DATTN + q] * h.WO[a][(size_t)q * M + c];
-          }
-          qk[(size_t)r * M + c] = s1 * isd;
-          vo[(size_t)r * M + c] = s2;
-        }
-      auto at = [](const std::vector<double> &v, int r, int c) { return (r < M && c < M) ? v[(size_t)r * M + c] : 0.0; };
-      // the attention products read these from global memory, in MFMA fragment order: per 16-column tile, three 32-k fragments of 64 lanes x 8 values (lane l:
-      // row l % 16, k = 32 s + 8 (l / 16) ..), then the k = 96..111 tail as 64 lanes x 4
-      auto frag112 = [](const std::vector<float> &v) {
-        std::vector<float> o(v.size());
-        for (int t = 0; t < 7; ++t)
-          for (int l = 0; l < 64; ++l) {
-            const size_t row = (size_t)(16 * t + l % 16) * 112;
-            for (int st = 0; st < 3; ++st)
-              for (int e = 0; e < 8; ++e) o[t * 1792 + st * 512 + l * 8 + e] = v[row + 32 * st + 8 * (l / 16) + e];
-            for (int e = 0; e < 4; ++e) o[t * 1792 + 1536 + l * 4 + e] = v[row + 96 + 4 * (l / 16) + e];
-          }
-        return o;
-      };
-      const auto qkT = mat(112, 112, [&](int c, int k) { return at(qk, k, c); });
-      const auto voT = mat(112, 112, [&](int c, int k) { return at(vo, k, c); });
-      op.push_back(hi_lo(frag112(qkT), 0));
-      op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(qk, c, k); })), 0));
-      op.push_back(hi_lo(frag112(voT), 0));
-      op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(vo, c, k); })), 0));
+      f.push_back(pk.addf(transpose(QK[a], M, M)));
+      f.push_back(pk.addf(tof(QK[a])));
+      f.push_back(pk.addf(transpose(VO[a], M, M)));
+      f.push_back(pk.addf(tof(VO[a])));
     }
-    auto F = [&](const std::vector<double> &v, int ld, int r, int c) { return v[(size_t)r * ld + c]; };
-    const auto f1t = mat(FH, ND, [&](int c, int k) { return F(h.F1, FH, k, c); });
-    const auto f1 = mat(ND, 256, [&](int c, int k) { return k < FH ? F(h.F1, FH, c, k) : 0.0; });
-    const auto f2t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, k, c) : 0.0; });
-    const auto f2 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, c, k) : 0.0; });
-    const auto f3t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, k, c) : 0.0; });
-    const auto f3 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, c, k) : 0.0; });
-    // the fitting operands in MFMA fragment order: the 16 x 32 fragment (column tile t,
-    // k step s) is 64 lanes x 8 contiguous values, lane l holding row 16 t + l % 16,
-    // k = 32 s + 8 (l / 16) .. + 8; so one wave's fragment load is 1 KB of whole lines
-    auto frag = [](const std::vector<float> &v, int R, int K) {
+    f.push_back(pk.addf(transpose(h.F1, ND, FH)));
+    f.push_back(pk.addf(tof(h.F1)));
+    f.push_back(pk.addf(transpose(h.F2, FH, FH)));
+    f.push_back(pk.addf(tof(h.F2)));
+    f.push_back(pk.addf(transpose(h.F3, FH, FH)));
+    f.push_back(pk.addf(tof(h.F3)));
+    return;
+  }
+  // padded [rows][k] bf16 operands of the bfloat16 kernels (zero outside the real extent)
+  std::vector<size_t> &op = im.b16;
+  auto mat = [](int R, int K, auto f) {
+    std::vector<float> v((size_t)R * K, 0.f);
+    for (int r = 0; r < R; ++r)
+      for (int k = 0; k < K; ++k) v[(size_t)r * K + k] = (float)f(r, k);
+    return v;
+  };
+  auto hi_lo = [&](const std::vector<float> &v, int part) {
+    std::vector<uint16_t> b(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+      const uint16_t hb = to_bf16(v[i]);
+      uint32_t hu = (uint32_t)hb << 16;
+      float hf;
+      std::memcpy(&hf, &hu, 4);
+      b[i] = part == 0 ? hb : to_bf16(v[i] - hf);
+    }
+    return pk.add(b.data(), b.size() * 2);
+  };
+  auto W2 = [&](int a, int b) { return h.W2[(size_t)a * E2 + b]; };
+  auto W3 = [&](int a, int b) { return h.W3[(size_t)a * M + b]; };
+  op.push_back(hi_lo(mat(64, 32, [&](int c, int k) { return (c < E2 && k < E1) ? W2(k, c) : 0.0; }), 0));
+  op.push_back(hi_lo(mat(112, 64, [&](int c, int k) { return (c < M && k < E2) ? W3(k, c) : 0.0; }), 0));
+  op.push_back(hi_lo(mat(64, 112, [&](int c, int k) { return (c < E2 && k < M) ? W3(c, k) : 0.0; }), 0));
+  op.push_back(hi_lo(mat(32, 64, [&](int c, int k) { return (c < E1 && k < E2) ? W2(c, k) : 0.0; }), 0));
+  for (int a = 0; a < NATTN; ++a) {
+    const std::vector<double> &qk = QK[a], &vo = VO[a];
+    auto at = [](const std::vector<double> &v, int r, int c) { return (r < M && c < M) ? v[(size_t)r * M + c] : 0.0; };
+    // the attention products read these from global memory, in MFMA fragment order: per 16-column tile, three 32-k fragments of 64 lanes x 8 values (lane l:
+    // row l % 16, k = 32 s + 8 (l / 16) ..), then the k = 96..111 tail as 64 lanes x 4
+    auto frag112 = [](const std::vector<float> &v) {
       std::vector<float> o(v.size());
-      const int S = K / 32;
-      for (int t = 0; t < R / 16; ++t)
-        for (int st = 0; st < S; ++st)
-          for (int l = 0; l < 64; ++l)
-            for (int e = 0; e < 8; ++e)
-              o[(((size_t)t * S + st) * 64 + l) * 8 + e] = v[(size_t)(16 * t + l % 16) * K + 32 * st + 8 * (l / 16) + e];
+      for (int t = 0; t < 7; ++t)
+        for (int l = 0; l < 64; ++l) {
+          const size_t row = (size_t)(16 * t + l % 16) * 112;
+          for (int st = 0; st < 3; ++st)
+            for (int e = 0; e < 8; ++e) o[t * 1792 + st * 512 + l * 8 + e] = v[row + 32 * st + 8 * (l / 16) + e];
+          for (int e = 0; e < 4; ++e) o[t * 1792 + 1536 + l * 4 + e] = v[row + 96 + 4 * (l / 16) + e];
+        }
       return o;
     };
-    const std::vector<float> fr[] = {frag(f1t, FH, ND), frag(f1, ND, 256), frag(f2t, FH, 256),
-                                     frag(f2, FH, 256), frag(f3t, FH, 256), frag(f3, FH, 256)};
-    for (const auto &v : fr) {
-      op.push_back(hi_lo(v, 0));
-      op.push_back(hi_lo(v, 1));
-    }
+    op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(qk, k, c); })), 0));
+    op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(qk, c, k); })), 0));
+    op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(vo, k, c); })), 0));
+    op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(vo, c, k); })), 0));
   }
-  HIP_TRY(hipMalloc(&m->wbuf, pk.bytes.size()));
-  HIP_TRY(hipMemcpy(m->wbuf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice));
-  const float c4 = (float)h.c4[0];
-  const unsigned char *base = (const unsigned char *)m->wbuf;
-  bind_weights(m->wf, base, o, c4);
-  bind_weights(m->wb, base, o, c4);
-  if (pr == DP_BF16) {
-    int k = 0;
-    auto P = [&]() { return (const bf16_t *)(base + op[k++]); };
-    WeightsB16 &w = m->wp;
-    w.W2T = P(); w.W3T = P(); w.W3 = P(); w.W2 = P();
+  auto F = [&](const std::vector<double> &v, int ld, int r, int c) { return v[(size_t)r * ld + c]; };
+  const auto f1t = mat(FH, ND, [&](int c, int k) { return F(h.F1, FH, k, c); });
+  const auto f1 = mat(ND, 256, [&](int c, int k) { return k < FH ? F(h.F1, FH, c, k) : 0.0; });
+  const auto f2t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, k, c) : 0.0; });
+  const auto f2 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, c, k) : 0.0; });
+  const auto f3t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, k, c) : 0.0; });
+  const auto f3 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, c, k) : 0.0; });
+  // the fitting operands in MFMA fragment order: the 16 x 32 fragment (column tile t,
+  // k step s) is 64 lanes x 8 contiguous values, lane l holding row 16 t + l % 16,
+  // k = 32 s + 8 (l / 16) .. + 8; so one wave's fragment load is 1 KB of whole lines
+  auto frag = [](const std::vector<float> &v, int R, int K) {
+    std::vector<float> o(v.size());
+    const int S = K / 32;
+    for (int t = 0; t < R / 16; ++t)
+      for (int st = 0; st < S; ++st)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e)
+            o[(((size_t)t * S + st) * 64 + l) * 8 + e] = v[(size_t)(16 * t + l % 16) * K + 32 * st + 8 * (l / 16) + e];
+    return o;
+  };
+  const std::vector<float> fr[] = {frag(f1t, FH, ND), frag(f1, ND, 256), frag(f2t, FH, 256),
+                                   frag(f2, FH, 256), frag(f3t, FH, 256), frag(f3, FH, 256)};
+  for (const auto &v : fr) {
+    op.push_back(hi_lo(v, 0));
+    op.push_back(hi_lo(v, 1));
+  }
+}
+
+// Points the structures at a weight image based at `base` (a device address, or any
+// placeholder for the host-side check).
+void bind_image(const Image &im, int pr, const unsigned char *base, Weights<float> &w, WeightsB16 &wp) {
+  w = Weights<float>{};
+  wp = WeightsB16{};
+  size_t k = 0;
+  auto F = [&]() { return (const float *)(base + im.tab[k++]); };
+  w.w1s = F(); w.Bt = F(); w.b2 = F(); w.b3 = F();
+  for (int a = 0; a < NATTN; ++a) {
+    w.gamma[a] = F(); w.beta[a] = F();
+  }
+  w.c1 = F(); w.c2 = F(); w.c3 = F(); w.F4 = F();
+  w.F4d = (const double *)(base + im.tab[k++]);
+  w.ebias = (const double *)(base + im.tab[k++]);
+  w.c4 = im.c4;
+  if (pr == DP_FP32) {
+    k = 0;
+    auto P = [&]() { return (const float *)(base + im.f32[k++]); };
+    w.W2T = P(); w.W2 = P(); w.W3T = P(); w.W3 = P();
     for (int a = 0; a < NATTN; ++a) {
       w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P();
     }
-    w.F1T[0] = P(); w.F1T[1] = P(); w.F1[0] = P(); w.F1[1] = P();
-    w.F2T[0] = P(); w.F2T[1] = P(); w.F2[0] = P(); w.F2[1] = P();
-    w.F3T[0] = P(); w.F3T[1] = P(); w.F3[0] = P(); w.F3[1] = P();
+    w.F1T = P(); w.F1 = P(); w.F2T = P(); w.F2 = P(); w.F3T = P(); w.F3 = P();
+  } else {
+    k = 0;
+    auto P = [&]() { return (const bf16_t *)(base + im.b16[k++]); };
+    wp.W2T = P(); wp.W3T = P(); wp.W3 = P(); wp.W2 = P();
+    for (int a = 0; a < NATTN; ++a) {
+      wp.WqkT[a] = P(); wp.Wqk[a] = P(); wp.WvoT[a] = P(); wp.Wvo[a] = P();
+    }
+    for (int x = 0; x < 2; ++x) { wp.F1T[x] = P(); }
+    for (int x = 0; x < 2; ++x) { wp.F1[x] = P(); }
+    for (int x = 0; x < 2; ++x) { wp.F2T[x] = P(); }
+    for (int x = 0; x < 2; ++x) { wp.F2[x] = P(); }
+    for (int x = 0; x < 2; ++x) { wp.F3T[x] = P(); }
+    for (int x = 0; x < 2; ++x) { wp.F3[x] = P(); }
+  }
+}
+
+// The weight pointers the kernels of precision `pr` read, by name.
+std::vector<std::pair<std::string, const void **>> weight_fields(int pr, Weights<float> &w, WeightsB16 &wp) {
+  std::vector<std::pair<std::string, const void **>> f;
+  auto add = [&](const std::string &name, const void *member) { f.emplace_back(name, (const void **)member); };
+  add("w1s", &w.w1s); add("Bt", &w.Bt); add("b2", &w.b2); add("b3", &w.b3);
+  for (int a = 0; a < NATTN; ++a) {
+    add("gamma" + std::to_string(a), &w.gamma[a]);
+    add("beta" + std::to_string(a), &w.beta[a]);
+  }
+  add("c1", &w.c1); add("c2", &w.c2); add("c3", &w.c3); add("F4", &w.F4); add("F4d", &w.F4d);
+  add("ebias", &w.ebias);
+  if (pr == DP_FP32) {
+    add("W2T", &w.W2T); add("W2", &w.W2); add("W3T", &w.W3T); add("W3", &w.W3);
+    for (int a = 0; a < NATTN; ++a) {
+      const std::string t = std::to_string(a);
+      add("WqkT" + t, &w.WqkT[a]); add("Wqk" + t, &w.Wqk[a]); add("WvoT" + t, &w.WvoT[a]); add("Wvo" + t, &w.Wvo[a]);
+    }
+    add("F1T", &w.F1T); add("F1", &w.F1); add("F2T", &w.F2T); add("F2", &w.F2); add("F3T", &w.F3T); add("F3", &w.F3);
+    return f;
+  }
+  add("b16.W2T", &wp.W2T); add("b16.W3T", &wp.W3T); add("b16.W3", &wp.W3); add("b16.W2", &wp.W2);
+  for (int a = 0; a < NATTN; ++a) {
+    const std::string t = std::to_string(a);
+    add("b16.WqkT" + t, &wp.WqkT[a]); add("b16.Wqk" + t, &wp.Wqk[a]);
+    add("b16.WvoT" + t, &wp.WvoT[a]); add("b16.Wvo" + t, &wp.Wvo[a]);
+  }
+  for (int x = 0; x < 2; ++x) {
+    const std::string t = x ? ".lo" : ".hi";
+    add("b16.F1T" + t, &wp.F1T[x]); add("b16.F1" + t, &wp.F1[x]); add("b16.F2T" + t, &wp.F2T[x]);
+    add("b16.F2" + t, &wp.F2[x]); add("b16.F3T" + t, &wp.F3T[x]); add("b16.F3" + t, &wp.F3[x]);
+  }
+  return f;
+}
+
+// Every pointer the kernels of precision `pr` read lies inside the image [base, base + bytes).
+// A member left unbound (null) or pointing elsewhere is reported by name.
+bool check_bound(int pr, const unsigned char *base, size_t bytes, Weights<float> &w, WeightsB16 &wp,
+                 std::string &why) {
+  for (const auto &f : weight_fields(pr, w, wp)) {
+    const unsigned char *c = (const unsigned char *)*f.second;
+    if (!c || c < base || c >= base + bytes) {
+      why = "weight pointer " + f.first + (c ? " outside the weight image" : " is null");
+      return false;
+    }
+  }
+  return true;
+}
+
+int build_weights(dp_model *m, const HostModel &h) {
+  Image im;
+  pack_weights(h, m->prec, im);
+  HIP_TRY(hipMalloc(&m->wbuf, im.pk.bytes.size()));
+  HIP_TRY(hipMemcpy(m->wbuf, im.pk.bytes.data(), im.pk.bytes.size(), hipMemcpyHostToDevice));
+  const unsigned char *base = (const unsigned char *)m->wbuf;
+  bind_image(im, m->prec, base, m->wf, m->wp);
+  std::string why;
+  if (!check_bound(m->prec, base, im.pk.bytes.size(), m->wf, m->wp, why)) {
+    set_error("dp_model_load: " + why);
+    return DP_ERR_MODEL_FILE;
   }
   return DP_OK;
 }
@@ -365,6 +433,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipHostMalloc(&ws.grids_host, cs * sizeof(Grid), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&ws.off_host, (cs + 1) * sizeof(int), hipHostMallocDefault));
     ws.cap_sys = cs;
+    ws.gen += 1;
   }
   if (n > ws.cap) {
     const int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
@@ -393,6 +462,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
     ws.cap = cap;
     ws.skin_cap = 0;
+    ws.gen += 1;
   }
   if (skin && ws.skin_cap < ws.cap) {
     void *ps[] = {ws.slist, ws.snnei, ws.xref};
@@ -404,6 +474,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.snnei, ws.cap * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.xref, ws.cap * 3 * sizeof(double)));
     ws.skin_cap = ws.cap;
+    ws.gen += 1;
   }
   return DP_OK;
 }
@@ -515,12 +586,12 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   const bool bwd = a.forces || a.virial;
   if (pm) mark(pm, 1, st);
   if (m->prec == DP_BF16)
-    launch_descriptor_fwd_b16(m->wb, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
+    launch_descriptor_fwd_b16(m->wf, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
   else
     launch_descriptor_fwd<float>(m->wf, ws, a.X, a.types, n, rc, rcs, eps, st);
   if (pm) mark(pm, 2, st);
   if (m->prec == DP_BF16)
-    launch_fitting_b16(m->wb, m->wp, ws, a.types, n, bwd, st);
+    launch_fitting_b16(m->wf, m->wp, ws, a.types, n, bwd, st);
   else
     launch_fitting<float>(m->wf, ws, a.types, n, bwd, st);
   if (pm) mark(pm, 3, st);
@@ -528,13 +599,13 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   if (pm) mark(pm, 4, st);
   if (bwd) {
     if (m->prec == DP_BF16)
-      launch_descriptor_bwd_b16(m->wb, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
+      launch_descriptor_bwd_b16(m->wf, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
     else
       launch_descriptor_bwd<float>(m->wf, ws, a.X, a.types, n, rc, rcs, eps, st);
     if (pm) mark(pm, 5, st);
     double *F = a.forces;
     if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
-    launch_forces(ws, a.X, n, a.nsys, nullptr, F, a.virial, st);
+    launch_forces(ws, a.X, n, a.nsys, nullptr, F, a.virial, a.lists == LISTS_SKIN_REUSE, st);
     if (pm) mark(pm, 6, st);
   }
   HIP_TRY(hipGetLastError());
@@ -565,6 +636,13 @@ int launch_graph(dp_model *m, const StepArgs &a, hipStream_t st) {
   k.stream = st;
   k.open_single = a.open_single;
   if (!a.open_single) std::memcpy(k.box, m->ws.grids_host[0].L, 3 * sizeof(double));
+  k.ws_gen = m->ws.gen;
+  // graphs captured on an earlier workspace point at freed buffers: drop them
+  for (auto &e : m->graphs)
+    if (e.exec && e.key.ws_gen != k.ws_gen) {
+      (void)hipGraphExecDestroy(e.exec);
+      e.exec = nullptr;
+    }
   for (auto &e : m->graphs)
     if (e.exec && std::memcmp(&e.key, &k, sizeof(k)) == 0) {
       // the host-side grid table is uploaded outside the graph (same values as at capture)
@@ -649,6 +727,7 @@ int run_single(dp_model *m, StepArgs a, const double *box, hipStream_t st) {
       return s;
     }
     if (!graph) collect(m, (a.forces || a.virial) ? 6 : 4);
+    m->fwd_lists = a.lists;
     if (a.lists == LISTS_SKIN_BUILD) {
       m->skin_valid = true;
       m->skin_age = 1;
@@ -742,6 +821,42 @@ void dp_model_free(dp_model *m) {
   free_ws(m->ws);
   if (m->wbuf) (void)hipFree(m->wbuf);
   delete m;
+}
+
+int dp_check_model_file(const char *path, int precision, const char *unbind, size_t *image_bytes) {
+  g_last_error.clear();
+  if (!path || (precision != DP_FP32 && precision != DP_BF16)) {
+    set_error("dp_check_model_file: bad argument");
+    return DP_ERR_ARG;
+  }
+  HostModel h;
+  int s = read_model(path, h);
+  if (s != DP_OK) return s;
+  Image im;
+  pack_weights(h, precision, im);
+  const unsigned char *base = im.pk.bytes.data();
+  Weights<float> w;
+  WeightsB16 wp;
+  bind_image(im, precision, base, w, wp);
+  if (unbind) {
+    bool found = false;
+    for (const auto &f : weight_fields(precision, w, wp))
+      if (f.first == unbind) {
+        *f.second = nullptr;
+        found = true;
+      }
+    if (!found) {
+      set_error(std::string("dp_check_model_file: no weight named ") + unbind);
+      return DP_ERR_ARG;
+    }
+  }
+  if (image_bytes) *image_bytes = im.pk.bytes.size();
+  std::string why;
+  if (!check_bound(precision, base, im.pk.bytes.size(), w, wp, why)) {
+    set_error("dp_check_model_file: " + why);
+    return DP_ERR_MODEL_FILE;
+  }
+  return DP_OK;
 }
 
 int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g) {
@@ -930,10 +1045,10 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
     launch_fitting<float>(m->wf, ws, m->fwd_types, n, true, st);
     launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
   } else {
-    launch_fitting_b16(m->wb, m->wp, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd_b16(m->wb, m->wp, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
+    launch_fitting_b16(m->wf, m->wp, ws, m->fwd_types, n, true, st);
+    launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
   }
-  launch_forces(ws, m->fwd_coords, n, 1, d_grad_energy, d_grad_coords, d_virial, st);
+  launch_forces(ws, m->fwd_coords, n, 1, d_grad_energy, d_grad_coords, d_virial, m->fwd_lists == LISTS_SKIN_REUSE, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   m->fwd_valid = false;

@@ -613,11 +613,7 @@ void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const doubl
 
 template void launch_descriptor_fwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
                                            int, float, float, float, hipStream_t);
-template void launch_descriptor_fwd<bf16_t>(const Weights<bf16_t> &, const Workspace &, const double *, const int *,
-                                            int, float, float, float, hipStream_t);
 template void launch_descriptor_bwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
                                            int, float, float, float, hipStream_t);
-template void launch_descriptor_bwd<bf16_t>(const Weights<bf16_t> &, const Workspace &, const double *, const int *,
-                                            int, float, float, float, hipStream_t);
 
 }  // namespace dp

@@ -265,7 +265,7 @@ __device__ __forceinline__ void put_rows(bf16_t *Gb, bf16_t *GbT, const f4 (&gv)
 
 // Embedding net for the wave's rows (block jb) -> G (fp32 tiles).  h1 is staged (fp32) in
 // scr1 (>= 512 floats), h2 in scr2 (>= 1024 floats); both wave-private.
-__device__ void embed_rows(const Weights<bf16_t> &w, const bf16_t *w2T, int ld2, const bf16_t *w3T, int ld3,
+__device__ void embed_rows(const Tables &w, const bf16_t *w2T, int ld2, const bf16_t *w3T, int ld3,
                            const EnvB &e, int ti, int jb, float *scr1, float *scr2, f4 (&gv)[7]) {
   const int l = lane(), q = l >> 4, cl = l & 15;
   // per-lane weights: first layer column c1 = lane % 32 (type part for every neighbour
@@ -398,7 +398,7 @@ __device__ __forceinline__ void stage7(bf16_t *stg, const f4 (&v)[7]) {
 // Also returns xh (normalised residual) and isig (1/sigma per accumulator row).
 // If Uall is given, U rows are written there (and read from there for S).  The weight
 // operands wqkT and wvoT are read from global memory in MFMA fragment order.
-__device__ void layer_rows(const Weights<bf16_t> &w, const bf16_t *wqkT, const bf16_t *wvoT, int layer,
+__device__ void layer_rows(const Tables &w, const bf16_t *wqkT, const bf16_t *wvoT, int layer,
                            const EnvB &e, const bf16_t *Gb,
                            const bf16_t *GbT, bf16_t *stg, bf16_t *Uall, int jb, int n, int nb, int NP, float ln_eps,
                            f4 (&gv)[7], f4 (&sv)[8], f4 (&xh)[7], float (&isig)[4], float *rmax, float *rz) {

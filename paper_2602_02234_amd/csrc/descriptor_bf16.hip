@@ -16,7 +16,7 @@ struct __align__(16) SmemF16 {
 };
 
 __global__ void __launch_bounds__(NWF * 64)
-k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+k_desc_fwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
                const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
                float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
                float *__restrict__ D) {
@@ -97,7 +97,7 @@ k_desc_fwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, c
 
 }  // namespace
 
-void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,

@@ -34,7 +34,7 @@ template <int NW> struct __align__(16) SmemB16 {
 // column sums over every query row of the softmax-weight gradient W_jk (to dswa[k]) and
 // of the gate gradient dC_jk rhat_j (to drh[k]).
 template <int NW, int BPW>
-__device__ __forceinline__ void layer_bwd(const Weights<bf16_t> &w, const WeightsB16 &wp, int layer, bool top,
+__device__ __forceinline__ void layer_bwd(const Tables &w, const WeightsB16 &wp, int layer, bool top,
                                        SmemB16<NW> &sm, f4 (&gin)[BPW][7], const float *__restrict__ gs_next, int n,
                                        int nb, int NP, float ln_eps, f4 (&dg)[BPW][7]) {
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
@@ -357,7 +357,7 @@ __device__ __forceinline__ void put_layer_input(SmemB16<NW> &sm, const f4 (&gin)
 // to the instance whose block count fits their neighbour count.
 template <int NW, int BPW>
 __global__ void __launch_bounds__(NW * 64)
-k_desc_bwd_b16(Weights<bf16_t> w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+k_desc_bwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
                const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids,
                const int *__restrict__ sys_of, float rc, float rcs, float ln_eps, const float *__restrict__ Gsave,
                const float *__restrict__ Tsave, const float *__restrict__ dD, float4 *__restrict__ gout,
@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(1024) k_partition(const int *__restrict__ nnei
 
 }  // namespace
 
-void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, n, (int)ws.cap, ws.bidx, ws.bcnt);

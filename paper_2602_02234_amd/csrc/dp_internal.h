@@ -36,32 +36,40 @@ enum : unsigned {
   FLAG_ERRORS = 63u,  // any of the above: outputs are not written
 };
 
-// Device weights; T is float (DP_FP32) or __bf16 (DP_BF16) for GEMM operands.
-template <typename T> struct Weights {
+// Device weight tables read by both precision paths: biases, the first embedding
+// layer (its type part folded into Bt), LayerNorm parameters and the last fitting layer.
+struct Tables {
   const float *w1s;   // [E1]            first embedding layer, s column
   const float *Bt;    // [NTYPES][NTYPES][E1]  type part + bias of the first layer
+  const float *b2;    // [E2]
+  const float *b3;    // [M]
+  const float *gamma[NATTN];
+  const float *beta[NATTN];
+  const float *c1, *c2, *c3;
+  const float *F4;    // [FH]  last layer, float32 copy for the backward
+  // The last layer's energy terms stay float64: E_i = y3 . F4 + c4 + ebias[t_i] is summed
+  // in float64 from float32 y3, so the large, shared F4 and c4 add no rounding of their own.
+  const double *F4d;  // [FH]
+  double c4;
+  const double *ebias; // [NTYPES]
+};
+
+// GEMM operands of the float32 path, T = float, row-major as named.
+template <typename T> struct Weights : Tables {
   const T *W2T;       // [E2][E1]
   const T *W2;        // [E1][E2]
-  const float *b2;    // [E2]
   const T *W3T;       // [M][E2]
   const T *W3;        // [E2][M]
-  const float *b3;    // [M]
   const T *WqkT[NATTN];  // [M][M]  (WQ WK^T / sqrt(d))^T
   const T *Wqk[NATTN];   // [M][M]
   const T *WvoT[NATTN];  // [M][M]  (WV WO)^T
   const T *Wvo[NATTN];   // [M][M]
-  const float *gamma[NATTN];
-  const float *beta[NATTN];
   const T *F1T;       // [FH][ND]
   const T *F1;        // [ND][FH]
   const T *F2T;       // [FH][FH]
   const T *F2;
   const T *F3T;
   const T *F3;
-  const float *c1, *c2, *c3;
-  const float *F4;    // [FH]
-  float c4;
-  const float *ebias; // [NTYPES]
 };
 
 // Extra device weights of the bfloat16 path: GEMM operands zero-padded to MFMA
@@ -123,6 +131,7 @@ struct Workspace {
   double *gE = nullptr;       // [1] scale of the backward pass
   hipStream_t side = nullptr;  // second stream of the bf16 backward (its instances run side by side)
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  uint64_t gen = 0;           // bumped on every (re)allocation: graphs captured before it are stale
 };
 
 // How the neighbour lists of a step are made.
@@ -150,6 +159,7 @@ struct GraphKey {
   int64_t n;
   const void *X, *types, *energy, *forces, *virial, *atom_energy, *stream;
   double box[3];
+  uint64_t ws_gen;  // workspace generation the graph's buffers belong to
 };
 struct GraphEntry {
   GraphKey key;
@@ -164,15 +174,14 @@ struct dp_model {
   double rc = 0, rcs = 0, ln_eps = 1e-5;
   int sel = 0, ntypes = 0;
   void *wbuf = nullptr;
-  dp::Weights<float> wf{};
-  dp::Weights<dp::bf16_t> wb{};
-  dp::WeightsB16 wp{};
+  dp::Weights<float> wf{};   // float32 path (its Tables part is also what the bf16 kernels read)
+  dp::WeightsB16 wp{};       // bfloat16 path only
   dp::Workspace ws;
   // state kept between dp_compute_device (energy only) and dp_backward_device
   int64_t fwd_natoms = 0;
   const double *fwd_coords = nullptr;
   const int32_t *fwd_types = nullptr;
-  dp::Grid fwd_grid{};
+  int fwd_lists = 0;
   bool fwd_valid = false;
   // neighbour-list reuse with a skin (dp_set_skin)
   double skin = 0.0;
@@ -216,19 +225,21 @@ void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const doubl
 template <typename T>
 void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward,
                     hipStream_t st);
-void launch_descriptor_fwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n, float rc, float rcs, float ln_eps,
                                hipStream_t st);
-void launch_descriptor_bwd_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws,
+void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n, float rc, float rcs, float ln_eps,
                                hipStream_t st);
-void launch_fitting_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
+void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
                         bool backward, hipStream_t st);
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
                            int n, float rc, float rcs, float ln_eps, hipStream_t st);
+// skin_rows: the step reused skin lists (one-sided pairs are then found through the skin rows,
+// else through the cell list of the step).
 void launch_forces(const Workspace &ws, const double *coords, int n, int nsys, const double *gE, double *forces,
-                   double *virial_out, hipStream_t st);
+                   double *virial_out, bool skin_rows, hipStream_t st);
 void launch_energy(const Workspace &ws, int nsys, double *energy, double *atom_energy, hipStream_t st);
 // out[0] = Neumaier sum of src over the atoms of system 0 (fixed order).
 void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st);

@@ -63,9 +63,9 @@ k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D,
     const int r = threadIdx.x;
     int ty = types[a0 + r];
     ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
-    double e = 0.0;  // the last layer's dot product in float64: E_i is O(100) eV
-    for (int o = 0; o < FH; ++o) e += (double)bA[r * LDF + o] * (double)w.F4[o];
-    Ei[a0 + r] = e + (double)w.c4 + (double)w.ebias[ty];
+    double e = 0.0;  // the last layer's dot product in float64, with float64 F4, c4, ebias
+    for (int o = 0; o < FH; ++o) e += (double)bA[r * LDF + o] * w.F4d[o];
+    Ei[a0 + r] = e + w.c4 + w.ebias[ty];
   }
   if (!backward) return;
   for (int q = threadIdx.x; q < 16 * FH; q += NTHREADS) {
@@ -127,6 +127,5 @@ void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, 
                      backward ? 1 : 0);
 }
 template void launch_fitting<float>(const Weights<float> &, const Workspace &, const int *, int, bool, hipStream_t);
-template void launch_fitting<bf16_t>(const Weights<bf16_t> &, const Workspace &, const int *, int, bool, hipStream_t);
 
 }  // namespace dp

@@ -90,7 +90,7 @@ __device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, 
 }
 
 __global__ void __launch_bounds__(NWT * 64) __attribute__((amdgpu_waves_per_eu(4)))
-k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n, float *__restrict__ D,
+k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *__restrict__ D,
           double *__restrict__ Ei, int backward) {
   // y1, t2: the first two layers' outputs; y2: the third layer's input, later dE/dy2;
   // X: dE/dpre3, dE/dpre2, dE/dpre1 in turn.  Columns 240..255 stay zero.
@@ -137,7 +137,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
         const int r = 4 * q + ii, c = 16 * t + cl;
         const float tt = tanhf(acc[u][ii] + w.c3[c]);
         X[r * LDA + c] = w.F4[c] * (1.f - tt * tt);
-        double p = (double)(tt + y2[r * LDA + c]) * (double)w.F4[c];
+        double p = (double)(tt + y2[r * LDA + c]) * w.F4d[c];
         p += __shfl_xor(p, 1);
         p += __shfl_xor(p, 2);
         p += __shfl_xor(p, 4);
@@ -152,7 +152,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
     ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
     double e = 0.0;
     for (int t = 0; t < NT; ++t) e += ep[r][t];
-    Ei[a0 + r] = e + (double)w.c4 + (double)w.ebias[ty];
+    Ei[a0 + r] = e + w.c4 + w.ebias[ty];
   }
   if (!backward) return;
   // dy2 = dpre3 F3^T + F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
@@ -216,7 +216,7 @@ k_fit_b16(Weights<bf16_t> w, WeightsB16 wp, const int *__restrict__ types, int n
 
 }  // namespace
 
-void launch_fitting_b16(const Weights<bf16_t> &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
+void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
                         bool backward, hipStream_t st) {
   hipLaunchKernelGGL(k_fit_b16, dim3((n + 15) / 16), dim3(NWT * 64), 0, st, w, wp, types, n, ws.D, ws.Ei,
                      backward ? 1 : 0);

@@ -2,10 +2,12 @@
 //   F_i = sum_{j in N(i)} g_ij - sum_{j : i in N(j)} g_ji     (F = -dE/dx)
 //   Xi_ab = - sum_i sum_{j in N(i)} Delta_ij,a g_ij,b
 // The second force term is gathered through rev[][] (slot of i in the list of
-// j), so no floating-point atomics are needed while lists are symmetric; an
-// atom whose list overflowed can leave a pair one-sided, and only those pairs
-// are scattered with float64 atomics afterwards.  E and Xi are reduced per
+// j), so no floating-point atomics are needed.  An atom whose list overflowed can
+// leave a pair one-sided; those terms are gathered by a second pass over each
+// atom's cell neighbours, in a fixed order.  E and Xi are reduced per
 // system in float64 with Neumaier compensation in a fixed order.
+#include <algorithm>
+
 #include "dp_internal.h"
 
 namespace dp {
@@ -64,22 +66,94 @@ __global__ void __launch_bounds__(256) k_forces(const float4 *__restrict__ g, co
   }
 }
 
-// One-sided pairs (only after a list overflow): subtract g_ij from F_j.
-__global__ void k_forces_onesided(const float4 *__restrict__ g, const int *__restrict__ nlist,
-                                  const int *__restrict__ nnei, const int *__restrict__ rev, int n,
-                                  const double *__restrict__ gE, double *__restrict__ Fout,
-                                  const unsigned *__restrict__ flags) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)n * SEL || flags[2] == 0u || step_failed(flags)) return;
-  const int i = (int)(t / SEL), s = (int)(t % SEL);
-  if (s >= nnei[i] || rev[t] >= 0) return;
-  const int j = nlist[t];
-  if (j < 0 || j >= n) return;
-  const float4 gi = g[t];
-  const double sF = gE ? -gE[0] : 1.0;
-  atomicAdd(&Fout[3 * j], -sF * gi.x);
-  atomicAdd(&Fout[3 * j + 1], -sF * gi.y);
-  atomicAdd(&Fout[3 * j + 2], -sF * gi.z);
+// One-sided pairs (only after a list overflow, counted in flags[2] by the reverse-slot
+// pass): F_i -= sum of g_ci over the atoms c with i in N(c) but c not in N(i).  Such a c
+// lies within rc of i, so it is among the atoms of i's stencil cells (lists made this
+// step) or of i's skin row (reused skin lists).  The terms are summed in float64 in
+// ascending c, so the forces do not depend on the order the cells were filled in.
+// Grid-stride over atoms: without one-sided pairs every workgroup returns at once.
+__global__ void __launch_bounds__(64) k_forces_onesided(
+    const float4 *__restrict__ g, const int *__restrict__ nlist, const int *__restrict__ nnei,
+    const int *__restrict__ rev, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
+    const int *__restrict__ cell_of, const int *__restrict__ cell_start, const int *__restrict__ cell_atoms,
+    const int *__restrict__ slist, const int *__restrict__ snnei, int skin_rows, int n,
+    const double *__restrict__ gE, double *__restrict__ Fout, const unsigned *__restrict__ flags) {
+  __shared__ int oc[CAND_CAP];
+  __shared__ float4 og[CAND_CAP], sg[CAND_CAP];
+  if (flags[2] == 0u || step_failed(flags)) return;
+  const int lane = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    int count = 0;
+    // candidate c: keep it if i is in c's list at a slot whose pair is one-sided
+    auto consider = [&](int c) {
+      int slot = -1;
+      if (c >= 0 && c < n && c != i) {
+        const int *row = nlist + (size_t)c * SEL;
+        int lo = 0, hi = min(max(nnei[c], 0), SEL) - 1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int v = row[mid];
+          if (v == i) { slot = mid; break; }
+          if (v < i) lo = mid + 1; else hi = mid - 1;
+        }
+        if (slot >= 0 && rev[(size_t)c * SEL + slot] >= 0) slot = -1;
+      }
+      const unsigned long long mask = __ballot(slot >= 0);
+      const int pos = count + __popcll(mask & ((1ull << lane) - 1ull));
+      if (slot >= 0 && pos < CAND_CAP) {
+        oc[pos] = c;
+        og[pos] = g[(size_t)c * SEL + slot];
+      }
+      count += __popcll(mask);
+    };
+    if (skin_rows) {
+      const int ns = min(max(snnei[i], 0), SKIN_CAP);
+      for (int p = 0; p < ns; p += 64) consider(p + lane < ns ? slist[(size_t)i * SKIN_CAP + p + lane] : -1);
+    } else {
+      const Grid gr = grids[sys_of[i]];
+      const int cell = min(max(cell_of[i] - gr.cell_base, 0), gr.ncells - 1);
+      const int cz = cell % gr.nc[2], cy = (cell / gr.nc[2]) % gr.nc[1], cx = cell / (gr.nc[1] * gr.nc[2]);
+      int st[3][3], ns[3];
+      const int cc[3] = {cx, cy, cz};
+      for (int a = 0; a < 3; ++a) {  // distinct stencil cells along each axis
+        ns[a] = 0;
+        for (int o = -1; o <= 1; ++o) {
+          int v = cc[a] + o;
+          if (gr.periodic) v = (v + gr.nc[a]) % gr.nc[a];
+          else if (v < 0 || v >= gr.nc[a]) continue;
+          bool dup = false;
+          for (int q = 0; q < ns[a]; ++q) dup |= st[a][q] == v;
+          if (!dup) st[a][ns[a]++] = v;
+        }
+      }
+      for (int x = 0; x < ns[0]; ++x)
+        for (int y = 0; y < ns[1]; ++y)
+          for (int z = 0; z < ns[2]; ++z) {
+            const int c = gr.cell_base + (st[0][x] * gr.nc[1] + st[1][y]) * gr.nc[2] + st[2][z];
+            const int s0 = cell_start[c], s1 = cell_start[c + 1];
+            for (int p = s0; p < s1; p += 64) consider(p + lane < s1 ? cell_atoms[p + lane] : -1);
+          }
+    }
+    count = min(count, CAND_CAP);
+    __syncthreads();
+    for (int e = lane; e < count; e += 64) {  // the candidates are distinct: rank by index
+      int rank = 0;
+      for (int f = 0; f < count; ++f) rank += oc[f] < oc[e];
+      sg[rank] = og[e];
+    }
+    __syncthreads();
+    if (lane == 0 && count > 0) {
+      double s[3] = {0.0, 0.0, 0.0};
+      for (int e = 0; e < count; ++e) {
+        s[0] += sg[e].x;
+        s[1] += sg[e].y;
+        s[2] += sg[e].z;
+      }
+      const double sF = gE ? -gE[0] : 1.0;
+      for (int a = 0; a < 3; ++a) Fout[3 * i + a] -= sF * s[a];
+    }
+    __syncthreads();
+  }
 }
 
 struct Neu {
@@ -132,12 +206,12 @@ __global__ void __launch_bounds__(1024) k_seg_neumaier(const double *__restrict_
 }  // namespace
 
 void launch_forces(const Workspace &ws, const double *coords, int n, int nsys, const double *gE, double *forces,
-                   double *virial_out, hipStream_t st) {
+                   double *virial_out, bool skin_rows, hipStream_t st) {
   hipLaunchKernelGGL(k_forces, dim3((n + 3) / 4), dim3(256), 0, st, ws.g, ws.nlist, ws.nnei, ws.rev, coords,
                      ws.grids, ws.sys_of, n, gE, forces, ws.vpart, ws.flags);
-  const long long tot = (long long)n * SEL;
-  hipLaunchKernelGGL(k_forces_onesided, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.g, ws.nlist,
-                     ws.nnei, ws.rev, n, gE, forces, ws.flags);
+  hipLaunchKernelGGL(k_forces_onesided, dim3((unsigned)std::min(n, 2048)), dim3(64), 0, st, ws.g, ws.nlist,
+                     ws.nnei, ws.rev, ws.grids, ws.sys_of, ws.cell_of, ws.cell_start, ws.cell_atoms, ws.slist,
+                     ws.snnei, skin_rows ? 1 : 0, n, gE, forces, ws.flags);
   if (virial_out)
     hipLaunchKernelGGL(k_seg_neumaier, dim3(9 * nsys), dim3(1024), 0, st, ws.vpart, ws.sys_off, 9, virial_out,
                        (double *)nullptr, ws.flags);

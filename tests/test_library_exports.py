@@ -47,3 +47,30 @@ def test_model_load_without_device_fails_cleanly(model_path):
     from paper_2602_02234_amd import Model, DPError
     with pytest.raises(DPError):
         Model(model_path)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_weight_pointer_is_bound(model_path, prec):
+    """The host-side image check: every weight pointer the kernels of a precision read
+    is set and inside the image; clearing any one of them is reported by name."""
+    from paper_2602_02234_amd import _lib
+    lib = _lib.load()
+    nbytes = ctypes.c_size_t(0)
+    assert lib.dp_check_model_file(model_path.encode(), prec, None, ctypes.byref(nbytes)) == 0, \
+        lib.dp_last_error()
+    assert nbytes.value > 4 * 500_000 // (2 if prec else 1)
+    names = ["Bt", "F4d", "ebias", "gamma1"] + (["Wqk1", "F1T"] if prec == 0 else ["b16.Wvo0", "b16.F3.lo"])
+    for name in names:
+        s = lib.dp_check_model_file(model_path.encode(), prec, name.encode(), None)
+        assert s == -2, name
+        assert name.encode() in lib.dp_last_error()
+    assert lib.dp_check_model_file(model_path.encode(), prec, b"no_such_member", None) == -1
+
+
+def test_truncated_model_file_is_refused(model_path, tmp_path):
+    from paper_2602_02234_amd import _lib
+    lib = _lib.load()
+    raw = open(model_path, "rb").read()
+    bad = tmp_path / "short.bin"
+    bad.write_bytes(raw[:-8])
+    assert lib.dp_check_model_file(str(bad).encode(), 0, None, None) == -2

@@ -134,3 +134,9 @@ def test_energy_is_sum_of_atom_energies(omodel, oracle_water192):
 def test_force_scale_gives_unit_rms(oracle_water192):
     rms = float(np.sqrt(np.mean(oracle_water192["F"] ** 2)))
     assert abs(rms - 1.0) < 1e-9
+
+
+def test_last_layer_norm(omodel):
+    """The constant the energy bounds are derived from: ||F4||_2 of the seeded model."""
+    from tolerances import F4NORM
+    assert abs(np.linalg.norm(omodel.p["F4"]) - F4NORM) < 1.0
