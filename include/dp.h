@@ -130,6 +130,24 @@ int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g);
 int dp_profile_enable(dp_model *m, int enable);
 int dp_profile_read(const dp_model *m, double *ms, int64_t *calls, int max);
 
+/* Allocation-free variant of dp_compute_device, for callers that cannot allocate
+ * device memory during a step: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * dp_compute_device (fresh neighbour lists each call; dp_set_skin and
+ * dp_set_graph do not apply), bitwise the same results.  The workspace is a
+ * static device array of 128 MiB per GPU, reserved when the library's code is
+ * loaded on that GPU and held until the process ends; it fits natoms <=
+ * DP_NOALLOC_MAX_ATOMS, and larger systems get DP_ERR_TOO_LARGE.  The call makes
+ * no device or host allocation (dp_model_load sets up the array's address, pinned
+ * staging and streams once per device).  Every call on a GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (from several threads, streams or
+ * models) race and must be serialised by the caller.  The array keeps the last
+ * call's contents; the step clears what it needs cleared itself. */
+#define DP_NOALLOC_MAX_ATOMS 1024
+int dp_compute_device_noalloc(dp_model *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
+                              const double *box_host, double *d_energy, double *d_forces,
+                              double *d_virial, double *d_atom_energy, void *hip_stream);
+
 /* Several independent periodic systems in one step (paper, Section III: the
  * engine hands the potential one atom group per step; a server batches many).
  * System k has natoms[k] atoms, stored consecutively in d_coords [sum][3] and

@@ -30,6 +30,7 @@ SIGNATURES = {
     "dp_model_info": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "dp_compute": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "dp_compute_device": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dp_compute_device_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dp_backward_device": (C.c_int, [_P, _P, _P, _P, _P]),
     "dp_debug_neighbors": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
     "dp_debug_pair_grads": (C.c_int, [_P, _I64, _P]),

@@ -4,6 +4,8 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -479,6 +481,85 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
   return DP_OK;
 }
 
+// ------------------------------------------------------------ allocation-free step
+// Workspace of dp_compute_device_noalloc: one file-scope device array per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is only a stand-in); it passes the device address hipGetSymbolAddress
+// returns for the current device, kept per device in g_noalloc.
+constexpr size_t NOALLOC_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Points a workspace for `cap` atoms (one system) at consecutive 256-byte aligned pieces
+// from `base`; returns the bytes used.  base == nullptr only measures.
+size_t carve_ws(Workspace &ws, unsigned char *base, int64_t cap) {
+  size_t off = 0;
+  auto take = [&](auto *&p, size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base ? base + off : nullptr);
+    off += bytes;
+  };
+  const size_t c = (size_t)cap;
+  take(ws.flags, 4 * sizeof(unsigned));
+  take(ws.cell_count, (MAX_CELLS + 1) * sizeof(int));
+  take(ws.cell_start, (MAX_CELLS + 1) * sizeof(int));
+  take(ws.cell_cursor, MAX_CELLS * sizeof(int));
+  take(ws.red, 64 * sizeof(double));
+  take(ws.gE, sizeof(double));
+  take(ws.bcnt, 2 * sizeof(int));
+  take(ws.grids, sizeof(Grid));
+  take(ws.sys_off, 2 * sizeof(int));
+  take(ws.sys_of, c * sizeof(int));
+  take(ws.cell_of, c * sizeof(int));
+  take(ws.cell_atoms, c * sizeof(int));
+  take(ws.nlist, c * SEL * sizeof(int));
+  take(ws.nnei, c * sizeof(int));
+  take(ws.rev, c * SEL * sizeof(int));
+  take(ws.Gsave, c * NATTN * GSAVE_LAYER * sizeof(float));
+  take(ws.Tsave, c * M * 4 * sizeof(float));
+  take(ws.bidx, 2 * c * sizeof(int));
+  take(ws.D, (c + 16) * ND * sizeof(float));
+  take(ws.Ei, c * sizeof(double));
+  take(ws.g, c * SEL * sizeof(float4));
+  take(ws.vpart, c * 9 * sizeof(double));
+  ws.cap = cap;
+  ws.cap_sys = 1;
+  return off;
+}
+
+struct NoAllocDevice {
+  bool ready = false;
+  Workspace ws;  // device pieces inside `scratch`; pinned staging, side stream and events made at set-up
+};
+constexpr int NOALLOC_MAX_DEVICES = 64;
+NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+std::mutex g_noalloc_mu;
+
+// Once per device, with that device current (called by dp_model_load): the device
+// address of `scratch`, the workspace carved from it, and the host-side objects the step
+// needs (pinned staging, the side stream and events of the bf16 backward).
+int noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return DP_OK;  // entry point then reports it
+  NoAllocDevice &d = g_noalloc[device];
+  if (d.ready) return DP_OK;
+  void *ptr = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  Workspace ws;
+  if (carve_ws(ws, (unsigned char *)ptr, DP_NOALLOC_MAX_ATOMS) > NOALLOC_BYTES) {
+    set_error("allocation-free workspace: layout exceeds the static array");
+    return DP_ERR_HIP;
+  }
+  HIP_TRY(hipHostMalloc(&ws.flags_host, 4 * sizeof(unsigned), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(&ws.grids_host, sizeof(Grid), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(&ws.off_host, 2 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&ws.fork_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&ws.join_ev, hipEventDisableTiming));
+  d.ws = ws;
+  d.ready = true;
+  return DP_OK;
+}
+
 constexpr int64_t MAX_ATOMS = 1 << 24;
 
 // Validates a box and fills the cell grid for cells of edge >= cutoff.  box == NULL:
@@ -795,6 +876,7 @@ int dp_model_load(const char *path, int precision, int device, dp_model **out) {
   m->sel = h.sel;
   m->ntypes = h.ntypes;
   s = build_weights(m, h);
+  if (s == DP_OK) s = noalloc_setup(device);
   if (s == DP_OK && (hipStreamCreateWithFlags(&m->own_stream, hipStreamNonBlocking) != hipSuccess ||
                      hipEventCreateWithFlags(&m->dep_ev, hipEventDisableTiming) != hipSuccess)) {
     set_error("dp_model_load: stream creation failed");
@@ -931,6 +1013,52 @@ int dp_compute_device(dp_model *m, int64_t natoms, const double *d_coords, const
   m->fwd_coords = d_coords;
   m->fwd_types = d_types;
   return s;
+}
+
+int dp_compute_device_noalloc(dp_model *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
+                              const double *box_host, double *d_energy, double *d_forces, double *d_virial,
+                              double *d_atom_energy, void *hip_stream) {
+  g_last_error.clear();
+  if (!m || natoms < 1 || !d_coords || !d_types || !d_energy) {
+    set_error("dp_compute_device_noalloc: bad argument");
+    return DP_ERR_ARG;
+  }
+  if (natoms > DP_NOALLOC_MAX_ATOMS) {
+    set_error("dp_compute_device_noalloc: natoms above DP_NOALLOC_MAX_ATOMS (" +
+              std::to_string(DP_NOALLOC_MAX_ATOMS) + "); use dp_compute_device");
+    return DP_ERR_TOO_LARGE;
+  }
+  if (m->device < 0 || m->device >= NOALLOC_MAX_DEVICES || !g_noalloc[m->device].ready) {
+    set_error("dp_compute_device_noalloc: no allocation-free workspace on this device");
+    return DP_ERR_ARG;
+  }
+  Grid g;
+  int s = make_grid(m->rc, m->rc, box_host, g);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipSetDevice(m->device));
+  Workspace &ws = g_noalloc[m->device].ws;
+  ws.grids_host[0] = g;
+  ws.off_host[0] = 0;
+  ws.off_host[1] = (int)natoms;
+  StepArgs a;
+  a.n = natoms;
+  a.nsys = 1;
+  a.X = d_coords;
+  a.types = d_types;
+  a.energy = d_energy;
+  a.forces = d_forces;
+  a.virial = d_virial;
+  a.atom_energy = d_atom_energy;
+  a.open_single = box_host == nullptr;
+  a.ncells = a.open_single ? MAX_CELLS : g.ncells;
+  a.lists = LISTS_FRESH;
+  hipStream_t st = (hipStream_t)hip_stream;
+  s = enqueue_step(m, ws, a, st, false);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  m->fwd_valid = false;
+  return step_status(ws);
 }
 
 int dp_compute_batch_device(dp_model *m, int nsys, const int64_t *natoms, const double *boxes,
