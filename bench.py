@@ -15,7 +15,7 @@ atoms against the FP64 oracle, and the oracle's own throughput on the host
 cores (a bounded sample of the same workload).
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision bf16|fp32]
-                       [--workload chain10k] [--no-cpu-baseline]
+                       [--workload chain25k] [--serve-requests 2000] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -67,29 +67,56 @@ def flop_per_atom_eval(n):
     return 2.0 * (mac_desc_fwd(n) + mac_desc_bwd_alg(n) + 2 * FIT_MAC)
 
 
-def cpu_baseline(system, budget_s=15.0):
-    """The FP64 oracle on the host: E_i and dE_i/dDelta for sampled centre atoms until the
-    budget is spent, with its BLAS limited to one thread (so `cores` is what it used)."""
+def _cpu_worker(args):
+    """Oracle E_i and dE_i/dDelta_ij for consecutive chunks of 16 centre atoms of one
+    worker's share, until the time budget is spent (one BLAS thread per process)."""
     from threadpoolctl import threadpool_limits
-    from synth import default_model_file
-    from oracle import load_model
     from oracle.dp import evaluate_subset
-    from oracle.neighbors import neighbor_list_cells
-    m = load_model(default_model_file())
-    nl, nn, _ = neighbor_list_cells(system.coords, system.box, m.rc, m.sel)
-    rng = np.random.default_rng(0)
-    order = rng.permutation(system.natoms)
+    m, system, nl, nn, atoms, budget_s = args
     done = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < budget_s and done < system.natoms:
-            evaluate_subset(m, system.coords, system.types, system.box, order[done:done + 16], nl, nn)
+        while time.perf_counter() - t0 < budget_s and done < len(atoms):
+            evaluate_subset(m, system.coords, system.types, system.box, atoms[done:done + 16], nl, nn)
             done += 16
         dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "atom-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} random centre atoms of the 9,999-atom box: E_i and dE_i/dDelta_ij in float64 NumPy "
-                      f"(per-atom loop, BLAS limited to 1 thread), {dt:.1f} s; neighbour search excluded",
-            "host_cores_visible": len(os.sched_getaffinity(0))}
+    return done, dt
+
+
+def cpu_baseline(system, workload, budget_s=10.0):
+    """The FP64 oracle on the host cores, on random centre atoms of the benchmark system:
+    once in one process with one BLAS thread, once in one process per host core (each with
+    one BLAS thread).  Runs before anything touches the GPU (it forks)."""
+    import multiprocessing as mp
+    import platform
+    from threadpoolctl import threadpool_info
+    from synth import default_model_file
+    from oracle import load_model
+    from oracle.neighbors import neighbor_list_cells
+    m = load_model(default_model_file())
+    nl, nn, _ = neighbor_list_cells(system.coords, system.box, m.rc, m.sel)
+    order = np.random.default_rng(0).permutation(system.natoms)
+    one, dt1 = _cpu_worker((m, system, nl, nn, order, budget_s))
+    cores = max(1, min(len(os.sched_getaffinity(0)), 64))
+    shares = np.array_split(order, cores)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(m, system, nl, nn, sh, budget_s) for sh in shares], chunksize=1)
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    cpu_model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    blas = [f"{d.get('internal_api')} {d.get('version')}" for d in threadpool_info() if d.get("user_api") == "blas"]
+    return {"value": done / wall, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"random centre atoms of the {system.natoms:,}-atom {workload} box: E_i and dE_i/dDelta_ij "
+                      f"in float64 NumPy, {cores} processes x 1 BLAS thread for {budget_s:.0f} s each "
+                      f"({done} atoms in {wall:.1f} s wall); neighbour search excluded",
+            "single_thread": {"value": one / dt1, "cores": 1, "atoms": one, "seconds": dt1},
+            "cpu_model": cpu_model, "blas": blas, "host_cores_visible": len(os.sched_getaffinity(0))}
 
 
 def sampled_force_error(model_path, system, F, k=6, seed=1):
@@ -136,20 +163,21 @@ def make_trace(n_req, workers):
     return trace, systems
 
 
-def serving_bench(model_path, trace, systems, rates, budget_bytes):
+def serving_bench(model_path, trace_all, systems_all, legs, budget_bytes):
     """The Poisson request trace (sizes log-uniform 192..40,000 atoms, water boxes or solvated
     chains) replayed in real time against the BF16 continuous-batching server and against the
-    FP32 path evaluating one request at a time (host API), at each arrival rate."""
+    FP32 path evaluating one request at a time (host API).  legs: (arrival rate, number of
+    requests from the start of the trace); the trace's arrival times are scaled to the rate."""
     import time as _t
     from paper_2602_02234_amd import Model, Server
-    n_req = len(trace)
-    atoms = np.array([len(t) for _, t, _ in systems])
-    out = {"requests": n_req, "atoms_total": int(atoms.sum()), "atoms_median": float(np.median(atoms)),
-           "hbm_budget_GB": budget_bytes / 2**30, "rates": {}}
-    base_t = np.array([r["t"] for r in trace])
-    for rate in rates:
+    out = {"hbm_budget_GB": budget_bytes / 2**30, "rates": {}}
+    for rate, n_req in legs:
+        trace, systems = trace_all[:n_req], systems_all[:n_req]
+        atoms = np.array([len(t) for _, t, _ in systems])
+        base_t = np.array([r["t"] for r in trace])
         arr = base_t * (200.0 / rate)
-        row = {}
+        row = {"requests": len(trace), "atoms_total": int(atoms.sum()), "atoms_median": float(np.median(atoms)),
+               "trace_seconds": float(arr[-1])}
         # BF16 server, continuous batching
         m = Model(model_path, "bf16")
         srv = Server(m, budget_bytes)
@@ -233,17 +261,42 @@ def time_path(model, X, T, box, F, V, E, steps, warmup):
     return dt, prof
 
 
+def time_graph_replays(model, X, T, box, F, V, E, replays=20):
+    """Warm replays of the step's HIP graph: device time of each replay (HIP events on the
+    stream the graph runs on) and host wall-clock per call (launch, status read-back)."""
+    import torch
+    model.set_graph(True)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        model.compute_device(X, T, box, forces=F, virial=V, energy=E)
+    torch.cuda.synchronize()
+    dev_ms, host_ms = [], []
+    for _ in range(replays):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record(st)
+        model.compute_device(X, T, box, forces=F, virial=V, energy=E)
+        b.record(st)
+        b.synchronize()
+        host_ms.append(1e3 * (time.perf_counter() - t0))
+        dev_ms.append(a.elapsed_time(b))
+    model.set_graph(False)
+    return {"replays": replays, "median_device_ms": float(np.median(dev_ms)),
+            "median_host_ms": float(np.median(host_ms)), "min_device_ms": float(np.min(dev_ms))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
-    ap.add_argument("--workload", default="chain10k")
+    ap.add_argument("--workload", default="chain25k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
-    ap.add_argument("--serve-requests", type=int, default=100,
-                    help="requests of the serving trace to replay (0 = skip the serving run)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving trace replayed at 200 req/s (0 = skip the serving run); "
+                         "the first quarter of them is also replayed at 20 req/s")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -251,6 +304,17 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    from synth import config_system, default_model_file
+    system = None if args.copy_probe else config_system(args.workload)
+    # host-side work that forks (the oracle baseline, the serving trace) runs before anything
+    # touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_probe:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(system, args.workload)
+        print(f"[bench] oracle on {cpu['cores']} host cores: {cpu['value']:.4g} atom-evals/s "
+              f"(1 thread: {cpu['single_thread']['value']:.4g}) in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     trace = systems_trace = None
     if args.serve_requests > 0 and not args.copy_probe:
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -260,7 +324,6 @@ def main():
               file=sys.stderr, flush=True)
     import torch
     from paper_2602_02234_amd import Model
-    from synth import config_system, default_model_file
 
     dev = torch.device("cuda:0")
     if args.copy_probe:
@@ -271,7 +334,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4}))
         return
-    system = config_system(args.workload)
     N = system.natoms
     path = default_model_file()
     X = torch.tensor(system.coords, dtype=torch.float64, device=dev).contiguous()
@@ -291,9 +353,12 @@ def main():
         steps = args.steps if prec == args.precision else max(3, args.steps // 4)
         dt, prof = time_path(model, X, T, box, F, V, E, steps, args.warmup)
         f_rmse, f_max = sampled_force_error(path, system, F.cpu().numpy())
-        results[prec] = dict(dt=dt, steps=steps, prof=prof, f_rmse=f_rmse, f_max=f_max, E=float(E.item()))
+        graph = time_graph_replays(model, X, T, box, F, V, E) if prec == args.precision else None
+        results[prec] = dict(dt=dt, steps=steps, prof=prof, f_rmse=f_rmse, f_max=f_max, E=float(E.item()),
+                             graph=graph)
         print(f"[bench] {prec}: {steps} steps in {dt:.3f} s -> {N * steps / dt:.4g} atom-evals/s; "
-              f"sampled force RMSE {f_rmse:.2e}", file=sys.stderr, flush=True)
+              f"sampled force RMSE {f_rmse:.2e}" + (f"; graph replay median {graph['median_device_ms']:.3f} ms"
+                                                     if graph else ""), file=sys.stderr, flush=True)
         model.close()
 
     r = results[args.precision]
@@ -338,6 +403,7 @@ def main():
         "step_roofline": {"alg_flop_per_step": step_alg,
                           "frac": step_alg / (r["dt"] / r["steps"]) / PEAK[args.precision]},
         "phase_ms": avg,
+        "graph_replay": r["graph"],
         "accuracy": {"force_rmse_sampled": r["f_rmse"], "force_max_sampled": r["f_max"], "unit": "eV/A"},
     }
     for prec in precs[1:]:
@@ -347,11 +413,12 @@ def main():
         out[f"{prec}_force_rmse_sampled"] = o["f_rmse"]
         out[f"{prec}_phase_ms"] = {k: (ms / c if c else 0.0) for k, (ms, c) in o["prof"].items()}
     if trace is not None:
-        out["serving"] = serving_bench(path, trace, systems_trace, (200.0, 20.0), 16 << 30)
+        legs = [(200.0, len(trace)), (20.0, max(1, len(trace) // 4))]
+        out["serving"] = serving_bench(path, trace, systems_trace, legs, 16 << 30)
         r200 = out["serving"]["rates"]["200_req_per_s"]["bf16_server"]
         out["latency_p50_ms"], out["latency_p99_ms"] = r200["p50_ms"], r200["p99_ms"]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(system)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

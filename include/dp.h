@@ -130,6 +130,29 @@ int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g);
 int dp_profile_enable(dp_model *m, int enable);
 int dp_profile_read(const dp_model *m, double *ms, int64_t *calls, int max);
 
+/* One GPU's share of a spatially decomposed system (paper, Section III: the DP
+ * group is spread over ranks, each holding its atoms plus a ghost region; the
+ * ghost forces have to be returned to the owners).  The first n_owned atoms of
+ * d_coords/d_types are this GPU's own atoms, the rest (natoms - n_owned) its
+ * ghosts: copies of atoms owned elsewhere that lie within rc of an owned atom, in
+ * the same frame (box_host periodic, or NULL with unwrapped coordinates).  E_i and
+ * the pair gradients g_ij = dE_i/dDelta_ij are computed for owned i only, with
+ * neighbours among all natoms.  Outputs (device):
+ *   d_energy[0]  = sum of E_i over the owned atoms;
+ *   d_forces[natoms][3] = sum_{owned i} of the terms this share contributes:
+ *       row k gets  sum_j g_kj (k owned)  -  sum_{owned i: k in N(i)} g_ik,
+ *     so owned rows hold their forces minus what other shares' centres add, and
+ *     ghost rows hold the contributions to be returned to the owners;
+ *   d_virial[9]  = -sum_{owned i} sum_j Delta_ij (x) g_ij;
+ *   d_atom_energy[n_owned] (or NULL) = E_i of the owned atoms.
+ * Adding every share's d_forces rows into the owners' atoms, and summing the
+ * energies and virials, gives the whole system's E, F and virial.  n_owned =
+ * natoms is dp_compute_device.  Synchronous on hip_stream; fresh neighbour lists
+ * (dp_set_skin and dp_set_graph do not apply). */
+int dp_compute_owned_device(dp_model *m, int64_t natoms, int64_t n_owned, const double *d_coords,
+                            const int32_t *d_types, const double *box_host, double *d_energy, double *d_forces,
+                            double *d_virial, double *d_atom_energy, void *hip_stream);
+
 /* Allocation-free variant of dp_compute_device, for callers that cannot allocate
  * device memory during a step: code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc.  Same arguments, results and errors as

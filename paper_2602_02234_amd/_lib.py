@@ -31,6 +31,7 @@ SIGNATURES = {
     "dp_compute": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "dp_compute_device": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dp_compute_device_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dp_compute_owned_device": (C.c_int, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dp_backward_device": (C.c_int, [_P, _P, _P, _P, _P]),
     "dp_debug_neighbors": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
     "dp_debug_pair_grads": (C.c_int, [_P, _I64, _P]),

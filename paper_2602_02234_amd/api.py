@@ -147,6 +147,28 @@ class Model:
         self.last_status = check(st, "dp_compute_device")
         return energy
 
+    def compute_owned_device(self, coords, types, n_owned: int, box=None, forces=None, virial=None, energy=None,
+                             atom_energy=None, stream=None):
+        """One share of a decomposed system (dp_compute_owned_device): the first n_owned atoms
+        are owned, the rest ghosts.  Torch CUDA tensors; outputs written in place."""
+        self.calls += 1
+        import torch
+        n = coords.shape[0]
+        assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
+        assert types.is_cuda and types.dtype == torch.int32 and types.is_contiguous()
+        if energy is None:
+            energy = torch.empty(1, dtype=torch.float64, device=coords.device)
+        s = stream if stream is not None else torch.cuda.current_stream(coords.device).cuda_stream
+        b = _box9(box)
+
+        def dp(t):
+            return C.c_void_p(t.data_ptr()) if t is not None else None
+
+        st = _lib.load().dp_compute_owned_device(self._h, n, int(n_owned), dp(coords), dp(types), _ptr(b), dp(energy),
+                                                 dp(forces), dp(virial), dp(atom_energy), C.c_void_p(s))
+        self.last_status = check(st, "dp_compute_owned_device")
+        return energy
+
     def compute_batch(self, systems, forces: bool = True):
         """Several periodic systems [(coords, types, box), ...] in one batched step (through
         device buffers).  Returns one dict per system (E, F, virial)."""

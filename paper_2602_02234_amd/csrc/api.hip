@@ -431,7 +431,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     ws.grids = nullptr; ws.sys_off = nullptr; ws.grids_host = nullptr; ws.off_host = nullptr;
     ws.cap_sys = 0;
     HIP_TRY(hipMalloc(&ws.grids, cs * sizeof(Grid)));
-    HIP_TRY(hipMalloc(&ws.sys_off, (cs + 1) * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.sys_off, (cs + 1) * sizeof(int)));  // cs >= 8: [2..3] also hold a centre range
     HIP_TRY(hipHostMalloc(&ws.grids_host, cs * sizeof(Grid), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&ws.off_host, (cs + 1) * sizeof(int), hipHostMallocDefault));
     ws.cap_sys = cs;
@@ -507,7 +507,7 @@ size_t carve_ws(Workspace &ws, unsigned char *base, int64_t cap) {
   take(ws.gE, sizeof(double));
   take(ws.bcnt, 2 * sizeof(int));
   take(ws.grids, sizeof(Grid));
-  take(ws.sys_off, 2 * sizeof(int));
+  take(ws.sys_off, 4 * sizeof(int));
   take(ws.sys_of, c * sizeof(int));
   take(ws.cell_of, c * sizeof(int));
   take(ws.cell_atoms, c * sizeof(int));
@@ -551,7 +551,7 @@ int noalloc_setup(int device) {
   }
   HIP_TRY(hipHostMalloc(&ws.flags_host, 4 * sizeof(unsigned), hipHostMallocDefault));
   HIP_TRY(hipHostMalloc(&ws.grids_host, sizeof(Grid), hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc(&ws.off_host, 2 * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(&ws.off_host, 4 * sizeof(int), hipHostMallocDefault));
   HIP_TRY(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&ws.fork_ev, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&ws.join_ev, hipEventDisableTiming));
@@ -638,19 +638,26 @@ void collect(dp_model *m, int last) {
 int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, bool profile) {
   dp_model *pm = profile ? m : nullptr;
   const int n = (int)a.n;
+  // centres: every atom, or (one system with ghost atoms) the first n_centres
+  const int nc = (a.nsys == 1 && a.n_centres >= 0 && a.n_centres < a.n) ? (int)a.n_centres : n;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
   if (!a.open_single) HIP_TRY(hipMemcpyAsync(ws.grids, ws.grids_host, a.nsys * sizeof(Grid), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, (a.nsys + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  if (nc < n) {  // off_host[2..3]: the centre range, reduced for the energy
+    ws.off_host[2] = 0;
+    ws.off_host[3] = nc;
+  }
+  HIP_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, (nc < n ? 4 : a.nsys + 1) * sizeof(int), hipMemcpyHostToDevice,
+                         st));
   launch_sys_of(ws, a.nsys, n, st);
   if (pm) mark(pm, 0, st);
   switch (a.lists) {
     case LISTS_FRESH:
       launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc, st);
-      launch_nlist(ws, a.X, n, m->rc, false, st);
+      launch_nlist(ws, a.X, n, nc, m->rc, false, st);
       break;
     case LISTS_SKIN_BUILD:
       launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc + m->skin, st);
-      launch_nlist(ws, a.X, n, m->rc + m->skin, true, st);
+      launch_nlist(ws, a.X, n, n, m->rc + m->skin, true, st);
       launch_skin_ref(ws, a.X, n, st);
       launch_filter(ws, a.X, n, m->rc, st);
       break;
@@ -667,22 +674,22 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   const bool bwd = a.forces || a.virial;
   if (pm) mark(pm, 1, st);
   if (m->prec == DP_BF16)
-    launch_descriptor_fwd_b16(m->wf, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
+    launch_descriptor_fwd_b16(m->wf, m->wp, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
   else
-    launch_descriptor_fwd<float>(m->wf, ws, a.X, a.types, n, rc, rcs, eps, st);
+    launch_descriptor_fwd<float>(m->wf, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
   if (pm) mark(pm, 2, st);
   if (m->prec == DP_BF16)
-    launch_fitting_b16(m->wf, m->wp, ws, a.types, n, bwd, st);
+    launch_fitting_b16(m->wf, m->wp, ws, a.types, nc, bwd, st);
   else
-    launch_fitting<float>(m->wf, ws, a.types, n, bwd, st);
+    launch_fitting<float>(m->wf, ws, a.types, nc, bwd, st);
   if (pm) mark(pm, 3, st);
-  launch_energy(ws, a.nsys, a.energy, a.atom_energy, st);
+  launch_energy(ws, nc < n ? ws.sys_off + 2 : ws.sys_off, a.nsys, a.energy, a.atom_energy, st);
   if (pm) mark(pm, 4, st);
   if (bwd) {
     if (m->prec == DP_BF16)
-      launch_descriptor_bwd_b16(m->wf, m->wp, ws, a.X, a.types, n, rc, rcs, eps, st);
+      launch_descriptor_bwd_b16(m->wf, m->wp, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
     else
-      launch_descriptor_bwd<float>(m->wf, ws, a.X, a.types, n, rc, rcs, eps, st);
+      launch_descriptor_bwd<float>(m->wf, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
     if (pm) mark(pm, 5, st);
     double *F = a.forces;
     if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
@@ -1015,6 +1022,53 @@ int dp_compute_device(dp_model *m, int64_t natoms, const double *d_coords, const
   return s;
 }
 
+int dp_compute_owned_device(dp_model *m, int64_t natoms, int64_t n_owned, const double *d_coords,
+                            const int32_t *d_types, const double *box_host, double *d_energy, double *d_forces,
+                            double *d_virial, double *d_atom_energy, void *hip_stream) {
+  g_last_error.clear();
+  if (!m || natoms < 1 || n_owned < 0 || n_owned > natoms || !d_coords || !d_types || !d_energy) {
+    set_error("dp_compute_owned_device: bad argument");
+    return DP_ERR_ARG;
+  }
+  if (natoms > MAX_ATOMS) {
+    set_error("natoms above the library limit");
+    return DP_ERR_TOO_LARGE;
+  }
+  Grid g;
+  int s = make_grid(m->rc, m->rc, box_host, g);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipSetDevice(m->device));
+  Workspace &ws = m->ws;
+  s = ensure_ws(ws, m->prec, natoms, 1, false);
+  if (s != DP_OK) return s;
+  ws.grids_host[0] = g;
+  ws.off_host[0] = 0;
+  ws.off_host[1] = (int)natoms;
+  StepArgs a;
+  a.n = natoms;
+  a.nsys = 1;
+  a.n_centres = n_owned;
+  a.X = d_coords;
+  a.types = d_types;
+  a.energy = d_energy;
+  a.forces = d_forces;
+  a.virial = d_virial;
+  a.atom_energy = d_atom_energy;
+  a.open_single = box_host == nullptr;
+  a.ncells = a.open_single ? MAX_CELLS : g.ncells;
+  a.lists = LISTS_FRESH;
+  hipStream_t st = (hipStream_t)hip_stream;
+  s = enqueue_step(m, ws, a, st, false);
+  if (s != DP_OK) return s;
+  HIP_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  m->fwd_valid = false;
+  s = step_status(ws);
+  // one-sided pairs are expected here (a centre's ghost neighbours have no lists); only a
+  // truncated list is a warning
+  return s;
+}
+
 int dp_compute_device_noalloc(dp_model *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
                               const double *box_host, double *d_energy, double *d_forces, double *d_virial,
                               double *d_atom_energy, void *hip_stream) {
@@ -1171,10 +1225,10 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
   // net with its backward
   if (m->prec == DP_FP32) {
     launch_fitting<float>(m->wf, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
+    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, n, rc, rcs, eps, st);
   } else {
     launch_fitting_b16(m->wf, m->wp, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, rc, rcs, eps, st);
+    launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, n, rc, rcs, eps, st);
   }
   launch_forces(ws, m->fwd_coords, n, 1, d_grad_energy, d_grad_coords, d_virial, m->fwd_lists == LISTS_SKIN_REUSE, st);
   HIP_TRY(hipGetLastError());
@@ -1271,7 +1325,7 @@ int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const 
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
     launch_sys_of(ws, 1, (int)natoms, st);
     launch_cells(ws, dX, dT, (int)natoms, m->ntypes, open, open ? MAX_CELLS : g.ncells, m->rc, st);
-    launch_nlist(ws, dX, (int)natoms, m->rc, false, st);
+    launch_nlist(ws, dX, (int)natoms, (int)natoms, m->rc, false, st);
     if (hipStreamSynchronize(st) != hipSuccess ||
         hipMemcpy(nlist, ws.nlist, n * SEL * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(nnei, ws.nnei, n * 4, hipMemcpyDeviceToHost) != hipSuccess ||

@@ -599,21 +599,21 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
 
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
-                           float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                           int ncen, float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(ncen), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
 }
 
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
-                           float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(n), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                           int ncen, float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(ncen), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
 }
 
 template void launch_descriptor_fwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
-                                           int, float, float, float, hipStream_t);
+                                           int, int, float, float, float, hipStream_t);
 template void launch_descriptor_bwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
-                                           int, float, float, float, hipStream_t);
+                                           int, int, float, float, float, hipStream_t);
 
 }  // namespace dp

@@ -98,9 +98,9 @@ k_desc_fwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int 
 }  // namespace
 
 void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n,
+                               const double *coords, const int *types, int n, int ncen,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(n), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(ncen), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
 }
 

@@ -605,17 +605,17 @@ __global__ void __launch_bounds__(1024) k_partition(const int *__restrict__ nnei
 }  // namespace
 
 void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n,
+                               const double *coords, const int *types, int n, int ncen,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, n, (int)ws.cap, ws.bidx, ws.bcnt);
+  hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, ncen, (int)ws.cap, ws.bidx, ws.bcnt);
   // atoms with up to 7 row blocks: 7 waves, one block each (on st); the rest: 4 waves,
   // two blocks each, on the side stream, so that a few dense atoms overlap the bulk
   (void)hipEventRecord(ws.fork_ev, st);
   (void)hipStreamWaitEvent(ws.side, ws.fork_ev, 0);
-  hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(n), dim3(4 * 64), 0, ws.side, w, wp, coords, types, n, ws.nlist,
+  hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(ncen), dim3(4 * 64), 0, ws.side, w, wp, coords, types, n, ws.nlist,
                      ws.nnei, ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx + ws.cap,
                      ws.bcnt + 1);
-  hipLaunchKernelGGL((k_desc_bwd_b16<7, 1>), dim3(n), dim3(7 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
+  hipLaunchKernelGGL((k_desc_bwd_b16<7, 1>), dim3(ncen), dim3(7 * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei,
                      ws.grids, ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g, ws.bidx, ws.bcnt);
   (void)hipEventRecord(ws.join_ev, ws.side);
   (void)hipStreamWaitEvent(st, ws.join_ev, 0);

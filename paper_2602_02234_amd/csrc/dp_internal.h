@@ -102,8 +102,9 @@ struct Workspace {
   int cap_sys = 0;            // systems
   Grid *grids = nullptr;      // [cap_sys]  per-system cell grid (device)
   Grid *grids_host = nullptr; // [cap_sys]  pinned staging
-  int *sys_off = nullptr;     // [cap_sys + 1]  first atom of each system (device)
-  int *off_host = nullptr;    // [cap_sys + 1]  pinned staging
+  int *sys_off = nullptr;     // [cap_sys + 1]  first atom of each system (device); with one system
+                              // and ghost atoms, [2..3] hold the centre range
+  int *off_host = nullptr;    // pinned staging of sys_off
   int *sys_of = nullptr;      // [cap]  system of each atom
   int *slist = nullptr;       // [cap][SKIN_CAP]  skin list (within rc + skin)
   int *snnei = nullptr;       // [cap]
@@ -151,6 +152,8 @@ struct StepArgs {
   bool open_single = false;       // one open-boundary system (grid made on the device)
   int ncells = 0;                 // cells over all systems
   int lists = LISTS_FRESH;
+  int64_t n_centres = -1;         // one system: only atoms 0 .. n_centres-1 are centres (E_i, g_ij);
+                                  // the rest are neighbours only (ghosts).  -1: every atom
 };
 
 struct GraphKey {
@@ -213,34 +216,40 @@ void set_error(const std::string &s);
 void launch_sys_of(const Workspace &ws, int nsys, int n, hipStream_t st);
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
                   int ncells_total, double cell_cutoff, hipStream_t st);
-void launch_nlist(const Workspace &ws, const double *coords, int n, double cutoff, bool skin, hipStream_t st);
+// Lists for the first ncen atoms (the others get empty lists), candidates among all n.
+void launch_nlist(const Workspace &ws, const double *coords, int n, int ncen, double cutoff, bool skin,
+                  hipStream_t st);
 void launch_filter(const Workspace &ws, const double *coords, int n, double rc, hipStream_t st);
 void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
                        hipStream_t st);
 void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st);
 void launch_rev(const Workspace &ws, int n, hipStream_t st);
+// The per-centre launchers run over the first ncen atoms (the centres), reading the
+// coordinates and types of all n atoms as neighbours.
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
-                           int n, float rc, float rcs, float ln_eps, hipStream_t st);
+                           int n, int ncen, float rc, float rcs, float ln_eps, hipStream_t st);
 template <typename T>
 void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward,
                     hipStream_t st);
 void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, float rc, float rcs, float ln_eps,
-                               hipStream_t st);
+                               const double *coords, const int *types, int n, int ncen, float rc, float rcs,
+                               float ln_eps, hipStream_t st);
 void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, float rc, float rcs, float ln_eps,
-                               hipStream_t st);
+                               const double *coords, const int *types, int n, int ncen, float rc, float rcs,
+                               float ln_eps, hipStream_t st);
 void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
                         bool backward, hipStream_t st);
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
-                           int n, float rc, float rcs, float ln_eps, hipStream_t st);
+                           int n, int ncen, float rc, float rcs, float ln_eps, hipStream_t st);
 // skin_rows: the step reused skin lists (one-sided pairs are then found through the skin rows,
 // else through the cell list of the step).
 void launch_forces(const Workspace &ws, const double *coords, int n, int nsys, const double *gE, double *forces,
                    double *virial_out, bool skin_rows, hipStream_t st);
-void launch_energy(const Workspace &ws, int nsys, double *energy, double *atom_energy, hipStream_t st);
+// Per-system energies over the atom ranges off[s] .. off[s+1]-1 (device offsets).
+void launch_energy(const Workspace &ws, const int *off, int nsys, double *energy, double *atom_energy,
+                   hipStream_t st);
 // out[0] = Neumaier sum of src over the atoms of system 0 (fixed order).
 void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st);
 

@@ -222,9 +222,9 @@ void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t
                      ws.flags);
 }
 
-void launch_energy(const Workspace &ws, int nsys, double *energy, double *atom_energy, hipStream_t st) {
-  hipLaunchKernelGGL(k_seg_neumaier, dim3(nsys), dim3(1024), 0, st, ws.Ei, ws.sys_off, 1, energy, atom_energy,
-                     ws.flags);
+void launch_energy(const Workspace &ws, const int *off, int nsys, double *energy, double *atom_energy,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_neumaier, dim3(nsys), dim3(1024), 0, st, ws.Ei, off, 1, energy, atom_energy, ws.flags);
 }
 
 }  // namespace dp

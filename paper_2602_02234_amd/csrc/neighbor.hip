@@ -210,7 +210,7 @@ __device__ bool write_row(const int *cj, const double *cd2, int *keep, int count
 __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int n, const Grid *__restrict__ grids,
                                               const int *__restrict__ sys_of, double cut2,
                                               const int *__restrict__ cell_of, const int *__restrict__ cell_start,
-                                              const int *__restrict__ cell_atoms, int cap, int skin,
+                                              const int *__restrict__ cell_atoms, int cap, int skin, int ncen,
                                               int *__restrict__ nlist, int *__restrict__ nnei,
                                               unsigned *__restrict__ flags) {
   __shared__ int cj[CAND_CAP];
@@ -219,6 +219,10 @@ __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int 
   const int i = blockIdx.x;
   if (i >= n) return;
   const int lane = threadIdx.x;
+  if (i >= ncen) {  // not a centre (a ghost atom): an empty list
+    if (lane == 0) nnei[i] = 0;
+    return;
+  }
   const Grid g = grids[sys_of[i]];
   const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
   const int cell = clampi(cell_of[i] - g.cell_base, 0, g.ncells - 1);
@@ -386,10 +390,11 @@ void launch_cells(const Workspace &ws, const double *coords, const int *types, i
                      ws.cell_atoms, n);
 }
 
-void launch_nlist(const Workspace &ws, const double *coords, int n, double cutoff, bool skin, hipStream_t st) {
+void launch_nlist(const Workspace &ws, const double *coords, int n, int ncen, double cutoff, bool skin,
+                  hipStream_t st) {
   hipLaunchKernelGGL(k_nlist, dim3(n), dim3(64), 0, st, coords, n, ws.grids, ws.sys_of, cutoff * cutoff, ws.cell_of,
-                     ws.cell_start, ws.cell_atoms, skin ? SKIN_CAP : SEL, skin ? 1 : 0, skin ? ws.slist : ws.nlist,
-                     skin ? ws.snnei : ws.nnei, ws.flags);
+                     ws.cell_start, ws.cell_atoms, skin ? SKIN_CAP : SEL, skin ? 1 : 0, ncen,
+                     skin ? ws.slist : ws.nlist, skin ? ws.snnei : ws.nnei, ws.flags);
 }
 
 void launch_filter(const Workspace &ws, const double *coords, int n, double rc, hipStream_t st) {

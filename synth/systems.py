@@ -79,20 +79,35 @@ def _water_template() -> np.ndarray:
 
 
 class _Grid:
-    """Periodic bucket grid used to reject insertions that come too close."""
+    """Periodic bucket grid used to reject insertions that come too close.
 
-    def __init__(self, L: float, cell: float):
+    The points are kept twice: in per-cell lists (the exact scalar test) and in a
+    NaN-padded array [n][n][n][K][3] for a vectorised test of many candidates at once.
+    """
+
+    def __init__(self, L: float, cell: float, k_max: int = 8):
         self.L = L
         self.n = max(1, int(L // cell))
         self.cell = L / self.n
         self.buckets: dict[tuple, list] = {}
+        self.arr = np.full((self.n, self.n, self.n, k_max, 3), np.nan)
+        self.cnt = np.zeros((self.n, self.n, self.n), dtype=np.int64)
 
     def _key(self, p):
         c = np.floor((p % self.L) / self.cell).astype(int) % self.n
         return int(c[0]), int(c[1]), int(c[2])
 
     def add(self, p):
-        self.buckets.setdefault(self._key(p), []).append(np.asarray(p, dtype=float))
+        p = np.asarray(p, dtype=float)
+        key = self._key(p)
+        self.buckets.setdefault(key, []).append(p)
+        k = self.cnt[key]
+        if k >= self.arr.shape[3]:  # grow the padded array
+            grown = np.full(self.arr.shape[:3] + (2 * self.arr.shape[3], 3), np.nan)
+            grown[:, :, :, :self.arr.shape[3]] = self.arr
+            self.arr = grown
+        self.arr[key][k] = p
+        self.cnt[key] += 1
 
     def too_close(self, p, dmin: float) -> bool:
         cx, cy, cz = self._key(p)
@@ -113,24 +128,74 @@ class _Grid:
                             return True
         return False
 
+    def too_close_many(self, P, dmin: float) -> np.ndarray:
+        """too_close for each row of P, against the points present now.  The vectorised
+        squared distances decide every clear case; a candidate within a relative 1e-9 of
+        the limit is decided by the scalar test, so the answers are exactly too_close's."""
+        P = np.asarray(P, dtype=float)
+        reach = int(math.ceil(dmin / self.cell))
+        n = self.n
+        c = np.floor((P % self.L) / self.cell).astype(int) % n
+        if getattr(self, "_stencil", (None,))[0] != reach:
+            offs = np.arange(-reach, reach + 1)
+            ox, oy, oz = np.meshgrid(offs, offs, offs, indexing="ij")
+            self._stencil = (reach, np.stack([ox.ravel(), oy.ravel(), oz.ravel()], 1))
+        cells = (c[:, None, :] + self._stencil[1][None]) % n                                   # [m][27][3]
+        # a cell reached twice (n < 2 reach + 1) holds the same points: counting them twice is harmless
+        kmax = max(1, int(self.cnt.max()))
+        Q = self.arr[cells[..., 0], cells[..., 1], cells[..., 2], :kmax]                        # [m][27][K][3]
+        d = Q - P[:, None, None, :]
+        d -= self.L * np.rint(d / self.L)
+        d2 = np.sum(d * d, axis=-1)
+        lim = dmin * dmin
+        with np.errstate(invalid="ignore"):
+            close = np.any(d2 < lim * (1.0 - 1e-9), axis=(1, 2))
+            edge = np.any(np.abs(d2 - lim) <= lim * 1e-9, axis=(1, 2)) & ~close
+        for i in np.nonzero(edge)[0]:
+            close[i] = self.too_close(P[i], dmin)
+        return close
+
 
 def _insert_waters(rng, L, n_water, chain_grid=None, max_tries=2000):
+    """Random sequential insertion of rigid waters.  Each batch of candidates is first
+    tested against the oxygens already placed (vectorised); the survivors are then taken
+    in order, each tested against the oxygens accepted earlier in the same batch and
+    against the chain, exactly as a one-by-one insertion would."""
     tmpl = _water_template()
     o_grid = _Grid(L, OO_MIN)
     out = []
     batch = 256
+    lim = OO_MIN * OO_MIN
     while len(out) < n_water:
         cand = rng.uniform(0.0, L, size=(batch, 3))
         rots = _random_rotations(rng, batch)
-        for c, R in zip(cand, rots):
+        free = np.nonzero(~o_grid.too_close_many(cand, OO_MIN))[0]
+        # clash[a, b]: free candidates a and b closer than OO_MIN (decided as too_close does)
+        F = cand[free]
+        d = F[:, None, :] - F[None, :, :]
+        d -= L * np.rint(d / L)
+        d2 = np.sum(d * d, axis=-1)
+        clash = d2 < lim * (1.0 - 1e-9)
+        for a, b in zip(*np.nonzero((np.abs(d2 - lim) <= lim * 1e-9) & ~clash)):
+            e = F[a] - F[b]
+            e -= L * np.rint(e / L)
+            clash[a, b] = e @ e < lim
+        mols = [cand[k] + tmpl @ rots[k].T for k in free]
+        if chain_grid is not None and len(free):
+            wet = chain_grid.too_close_many(np.concatenate(mols, 0), CHAIN_WATER_MIN).reshape(-1, 3).any(1)
+        else:
+            wet = np.zeros(len(free), dtype=bool)
+        taken = []
+        for a, k in enumerate(free):
             if len(out) >= n_water:
                 break
-            if o_grid.too_close(c, OO_MIN):
+            if taken and clash[taken, a].any():
                 continue
-            mol = c + tmpl @ R.T
-            if chain_grid is not None and any(chain_grid.too_close(a, CHAIN_WATER_MIN) for a in mol):
+            mol = mols[a]
+            if wet[a]:
                 continue
-            o_grid.add(c)
+            o_grid.add(cand[k])
+            taken.append(a)
             out.append(mol)
         max_tries -= 1
         if max_tries <= 0:
