@@ -124,7 +124,8 @@ int dp_debug_pair_grads(dp_model *m, int64_t natoms, float *g);
  * enable != 0 clears and starts accumulating, 0 stops.  dp_profile_read fills,
  * for up to `max` phases, the summed milliseconds and the number of calls:
  * phase 0 neighbour lists, 1 descriptor forward, 2 fitting net, 3 energy
- * reduction, 4 descriptor backward, 5 forces and virial.  Returns the number
+ * reduction (energy-only calls; a full step reduces the energy with the virial in
+ * phase 5), 4 descriptor backward, 5 forces, energy and virial reductions.  Returns the number
  * of phases (DP_NPHASES). */
 #define DP_NPHASES 6
 int dp_profile_enable(dp_model *m, int enable);

@@ -380,7 +380,7 @@ int build_weights(dp_model *m, const HostModel &h) {
 }  // namespace
 
 void free_ws(Workspace &ws) {
-  void *ps[] = {ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev,
+  void *ps[] = {ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ws.cell_atoms, ws.nlist, ws.nnei, ws.done,
                 ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart, ws.red, ws.grids, ws.sys_off, ws.sys_of, ws.slist,
                 ws.snnei, ws.xref, ws.flags, ws.gE, ws.bidx, ws.bcnt};
   for (void *p : ps)
@@ -397,7 +397,7 @@ void free_ws(Workspace &ws) {
 // Device bytes the workspace holds per atom (the serving admission model uses it).
 size_t ws_bytes_per_atom(int prec) {
   size_t b = 4 * sizeof(int)                              // cell_of, cell_atoms, nnei, sys_of
-             + 2 * (size_t)SEL * sizeof(int)              // nlist, rev
+             + (size_t)SEL * sizeof(int)                  // nlist
              + (size_t)M * 4 * sizeof(float)              // Tsave
              + (size_t)ND * sizeof(float)                 // D
              + sizeof(double)                             // Ei
@@ -426,12 +426,14 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     const int cs = std::max(nsys, 8);
     if (ws.grids) (void)hipFree(ws.grids);
     if (ws.sys_off) (void)hipFree(ws.sys_off);
+    if (ws.done) (void)hipFree(ws.done);
     if (ws.grids_host) (void)hipHostFree(ws.grids_host);
     if (ws.off_host) (void)hipHostFree(ws.off_host);
-    ws.grids = nullptr; ws.sys_off = nullptr; ws.grids_host = nullptr; ws.off_host = nullptr;
+    ws.grids = nullptr; ws.sys_off = nullptr; ws.done = nullptr; ws.grids_host = nullptr; ws.off_host = nullptr;
     ws.cap_sys = 0;
     HIP_TRY(hipMalloc(&ws.grids, cs * sizeof(Grid)));
     HIP_TRY(hipMalloc(&ws.sys_off, (cs + 1) * sizeof(int)));  // cs >= 8: [2..3] also hold a centre range
+    HIP_TRY(hipMalloc(&ws.done, (2 * cs + 1) * sizeof(int)));
     HIP_TRY(hipHostMalloc(&ws.grids_host, cs * sizeof(Grid), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&ws.off_host, (cs + 1) * sizeof(int), hipHostMallocDefault));
     ws.cap_sys = cs;
@@ -439,11 +441,11 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
   }
   if (n > ws.cap) {
     const int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
-    void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.rev, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g,
+    void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g,
                   ws.vpart, ws.sys_of, ws.slist, ws.snnei, ws.xref, ws.bidx};
     for (void *p : ps)
       if (p) (void)hipFree(p);
-    ws.cell_of = ws.cell_atoms = ws.nlist = ws.nnei = ws.rev = ws.sys_of = ws.slist = ws.snnei = ws.bidx = nullptr;
+    ws.cell_of = ws.cell_atoms = ws.nlist = ws.nnei = ws.sys_of = ws.slist = ws.snnei = ws.bidx = nullptr;
     ws.Gsave = ws.Tsave = ws.D = nullptr;
     ws.Ei = ws.vpart = ws.xref = nullptr;
     ws.g = nullptr;
@@ -453,7 +455,6 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.sys_of, cap * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.nlist, cap * SEL * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.nnei, cap * sizeof(int)));
-    HIP_TRY(hipMalloc(&ws.rev, cap * SEL * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * GSAVE_LAYER * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.bidx, 2 * cap * sizeof(int)));
@@ -508,12 +509,12 @@ size_t carve_ws(Workspace &ws, unsigned char *base, int64_t cap) {
   take(ws.bcnt, 2 * sizeof(int));
   take(ws.grids, sizeof(Grid));
   take(ws.sys_off, 4 * sizeof(int));
+  take(ws.done, 3 * sizeof(int));
   take(ws.sys_of, c * sizeof(int));
   take(ws.cell_of, c * sizeof(int));
   take(ws.cell_atoms, c * sizeof(int));
   take(ws.nlist, c * SEL * sizeof(int));
   take(ws.nnei, c * sizeof(int));
-  take(ws.rev, c * SEL * sizeof(int));
   take(ws.Gsave, c * NATTN * GSAVE_LAYER * sizeof(float));
   take(ws.Tsave, c * M * 4 * sizeof(float));
   take(ws.bidx, 2 * c * sizeof(int));
@@ -610,10 +611,6 @@ int flags_status(unsigned f) {
   return DP_OK;
 }
 
-__global__ void k_zero_u32(unsigned *p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
-}
-
 // Event k is recorded before phase k (k = 0..5) and after the last phase.
 void mark(dp_model *m, int k, hipStream_t st) {
   if (m->prof) (void)hipEventRecord(m->ev[k], st);
@@ -640,7 +637,6 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   const int n = (int)a.n;
   // centres: every atom, or (one system with ghost atoms) the first n_centres
   const int nc = (a.nsys == 1 && a.n_centres >= 0 && a.n_centres < a.n) ? (int)a.n_centres : n;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
   if (!a.open_single) HIP_TRY(hipMemcpyAsync(ws.grids, ws.grids_host, a.nsys * sizeof(Grid), hipMemcpyHostToDevice, st));
   if (nc < n) {  // off_host[2..3]: the centre range, reduced for the energy
     ws.off_host[2] = 0;
@@ -648,7 +644,7 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   }
   HIP_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, (nc < n ? 4 : a.nsys + 1) * sizeof(int), hipMemcpyHostToDevice,
                          st));
-  launch_sys_of(ws, a.nsys, n, st);
+  launch_prologue(ws, a.nsys, n, a.lists == LISTS_SKIN_REUSE ? 0 : a.ncells + 1, st);
   if (pm) mark(pm, 0, st);
   switch (a.lists) {
     case LISTS_FRESH:
@@ -668,7 +664,6 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
       break;
     }
   }
-  launch_rev(ws, n, st);
   HIP_TRY(hipGetLastError());
   const float rc = (float)m->rc, rcs = (float)m->rcs, eps = (float)m->ln_eps;
   const bool bwd = a.forces || a.virial;
@@ -683,7 +678,9 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   else
     launch_fitting<float>(m->wf, ws, a.types, nc, bwd, st);
   if (pm) mark(pm, 3, st);
-  launch_energy(ws, nc < n ? ws.sys_off + 2 : ws.sys_off, a.nsys, a.energy, a.atom_energy, st);
+  // energies over the centre atoms (every atom, or the first nc of one system with ghosts)
+  const int *eoff = nc < n ? ws.sys_off + 2 : ws.sys_off;
+  if (!bwd) launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, nullptr, st);
   if (pm) mark(pm, 4, st);
   if (bwd) {
     if (m->prec == DP_BF16)
@@ -693,7 +690,8 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
     if (pm) mark(pm, 5, st);
     double *F = a.forces;
     if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
-    launch_forces(ws, a.X, n, a.nsys, nullptr, F, a.virial, a.lists == LISTS_SKIN_REUSE, st);
+    launch_forces(ws, a.X, n, nullptr, F, a.lists == LISTS_SKIN_REUSE, nc < n, st);
+    launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, a.virial, st);
     if (pm) mark(pm, 6, st);
   }
   HIP_TRY(hipGetLastError());
@@ -1230,7 +1228,8 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
     launch_fitting_b16(m->wf, m->wp, ws, m->fwd_types, n, true, st);
     launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, n, rc, rcs, eps, st);
   }
-  launch_forces(ws, m->fwd_coords, n, 1, d_grad_energy, d_grad_coords, d_virial, m->fwd_lists == LISTS_SKIN_REUSE, st);
+  launch_forces(ws, m->fwd_coords, n, d_grad_energy, d_grad_coords, m->fwd_lists == LISTS_SKIN_REUSE, false, st);
+  if (d_virial) launch_reduce(ws, ws.sys_off, 1, nullptr, nullptr, d_virial, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   m->fwd_valid = false;
@@ -1322,8 +1321,7 @@ int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const 
       hipMemcpy(ws.sys_off, ws.off_host, 2 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     s = DP_ERR_HIP;
   } else {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ws.flags, 4);
-    launch_sys_of(ws, 1, (int)natoms, st);
+    launch_prologue(ws, 1, (int)natoms, (open ? MAX_CELLS : g.ncells) + 1, st);
     launch_cells(ws, dX, dT, (int)natoms, m->ntypes, open, open ? MAX_CELLS : g.ncells, m->rc, st);
     launch_nlist(ws, dX, (int)natoms, (int)natoms, m->rc, false, st);
     if (hipStreamSynchronize(st) != hipSuccess ||

@@ -102,6 +102,7 @@ constexpr int KM = 112;   // padded feature width
 constexpr int LDK = 120;  // stride (elements) of [token][feature] bf16 arrays
 constexpr int LDT = 136;  // stride of [feature or row][token] bf16 arrays (tokens padded to 128)
 constexpr int NWF = 8;    // waves per workgroup, forward
+constexpr int SPLIT_NB = 7;  // atoms with up to this many row blocks go to the 7-wave backward instance
 typedef short s4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf8 ld8(const bf16_t *p) { return *(const bf8 *)p; }

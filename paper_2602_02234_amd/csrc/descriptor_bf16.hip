@@ -19,13 +19,17 @@ __global__ void __launch_bounds__(NWF * 64)
 k_desc_fwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
                const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
                float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
-               float *__restrict__ D) {
+               float *__restrict__ D, int *__restrict__ bidx, int *__restrict__ bcnt, int cap) {
   __shared__ SmemF16 sm;
   const int i = blockIdx.x;
   const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
   const int nb = NP / 16;
+  if (threadIdx.x == 0) {  // list the atom for the backward instance that fits its block count
+    const int cls = nb <= SPLIT_NB ? 0 : 1;
+    bidx[cls * cap + atomicAdd(&bcnt[cls], 1)] = i;
+  }
   const int ti = clamp_type(types[i]);
   const int wv = wave_id(), l = lane(), q = l >> 4, cl = l & 15;
   build_envb(sm.e, X, types, nlist, i, n, natoms, g, rc, rcs);
@@ -101,7 +105,7 @@ void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Work
                                const double *coords, const int *types, int n, int ncen,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
   hipLaunchKernelGGL(k_desc_fwd_b16, dim3(ncen), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
-                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
+                     ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.bidx, ws.bcnt, (int)ws.cap);
 }
 
 }  // namespace dp

@@ -557,59 +557,14 @@ k_desc_bwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int 
   for (int j = NP + threadIdx.x; j < SEL; j += NW * 64) gout[(size_t)i * SEL + j] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Stable partition of the atoms by row-block count: idx[0..c0) the atoms with at most
-// SPLIT_NB blocks of 16 neighbours, idx[cap..cap+c1) the others; count[0] = c0, count[1] = c1.
-constexpr int SPLIT_NB = 7;
-__global__ void __launch_bounds__(1024) k_partition(const int *__restrict__ nnei, int n, int cap, int *__restrict__ idx,
-                                                    int *__restrict__ count) {
-  __shared__ int sc[1024];
-  __shared__ int base[2];
-  if (threadIdx.x == 0) base[0] = base[1] = 0;
-  __syncthreads();
-  for (int c0 = 0; c0 < n; c0 += 1024) {
-    const int a = c0 + threadIdx.x;
-    int f = 0;  // 1: small, 2: large, 0: none
-    if (a < n) {
-      const int na = min(max(nnei[a], 0), SEL);
-      f = ((max(na, 1) + 15) / 16 <= SPLIT_NB) ? 1 : 2;
-    }
-    // inclusive scan of the small flags (Hillis-Steele)
-    sc[threadIdx.x] = (f == 1);
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
-      __syncthreads();
-      sc[threadIdx.x] += v;
-      __syncthreads();
-    }
-    const int small_incl = sc[threadIdx.x];
-    const int small_tot = sc[1023];
-    const int valid = min(1024, n - c0);
-    const int pos_small = base[0] + small_incl - 1;
-    const int pos_large = base[1] + ((int)threadIdx.x - small_incl + (f == 1 ? 1 : 0));
-    if (f == 1) idx[pos_small] = a;
-    if (f == 2) idx[cap + pos_large] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      base[0] += small_tot;
-      base[1] += valid - small_tot;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    count[0] = base[0];
-    count[1] = base[1];
-  }
-}
-
 }  // namespace
 
 void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
                                const double *coords, const int *types, int n, int ncen,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_partition, dim3(1), dim3(1024), 0, st, ws.nnei, ncen, (int)ws.cap, ws.bidx, ws.bcnt);
   // atoms with up to 7 row blocks: 7 waves, one block each (on st); the rest: 4 waves,
-  // two blocks each, on the side stream, so that a few dense atoms overlap the bulk
+  // two blocks each, on the side stream, so that a few dense atoms overlap the bulk.  The
+  // forward pass listed the atoms of each instance (bidx, bcnt).
   (void)hipEventRecord(ws.fork_ev, st);
   (void)hipStreamWaitEvent(ws.side, ws.fork_ev, 0);
   hipLaunchKernelGGL((k_desc_bwd_b16<4, 2>), dim3(ncen), dim3(4 * 64), 0, ws.side, w, wp, coords, types, n, ws.nlist,

@@ -117,11 +117,12 @@ struct Workspace {
   int *cell_atoms = nullptr;  // [cap]
   int *nlist = nullptr;       // [cap][SEL]
   int *nnei = nullptr;        // [cap]
-  int *rev = nullptr;         // [cap][SEL]
   float *Gsave = nullptr;     // [cap][NATTN][GSAVE_LAYER]  inputs of each attention layer
   float *Tsave = nullptr;     // [cap][M][4]
   int *bidx = nullptr;        // [2][cap]  atoms of each backward kernel instance (bf16 path)
   int *bcnt = nullptr;        // [2]
+  int *done = nullptr;        // [2 cap_sys + 1]  completion counters (the cell pass's workgroup counter
+                              // at [2 cap_sys]); cleared at the start of each step
   float *D = nullptr;         // [cap][ND]  descriptor, then dE/dD
   double *Ei = nullptr;       // [cap] atomic energies
   float4 *g = nullptr;        // [cap][SEL]  dE_i/dDelta_ij
@@ -213,7 +214,8 @@ void set_error(const std::string &s);
 
 // Launchers (defined in the kernel translation units); all enqueue on `st` and read the
 // per-system grids (ws.grids), atom ranges (ws.sys_off) and atom -> system map (ws.sys_of).
-void launch_sys_of(const Workspace &ws, int nsys, int n, hipStream_t st);
+// Clears the step's counters and flags (and ncells_zero cell counts) and maps atoms to systems.
+void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, hipStream_t st);
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
                   int ncells_total, double cell_cutoff, hipStream_t st);
 // Lists for the first ncen atoms (the others get empty lists), candidates among all n.
@@ -223,12 +225,12 @@ void launch_filter(const Workspace &ws, const double *coords, int n, double rc, 
 void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
                        hipStream_t st);
 void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st);
-void launch_rev(const Workspace &ws, int n, hipStream_t st);
 // The per-centre launchers run over the first ncen atoms (the centres), reading the
 // coordinates and types of all n atoms as neighbours.
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
                            int n, int ncen, float rc, float rcs, float ln_eps, hipStream_t st);
+// The fitting net over the first n atoms (E_i, and dE/dD over D when backward).
 template <typename T>
 void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward,
                     hipStream_t st);
@@ -243,13 +245,15 @@ void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
                            int n, int ncen, float rc, float rcs, float ln_eps, hipStream_t st);
-// skin_rows: the step reused skin lists (one-sided pairs are then found through the skin rows,
-// else through the cell list of the step).
-void launch_forces(const Workspace &ws, const double *coords, int n, int nsys, const double *gE, double *forces,
-                   double *virial_out, bool skin_rows, hipStream_t st);
-// Per-system energies over the atom ranges off[s] .. off[s+1]-1 (device offsets).
-void launch_energy(const Workspace &ws, const int *off, int nsys, double *energy, double *atom_energy,
-                   hipStream_t st);
+// Forces of all n atoms and the per-atom virial partials.  skin_rows: the step reused skin
+// lists (one-sided pairs are then found through the skin rows, else through the cell list
+// of the step); ghosts: atoms without lists are present.
+void launch_forces(const Workspace &ws, const double *coords, int n, const double *gE, double *forces,
+                   bool skin_rows, bool ghosts, hipStream_t st);
+// Per-system energies (E_i over the device ranges eoff) and, if virial, virials (vpart over
+// ws.sys_off), float64 Neumaier in a fixed order; energy and atom_energy may be NULL.
+void launch_reduce(const Workspace &ws, const int *eoff, int nsys, double *energy, double *atom_energy,
+                   double *virial, hipStream_t st);
 // out[0] = Neumaier sum of src over the atoms of system 0 (fixed order).
 void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st);
 

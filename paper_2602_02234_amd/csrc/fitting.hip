@@ -14,6 +14,10 @@ namespace {
 constexpr int LDF = FH + 4;
 
 template <typename T>
+__device__ void fit_backward(const Weights<T> &w, int a0, int n, float *__restrict__ D, float *y1, float *t2,
+                             float *t3, float *bA, float *bB);
+
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
 k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D, double *__restrict__ Ei,
       int backward) {
@@ -67,7 +71,15 @@ k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D,
     for (int o = 0; o < FH; ++o) e += (double)bA[r * LDF + o] * w.F4d[o];
     Ei[a0 + r] = e + w.c4 + w.ebias[ty];
   }
-  if (!backward) return;
+  if (backward) fit_backward(w, a0, n, D, y1, t2, t3, bA, bB);
+}
+
+// dE/dD of the workgroup's 16 atoms, written over D (activations from the forward in LDS).
+template <typename T>
+__device__ void fit_backward(const Weights<T> &w, int a0, int n, float *__restrict__ D, float *y1, float *t2,
+                             float *t3, float *bA, float *bB) {
+  const int wv = wave_id();
+  constexpr int NT = FH / 16;
   for (int q = threadIdx.x; q < 16 * FH; q += NTHREADS) {
     const int r = q / FH, o = q % FH;
     const float tt = t3[r * LDF + o];

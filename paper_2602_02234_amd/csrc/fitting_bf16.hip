@@ -154,62 +154,63 @@ k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *
     for (int t = 0; t < NT; ++t) e += ep[r][t];
     Ei[a0 + r] = e + w.c4 + w.ebias[ty];
   }
-  if (!backward) return;
-  // dy2 = dpre3 F3^T + F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
-  mm_split2(acc, X, LDA, wp.F3[0], wp.F3[1], KH);
-  __syncthreads();  // every wave has read X
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = wv + NWT * u;
-    if (t < NT)
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii, c = 16 * t + cl;
-        const float dy2 = acc[u][ii] + w.F4[c];
-        const float tt = t2[r * LDA + c];
-        y2[r * LDA + c] = dy2;
-        X[r * LDA + c] = dy2 * (1.f - tt * tt);
-      }
-  }
-  __syncthreads();
-  // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
-  mm_split2(acc, X, LDA, wp.F2[0], wp.F2[1], KH);
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = wv + NWT * u;
-    if (t < NT)
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii, c = 16 * t + cl;
-        const float dy1 = acc[u][ii] + y2[r * LDA + c];
-        const float yy = y1[r * LDA + c];
-        X[r * LDA + c] = dy1 * (1.f - yy * yy);
-      }
-  }
-  __syncthreads();
-  // dE/dD = dpre1 F1^T  (100 column tiles, in two passes over k)
-  {
-    f4 dacc[7];
-    mm_split_dd<0, 7>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
-#pragma unroll
-    for (int u = 0; u < 7; ++u) {
+  if (backward) {
+    // dy2 = dpre3 F3^T + F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
+    mm_split2(acc, X, LDA, wp.F3[0], wp.F3[1], KH);
+    __syncthreads();  // every wave has read X
+  #pragma unroll
+    for (int u = 0; u < 2; ++u) {
       const int t = wv + NWT * u;
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii;
-        if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
-      }
+      if (t < NT)
+        for (int ii = 0; ii < 4; ++ii) {
+          const int r = 4 * q + ii, c = 16 * t + cl;
+          const float dy2 = acc[u][ii] + w.F4[c];
+          const float tt = t2[r * LDA + c];
+          y2[r * LDA + c] = dy2;
+          X[r * LDA + c] = dy2 * (1.f - tt * tt);
+        }
     }
-  }
-  {
-    f4 dacc[6];
-    mm_split_dd<7, 13>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
-#pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      const int t = wv + NWT * (u + 7);
-      if (t < ND / 16)
+    __syncthreads();
+    // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
+    mm_split2(acc, X, LDA, wp.F2[0], wp.F2[1], KH);
+    __syncthreads();
+  #pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = wv + NWT * u;
+      if (t < NT)
+        for (int ii = 0; ii < 4; ++ii) {
+          const int r = 4 * q + ii, c = 16 * t + cl;
+          const float dy1 = acc[u][ii] + y2[r * LDA + c];
+          const float yy = y1[r * LDA + c];
+          X[r * LDA + c] = dy1 * (1.f - yy * yy);
+        }
+    }
+    __syncthreads();
+    // dE/dD = dpre1 F1^T  (100 column tiles, in two passes over k)
+    {
+      f4 dacc[7];
+      mm_split_dd<0, 7>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
+  #pragma unroll
+      for (int u = 0; u < 7; ++u) {
+        const int t = wv + NWT * u;
         for (int ii = 0; ii < 4; ++ii) {
           const int r = 4 * q + ii;
           if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
         }
+      }
+    }
+    {
+      f4 dacc[6];
+      mm_split_dd<7, 13>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
+  #pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        const int t = wv + NWT * (u + 7);
+        if (t < ND / 16)
+          for (int ii = 0; ii < 4; ++ii) {
+            const int r = 4 * q + ii;
+            if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
+          }
+      }
     }
   }
 }

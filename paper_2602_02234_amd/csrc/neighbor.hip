@@ -12,6 +12,8 @@
 // This file is built with -ffp-contract=off; the pragma keeps that true here.
 #pragma clang fp contract(off)
 
+#include <algorithm>
+
 #include "dp_internal.h"
 
 namespace dp {
@@ -68,72 +70,86 @@ __global__ void __launch_bounds__(1024) k_grid_open(const double *__restrict__ X
   }
 }
 
-__global__ void k_fill_int(int *__restrict__ p, int n, int v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-// sys_of[a] = s for off[s] <= a < off[s + 1].
-__global__ void k_sys_of(const int *__restrict__ off, int nsys, int n, int *__restrict__ sys_of) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  int lo = 0, hi = nsys - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= a) lo = mid; else hi = mid - 1;
+// Start of a step: clears the status words, the per-system completion counters and the
+// backward instances' atom counts, clears the cell counts (ncz entries), and writes
+// sys_of[a] = s for off[s] <= a < off[s + 1].  Grid-stride; no workgroup depends on another.
+__global__ void k_prologue(const int *__restrict__ off, int nsys, int n, int *__restrict__ sys_of,
+                           int *__restrict__ cell_count, int ncz, unsigned *__restrict__ flags,
+                           int *__restrict__ done, int ndone, int *__restrict__ bcnt) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < max(max(n, ncz), ndone); t += stride) {
+    if (t < 4) flags[t] = 0u;
+    if (t < 2) bcnt[t] = 0;
+    if (t < ndone) done[t] = 0;
+    if (t < ncz) cell_count[t] = 0;
+    if (t < n) {
+      int lo = 0, hi = nsys - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      sys_of[t] = lo;
+    }
   }
-  sys_of[a] = lo;
 }
 
-__global__ void k_cell_assign(const double *__restrict__ X, const int *__restrict__ types, int n, int ntypes,
-                              const Grid *__restrict__ grids, const int *__restrict__ sys_of, int *__restrict__ cell_of,
-                              int *__restrict__ cell_count, unsigned *__restrict__ flags) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Grid g = grids[sys_of[i]];
-  const int t = types[i];
-  if (t < 0 || t >= ntypes) atomicOr(flags, FLAG_TYPE);
-  int c[3];
-  bool ok = true;
-  for (int a = 0; a < 3; ++a) {
-    const double x = X[3 * i + a];
-    if (!isfinite(x)) { ok = false; c[a] = 0; continue; }
-    double w;
-    if (g.periodic) w = x - g.L[a] * floor(x * g.invL[a]);
-    else w = x - g.origin[a];
-    c[a] = clampi((int)floor(w * g.icw[a]), 0, g.nc[a] - 1);
-  }
-  if (!ok) atomicOr(flags, FLAG_NONFINITE);
-  const int cell = g.cell_base + (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
-  cell_of[i] = cell;
-  atomicAdd(&cell_count[cell], 1);
-}
-
-// Exclusive scan of the cell counts; one workgroup of 1024 threads.  The number of
-// cells is nc_host, or the cell count of *open_grid when that is given.
-__global__ void __launch_bounds__(1024) k_cell_scan(const int *__restrict__ count, int *__restrict__ start,
-                                                    int *__restrict__ cursor, int nc_host,
-                                                    const Grid *__restrict__ open_grid) {
+// Cell of each atom and the cell counts; the last workgroup to finish then turns the
+// counts into start offsets (exclusive scan over the ncells_host cells, or the cell count
+// of *open_grid) and resets the fill cursors.  *blocks_done must be zero at the start.
+__global__ void __launch_bounds__(1024) k_cell_assign(
+    const double *__restrict__ X, const int *__restrict__ types, int n, int ntypes, const Grid *__restrict__ grids,
+    const int *__restrict__ sys_of, int *__restrict__ cell_of, int *__restrict__ cell_count,
+    int *__restrict__ start, int *__restrict__ cursor, int ncells_host, const Grid *__restrict__ open_grid,
+    int *__restrict__ blocks_done, unsigned *__restrict__ flags) {
   __shared__ int part[1024];
-  const int nc = open_grid ? open_grid->ncells : nc_host;
+  __shared__ bool is_last;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const Grid g = grids[sys_of[i]];
+    const int t = types[i];
+    if (t < 0 || t >= ntypes) atomicOr(flags, FLAG_TYPE);
+    int c[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      const double x = X[3 * i + a];
+      if (!isfinite(x)) { ok = false; c[a] = 0; continue; }
+      double w;
+      if (g.periodic) w = x - g.L[a] * floor(x * g.invL[a]);
+      else w = x - g.origin[a];
+      c[a] = clampi((int)floor(w * g.icw[a]), 0, g.nc[a] - 1);
+    }
+    if (!ok) atomicOr(flags, FLAG_NONFINITE);
+    const int cell = g.cell_base + (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+    cell_of[i] = cell;
+    atomicAdd(&cell_count[cell], 1);
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    is_last = atomicAdd(blocks_done, 1) == (int)gridDim.x - 1;
+    __threadfence();
+  }
+  __syncthreads();
+  if (!is_last) return;
+  // exclusive scan of the cell counts by this (last) workgroup
+  const int nc = open_grid ? open_grid->ncells : ncells_host;
   const int per = (nc + 1023) / 1024;
   const int b = threadIdx.x * per, e = min(nc, b + per);
-  int s = 0;
-  for (int c = b; c < e; ++c) s += count[c];
-  part[threadIdx.x] = s;
+  int sum = 0;
+  for (int k = b; k < e; ++k) sum += cell_count[k];
+  part[threadIdx.x] = sum;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 partial sums
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+  for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan of the partial sums
+    const int v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
     __syncthreads();
     part[threadIdx.x] += v;
     __syncthreads();
   }
   int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-  for (int c = b; c < e; ++c) {
-    start[c] = run;
-    cursor[c] = run;
-    run += count[c];
+  for (int k = b; k < e; ++k) {
+    start[k] = run;
+    cursor[k] = run;
+    run += cell_count[k];
   }
   if (threadIdx.x == 1023) start[nc] = part[1023];
 }
@@ -343,49 +359,23 @@ __global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ 
   if (i < n) dst[i] = src[i];
 }
 
-// rev[i][s] = slot of i in the list of j = nlist[i][s], or -1 (lists sorted ascending).
-__global__ void k_rev(const int *__restrict__ nlist, const int *__restrict__ nnei, int *__restrict__ rev, int n,
-                      unsigned *__restrict__ flags) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)n * SEL) return;
-  const int i = (int)(t / SEL), s = (int)(t % SEL);
-  int r = -1;
-  if (s < nnei[i]) {
-    const int j = nlist[t];
-    if (j < 0 || j >= n) {
-      rev[t] = -1;
-      return;
-    }
-    const int *row = nlist + (size_t)j * SEL;
-    int lo = 0, hi = min(nnei[j], SEL) - 1;
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int v = row[mid];
-      if (v == i) { r = mid; break; }
-      if (v < i) lo = mid + 1; else hi = mid - 1;
-    }
-    if (r < 0) atomicAdd(flags + 2, 1u);
-  }
-  rev[t] = r;
-}
-
 }  // namespace
 
-void launch_sys_of(const Workspace &ws, int nsys, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_sys_of, dim3((n + 255) / 256), dim3(256), 0, st, ws.sys_off, nsys, n, ws.sys_of);
+void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, hipStream_t st) {
+  const int work = std::max(n, ncells_zero);
+  const int blocks = std::max(1, std::min((work + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_prologue, dim3(blocks), dim3(256), 0, st, ws.sys_off, nsys, n, ws.sys_of, ws.cell_count,
+                     ncells_zero, ws.flags, ws.done, 2 * ws.cap_sys + 1, ws.bcnt);
 }
 
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
                   int ncells_total, double cell_cutoff, hipStream_t st) {
   if (open_single)
     hipLaunchKernelGGL(k_grid_open, dim3(1), dim3(1024), 0, st, coords, n, cell_cutoff, ws.grids, ws.flags);
-  const int ncell_alloc = open_single ? MAX_CELLS : ncells_total;
-  hipLaunchKernelGGL(k_fill_int, dim3((ncell_alloc + 1 + 255) / 256), dim3(256), 0, st, ws.cell_count,
-                     ncell_alloc + 1, 0);
-  hipLaunchKernelGGL(k_cell_assign, dim3((n + 255) / 256), dim3(256), 0, st, coords, types, n, ntypes, ws.grids,
-                     ws.sys_of, ws.cell_of, ws.cell_count, ws.flags);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, ws.cell_count, ws.cell_start, ws.cell_cursor,
-                     ncells_total, open_single ? ws.grids : (const Grid *)nullptr);
+  // the block counter of the assign pass is the last completion counter (cleared by the prologue)
+  hipLaunchKernelGGL(k_cell_assign, dim3((n + 1023) / 1024), dim3(1024), 0, st, coords, types, n, ntypes, ws.grids,
+                     ws.sys_of, ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ncells_total,
+                     open_single ? ws.grids : (const Grid *)nullptr, ws.done + 2 * ws.cap_sys, ws.flags);
   hipLaunchKernelGGL(k_cell_fill, dim3((n + 255) / 256), dim3(256), 0, st, ws.cell_of, ws.cell_cursor,
                      ws.cell_atoms, n);
 }
@@ -410,12 +400,6 @@ void launch_skin_check(const Workspace &ws, const double *coords, const int *typ
 
 void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_f64, dim3((3 * n + 255) / 256), dim3(256), 0, st, coords, ws.xref, 3 * n);
-}
-
-void launch_rev(const Workspace &ws, int n, hipStream_t st) {
-  const long long tot = (long long)n * SEL;
-  hipLaunchKernelGGL(k_rev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.nlist, ws.nnei, ws.rev, n,
-                     ws.flags);
 }
 
 }  // namespace dp
