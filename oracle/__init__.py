@@ -15,7 +15,8 @@ the potential; neighbour lists within a cutoff, Section II and IV):
 * :mod:`oracle.neighbors` -- brute-force O(N^2) neighbour lists under an
   exact FP64 rule, and an independent cell-list search that must equal it;
 * :mod:`oracle.dp` -- the model forward, its reverse-mode gradient written by
-  hand, forces by gather, virial, and per-atom evaluation of a subset;
+  hand, forces by gather, virial, per-atom evaluation of a subset, and models
+  with several fitting heads on one descriptor;
 * :mod:`oracle.nve` -- a velocity-Verlet driver for the energy-drift check.
 
 The paper prints no model equations; the functional form follows the reading
@@ -28,5 +29,5 @@ DPA models themselves is parity unpinned (no weights, no equations).
 from .model_file import load_model  # noqa: F401
 from .neighbors import neighbor_list_bruteforce, neighbor_list_cells  # noqa: F401
 from .dp import (  # noqa: F401
-    switch, atom_energy_and_grad, evaluate, evaluate_subset, forces_from_pairs,
+    switch, atom_energy_and_grad, evaluate, evaluate_subset, forces_from_pairs, head_view, evaluate_heads,
 )

@@ -245,3 +245,34 @@ def local_energy(m, X, types, box, atoms):
         Ei, _ = atom_energy_and_grad(m, int(types[i]), types[js], _pair_vectors(X, L, i, js), want_grad=False)
         out.append(Ei)
     return math.fsum(out)
+
+
+# ----------------------------------------------------------------------------- fitting heads
+def head_view(m, h: int):
+    """The model with fitting head h in place of head 0; every other array is shared.
+
+    Several fitting nets on one descriptor (the paper's multi-task models, Section II,
+    share one descriptor between branches): head h maps the same D to its own E_i^h.
+    """
+    import copy
+    v = copy.copy(m)
+    v.p = dict(m.p)
+    v.p.update(m.heads[h])
+    return v
+
+
+def evaluate_heads(m, X, types, box, weights):
+    """Energy, forces and virial of the weighted head combination E = sum_h w_h E^h, plus
+    every head's total energy.  Each head is a plain evaluation of its own model view;
+    forces and virial are linear in the energy, so they combine with the same weights."""
+    out = {"E_heads": [], "E": 0.0, "F": 0.0, "virial": 0.0, "E_i": 0.0}
+    for h in range(len(m.heads)):
+        r = evaluate(head_view(m, h), X, types, box)
+        out["E_heads"].append(r["E"])
+        w = float(weights[h])
+        out["E"] = out["E"] + w * r["E"]
+        out["F"] = out["F"] + w * r["F"]
+        out["virial"] = out["virial"] + w * r["virial"]
+        out["E_i"] = out["E_i"] + w * r["E_i"]
+    out["E_heads"] = np.array(out["E_heads"])
+    return out

@@ -7,7 +7,10 @@ uint64 seed; 16 reserved bytes) followed by float64 arrays in this order:
 type embedding [ntypes][tebd]; embedding layers (W [in][out], b [out]) for
 17->e1->e2->M; per attention layer WQ, WK, WV [M][d], WO [d][M], gamma, beta
 [M]; fitting layers (W [in][out], b [out]) for M*M2 -> H -> ... -> 1; per-type
-energy bias [ntypes].
+energy bias [ntypes].  The first reserved int is the number of fitting heads
+(0 or 1: one); a model with more appends, for each further head, its fitting
+layers and energy bias in the same order (``Model.heads[h]``, head 0 being the
+arrays above).
 """
 from __future__ import annotations
 
@@ -36,6 +39,7 @@ class Model:
     force_scale: float
     seed: int
     p: dict = field(default_factory=dict)
+    heads: list = field(default_factory=list)  # per head: {"F1", "c1", ..., "F4", "c4", "ebias"}
 
 
 def load_model(path: str) -> Model:
@@ -44,7 +48,8 @@ def load_model(path: str) -> Model:
     if raw[:8] != b"DPAMDv01":
         raise ValueError("not a model file")
     ints = struct.unpack_from("<16i", raw, 8)
-    version, ntypes, tebd, e1, e2, M, n_attn, d_attn, M2, H, nfh, sel = ints[:12]
+    version, ntypes, tebd, e1, e2, M, n_attn, d_attn, M2, H, nfh, sel, nheads = ints[:13]
+    nheads = max(1, nheads)
     if version != 1:
         raise ValueError(f"unsupported model file version {version}")
     rc, rcs, eps, fscale = struct.unpack_from("<4d", raw, 72)
@@ -52,12 +57,12 @@ def load_model(path: str) -> Model:
     m = Model(ntypes, tebd, e1, e2, M, n_attn, d_attn, M2, H, nfh, sel, rc, rcs, eps, fscale, seed)
     off = 128
 
-    def take(name, *shape):
+    def take(name, *shape, into=None):
         nonlocal off
         n = int(np.prod(shape))
         a = np.frombuffer(raw, dtype="<f8", count=n, offset=off).reshape(shape).astype(np.float64)
         off += 8 * n
-        m.p[name] = a
+        (m.p if into is None else into)[name] = a
 
     take("TE", ntypes, tebd)
     dims = [1 + 2 * tebd, e1, e2, M]
@@ -72,10 +77,14 @@ def load_model(path: str) -> Model:
         take(f"gamma{a}", M)
         take(f"beta{a}", M)
     fd = [M * M2] + [H] * nfh + [1]
-    for li in range(len(fd) - 1):
-        take(f"F{li + 1}", fd[li], fd[li + 1])
-        take(f"c{li + 1}", fd[li + 1])
-    take("ebias", ntypes)
+    for h in range(nheads):
+        d = m.p if h == 0 else {}
+        for li in range(len(fd) - 1):
+            take(f"F{li + 1}", fd[li], fd[li + 1], into=d)
+            take(f"c{li + 1}", fd[li + 1], into=d)
+        take("ebias", ntypes, into=d)
+        m.heads.append({k: d[k] for k in [f"F{li + 1}" for li in range(len(fd) - 1)] +
+                        [f"c{li + 1}" for li in range(len(fd) - 1)] + ["ebias"]})
     if off != len(raw):
         raise ValueError(f"model file size mismatch: parsed {off} of {len(raw)} bytes")
     return m

@@ -23,12 +23,20 @@ offset type    field
 ====== ======= ==================================================
 0      8 bytes magic ``DPAMDv01``
 8      16 i32  version, ntypes, tebd, e1, e2, M, n_attn, d_attn,
-               M2, fit_hidden, n_fit_hidden, sel, 4 x reserved
+               M2, fit_hidden, n_fit_hidden, sel, nheads (0 or 1:
+               one fitting net), 3 x reserved
 72     4 f64   rc, rcs, ln_eps, force_scale
 104    u64     seed
 112    16      reserved (zero)
 128    f64[]   arrays, in ``ModelSpec.array_shapes()`` order
 ====== ======= ==================================================
+
+A model with nheads > 1 fitting nets (one descriptor shared by several fitting
+heads, as the paper's multi-task models share one descriptor between branches)
+appends, for each head h = 1 .. nheads-1, that head's fitting layers and energy
+bias in the same order and shapes as head 0's (``ModelSpec.head_shapes``).  The
+extra heads are drawn after every array of the single-head model, so head 0 and
+everything before it are the same numbers as in the single-head file.
 """
 from __future__ import annotations
 
@@ -62,6 +70,23 @@ class ModelSpec:
     rc: float = 6.0
     rcs: float = 0.5
     ln_eps: float = 1e-5
+    nheads: int = 1
+
+    def fitting_shapes(self, prefix=""):
+        fd = [self.M * self.M2] + [self.fit_hidden] * self.n_fit_hidden + [1]
+        out = []
+        for li in range(len(fd) - 1):
+            out.append((f"{prefix}fit_W{li + 1}", (fd[li], fd[li + 1]), "glorot"))
+            out.append((f"{prefix}fit_b{li + 1}", (fd[li + 1],), "unit"))
+        out.append((f"{prefix}energy_bias", (self.ntypes,), "zero"))
+        return out
+
+    def head_shapes(self):
+        """The arrays of the extra fitting heads 1 .. nheads-1, in file order."""
+        out = []
+        for h in range(1, self.nheads):
+            out += self.fitting_shapes(f"head{h}_")
+        return out
 
     def array_shapes(self):
         """(name, shape, kind) in file order; kind selects the init distribution."""
@@ -77,12 +102,7 @@ class ModelSpec:
             out.append((f"attn{a}_WO", (self.d_attn, self.M), "fanin"))
             out.append((f"attn{a}_gamma", (self.M,), "one"))
             out.append((f"attn{a}_beta", (self.M,), "zero"))
-        fd = [self.M * self.M2] + [self.fit_hidden] * self.n_fit_hidden + [1]
-        for li in range(len(fd) - 1):
-            out.append((f"fit_W{li + 1}", (fd[li], fd[li + 1]), "glorot"))
-            out.append((f"fit_b{li + 1}", (fd[li + 1],), "unit"))
-        out.append(("energy_bias", (self.ntypes,), "zero"))
-        return out
+        return out + self.fitting_shapes()
 
 
 def make_params(spec: ModelSpec = ModelSpec(), seed: int = 2602, force_scale: float | None = None):
@@ -91,7 +111,7 @@ def make_params(spec: ModelSpec = ModelSpec(), seed: int = 2602, force_scale: fl
         force_scale = FORCE_SCALE
     rng = np.random.default_rng(seed)
     params = {}
-    for name, shape, kind in spec.array_shapes():
+    for name, shape, kind in spec.array_shapes() + spec.head_shapes():
         if kind == "unit":
             a = rng.normal(0.0, 1.0, size=shape)
         elif kind == "glorot":
@@ -104,8 +124,10 @@ def make_params(spec: ModelSpec = ModelSpec(), seed: int = 2602, force_scale: fl
             a = np.zeros(shape)
         params[name] = a.astype(np.float64)
     last = spec.n_fit_hidden + 1
-    params[f"fit_W{last}"] *= force_scale
-    params[f"fit_b{last}"] *= force_scale
+    for h in range(spec.nheads):
+        pre = f"head{h}_" if h else ""
+        params[f"{pre}fit_W{last}"] *= force_scale
+        params[f"{pre}fit_b{last}"] *= force_scale
     return params
 
 
@@ -116,27 +138,29 @@ def write_model_file(path: str, spec: ModelSpec = ModelSpec(), seed: int = 2602,
     if params is None:
         params = make_params(spec, seed, force_scale)
     ints = [VERSION, spec.ntypes, spec.tebd, spec.e1, spec.e2, spec.M, spec.n_attn, spec.d_attn,
-            spec.M2, spec.fit_hidden, spec.n_fit_hidden, spec.sel, 0, 0, 0, 0]
+            spec.M2, spec.fit_hidden, spec.n_fit_hidden, spec.sel, spec.nheads if spec.nheads > 1 else 0, 0, 0, 0]
     head = MAGIC + struct.pack("<16i", *ints)
     head += struct.pack("<4d", spec.rc, spec.rcs, spec.ln_eps, force_scale)
     head += struct.pack("<Q", seed) + bytes(16)
     assert len(head) == 128
     with open(path, "wb") as f:
         f.write(head)
-        for name, shape, _ in spec.array_shapes():
+        for name, shape, _ in spec.array_shapes() + spec.head_shapes():
             a = np.ascontiguousarray(params[name], dtype="<f8")
             assert a.shape == tuple(shape), (name, a.shape, shape)
             f.write(a.tobytes())
     return path
 
 
-def default_model_file(seed: int = 2602) -> str:
-    """Write (once per process and seed) the default model file to a temp dir and return its path."""
+def default_model_file(seed: int = 2602, nheads: int = 1) -> str:
+    """Write (once per process, seed and head count) the default model file to a temp dir
+    and return its path.  nheads > 1: the same model with extra fitting heads."""
     d = os.path.join(tempfile.gettempdir(), f"dpamd_models_{os.getuid()}")
     os.makedirs(d, exist_ok=True)
-    path = os.path.join(d, f"model_seed{seed}_fs{FORCE_SCALE!r}.bin")
+    tag = f"_h{nheads}" if nheads > 1 else ""
+    path = os.path.join(d, f"model_seed{seed}_fs{FORCE_SCALE!r}{tag}.bin")
     if not os.path.exists(path):
         tmp = path + f".{os.getpid()}.tmp"
-        write_model_file(tmp, seed=seed)
+        write_model_file(tmp, spec=ModelSpec(nheads=nheads), seed=seed)
         os.replace(tmp, path)
     return path
