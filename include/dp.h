@@ -185,6 +185,25 @@ int dp_compute_batch_device(dp_model *m, int nsys, const int64_t *natoms, const 
                             const double *d_coords, const int32_t *d_types, double *d_energy,
                             double *d_forces, double *d_virial, void *hip_stream);
 
+/* Several fitting heads on one descriptor (paper, Section II: the multi-task
+ * pre-trained models share one descriptor between output branches, e.g. the
+ * solvated-protein and small-molecule branches of Section IV).  A model file may
+ * carry up to 4 fitting nets; every step evaluates the descriptor once and all
+ * heads on it, and reports the weighted combination E = sum_h w_h E^h as its
+ * energy, with forces and virial of that combination (one backward pass through
+ * the shared descriptor).  The weights start as (1, 0, ...): head 0 alone, the
+ * single-head result bit for bit.
+ *   dp_model_heads:      *nheads = the number of fitting heads (1 .. 4).
+ *   dp_set_head_weights: w[nheads] (finite; DP_ERR_ARG if nheads differs from the
+ *                        model's); a weight of 0 skips that head's backward.
+ *                        Applies to every later call, graphs included.
+ *   dp_head_energies:    each head's own energy E^h of the last step, for its
+ *                        first nsys systems: energies[nsys][nheads] (host,
+ *                        synchronous); models with several heads only. */
+int dp_model_heads(const dp_model *m, int *nheads);
+int dp_set_head_weights(dp_model *m, int nheads, const double *weights);
+int dp_head_energies(dp_model *m, int nsys, double *energies);
+
 /* Neighbour-list reuse across calls (paper, Section IV: Verlet lists with a
  * buffer, rebuilt every 10 steps).  With skin > 0 a list within rc + skin
  * (at most 192 entries per atom) is built on the first call and then every

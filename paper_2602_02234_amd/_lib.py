@@ -39,6 +39,9 @@ SIGNATURES = {
     "dp_profile_read": (C.c_int, [_P, _P, _P, C.c_int]),
     "dp_compute_batch_device": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dp_set_skin": (C.c_int, [_P, C.c_double, C.c_int]),
+    "dp_model_heads": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    "dp_set_head_weights": (C.c_int, [_P, C.c_int, _P]),
+    "dp_head_energies": (C.c_int, [_P, C.c_int, _P]),
     "dp_skin_stats": (C.c_int, [_P, _P, _P]),
     "dp_set_graph": (C.c_int, [_P, C.c_int]),
     "dp_server_footprint": (C.c_size_t, [_P, _I64]),

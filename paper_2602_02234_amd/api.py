@@ -105,6 +105,23 @@ class Model:
         check(_lib.load().dp_skin_stats(self._h, _ptr(b), _ptr(f)), "dp_skin_stats")
         return {"builds": int(b[0]), "forced": int(f[0])}
 
+    @property
+    def nheads(self) -> int:
+        k = C.c_int()
+        check(_lib.load().dp_model_heads(self._h, C.byref(k)), "dp_model_heads")
+        return k.value
+
+    def set_head_weights(self, weights):
+        """E = sum_h w_h E^h of the fitting heads (forces and virial follow)."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        check(_lib.load().dp_set_head_weights(self._h, len(w), _ptr(w)), "dp_set_head_weights")
+
+    def head_energies(self, nsys: int = 1):
+        """Each head's energy E^h of the last step, [nsys][nheads]."""
+        out = np.zeros((nsys, self.nheads))
+        check(_lib.load().dp_head_energies(self._h, nsys, _ptr(out)), "dp_head_energies")
+        return out
+
     def set_graph(self, enable: bool = True):
         """Capture each step configuration in a HIP graph and replay it."""
         check(_lib.load().dp_set_graph(self._h, 1 if enable else 0), "dp_set_graph")

@@ -37,10 +37,12 @@ uint16_t to_bf16(float f) {  // round to nearest even
 }
 
 struct HostModel {
-  int ntypes, tebd, e1, e2, M_, natt, d, m2, fh, nfh, sel;
+  int ntypes, tebd, e1, e2, M_, natt, d, m2, fh, nfh, sel, nheads;
   double rc, rcs, eps, fscale;
-  std::vector<double> TE, W1, b1, W2, b2, W3, b3, F1, c1, F2, c2, F3, c3, F4, c4, ebias;
+  std::vector<double> TE, W1, b1, W2, b2, W3, b3;
   std::vector<double> WQ[NATTN], WK[NATTN], WV[NATTN], WO[NATTN], gam[NATTN], bet[NATTN];
+  // per fitting head
+  std::vector<double> F1[MAXH], c1[MAXH], F2[MAXH], c2[MAXH], F3[MAXH], c3[MAXH], F4[MAXH], c4[MAXH], ebias[MAXH];
 };
 
 int read_model(const char *path, HostModel &h) {
@@ -64,6 +66,11 @@ int read_model(const char *path, HostModel &h) {
   }
   h.ntypes = iv[1]; h.tebd = iv[2]; h.e1 = iv[3]; h.e2 = iv[4]; h.M_ = iv[5]; h.natt = iv[6]; h.d = iv[7];
   h.m2 = iv[8]; h.fh = iv[9]; h.nfh = iv[10]; h.sel = iv[11];
+  h.nheads = iv[12] > 1 ? iv[12] : 1;  // the first reserved int: number of fitting heads
+  if (iv[12] < 0 || h.nheads > MAXH) {
+    set_error("model file: more fitting heads than the library supports (" + std::to_string(MAXH) + ")");
+    return DP_ERR_MODEL_FILE;
+  }
   h.rc = dv[0]; h.rcs = dv[1]; h.eps = dv[2]; h.fscale = dv[3];
   if (h.ntypes != NTYPES || h.tebd != TEBD || h.e1 != E1 || h.e2 != E2 || h.M_ != M || h.natt != NATTN ||
       h.d != DATTN || h.m2 != M2 || h.fh != FH || h.nfh != 3 || h.sel != SEL) {
@@ -90,11 +97,13 @@ int read_model(const char *path, HostModel &h) {
     take(h.WQ[a], M * DATTN); take(h.WK[a], M * DATTN); take(h.WV[a], M * DATTN); take(h.WO[a], DATTN * M);
     take(h.gam[a], M); take(h.bet[a], M);
   }
-  take(h.F1, ND * FH); take(h.c1, FH);
-  take(h.F2, FH * FH); take(h.c2, FH);
-  take(h.F3, FH * FH); take(h.c3, FH);
-  take(h.F4, FH); take(h.c4, 1);
-  take(h.ebias, NTYPES);
+  for (int k = 0; k < h.nheads; ++k) {
+    take(h.F1[k], ND * FH); take(h.c1[k], FH);
+    take(h.F2[k], FH * FH); take(h.c2[k], FH);
+    take(h.F3[k], FH * FH); take(h.c3[k], FH);
+    take(h.F4[k], FH); take(h.c4[k], 1);
+    take(h.ebias[k], NTYPES);
+  }
   if (bad || off != raw.size()) {
     set_error("model file: size does not match its header");
     return DP_ERR_MODEL_FILE;
@@ -128,7 +137,8 @@ std::vector<float> transpose(const std::vector<double> &v, int rows, int cols) {
 struct Image {
   Packer pk;
   std::vector<size_t> tab, f32, b16;
-  double c4 = 0.0;
+  int nheads = 1;
+  double c4[MAXH] = {};
 };
 
 // The whole device weight image on the host (no HIP call): the tables both paths read,
@@ -157,13 +167,16 @@ void pack_weights(const HostModel &h, int pr, Image &im) {
     o.push_back(pk.addf(tof(h.gam[a])));
     o.push_back(pk.addf(tof(h.bet[a])));
   }
-  o.push_back(pk.addf(tof(h.c1)));
-  o.push_back(pk.addf(tof(h.c2)));
-  o.push_back(pk.addf(tof(h.c3)));
-  o.push_back(pk.addf(tof(h.F4)));
-  o.push_back(pk.addd(h.F4));
-  o.push_back(pk.addd(h.ebias));
-  im.c4 = h.c4[0];
+  im.nheads = h.nheads;
+  for (int k = 0; k < h.nheads; ++k) {
+    o.push_back(pk.addf(tof(h.c1[k])));
+    o.push_back(pk.addf(tof(h.c2[k])));
+    o.push_back(pk.addf(tof(h.c3[k])));
+    o.push_back(pk.addf(tof(h.F4[k])));
+    o.push_back(pk.addd(h.F4[k]));
+    o.push_back(pk.addd(h.ebias[k]));
+    im.c4[k] = h.c4[k][0];
+  }
   // the fused single-head attention operands, formed in float64
   const double isd = 1.0 / std::sqrt((double)DATTN);
   std::vector<double> QK[NATTN], VO[NATTN];
@@ -193,12 +206,14 @@ void pack_weights(const HostModel &h, int pr, Image &im) {
       f.push_back(pk.addf(transpose(VO[a], M, M)));
       f.push_back(pk.addf(tof(VO[a])));
     }
-    f.push_back(pk.addf(transpose(h.F1, ND, FH)));
-    f.push_back(pk.addf(tof(h.F1)));
-    f.push_back(pk.addf(transpose(h.F2, FH, FH)));
-    f.push_back(pk.addf(tof(h.F2)));
-    f.push_back(pk.addf(transpose(h.F3, FH, FH)));
-    f.push_back(pk.addf(tof(h.F3)));
+    for (int k = 0; k < h.nheads; ++k) {
+      f.push_back(pk.addf(transpose(h.F1[k], ND, FH)));
+      f.push_back(pk.addf(tof(h.F1[k])));
+      f.push_back(pk.addf(transpose(h.F2[k], FH, FH)));
+      f.push_back(pk.addf(tof(h.F2[k])));
+      f.push_back(pk.addf(transpose(h.F3[k], FH, FH)));
+      f.push_back(pk.addf(tof(h.F3[k])));
+    }
     return;
   }
   // padded [rows][k] bf16 operands of the bfloat16 kernels (zero outside the real extent)
@@ -248,12 +263,6 @@ void pack_weights(const HostModel &h, int pr, Image &im) {
     op.push_back(hi_lo(frag112(mat(112, 112, [&](int c, int k) { return at(vo, c, k); })), 0));
   }
   auto F = [&](const std::vector<double> &v, int ld, int r, int c) { return v[(size_t)r * ld + c]; };
-  const auto f1t = mat(FH, ND, [&](int c, int k) { return F(h.F1, FH, k, c); });
-  const auto f1 = mat(ND, 256, [&](int c, int k) { return k < FH ? F(h.F1, FH, c, k) : 0.0; });
-  const auto f2t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, k, c) : 0.0; });
-  const auto f2 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2, FH, c, k) : 0.0; });
-  const auto f3t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, k, c) : 0.0; });
-  const auto f3 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3, FH, c, k) : 0.0; });
   // the fitting operands in MFMA fragment order: the 16 x 32 fragment (column tile t,
   // k step s) is 64 lanes x 8 contiguous values, lane l holding row 16 t + l % 16,
   // k = 32 s + 8 (l / 16) .. + 8; so one wave's fragment load is 1 KB of whole lines
@@ -267,11 +276,19 @@ void pack_weights(const HostModel &h, int pr, Image &im) {
             o[(((size_t)t * S + st) * 64 + l) * 8 + e] = v[(size_t)(16 * t + l % 16) * K + 32 * st + 8 * (l / 16) + e];
     return o;
   };
-  const std::vector<float> fr[] = {frag(f1t, FH, ND), frag(f1, ND, 256), frag(f2t, FH, 256),
-                                   frag(f2, FH, 256), frag(f3t, FH, 256), frag(f3, FH, 256)};
-  for (const auto &v : fr) {
-    op.push_back(hi_lo(v, 0));
-    op.push_back(hi_lo(v, 1));
+  for (int hd = 0; hd < h.nheads; ++hd) {
+    const auto f1t = mat(FH, ND, [&](int c, int k) { return F(h.F1[hd], FH, k, c); });
+    const auto f1 = mat(ND, 256, [&](int c, int k) { return k < FH ? F(h.F1[hd], FH, c, k) : 0.0; });
+    const auto f2t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2[hd], FH, k, c) : 0.0; });
+    const auto f2 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F2[hd], FH, c, k) : 0.0; });
+    const auto f3t = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3[hd], FH, k, c) : 0.0; });
+    const auto f3 = mat(FH, 256, [&](int c, int k) { return k < FH ? F(h.F3[hd], FH, c, k) : 0.0; });
+    const std::vector<float> fr[] = {frag(f1t, FH, ND), frag(f1, ND, 256), frag(f2t, FH, 256),
+                                     frag(f2, FH, 256), frag(f3t, FH, 256), frag(f3, FH, 256)};
+    for (const auto &v : fr) {
+      op.push_back(hi_lo(v, 0));
+      op.push_back(hi_lo(v, 1));
+    }
   }
 }
 
@@ -286,10 +303,14 @@ void bind_image(const Image &im, int pr, const unsigned char *base, Weights<floa
   for (int a = 0; a < NATTN; ++a) {
     w.gamma[a] = F(); w.beta[a] = F();
   }
-  w.c1 = F(); w.c2 = F(); w.c3 = F(); w.F4 = F();
-  w.F4d = (const double *)(base + im.tab[k++]);
-  w.ebias = (const double *)(base + im.tab[k++]);
-  w.c4 = im.c4;
+  w.nheads = im.nheads;
+  for (int hd = 0; hd < im.nheads; ++hd) {
+    w.c1[hd] = F(); w.c2[hd] = F(); w.c3[hd] = F(); w.F4[hd] = F();
+    w.F4d[hd] = (const double *)(base + im.tab[k++]);
+    w.ebias[hd] = (const double *)(base + im.tab[k++]);
+    w.c4[hd] = im.c4[hd];
+    w.hw[hd] = hd == 0 ? 1.0 : 0.0;  // head 0 alone until dp_set_head_weights
+  }
   if (pr == DP_FP32) {
     k = 0;
     auto P = [&]() { return (const float *)(base + im.f32[k++]); };
@@ -297,7 +318,9 @@ void bind_image(const Image &im, int pr, const unsigned char *base, Weights<floa
     for (int a = 0; a < NATTN; ++a) {
       w.WqkT[a] = P(); w.Wqk[a] = P(); w.WvoT[a] = P(); w.Wvo[a] = P();
     }
-    w.F1T = P(); w.F1 = P(); w.F2T = P(); w.F2 = P(); w.F3T = P(); w.F3 = P();
+    for (int hd = 0; hd < im.nheads; ++hd) {
+      w.F1T[hd] = P(); w.F1[hd] = P(); w.F2T[hd] = P(); w.F2[hd] = P(); w.F3T[hd] = P(); w.F3[hd] = P();
+    }
   } else {
     k = 0;
     auto P = [&]() { return (const bf16_t *)(base + im.b16[k++]); };
@@ -305,12 +328,14 @@ void bind_image(const Image &im, int pr, const unsigned char *base, Weights<floa
     for (int a = 0; a < NATTN; ++a) {
       wp.WqkT[a] = P(); wp.Wqk[a] = P(); wp.WvoT[a] = P(); wp.Wvo[a] = P();
     }
-    for (int x = 0; x < 2; ++x) { wp.F1T[x] = P(); }
-    for (int x = 0; x < 2; ++x) { wp.F1[x] = P(); }
-    for (int x = 0; x < 2; ++x) { wp.F2T[x] = P(); }
-    for (int x = 0; x < 2; ++x) { wp.F2[x] = P(); }
-    for (int x = 0; x < 2; ++x) { wp.F3T[x] = P(); }
-    for (int x = 0; x < 2; ++x) { wp.F3[x] = P(); }
+    for (int hd = 0; hd < im.nheads; ++hd) {
+      for (int x = 0; x < 2; ++x) { wp.F1T[hd][x] = P(); }
+      for (int x = 0; x < 2; ++x) { wp.F1[hd][x] = P(); }
+      for (int x = 0; x < 2; ++x) { wp.F2T[hd][x] = P(); }
+      for (int x = 0; x < 2; ++x) { wp.F2[hd][x] = P(); }
+      for (int x = 0; x < 2; ++x) { wp.F3T[hd][x] = P(); }
+      for (int x = 0; x < 2; ++x) { wp.F3[hd][x] = P(); }
+    }
   }
 }
 
@@ -323,15 +348,22 @@ std::vector<std::pair<std::string, const void **>> weight_fields(int pr, Weights
     add("gamma" + std::to_string(a), &w.gamma[a]);
     add("beta" + std::to_string(a), &w.beta[a]);
   }
-  add("c1", &w.c1); add("c2", &w.c2); add("c3", &w.c3); add("F4", &w.F4); add("F4d", &w.F4d);
-  add("ebias", &w.ebias);
+  for (int hd = 0; hd < w.nheads; ++hd) {
+    const std::string t = hd ? "." + std::to_string(hd) : "";
+    add("c1" + t, &w.c1[hd]); add("c2" + t, &w.c2[hd]); add("c3" + t, &w.c3[hd]); add("F4" + t, &w.F4[hd]);
+    add("F4d" + t, &w.F4d[hd]); add("ebias" + t, &w.ebias[hd]);
+  }
   if (pr == DP_FP32) {
     add("W2T", &w.W2T); add("W2", &w.W2); add("W3T", &w.W3T); add("W3", &w.W3);
     for (int a = 0; a < NATTN; ++a) {
       const std::string t = std::to_string(a);
       add("WqkT" + t, &w.WqkT[a]); add("Wqk" + t, &w.Wqk[a]); add("WvoT" + t, &w.WvoT[a]); add("Wvo" + t, &w.Wvo[a]);
     }
-    add("F1T", &w.F1T); add("F1", &w.F1); add("F2T", &w.F2T); add("F2", &w.F2); add("F3T", &w.F3T); add("F3", &w.F3);
+    for (int hd = 0; hd < w.nheads; ++hd) {
+      const std::string t = hd ? "." + std::to_string(hd) : "";
+      add("F1T" + t, &w.F1T[hd]); add("F1" + t, &w.F1[hd]); add("F2T" + t, &w.F2T[hd]); add("F2" + t, &w.F2[hd]);
+      add("F3T" + t, &w.F3T[hd]); add("F3" + t, &w.F3[hd]);
+    }
     return f;
   }
   add("b16.W2T", &wp.W2T); add("b16.W3T", &wp.W3T); add("b16.W3", &wp.W3); add("b16.W2", &wp.W2);
@@ -340,11 +372,12 @@ std::vector<std::pair<std::string, const void **>> weight_fields(int pr, Weights
     add("b16.WqkT" + t, &wp.WqkT[a]); add("b16.Wqk" + t, &wp.Wqk[a]);
     add("b16.WvoT" + t, &wp.WvoT[a]); add("b16.Wvo" + t, &wp.Wvo[a]);
   }
-  for (int x = 0; x < 2; ++x) {
-    const std::string t = x ? ".lo" : ".hi";
-    add("b16.F1T" + t, &wp.F1T[x]); add("b16.F1" + t, &wp.F1[x]); add("b16.F2T" + t, &wp.F2T[x]);
-    add("b16.F2" + t, &wp.F2[x]); add("b16.F3T" + t, &wp.F3T[x]); add("b16.F3" + t, &wp.F3[x]);
-  }
+  for (int hd = 0; hd < w.nheads; ++hd)
+    for (int x = 0; x < 2; ++x) {
+      const std::string t = (hd ? "." + std::to_string(hd) : "") + (x ? ".lo" : ".hi");
+      add("b16.F1T" + t, &wp.F1T[hd][x]); add("b16.F1" + t, &wp.F1[hd][x]); add("b16.F2T" + t, &wp.F2T[hd][x]);
+      add("b16.F2" + t, &wp.F2[hd][x]); add("b16.F3T" + t, &wp.F3T[hd][x]); add("b16.F3" + t, &wp.F3[hd][x]);
+    }
   return f;
 }
 
@@ -381,7 +414,7 @@ int build_weights(dp_model *m, const HostModel &h) {
 
 void free_ws(Workspace &ws) {
   void *ps[] = {ws.cell_of, ws.cell_count, ws.cell_start, ws.cell_cursor, ws.cell_atoms, ws.nlist, ws.nnei, ws.done,
-                ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g, ws.vpart, ws.red, ws.grids, ws.sys_off, ws.sys_of, ws.slist,
+                ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.Eh, ws.Ehsys, ws.g, ws.vpart, ws.red, ws.grids, ws.sys_off, ws.sys_of, ws.slist,
                 ws.snnei, ws.xref, ws.flags, ws.gE, ws.bidx, ws.bcnt};
   for (void *p : ps)
     if (p) (void)hipFree(p);
@@ -400,7 +433,7 @@ size_t ws_bytes_per_atom(int prec) {
              + (size_t)SEL * sizeof(int)                  // nlist
              + (size_t)M * 4 * sizeof(float)              // Tsave
              + (size_t)ND * sizeof(float)                 // D
-             + sizeof(double)                             // Ei
+             + (1 + MAXH) * sizeof(double)                // Ei, Eh
              + (size_t)SEL * sizeof(float4)               // g
              + 9 * sizeof(double)                         // vpart
              + 2 * sizeof(int);                           // backward atom lists
@@ -427,13 +460,16 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     if (ws.grids) (void)hipFree(ws.grids);
     if (ws.sys_off) (void)hipFree(ws.sys_off);
     if (ws.done) (void)hipFree(ws.done);
+    if (ws.Ehsys) (void)hipFree(ws.Ehsys);
     if (ws.grids_host) (void)hipHostFree(ws.grids_host);
     if (ws.off_host) (void)hipHostFree(ws.off_host);
-    ws.grids = nullptr; ws.sys_off = nullptr; ws.done = nullptr; ws.grids_host = nullptr; ws.off_host = nullptr;
+    ws.grids = nullptr; ws.sys_off = nullptr; ws.done = nullptr; ws.Ehsys = nullptr; ws.grids_host = nullptr;
+    ws.off_host = nullptr;
     ws.cap_sys = 0;
     HIP_TRY(hipMalloc(&ws.grids, cs * sizeof(Grid)));
     HIP_TRY(hipMalloc(&ws.sys_off, (cs + 1) * sizeof(int)));  // cs >= 8: [2..3] also hold a centre range
     HIP_TRY(hipMalloc(&ws.done, (2 * cs + 1) * sizeof(int)));
+    HIP_TRY(hipMalloc(&ws.Ehsys, (size_t)cs * MAXH * sizeof(double)));
     HIP_TRY(hipHostMalloc(&ws.grids_host, cs * sizeof(Grid), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&ws.off_host, (cs + 1) * sizeof(int), hipHostMallocDefault));
     ws.cap_sys = cs;
@@ -441,13 +477,13 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
   }
   if (n > ws.cap) {
     const int64_t cap = std::max<int64_t>(n, ws.cap + ws.cap / 4);
-    void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.g,
+    void *ps[] = {ws.cell_of, ws.cell_atoms, ws.nlist, ws.nnei, ws.Gsave, ws.Tsave, ws.D, ws.Ei, ws.Eh, ws.g,
                   ws.vpart, ws.sys_of, ws.slist, ws.snnei, ws.xref, ws.bidx};
     for (void *p : ps)
       if (p) (void)hipFree(p);
     ws.cell_of = ws.cell_atoms = ws.nlist = ws.nnei = ws.sys_of = ws.slist = ws.snnei = ws.bidx = nullptr;
     ws.Gsave = ws.Tsave = ws.D = nullptr;
-    ws.Ei = ws.vpart = ws.xref = nullptr;
+    ws.Ei = ws.Eh = ws.vpart = ws.xref = nullptr;
     ws.g = nullptr;
     ws.cap = 0;
     HIP_TRY(hipMalloc(&ws.cell_of, cap * sizeof(int)));
@@ -461,6 +497,7 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
     HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
     HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));
+    HIP_TRY(hipMalloc(&ws.Eh, cap * MAXH * sizeof(double)));
     HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
     HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
     ws.cap = cap;
@@ -520,6 +557,8 @@ size_t carve_ws(Workspace &ws, unsigned char *base, int64_t cap) {
   take(ws.bidx, 2 * c * sizeof(int));
   take(ws.D, (c + 16) * ND * sizeof(float));
   take(ws.Ei, c * sizeof(double));
+  take(ws.Eh, c * MAXH * sizeof(double));
+  take(ws.Ehsys, MAXH * sizeof(double));
   take(ws.g, c * SEL * sizeof(float4));
   take(ws.vpart, c * 9 * sizeof(double));
   ws.cap = cap;
@@ -680,7 +719,7 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   if (pm) mark(pm, 3, st);
   // energies over the centre atoms (every atom, or the first nc of one system with ghosts)
   const int *eoff = nc < n ? ws.sys_off + 2 : ws.sys_off;
-  if (!bwd) launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, nullptr, st);
+  if (!bwd) launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, nullptr, m->wf.nheads, st);
   if (pm) mark(pm, 4, st);
   if (bwd) {
     if (m->prec == DP_BF16)
@@ -691,7 +730,7 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
     double *F = a.forces;
     if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
     launch_forces(ws, a.X, n, nullptr, F, a.lists == LISTS_SKIN_REUSE, nc < n, st);
-    launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, a.virial, st);
+    launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, a.virial, m->wf.nheads, st);
     if (pm) mark(pm, 6, st);
   }
   HIP_TRY(hipGetLastError());
@@ -1171,6 +1210,50 @@ int dp_compute_batch_device(dp_model *m, int nsys, const int64_t *natoms, const 
   return step_status(ws);
 }
 
+int dp_model_heads(const dp_model *m, int *nheads) {
+  if (!m || !nheads) return DP_ERR_ARG;
+  *nheads = m->wf.nheads;
+  return DP_OK;
+}
+
+int dp_set_head_weights(dp_model *m, int nheads, const double *weights) {
+  g_last_error.clear();
+  if (!m || !weights || nheads != m->wf.nheads) {
+    set_error("dp_set_head_weights: bad argument (give one weight per fitting head)");
+    return DP_ERR_ARG;
+  }
+  for (int h = 0; h < nheads; ++h)
+    if (!std::isfinite(weights[h])) {
+      set_error("dp_set_head_weights: non-finite weight");
+      return DP_ERR_NONFINITE;
+    }
+  HIP_TRY(hipSetDevice(m->device));
+  HIP_TRY(hipDeviceSynchronize());
+  for (int h = 0; h < nheads; ++h) m->wf.hw[h] = weights[h];
+  // the weights travel as kernel arguments: graphs captured with the old ones are dropped
+  for (auto &e : m->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    e.exec = nullptr;
+  }
+  m->fwd_valid = false;
+  return DP_OK;
+}
+
+int dp_head_energies(dp_model *m, int nsys, double *energies) {
+  g_last_error.clear();
+  if (!m || !energies || nsys < 1 || nsys > m->ws.cap_sys || m->wf.nheads < 2) {
+    set_error("dp_head_energies: bad argument (a model with several fitting heads and a finished step)");
+    return DP_ERR_ARG;
+  }
+  HIP_TRY(hipSetDevice(m->device));
+  HIP_TRY(hipDeviceSynchronize());
+  std::vector<double> all((size_t)nsys * MAXH);
+  HIP_TRY(hipMemcpy(all.data(), m->ws.Ehsys, all.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int s = 0; s < nsys; ++s)
+    for (int h = 0; h < m->wf.nheads; ++h) energies[s * m->wf.nheads + h] = all[(size_t)s * MAXH + h];
+  return DP_OK;
+}
+
 int dp_set_skin(dp_model *m, double skin, int rebuild_every) {
   g_last_error.clear();
   if (!m || !(skin >= 0.0) || !std::isfinite(skin) || rebuild_every < 1) {
@@ -1229,7 +1312,7 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
     launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, n, rc, rcs, eps, st);
   }
   launch_forces(ws, m->fwd_coords, n, d_grad_energy, d_grad_coords, m->fwd_lists == LISTS_SKIN_REUSE, false, st);
-  if (d_virial) launch_reduce(ws, ws.sys_off, 1, nullptr, nullptr, d_virial, st);
+  if (d_virial) launch_reduce(ws, ws.sys_off, 1, nullptr, nullptr, d_virial, 1, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   m->fwd_valid = false;

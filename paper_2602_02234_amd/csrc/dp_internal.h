@@ -36,8 +36,11 @@ enum : unsigned {
   FLAG_ERRORS = 63u,  // any of the above: outputs are not written
 };
 
+constexpr int MAXH = 4;  // fitting heads one model may carry
+
 // Device weight tables read by both precision paths: biases, the first embedding
-// layer (its type part folded into Bt), LayerNorm parameters and the last fitting layer.
+// layer (its type part folded into Bt), LayerNorm parameters and, per fitting head, the
+// fitting biases and last layer.
 struct Tables {
   const float *w1s;   // [E1]            first embedding layer, s column
   const float *Bt;    // [NTYPES][NTYPES][E1]  type part + bias of the first layer
@@ -45,13 +48,15 @@ struct Tables {
   const float *b3;    // [M]
   const float *gamma[NATTN];
   const float *beta[NATTN];
-  const float *c1, *c2, *c3;
-  const float *F4;    // [FH]  last layer, float32 copy for the backward
+  int nheads;         // fitting heads (1 .. MAXH)
+  double hw[MAXH];    // head weights: E_i = sum_h hw[h] E_i^h (forces and virial follow)
+  const float *c1[MAXH], *c2[MAXH], *c3[MAXH];
+  const float *F4[MAXH];    // [FH]  last layer, float32 copy for the backward
   // The last layer's energy terms stay float64: E_i = y3 . F4 + c4 + ebias[t_i] is summed
   // in float64 from float32 y3, so the large, shared F4 and c4 add no rounding of their own.
-  const double *F4d;  // [FH]
-  double c4;
-  const double *ebias; // [NTYPES]
+  const double *F4d[MAXH];  // [FH]
+  double c4[MAXH];
+  const double *ebias[MAXH];  // [NTYPES]
 };
 
 // GEMM operands of the float32 path, T = float, row-major as named.
@@ -64,12 +69,12 @@ template <typename T> struct Weights : Tables {
   const T *Wqk[NATTN];   // [M][M]
   const T *WvoT[NATTN];  // [M][M]  (WV WO)^T
   const T *Wvo[NATTN];   // [M][M]
-  const T *F1T;       // [FH][ND]
-  const T *F1;        // [ND][FH]
-  const T *F2T;       // [FH][FH]
-  const T *F2;
-  const T *F3T;
-  const T *F3;
+  const T *F1T[MAXH];    // [FH][ND]  per fitting head
+  const T *F1[MAXH];     // [ND][FH]
+  const T *F2T[MAXH];    // [FH][FH]
+  const T *F2[MAXH];
+  const T *F3T[MAXH];
+  const T *F3[MAXH];
 };
 
 // Extra device weights of the bfloat16 path: GEMM operands zero-padded to MFMA
@@ -87,14 +92,14 @@ struct WeightsB16 {
   const bf16_t *Wqk[NATTN];
   const bf16_t *WvoT[NATTN];
   const bf16_t *Wvo[NATTN];
-  // fitting operands, hi and lo parts, in MFMA fragment order (fragment (t, s) of a
-  // [cols][K] matrix at ((t * K / 32 + s) * 64 + lane) * 8)
-  const bf16_t *F1T[2];        // [240][1600]
-  const bf16_t *F1[2];         // [1600][256]
-  const bf16_t *F2T[2];        // [240][256]
-  const bf16_t *F2[2];         // [240][256]
-  const bf16_t *F3T[2];        // [240][256]
-  const bf16_t *F3[2];         // [240][256]
+  // fitting operands per head, hi and lo parts, in MFMA fragment order (fragment (t, s)
+  // of a [cols][K] matrix at ((t * K / 32 + s) * 64 + lane) * 8)
+  const bf16_t *F1T[MAXH][2];  // [240][1600]
+  const bf16_t *F1[MAXH][2];   // [1600][256]
+  const bf16_t *F2T[MAXH][2];  // [240][256]
+  const bf16_t *F2[MAXH][2];   // [240][256]
+  const bf16_t *F3T[MAXH][2];  // [240][256]
+  const bf16_t *F3[MAXH][2];   // [240][256]
 };
 
 struct Workspace {
@@ -124,7 +129,9 @@ struct Workspace {
   int *done = nullptr;        // [2 cap_sys + 1]  completion counters (the cell pass's workgroup counter
                               // at [2 cap_sys]); cleared at the start of each step
   float *D = nullptr;         // [cap][ND]  descriptor, then dE/dD
-  double *Ei = nullptr;       // [cap] atomic energies
+  double *Ei = nullptr;       // [cap] atomic energies (the weighted head combination)
+  double *Eh = nullptr;       // [cap][MAXH]  atomic energy of each fitting head (models with several)
+  double *Ehsys = nullptr;    // [cap_sys][MAXH]  each head's energy per system
   float4 *g = nullptr;        // [cap][SEL]  dE_i/dDelta_ij
   double *vpart = nullptr;    // [cap][9]   per-atom virial
   double *red = nullptr;      // scratch for the compensated reductions
@@ -253,7 +260,7 @@ void launch_forces(const Workspace &ws, const double *coords, int n, const doubl
 // Per-system energies (E_i over the device ranges eoff) and, if virial, virials (vpart over
 // ws.sys_off), float64 Neumaier in a fixed order; energy and atom_energy may be NULL.
 void launch_reduce(const Workspace &ws, const int *eoff, int nsys, double *energy, double *atom_energy,
-                   double *virial, hipStream_t st);
+                   double *virial, int nheads, hipStream_t st);
 // out[0] = Neumaier sum of src over the atoms of system 0 (fixed order).
 void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st);
 

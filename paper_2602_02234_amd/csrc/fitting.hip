@@ -2,7 +2,7 @@
 // backward pass, dE_i/dD (paper, Section II: a fitting net maps each atom's
 // representation to its energy; E is the sum of the atomic energies).
 //   y1 = tanh(D F1 + c1);  y2 = tanh(y1 F2 + c2) + y1;  y3 = tanh(y2 F3 + c3) + y2
-//   E_i = y3 . F4 + c4 + ebias[t_i]
+//   E_i = y3 . F4 + c4 + ebias[t_i]    (per fitting head; see k_fit)
 // Batched over 16 atoms per workgroup so each weight fragment is fetched once per
 // 16 atoms; the 1600 -> 240 products and their transposes run on MFMA.
 // dE/dD overwrites D in place (each workgroup owns its 16 rows).
@@ -13,116 +13,124 @@ namespace {
 
 constexpr int LDF = FH + 4;
 
-template <typename T>
-__device__ void fit_backward(const Weights<T> &w, int a0, int n, float *__restrict__ D, float *y1, float *t2,
-                             float *t3, float *bA, float *bB);
-
-template <typename T>
+// NH fitting heads on the same descriptor: each head's forward gives E_i^h (kept in
+// Eh[i][h] when NH > 1) and E_i = sum_h hw_h E_i^h; every head with a non-zero weight runs
+// its backward with dE/dy3 = hw_h F4^h, and dE/dD = sum_h dE/dpre1^h F1^hT.
+template <typename T, int NH>
 __global__ void __launch_bounds__(NTHREADS)
 k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D, double *__restrict__ Ei,
-      int backward) {
+      double *__restrict__ Eh, int backward) {
   __shared__ float y1[16 * LDF], t2[16 * LDF], y2[16 * LDF], t3[16 * LDF], bA[16 * LDF], bB[16 * LDF];
+  __shared__ float bS[NH > 1 ? NH : 1][NH > 1 ? 16 * LDF : 4];  // dE/dpre1 of each head (NH > 1)
+  __shared__ double eacc[16];
   const int a0 = blockIdx.x * 16;
   const int wv = wave_id();
   constexpr int NT = FH / 16;  // 15 column tiles of the hidden width
-  // layer 1: y1 = tanh(D F1 + c1)
-  for (int t = wv; t < NT; t += NW) {
-    const int c0 = t * 16;
-    f4 acc = {0, 0, 0, 0};
-    Mma<T>::tile(acc, [&](int r, int k) { return (a0 + r < n) ? D[(size_t)(a0 + r) * ND + k] : 0.f; },
-                 [&](int c, int k) { return ldw(w.F1T, (c0 + c) * ND + k); }, ND);
-    const int col = c0 + acc_col();
-    for (int i = 0; i < 4; ++i) y1[acc_row(i) * LDF + col] = tanhf(acc[i] + w.c1[col]);
-  }
-  __syncthreads();
-  for (int t = wv; t < NT; t += NW) {
-    const int c0 = t * 16;
-    f4 acc = {0, 0, 0, 0};
-    Mma<T>::tile(acc, [&](int r, int k) { return y1[r * LDF + k]; },
-                 [&](int c, int k) { return ldw(w.F2T, (c0 + c) * FH + k); }, FH);
-    const int col = c0 + acc_col();
-    for (int i = 0; i < 4; ++i) {
-      const int r = acc_row(i);
-      const float tt = tanhf(acc[i] + w.c2[col]);
-      t2[r * LDF + col] = tt;
-      y2[r * LDF + col] = tt + y1[r * LDF + col];
+  if (threadIdx.x < 16) eacc[threadIdx.x] = 0.0;
+#pragma unroll 1
+  for (int h = 0; h < NH; ++h) {
+    const float hw = (float)w.hw[h];
+    // layer 1: y1 = tanh(D F1 + c1)
+    for (int t = wv; t < NT; t += NW) {
+      const int c0 = t * 16;
+      f4 acc = {0, 0, 0, 0};
+      Mma<T>::tile(acc, [&](int r, int k) { return (a0 + r < n) ? D[(size_t)(a0 + r) * ND + k] : 0.f; },
+                   [&](int c, int k) { return ldw(w.F1T[h], (c0 + c) * ND + k); }, ND);
+      const int col = c0 + acc_col();
+      for (int i = 0; i < 4; ++i) y1[acc_row(i) * LDF + col] = tanhf(acc[i] + w.c1[h][col]);
     }
-  }
-  __syncthreads();
-  for (int t = wv; t < NT; t += NW) {
-    const int c0 = t * 16;
-    f4 acc = {0, 0, 0, 0};
-    Mma<T>::tile(acc, [&](int r, int k) { return y2[r * LDF + k]; },
-                 [&](int c, int k) { return ldw(w.F3T, (c0 + c) * FH + k); }, FH);
-    const int col = c0 + acc_col();
-    for (int i = 0; i < 4; ++i) {
-      const int r = acc_row(i);
-      const float tt = tanhf(acc[i] + w.c3[col]);
-      t3[r * LDF + col] = tt;
-      bA[r * LDF + col] = tt + y2[r * LDF + col];
+    __syncthreads();
+    for (int t = wv; t < NT; t += NW) {
+      const int c0 = t * 16;
+      f4 acc = {0, 0, 0, 0};
+      Mma<T>::tile(acc, [&](int r, int k) { return y1[r * LDF + k]; },
+                   [&](int c, int k) { return ldw(w.F2T[h], (c0 + c) * FH + k); }, FH);
+      const int col = c0 + acc_col();
+      for (int i = 0; i < 4; ++i) {
+        const int r = acc_row(i);
+        const float tt = tanhf(acc[i] + w.c2[h][col]);
+        t2[r * LDF + col] = tt;
+        y2[r * LDF + col] = tt + y1[r * LDF + col];
+      }
     }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) {
-    const int r = threadIdx.x;
-    int ty = types[a0 + r];
-    ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
-    double e = 0.0;  // the last layer's dot product in float64, with float64 F4, c4, ebias
-    for (int o = 0; o < FH; ++o) e += (double)bA[r * LDF + o] * w.F4d[o];
-    Ei[a0 + r] = e + w.c4 + w.ebias[ty];
-  }
-  if (backward) fit_backward(w, a0, n, D, y1, t2, t3, bA, bB);
-}
-
-// dE/dD of the workgroup's 16 atoms, written over D (activations from the forward in LDS).
-template <typename T>
-__device__ void fit_backward(const Weights<T> &w, int a0, int n, float *__restrict__ D, float *y1, float *t2,
-                             float *t3, float *bA, float *bB) {
-  const int wv = wave_id();
-  constexpr int NT = FH / 16;
-  for (int q = threadIdx.x; q < 16 * FH; q += NTHREADS) {
-    const int r = q / FH, o = q % FH;
-    const float tt = t3[r * LDF + o];
-    bB[r * LDF + o] = w.F4[o] * (1.f - tt * tt);
-  }
-  __syncthreads();
-  // dy2 = dpre3 F3^T + dy3  (dy3 = F4);  dpre2 = dy2 (1 - t2^2)
-  for (int t = wv; t < NT; t += NW) {
-    const int c0 = t * 16;
-    f4 acc = {0, 0, 0, 0};
-    Mma<T>::tile(acc, [&](int r, int k) { return bB[r * LDF + k]; },
-                 [&](int c, int k) { return ldw(w.F3, (c0 + c) * FH + k); }, FH);
-    const int col = c0 + acc_col();
-    for (int i = 0; i < 4; ++i) {
-      const int r = acc_row(i);
-      const float dy2 = acc[i] + w.F4[col];
-      const float tt = t2[r * LDF + col];
-      bA[r * LDF + col] = dy2;
-      t3[r * LDF + col] = dy2 * (1.f - tt * tt);
+    __syncthreads();
+    for (int t = wv; t < NT; t += NW) {
+      const int c0 = t * 16;
+      f4 acc = {0, 0, 0, 0};
+      Mma<T>::tile(acc, [&](int r, int k) { return y2[r * LDF + k]; },
+                   [&](int c, int k) { return ldw(w.F3T[h], (c0 + c) * FH + k); }, FH);
+      const int col = c0 + acc_col();
+      for (int i = 0; i < 4; ++i) {
+        const int r = acc_row(i);
+        const float tt = tanhf(acc[i] + w.c3[h][col]);
+        t3[r * LDF + col] = tt;
+        bA[r * LDF + col] = tt + y2[r * LDF + col];
+      }
     }
-  }
-  __syncthreads();
-  // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
-  for (int t = wv; t < NT; t += NW) {
-    const int c0 = t * 16;
-    f4 acc = {0, 0, 0, 0};
-    Mma<T>::tile(acc, [&](int r, int k) { return t3[r * LDF + k]; },
-                 [&](int c, int k) { return ldw(w.F2, (c0 + c) * FH + k); }, FH);
-    const int col = c0 + acc_col();
-    for (int i = 0; i < 4; ++i) {
-      const int r = acc_row(i);
-      const float dy1 = acc[i] + bA[r * LDF + col];
-      const float yy = y1[r * LDF + col];
-      bB[r * LDF + col] = dy1 * (1.f - yy * yy);
+    __syncthreads();
+    if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) {
+      const int r = threadIdx.x;
+      int ty = types[a0 + r];
+      ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
+      double e = 0.0;  // the last layer's dot product in float64, with float64 F4, c4, ebias
+      for (int o = 0; o < FH; ++o) e += (double)bA[r * LDF + o] * w.F4d[h][o];
+      e += w.c4[h] + w.ebias[h][ty];
+      eacc[r] += w.hw[h] * e;
+      if (NH > 1) Eh[(size_t)(a0 + r) * MAXH + h] = e;
     }
+    if (backward && w.hw[h] != 0.0) {
+      for (int q = threadIdx.x; q < 16 * FH; q += NTHREADS) {
+        const int r = q / FH, o = q % FH;
+        const float tt = t3[r * LDF + o];
+        bB[r * LDF + o] = hw * w.F4[h][o] * (1.f - tt * tt);
+      }
+      __syncthreads();
+      // dy2 = dpre3 F3^T + dy3  (dy3 = hw F4);  dpre2 = dy2 (1 - t2^2)
+      for (int t = wv; t < NT; t += NW) {
+        const int c0 = t * 16;
+        f4 acc = {0, 0, 0, 0};
+        Mma<T>::tile(acc, [&](int r, int k) { return bB[r * LDF + k]; },
+                     [&](int c, int k) { return ldw(w.F3[h], (c0 + c) * FH + k); }, FH);
+        const int col = c0 + acc_col();
+        for (int i = 0; i < 4; ++i) {
+          const int r = acc_row(i);
+          const float dy2 = acc[i] + hw * w.F4[h][col];
+          const float tt = t2[r * LDF + col];
+          bA[r * LDF + col] = dy2;
+          t3[r * LDF + col] = dy2 * (1.f - tt * tt);
+        }
+      }
+      __syncthreads();
+      // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
+      float *bo = NH > 1 ? bS[h] : bB;
+      for (int t = wv; t < NT; t += NW) {
+        const int c0 = t * 16;
+        f4 acc = {0, 0, 0, 0};
+        Mma<T>::tile(acc, [&](int r, int k) { return t3[r * LDF + k]; },
+                     [&](int c, int k) { return ldw(w.F2[h], (c0 + c) * FH + k); }, FH);
+        const int col = c0 + acc_col();
+        for (int i = 0; i < 4; ++i) {
+          const int r = acc_row(i);
+          const float dy1 = acc[i] + bA[r * LDF + col];
+          const float yy = y1[r * LDF + col];
+          bo[r * LDF + col] = dy1 * (1.f - yy * yy);
+        }
+      }
+    }
+    __syncthreads();  // the next head overwrites the activations
   }
-  __syncthreads();
-  // dE/dD = dpre1 F1^T, written over D
+  if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) Ei[a0 + threadIdx.x] = eacc[threadIdx.x];
+  if (!backward) return;
+  // dE/dD = sum over heads of dpre1 F1^T, written over D
   for (int t = wv; t < ND / 16; t += NW) {
     const int c0 = t * 16;
     f4 acc = {0, 0, 0, 0};
-    Mma<T>::tile(acc, [&](int r, int k) { return bB[r * LDF + k]; },
-                 [&](int c, int k) { return ldw(w.F1, (c0 + c) * FH + k); }, FH);
+    for (int h = 0; h < NH; ++h)
+      if (w.hw[h] != 0.0) {
+        const float *bi = NH > 1 ? bS[h] : bB;
+        Mma<T>::tile(acc, [&](int r, int k) { return bi[r * LDF + k]; },
+                     [&](int c, int k) { return ldw(w.F1[h], (c0 + c) * FH + k); }, FH);
+      }
     const int col = c0 + acc_col();
     for (int i = 0; i < 4; ++i) {
       const int r = acc_row(i);
@@ -135,8 +143,14 @@ __device__ void fit_backward(const Weights<T> &w, int a0, int n, float *__restri
 
 template <typename T>
 void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward, hipStream_t st) {
-  hipLaunchKernelGGL(k_fit<T>, dim3((n + 15) / 16), dim3(NTHREADS), 0, st, w, types, n, ws.D, ws.Ei,
-                     backward ? 1 : 0);
+  const dim3 grid((n + 15) / 16), block(NTHREADS);
+  const int b = backward ? 1 : 0;
+  switch (w.nheads) {
+    case 1: hipLaunchKernelGGL((k_fit<T, 1>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 2: hipLaunchKernelGGL((k_fit<T, 2>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 3: hipLaunchKernelGGL((k_fit<T, 3>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    default: hipLaunchKernelGGL((k_fit<T, 4>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+  }
 }
 template void launch_fitting<float>(const Weights<float> &, const Workspace &, const int *, int, bool, hipStream_t);
 

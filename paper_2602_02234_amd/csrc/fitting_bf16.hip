@@ -70,10 +70,12 @@ __device__ __forceinline__ void mm_split2(f4 (&acc)[2], const float *a, int lda,
 // A from LDS (K = 256), B in fragment order.
 template <int U0, int U1>
 __device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, int lda, const bf16_t *bh,
-                                            const bf16_t *bl) {
+                                            const bf16_t *bl, bool zero = true) {
   const int l = lane_id(), r = l & 15, q = l >> 4, wv = wave_id();
+  if (zero) {
 #pragma unroll
-  for (int u = 0; u < U1 - U0; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < U1 - U0; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
+  }
   for (int k0 = 0; k0 < KH; k0 += 32) {
     bf8 xh, xl;
     const float *ar = a + r * lda + k0 + 8 * q;
@@ -89,128 +91,168 @@ __device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, 
   }
 }
 
+// NH fitting heads on the same descriptor: each head's forward gives E_i^h (kept in
+// Eh[i][h] when NH > 1) and E_i = sum_h hw_h E_i^h; the backward of every head with a
+// non-zero weight runs with dE/dy3 = hw_h F4^h, and dE/dD = sum_h dE/dpre1^h F1^hT.
+template <int NH>
 __global__ void __launch_bounds__(NWT * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *__restrict__ D,
-          double *__restrict__ Ei, int backward) {
+          double *__restrict__ Ei, double *__restrict__ Eh, int backward) {
   // y1, t2: the first two layers' outputs; y2: the third layer's input, later dE/dy2;
-  // X: dE/dpre3, dE/dpre2, dE/dpre1 in turn.  Columns 240..255 stay zero.
+  // X: dE/dpre3, dE/dpre2, dE/dpre1 in turn (Xs: dE/dpre1 of each head, NH > 1).
+  // Columns 240..255 stay zero.
   __shared__ __align__(16) float y1[16 * LDA], t2[16 * LDA], y2[16 * LDA], X[16 * LDA];
+  __shared__ __align__(16) float Xs[NH > 1 ? NH : 1][NH > 1 ? 16 * LDA : 4];
   __shared__ double ep[16][16];  // per-row energy partials, one per column tile
+  __shared__ double eacc[16];
   const int a0 = blockIdx.x * 16;
   const int l = lane_id(), q = l >> 4, cl = l & 15, wv = wave_id();
   for (int x = threadIdx.x; x < 16 * (KH - FH); x += NWT * 64) {
     const int r = x / (KH - FH), c = FH + x % (KH - FH);
     y1[r * LDA + c] = t2[r * LDA + c] = y2[r * LDA + c] = X[r * LDA + c] = 0.f;
   }
+  if (threadIdx.x < 16) eacc[threadIdx.x] = 0.0;
   f4 acc[2];
-  // y1 = tanh(D F1 + c1); the D allocation has 16 spare rows, so rows >= n of the
-  // last batch are read in bounds (their results are discarded)
-  mm_split2(acc, D + (size_t)a0 * ND, ND, wp.F1T[0], wp.F1T[1], ND);
+#pragma unroll 1
+  for (int h = 0; h < NH; ++h) {
+    const float hw = (float)w.hw[h];
+    const bool bwd = backward && w.hw[h] != 0.0;
+    // y1 = tanh(D F1 + c1); the D allocation has 16 spare rows, so rows >= n of the
+    // last batch are read in bounds (their results are discarded)
+    mm_split2(acc, D + (size_t)a0 * ND, ND, wp.F1T[h][0], wp.F1T[h][1], ND);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = wv + NWT * u;
-    if (t < NT)
-      for (int ii = 0; ii < 4; ++ii) y1[(4 * q + ii) * LDA + 16 * t + cl] = tanhf(acc[u][ii] + w.c1[16 * t + cl]);
-  }
-  __syncthreads();
-  mm_split2(acc, y1, LDA, wp.F2T[0], wp.F2T[1], KH);
+    for (int u = 0; u < 2; ++u) {
+      const int t = wv + NWT * u;
+      if (t < NT)
+        for (int ii = 0; ii < 4; ++ii)
+          y1[(4 * q + ii) * LDA + 16 * t + cl] = tanhf(acc[u][ii] + w.c1[h][16 * t + cl]);
+    }
+    __syncthreads();
+    mm_split2(acc, y1, LDA, wp.F2T[h][0], wp.F2T[h][1], KH);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = wv + NWT * u;
-    if (t < NT)
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii, c = 16 * t + cl;
-        const float tt = tanhf(acc[u][ii] + w.c2[c]);
-        t2[r * LDA + c] = tt;
-        y2[r * LDA + c] = tt + y1[r * LDA + c];
-      }
-  }
-  __syncthreads();
-  // y3 = tanh(y2 F3 + c3) + y2 stays in registers: E_i = y3 . F4 + c4 + ebias(t_i) as
-  // per-tile partials, and dE/dpre3 = F4 (1 - t3^2) goes to X
-  mm_split2(acc, y2, LDA, wp.F3T[0], wp.F3T[1], KH);
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = wv + NWT * u;
-    if (t < NT)
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * q + ii, c = 16 * t + cl;
-        const float tt = tanhf(acc[u][ii] + w.c3[c]);
-        X[r * LDA + c] = w.F4[c] * (1.f - tt * tt);
-        double p = (double)(tt + y2[r * LDA + c]) * w.F4d[c];
-        p += __shfl_xor(p, 1);
-        p += __shfl_xor(p, 2);
-        p += __shfl_xor(p, 4);
-        p += __shfl_xor(p, 8);
-        if (cl == 0) ep[r][t] = p;
-      }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) {
-    const int r = threadIdx.x;
-    int ty = types[a0 + r];
-    ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
-    double e = 0.0;
-    for (int t = 0; t < NT; ++t) e += ep[r][t];
-    Ei[a0 + r] = e + w.c4 + w.ebias[ty];
-  }
-  if (backward) {
-    // dy2 = dpre3 F3^T + F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
-    mm_split2(acc, X, LDA, wp.F3[0], wp.F3[1], KH);
-    __syncthreads();  // every wave has read X
-  #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int t = wv + NWT * u;
       if (t < NT)
         for (int ii = 0; ii < 4; ++ii) {
           const int r = 4 * q + ii, c = 16 * t + cl;
-          const float dy2 = acc[u][ii] + w.F4[c];
-          const float tt = t2[r * LDA + c];
-          y2[r * LDA + c] = dy2;
-          X[r * LDA + c] = dy2 * (1.f - tt * tt);
+          const float tt = tanhf(acc[u][ii] + w.c2[h][c]);
+          t2[r * LDA + c] = tt;
+          y2[r * LDA + c] = tt + y1[r * LDA + c];
         }
     }
     __syncthreads();
-    // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
-    mm_split2(acc, X, LDA, wp.F2[0], wp.F2[1], KH);
-    __syncthreads();
-  #pragma unroll
+    // y3 = tanh(y2 F3 + c3) + y2 stays in registers: E_i = y3 . F4 + c4 + ebias(t_i) as
+    // per-tile partials, and dE/dpre3 = hw F4 (1 - t3^2) goes to X
+    mm_split2(acc, y2, LDA, wp.F3T[h][0], wp.F3T[h][1], KH);
+#pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int t = wv + NWT * u;
       if (t < NT)
         for (int ii = 0; ii < 4; ++ii) {
           const int r = 4 * q + ii, c = 16 * t + cl;
-          const float dy1 = acc[u][ii] + y2[r * LDA + c];
-          const float yy = y1[r * LDA + c];
-          X[r * LDA + c] = dy1 * (1.f - yy * yy);
+          const float tt = tanhf(acc[u][ii] + w.c3[h][c]);
+          X[r * LDA + c] = hw * w.F4[h][c] * (1.f - tt * tt);
+          double p = (double)(tt + y2[r * LDA + c]) * w.F4d[h][c];
+          p += __shfl_xor(p, 1);
+          p += __shfl_xor(p, 2);
+          p += __shfl_xor(p, 4);
+          p += __shfl_xor(p, 8);
+          if (cl == 0) ep[r][t] = p;
         }
     }
     __syncthreads();
-    // dE/dD = dpre1 F1^T  (100 column tiles, in two passes over k)
-    {
-      f4 dacc[7];
-      mm_split_dd<0, 7>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
-  #pragma unroll
-      for (int u = 0; u < 7; ++u) {
+    if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) {
+      const int r = threadIdx.x;
+      int ty = types[a0 + r];
+      ty = ty < 0 ? 0 : (ty >= NTYPES ? NTYPES - 1 : ty);
+      double e = 0.0;
+      for (int t = 0; t < NT; ++t) e += ep[r][t];
+      e += w.c4[h] + w.ebias[h][ty];
+      eacc[r] += w.hw[h] * e;
+      if (NH > 1) Eh[(size_t)(a0 + r) * MAXH + h] = e;
+    }
+    if (bwd) {
+      // dy2 = dpre3 F3^T + hw F4 (into y2, free since the third layer);  dpre2 = dy2 (1 - t2^2)
+      mm_split2(acc, X, LDA, wp.F3[h][0], wp.F3[h][1], KH);
+      __syncthreads();  // every wave has read X
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
         const int t = wv + NWT * u;
+        if (t < NT)
+          for (int ii = 0; ii < 4; ++ii) {
+            const int r = 4 * q + ii, c = 16 * t + cl;
+            const float dy2 = acc[u][ii] + hw * w.F4[h][c];
+            const float tt = t2[r * LDA + c];
+            y2[r * LDA + c] = dy2;
+            X[r * LDA + c] = dy2 * (1.f - tt * tt);
+          }
+      }
+      __syncthreads();
+      // dy1 = dpre2 F2^T + dy2;  dpre1 = dy1 (1 - y1^2)
+      mm_split2(acc, X, LDA, wp.F2[h][0], wp.F2[h][1], KH);
+      __syncthreads();
+      float *xo = NH > 1 ? Xs[h] : X;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = wv + NWT * u;
+        if (t < NT)
+          for (int ii = 0; ii < 4; ++ii) {
+            const int r = 4 * q + ii, c = 16 * t + cl;
+            const float dy1 = acc[u][ii] + y2[r * LDA + c];
+            const float yy = y1[r * LDA + c];
+            xo[r * LDA + c] = dy1 * (1.f - yy * yy);
+          }
+      }
+      if (NH > 1)
+        for (int x = threadIdx.x; x < 16 * (KH - FH); x += NWT * 64) {
+          const int r = x / (KH - FH), c = FH + x % (KH - FH);
+          xo[r * LDA + c] = 0.f;
+        }
+    }
+    __syncthreads();  // the next head overwrites y1, t2, y2, X
+  }
+  if ((int)threadIdx.x < 16 && a0 + (int)threadIdx.x < n) Ei[a0 + threadIdx.x] = eacc[threadIdx.x];
+  if (!backward) return;
+  // dE/dD = sum over heads of dpre1 F1^T  (100 column tiles, in two passes over k)
+  {
+    f4 dacc[7];
+    bool first = true;
+#pragma unroll 1
+    for (int h = 0; h < NH; ++h)
+      if (w.hw[h] != 0.0) {
+        mm_split_dd<0, 7>(dacc, NH > 1 ? Xs[h] : X, LDA, wp.F1[h][0], wp.F1[h][1], first);
+        first = false;
+      }
+    if (first)
+      for (int u = 0; u < 7; ++u) dacc[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 7; ++u) {
+      const int t = wv + NWT * u;
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 4 * q + ii;
+        if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
+      }
+    }
+  }
+  {
+    f4 dacc[6];
+    bool first = true;
+#pragma unroll 1
+    for (int h = 0; h < NH; ++h)
+      if (w.hw[h] != 0.0) {
+        mm_split_dd<7, 13>(dacc, NH > 1 ? Xs[h] : X, LDA, wp.F1[h][0], wp.F1[h][1], first);
+        first = false;
+      }
+    if (first)
+      for (int u = 0; u < 6; ++u) dacc[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int t = wv + NWT * (u + 7);
+      if (t < ND / 16)
         for (int ii = 0; ii < 4; ++ii) {
           const int r = 4 * q + ii;
           if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
         }
-      }
-    }
-    {
-      f4 dacc[6];
-      mm_split_dd<7, 13>(dacc, X, LDA, wp.F1[0], wp.F1[1]);
-  #pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const int t = wv + NWT * (u + 7);
-        if (t < ND / 16)
-          for (int ii = 0; ii < 4; ++ii) {
-            const int r = 4 * q + ii;
-            if (a0 + r < n) D[(size_t)(a0 + r) * ND + 16 * t + cl] = dacc[u][ii];
-          }
-      }
     }
   }
 }
@@ -219,8 +261,14 @@ k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *
 
 void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
                         bool backward, hipStream_t st) {
-  hipLaunchKernelGGL(k_fit_b16, dim3((n + 15) / 16), dim3(NWT * 64), 0, st, w, wp, types, n, ws.D, ws.Ei,
-                     backward ? 1 : 0);
+  const dim3 grid((n + 15) / 16), block(NWT * 64);
+  const int b = backward ? 1 : 0;
+  switch (w.nheads) {
+    case 1: hipLaunchKernelGGL(k_fit_b16<1>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 2: hipLaunchKernelGGL(k_fit_b16<2>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 3: hipLaunchKernelGGL(k_fit_b16<3>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    default: hipLaunchKernelGGL(k_fit_b16<4>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+  }
 }
 
 }  // namespace dp

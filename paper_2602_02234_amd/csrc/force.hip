@@ -133,17 +133,23 @@ __global__ void __launch_bounds__(256) k_forces(
 
 // Per-system float64 sums in a fixed order, one workgroup per (system, component):
 // component 0 the energy (E_i over the energy ranges eoff[s] .. eoff[s+1]-1, copied to
-// atom_energy when given), components 1..9 the virial (vpart over off[s] .. off[s+1]-1).
+// atom_energy when given), components 1..nv the virial (vpart over off[s] .. off[s+1]-1,
+// nv = 9 or 0), then one per fitting head when there are several (Eh into Ehsys).
 // A system's sums do not depend on which other systems share the step.
 __global__ void __launch_bounds__(1024) k_reduce(const double *__restrict__ Ei, const double *__restrict__ vpart,
-                                                 const int *__restrict__ eoff, const int *__restrict__ off,
-                                                 int ncomp, double *__restrict__ energy,
-                                                 double *__restrict__ atom_energy, double *__restrict__ virial,
+                                                 const double *__restrict__ Eh, const int *__restrict__ eoff,
+                                                 const int *__restrict__ off, int ncomp, int nv,
+                                                 double *__restrict__ energy, double *__restrict__ atom_energy,
+                                                 double *__restrict__ virial, double *__restrict__ Ehsys,
                                                  const unsigned *__restrict__ flags) {
   __shared__ double ss[1024], sc[1024];
   if (step_failed(flags)) return;
   const int comp = blockIdx.x % ncomp, s = blockIdx.x / ncomp;
-  if (comp == 0) {
+  if (comp > nv) {
+    const int h = comp - nv - 1;
+    const double E = block_neumaier<1024>(Eh, eoff[s], eoff[s + 1], MAXH, h, ss, sc);
+    if (threadIdx.x == 0) Ehsys[s * MAXH + h] = E;
+  } else if (comp == 0) {
     const double E = block_neumaier<1024>(Ei, eoff[s], eoff[s + 1], 1, 0, ss, sc);
     if (energy && threadIdx.x == 0) energy[s] = E;
     if (atom_energy)
@@ -172,10 +178,11 @@ void launch_forces(const Workspace &ws, const double *coords, int n, const doubl
 }
 
 void launch_reduce(const Workspace &ws, const int *eoff, int nsys, double *energy, double *atom_energy,
-                   double *virial, hipStream_t st) {
-  const int ncomp = virial ? 10 : 1;
-  hipLaunchKernelGGL(k_reduce, dim3(nsys * ncomp), dim3(1024), 0, st, ws.Ei, ws.vpart, eoff, ws.sys_off, ncomp,
-                     energy, atom_energy, virial, ws.flags);
+                   double *virial, int nheads, hipStream_t st) {
+  const int nv = virial ? 9 : 0;
+  const int ncomp = 1 + nv + (nheads > 1 ? nheads : 0);
+  hipLaunchKernelGGL(k_reduce, dim3(nsys * ncomp), dim3(1024), 0, st, ws.Ei, ws.vpart, ws.Eh, eoff, ws.sys_off, ncomp,
+                     nv, energy, atom_energy, virial, ws.Ehsys, ws.flags);
 }
 
 void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t st) {

@@ -74,3 +74,14 @@ def test_truncated_model_file_is_refused(model_path, tmp_path):
     bad = tmp_path / "short.bin"
     bad.write_bytes(raw[:-8])
     assert lib.dp_check_model_file(str(bad).encode(), 0, None, None) == -2
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_three_head_model_binds_every_head(prec):
+    from paper_2602_02234_amd import _lib
+    from synth import default_model_file
+    lib = _lib.load()
+    path = default_model_file(nheads=3).encode()
+    assert lib.dp_check_model_file(path, prec, None, None) == 0, lib.dp_last_error()
+    for name in (["F1T.2", "ebias.1"] if prec == 0 else ["b16.F3.2.lo", "F4d.2"]):
+        assert lib.dp_check_model_file(path, prec, name.encode(), None) == -2, name
