@@ -217,6 +217,14 @@ int dp_head_energies(dp_model *m, int nsys, double *energies);
 int dp_set_skin(dp_model *m, double skin, int rebuild_every);
 int dp_skin_stats(const dp_model *m, int64_t *builds, int64_t *forced);
 
+/* chunk_atoms > 0: dp_compute_device (fresh lists, eager) evaluates the centre
+ * atoms of a larger system in chunks of chunk_atoms: every chunk builds the
+ * lists and runs the descriptor, fitting and backward for its own atoms, the last
+ * one then gathers the forces and reduces energy and virial.  Same results, bit
+ * for bit; the continuous-batching server splits large requests the same way so
+ * that small requests can run between the chunks.  0 switches chunking off. */
+int dp_set_chunk(dp_model *m, int64_t chunk_atoms);
+
 /* enable != 0: dp_compute_device captures its step (every kernel launch and
  * the small host-to-device copies of the cell grid) into a HIP graph the first
  * time it sees a configuration (natoms, buffer pointers, box, stream, list mode)

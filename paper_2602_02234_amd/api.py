@@ -122,6 +122,10 @@ class Model:
         check(_lib.load().dp_head_energies(self._h, nsys, _ptr(out)), "dp_head_energies")
         return out
 
+    def set_chunk(self, chunk_atoms: int):
+        """Evaluate the centres of larger systems in chunks of chunk_atoms (0 = off)."""
+        check(_lib.load().dp_set_chunk(self._h, int(chunk_atoms)), "dp_set_chunk")
+
     def set_graph(self, enable: bool = True):
         """Capture each step configuration in a HIP graph and replay it."""
         check(_lib.load().dp_set_graph(self._h, 1 if enable else 0), "dp_set_graph")

@@ -676,23 +676,34 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   const int n = (int)a.n;
   // centres: every atom, or (one system with ghost atoms) the first n_centres
   const int nc = (a.nsys == 1 && a.n_centres >= 0 && a.n_centres < a.n) ? (int)a.n_centres : n;
-  if (!a.open_single) HIP_TRY(hipMemcpyAsync(ws.grids, ws.grids_host, a.nsys * sizeof(Grid), hipMemcpyHostToDevice, st));
-  if (nc < n) {  // off_host[2..3]: the centre range, reduced for the energy
-    ws.off_host[2] = 0;
-    ws.off_host[3] = nc;
+  // this call's part of them: all, or one chunk c0 .. c1-1 of a single system
+  const int cb = a.nsys == 1 ? (int)a.c0 : 0;
+  const int ce = (a.nsys == 1 && a.c1 >= 0) ? (int)a.c1 : nc;
+  if (a.first_chunk) {
+    if (!a.open_single)
+      HIP_TRY(hipMemcpyAsync(ws.grids, ws.grids_host, a.nsys * sizeof(Grid), hipMemcpyHostToDevice, st));
+    if (nc < n) {  // off_host[2..3]: the centre range, reduced for the energy
+      ws.off_host[2] = 0;
+      ws.off_host[3] = nc;
+    }
+    HIP_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, (nc < n ? 4 : a.nsys + 1) * sizeof(int), hipMemcpyHostToDevice,
+                           st));
+    launch_prologue(ws, a.nsys, n, a.lists == LISTS_SKIN_REUSE ? 0 : a.ncells + 1, true, st);
+  } else {
+    launch_prologue(ws, a.nsys, 0, 0, false, st);  // a later chunk: only the backward's atom lists restart
   }
-  HIP_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, (nc < n ? 4 : a.nsys + 1) * sizeof(int), hipMemcpyHostToDevice,
-                         st));
-  launch_prologue(ws, a.nsys, n, a.lists == LISTS_SKIN_REUSE ? 0 : a.ncells + 1, st);
   if (pm) mark(pm, 0, st);
   switch (a.lists) {
     case LISTS_FRESH:
-      launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc, st);
-      launch_nlist(ws, a.X, n, nc, m->rc, false, st);
+      if (a.first_chunk) launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc, st);
+      if (nc < n)
+        launch_nlist(ws, a.X, n, 0, n, nc, m->rc, false, st);  // ghosts get empty lists
+      else
+        launch_nlist(ws, a.X, n, cb, ce, n, m->rc, false, st);
       break;
     case LISTS_SKIN_BUILD:
       launch_cells(ws, a.X, a.types, n, m->ntypes, a.open_single, a.ncells, m->rc + m->skin, st);
-      launch_nlist(ws, a.X, n, n, m->rc + m->skin, true, st);
+      launch_nlist(ws, a.X, n, 0, n, n, m->rc + m->skin, true, st);
       launch_skin_ref(ws, a.X, n, st);
       launch_filter(ws, a.X, n, m->rc, st);
       break;
@@ -708,29 +719,31 @@ int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, 
   const bool bwd = a.forces || a.virial;
   if (pm) mark(pm, 1, st);
   if (m->prec == DP_BF16)
-    launch_descriptor_fwd_b16(m->wf, m->wp, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
+    launch_descriptor_fwd_b16(m->wf, m->wp, ws, a.X, a.types, n, cb, ce, rc, rcs, eps, st);
   else
-    launch_descriptor_fwd<float>(m->wf, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
+    launch_descriptor_fwd<float>(m->wf, ws, a.X, a.types, n, cb, ce, rc, rcs, eps, st);
   if (pm) mark(pm, 2, st);
   if (m->prec == DP_BF16)
-    launch_fitting_b16(m->wf, m->wp, ws, a.types, nc, bwd, st);
+    launch_fitting_b16(m->wf, m->wp, ws, a.types, cb, ce, bwd, st);
   else
-    launch_fitting<float>(m->wf, ws, a.types, nc, bwd, st);
+    launch_fitting<float>(m->wf, ws, a.types, cb, ce, bwd, st);
   if (pm) mark(pm, 3, st);
   // energies over the centre atoms (every atom, or the first nc of one system with ghosts)
   const int *eoff = nc < n ? ws.sys_off + 2 : ws.sys_off;
-  if (!bwd) launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, nullptr, m->wf.nheads, st);
+  if (!bwd && a.last_chunk) launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, nullptr, m->wf.nheads, st);
   if (pm) mark(pm, 4, st);
   if (bwd) {
     if (m->prec == DP_BF16)
-      launch_descriptor_bwd_b16(m->wf, m->wp, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
+      launch_descriptor_bwd_b16(m->wf, m->wp, ws, a.X, a.types, n, cb, ce, rc, rcs, eps, st);
     else
-      launch_descriptor_bwd<float>(m->wf, ws, a.X, a.types, n, nc, rc, rcs, eps, st);
+      launch_descriptor_bwd<float>(m->wf, ws, a.X, a.types, n, cb, ce, rc, rcs, eps, st);
     if (pm) mark(pm, 5, st);
-    double *F = a.forces;
-    if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
-    launch_forces(ws, a.X, n, nullptr, F, a.lists == LISTS_SKIN_REUSE, nc < n, st);
-    launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, a.virial, m->wf.nheads, st);
+    if (a.last_chunk) {
+      double *F = a.forces;
+      if (!F) F = (double *)ws.D;  // forces not requested: park them in the (now free) descriptor buffer
+      launch_forces(ws, a.X, n, nullptr, F, a.lists == LISTS_SKIN_REUSE, nc < n, st);
+      launch_reduce(ws, eoff, a.nsys, a.energy, a.atom_energy, a.virial, m->wf.nheads, st);
+    }
     if (pm) mark(pm, 6, st);
   }
   HIP_TRY(hipGetLastError());
@@ -833,6 +846,16 @@ int run_single(dp_model *m, StepArgs a, const double *box, hipStream_t st) {
     a.ncells = a.open_single ? MAX_CELLS : ws.grids_host[0].ncells;
     if (graph) {
       s = launch_graph(m, a, st);
+    } else if (m->chunk > 0 && a.lists == LISTS_FRESH && a.n > m->chunk) {
+      // the centres in chunks of m->chunk atoms, each chunk a sequence of launches
+      for (int64_t c0 = 0; c0 < a.n && s == DP_OK; c0 += m->chunk) {
+        StepArgs c = a;
+        c.c0 = c0;
+        c.c1 = std::min<int64_t>(a.n, c0 + m->chunk);
+        c.first_chunk = c0 == 0;
+        c.last_chunk = c.c1 == a.n;
+        s = enqueue_step(m, ws, c, st, false);
+      }
     } else {
       s = enqueue_step(m, ws, a, st, m->prof);
     }
@@ -1273,6 +1296,16 @@ int dp_skin_stats(const dp_model *m, int64_t *builds, int64_t *forced) {
   return DP_OK;
 }
 
+int dp_set_chunk(dp_model *m, int64_t chunk_atoms) {
+  g_last_error.clear();
+  if (!m || chunk_atoms < 0) {
+    set_error("dp_set_chunk: bad argument");
+    return DP_ERR_ARG;
+  }
+  m->chunk = chunk_atoms;
+  return DP_OK;
+}
+
 int dp_set_graph(dp_model *m, int enable) {
   g_last_error.clear();
   if (!m) return DP_ERR_ARG;
@@ -1305,11 +1338,11 @@ int dp_backward_device(dp_model *m, const double *d_grad_energy, double *d_grad_
   // the energy-only pass left D, the lists and the grid in place; rerun the fitting
   // net with its backward
   if (m->prec == DP_FP32) {
-    launch_fitting<float>(m->wf, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, n, rc, rcs, eps, st);
+    launch_fitting<float>(m->wf, ws, m->fwd_types, 0, n, true, st);
+    launch_descriptor_bwd<float>(m->wf, ws, m->fwd_coords, m->fwd_types, n, 0, n, rc, rcs, eps, st);
   } else {
-    launch_fitting_b16(m->wf, m->wp, ws, m->fwd_types, n, true, st);
-    launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, n, rc, rcs, eps, st);
+    launch_fitting_b16(m->wf, m->wp, ws, m->fwd_types, 0, n, true, st);
+    launch_descriptor_bwd_b16(m->wf, m->wp, ws, m->fwd_coords, m->fwd_types, n, 0, n, rc, rcs, eps, st);
   }
   launch_forces(ws, m->fwd_coords, n, d_grad_energy, d_grad_coords, m->fwd_lists == LISTS_SKIN_REUSE, false, st);
   if (d_virial) launch_reduce(ws, ws.sys_off, 1, nullptr, nullptr, d_virial, 1, st);
@@ -1404,9 +1437,9 @@ int dp_debug_neighbors(dp_model *m, int64_t natoms, const double *coords, const 
       hipMemcpy(ws.sys_off, ws.off_host, 2 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     s = DP_ERR_HIP;
   } else {
-    launch_prologue(ws, 1, (int)natoms, (open ? MAX_CELLS : g.ncells) + 1, st);
+    launch_prologue(ws, 1, (int)natoms, (open ? MAX_CELLS : g.ncells) + 1, true, st);
     launch_cells(ws, dX, dT, (int)natoms, m->ntypes, open, open ? MAX_CELLS : g.ncells, m->rc, st);
-    launch_nlist(ws, dX, (int)natoms, (int)natoms, m->rc, false, st);
+    launch_nlist(ws, dX, (int)natoms, 0, (int)natoms, (int)natoms, m->rc, false, st);
     if (hipStreamSynchronize(st) != hipSuccess ||
         hipMemcpy(nlist, ws.nlist, n * SEL * 4, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(nnei, ws.nnei, n * 4, hipMemcpyDeviceToHost) != hipSuccess ||

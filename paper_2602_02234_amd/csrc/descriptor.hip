@@ -188,12 +188,12 @@ struct SmemFwd {
 
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
-k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+k_desc_fwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms, int c0,
            const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
            float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
            float *__restrict__ D) {
   __shared__ SmemFwd sm;
-  const int i = blockIdx.x;
+  const int i = c0 + blockIdx.x;
   const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
@@ -259,12 +259,12 @@ struct SmemBwd {
 
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS)
-k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ types, int natoms, int c0,
            const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
            float rc, float rcs, float ln_eps, const float *__restrict__ Gsave, const float *__restrict__ Tsave,
            const float *__restrict__ dD, float4 *__restrict__ gout) {
   __shared__ SmemBwd sm;
-  const int i = blockIdx.x;
+  const int i = c0 + blockIdx.x;
   const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
@@ -599,21 +599,21 @@ k_desc_bwd(Weights<T> w, const double *__restrict__ X, const int *__restrict__ t
 
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
-                           int ncen, float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(ncen), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                           int c0, int c1, float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_fwd<T>, dim3(c1 - c0), dim3(NTHREADS), 0, st, w, coords, types, n, c0, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D);
 }
 
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types, int n,
-                           int ncen, float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(ncen), dim3(NTHREADS), 0, st, w, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+                           int c0, int c1, float rc, float rcs, float ln_eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_desc_bwd<T>, dim3(c1 - c0), dim3(NTHREADS), 0, st, w, coords, types, n, c0, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.g);
 }
 
 template void launch_descriptor_fwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
-                                           int, int, float, float, float, hipStream_t);
+                                           int, int, int, float, float, float, hipStream_t);
 template void launch_descriptor_bwd<float>(const Weights<float> &, const Workspace &, const double *, const int *,
-                                           int, int, float, float, float, hipStream_t);
+                                           int, int, int, float, float, float, hipStream_t);
 
 }  // namespace dp

@@ -16,12 +16,12 @@ struct __align__(16) SmemF16 {
 };
 
 __global__ void __launch_bounds__(NWF * 64)
-k_desc_fwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms,
+k_desc_fwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int *__restrict__ types, int natoms, int c0,
                const int *__restrict__ nlist, const int *__restrict__ nnei, const Grid *__restrict__ grids, const int *__restrict__ sys_of,
                float rc, float rcs, float ln_eps, float *__restrict__ Gsave, float *__restrict__ Tsave,
                float *__restrict__ D, int *__restrict__ bidx, int *__restrict__ bcnt, int cap) {
   __shared__ SmemF16 sm;
-  const int i = blockIdx.x;
+  const int i = c0 + blockIdx.x;
   const Grid g = grids[sys_of[i]];
   const int n = min(max(nnei[i], 0), SEL);
   const int NP = n > 0 ? ((n + 15) / 16) * 16 : 16;
@@ -102,9 +102,9 @@ k_desc_fwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int 
 }  // namespace
 
 void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, int ncen,
+                               const double *coords, const int *types, int n, int c0, int c1,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(ncen), dim3(NWF * 64), 0, st, w, wp, coords, types, n, ws.nlist, ws.nnei, ws.grids,
+  hipLaunchKernelGGL(k_desc_fwd_b16, dim3(c1 - c0), dim3(NWF * 64), 0, st, w, wp, coords, types, n, c0, ws.nlist, ws.nnei, ws.grids,
                      ws.sys_of, rc, rcs, ln_eps, ws.Gsave, ws.Tsave, ws.D, ws.bidx, ws.bcnt, (int)ws.cap);
 }
 

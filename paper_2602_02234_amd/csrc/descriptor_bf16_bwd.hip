@@ -560,8 +560,9 @@ k_desc_bwd_b16(Tables w, WeightsB16 wp, const double *__restrict__ X, const int 
 }  // namespace
 
 void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, int ncen,
+                               const double *coords, const int *types, int n, int c0, int c1,
                                float rc, float rcs, float ln_eps, hipStream_t st) {
+  const int ncen = c1 - c0;  // the forward listed these atoms in ws.bidx
   // atoms with up to 7 row blocks: 7 waves, one block each (on st); the rest: 4 waves,
   // two blocks each, on the side stream, so that a few dense atoms overlap the bulk.  The
   // forward pass listed the atoms of each instance (bidx, bcnt).

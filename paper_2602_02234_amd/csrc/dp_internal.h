@@ -162,6 +162,12 @@ struct StepArgs {
   int lists = LISTS_FRESH;
   int64_t n_centres = -1;         // one system: only atoms 0 .. n_centres-1 are centres (E_i, g_ij);
                                   // the rest are neighbours only (ghosts).  -1: every atom
+  // one system in chunks: this call evaluates the centres c0 .. c1-1 (c1 = -1: to the end);
+  // the first chunk builds the cell list and clears the step's flags and counters, the last
+  // gathers forces and reduces energy and virial.  Chunks of a system run in order on one
+  // workspace; lists, E_i and g_ij of earlier chunks stay in it.
+  int64_t c0 = 0, c1 = -1;
+  bool first_chunk = true, last_chunk = true;
 };
 
 struct GraphKey {
@@ -203,6 +209,8 @@ struct dp_model {
   bool skin_open = false;
   double skin_box[9] = {};
   int64_t skin_builds = 0, skin_rebuilds_forced = 0;
+  // centres evaluated in chunks of this many atoms (dp_set_chunk; 0 = all at once)
+  int64_t chunk = 0;
   // step graphs (dp_set_graph)
   bool use_graph = false;
   dp::GraphEntry graphs[4];
@@ -222,36 +230,37 @@ void set_error(const std::string &s);
 // Launchers (defined in the kernel translation units); all enqueue on `st` and read the
 // per-system grids (ws.grids), atom ranges (ws.sys_off) and atom -> system map (ws.sys_of).
 // Clears the step's counters and flags (and ncells_zero cell counts) and maps atoms to systems.
-void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, hipStream_t st);
+void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, bool clear_flags, hipStream_t st);
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
                   int ncells_total, double cell_cutoff, hipStream_t st);
-// Lists for the first ncen atoms (the others get empty lists), candidates among all n.
-void launch_nlist(const Workspace &ws, const double *coords, int n, int ncen, double cutoff, bool skin,
-                  hipStream_t st);
+// Lists for the atoms i0 .. i1-1 with candidates among all n; those at or beyond ncen get
+// empty lists (ghost atoms).
+void launch_nlist(const Workspace &ws, const double *coords, int n, int i0, int i1, int ncen, double cutoff,
+                  bool skin, hipStream_t st);
 void launch_filter(const Workspace &ws, const double *coords, int n, double rc, hipStream_t st);
 void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
                        hipStream_t st);
 void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st);
-// The per-centre launchers run over the first ncen atoms (the centres), reading the
-// coordinates and types of all n atoms as neighbours.
+// The per-centre launchers run over the centre atoms c0 .. c1-1, reading the coordinates
+// and types of all n atoms as neighbours.
 template <typename T>
 void launch_descriptor_fwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
-                           int n, int ncen, float rc, float rcs, float ln_eps, hipStream_t st);
+                           int n, int c0, int c1, float rc, float rcs, float ln_eps, hipStream_t st);
 // The fitting net over the first n atoms (E_i, and dE/dD over D when backward).
 template <typename T>
-void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward,
+void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int c0, int c1, bool backward,
                     hipStream_t st);
 void launch_descriptor_fwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, int ncen, float rc, float rcs,
-                               float ln_eps, hipStream_t st);
+                               const double *coords, const int *types, int n, int c0, int c1, float rc,
+                               float rcs, float ln_eps, hipStream_t st);
 void launch_descriptor_bwd_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws,
-                               const double *coords, const int *types, int n, int ncen, float rc, float rcs,
-                               float ln_eps, hipStream_t st);
-void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
-                        bool backward, hipStream_t st);
+                               const double *coords, const int *types, int n, int c0, int c1, float rc,
+                               float rcs, float ln_eps, hipStream_t st);
+void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int c0,
+                        int c1, bool backward, hipStream_t st);
 template <typename T>
 void launch_descriptor_bwd(const Weights<T> &w, const Workspace &ws, const double *coords, const int *types,
-                           int n, int ncen, float rc, float rcs, float ln_eps, hipStream_t st);
+                           int n, int c0, int c1, float rc, float rcs, float ln_eps, hipStream_t st);
 // Forces of all n atoms and the per-atom virial partials.  skin_rows: the step reused skin
 // lists (one-sided pairs are then found through the skin rows, else through the cell list
 // of the step); ghosts: atoms without lists are present.

@@ -18,12 +18,12 @@ constexpr int LDF = FH + 4;
 // its backward with dE/dy3 = hw_h F4^h, and dE/dD = sum_h dE/dpre1^h F1^hT.
 template <typename T, int NH>
 __global__ void __launch_bounds__(NTHREADS)
-k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D, double *__restrict__ Ei,
+k_fit(Weights<T> w, const int *__restrict__ types, int c0, int n, float *__restrict__ D, double *__restrict__ Ei,
       double *__restrict__ Eh, int backward) {
   __shared__ float y1[16 * LDF], t2[16 * LDF], y2[16 * LDF], t3[16 * LDF], bA[16 * LDF], bB[16 * LDF];
   __shared__ float bS[NH > 1 ? NH : 1][NH > 1 ? 16 * LDF : 4];  // dE/dpre1 of each head (NH > 1)
   __shared__ double eacc[16];
-  const int a0 = blockIdx.x * 16;
+  const int a0 = c0 + blockIdx.x * 16;
   const int wv = wave_id();
   constexpr int NT = FH / 16;  // 15 column tiles of the hidden width
   if (threadIdx.x < 16) eacc[threadIdx.x] = 0.0;
@@ -142,16 +142,19 @@ k_fit(Weights<T> w, const int *__restrict__ types, int n, float *__restrict__ D,
 }  // namespace
 
 template <typename T>
-void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int n, bool backward, hipStream_t st) {
-  const dim3 grid((n + 15) / 16), block(NTHREADS);
+void launch_fitting(const Weights<T> &w, const Workspace &ws, const int *types, int c0, int c1, bool backward,
+                    hipStream_t st) {
+  const dim3 grid((c1 - c0 + 15) / 16), block(NTHREADS);
+  const int n = c1;
   const int b = backward ? 1 : 0;
   switch (w.nheads) {
-    case 1: hipLaunchKernelGGL((k_fit<T, 1>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
-    case 2: hipLaunchKernelGGL((k_fit<T, 2>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
-    case 3: hipLaunchKernelGGL((k_fit<T, 3>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
-    default: hipLaunchKernelGGL((k_fit<T, 4>), grid, block, 0, st, w, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 1: hipLaunchKernelGGL((k_fit<T, 1>), grid, block, 0, st, w, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 2: hipLaunchKernelGGL((k_fit<T, 2>), grid, block, 0, st, w, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 3: hipLaunchKernelGGL((k_fit<T, 3>), grid, block, 0, st, w, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
+    default: hipLaunchKernelGGL((k_fit<T, 4>), grid, block, 0, st, w, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
   }
 }
-template void launch_fitting<float>(const Weights<float> &, const Workspace &, const int *, int, bool, hipStream_t);
+template void launch_fitting<float>(const Weights<float> &, const Workspace &, const int *, int, int, bool,
+                                    hipStream_t);
 
 }  // namespace dp

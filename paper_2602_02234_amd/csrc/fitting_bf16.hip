@@ -96,7 +96,7 @@ __device__ __forceinline__ void mm_split_dd(f4 (&acc)[U1 - U0], const float *a, 
 // non-zero weight runs with dE/dy3 = hw_h F4^h, and dE/dD = sum_h dE/dpre1^h F1^hT.
 template <int NH>
 __global__ void __launch_bounds__(NWT * 64) __attribute__((amdgpu_waves_per_eu(4)))
-k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *__restrict__ D,
+k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int c0, int n, float *__restrict__ D,
           double *__restrict__ Ei, double *__restrict__ Eh, int backward) {
   // y1, t2: the first two layers' outputs; y2: the third layer's input, later dE/dy2;
   // X: dE/dpre3, dE/dpre2, dE/dpre1 in turn (Xs: dE/dpre1 of each head, NH > 1).
@@ -105,7 +105,7 @@ k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *
   __shared__ __align__(16) float Xs[NH > 1 ? NH : 1][NH > 1 ? 16 * LDA : 4];
   __shared__ double ep[16][16];  // per-row energy partials, one per column tile
   __shared__ double eacc[16];
-  const int a0 = blockIdx.x * 16;
+  const int a0 = c0 + blockIdx.x * 16;
   const int l = lane_id(), q = l >> 4, cl = l & 15, wv = wave_id();
   for (int x = threadIdx.x; x < 16 * (KH - FH); x += NWT * 64) {
     const int r = x / (KH - FH), c = FH + x % (KH - FH);
@@ -259,15 +259,16 @@ k_fit_b16(Tables w, WeightsB16 wp, const int *__restrict__ types, int n, float *
 
 }  // namespace
 
-void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int n,
+void launch_fitting_b16(const Tables &w, const WeightsB16 &wp, const Workspace &ws, const int *types, int c0, int c1,
                         bool backward, hipStream_t st) {
-  const dim3 grid((n + 15) / 16), block(NWT * 64);
+  const dim3 grid((c1 - c0 + 15) / 16), block(NWT * 64);
+  const int n = c1;
   const int b = backward ? 1 : 0;
   switch (w.nheads) {
-    case 1: hipLaunchKernelGGL(k_fit_b16<1>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
-    case 2: hipLaunchKernelGGL(k_fit_b16<2>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
-    case 3: hipLaunchKernelGGL(k_fit_b16<3>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
-    default: hipLaunchKernelGGL(k_fit_b16<4>, grid, block, 0, st, w, wp, types, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 1: hipLaunchKernelGGL(k_fit_b16<1>, grid, block, 0, st, w, wp, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 2: hipLaunchKernelGGL(k_fit_b16<2>, grid, block, 0, st, w, wp, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
+    case 3: hipLaunchKernelGGL(k_fit_b16<3>, grid, block, 0, st, w, wp, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
+    default: hipLaunchKernelGGL(k_fit_b16<4>, grid, block, 0, st, w, wp, types, c0, n, ws.D, ws.Ei, ws.Eh, b); break;
   }
 }
 

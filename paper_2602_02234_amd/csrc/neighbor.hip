@@ -70,15 +70,16 @@ __global__ void __launch_bounds__(1024) k_grid_open(const double *__restrict__ X
   }
 }
 
-// Start of a step: clears the status words, the per-system completion counters and the
-// backward instances' atom counts, clears the cell counts (ncz entries), and writes
-// sys_of[a] = s for off[s] <= a < off[s + 1].  Grid-stride; no workgroup depends on another.
+// Start of a step: clears the status words (nflags of them), the completion counters
+// (ndone) and the backward instances' atom counts, clears the cell counts (ncz entries),
+// and writes sys_of[a] = s for off[s] <= a < off[s + 1], a < n.  Grid-stride; no
+// workgroup depends on another.
 __global__ void k_prologue(const int *__restrict__ off, int nsys, int n, int *__restrict__ sys_of,
-                           int *__restrict__ cell_count, int ncz, unsigned *__restrict__ flags,
+                           int *__restrict__ cell_count, int ncz, unsigned *__restrict__ flags, int nflags,
                            int *__restrict__ done, int ndone, int *__restrict__ bcnt) {
   const int stride = gridDim.x * blockDim.x;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < max(max(n, ncz), ndone); t += stride) {
-    if (t < 4) flags[t] = 0u;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < max(max(n, ncz), max(ndone, 2)); t += stride) {
+    if (t < nflags) flags[t] = 0u;
     if (t < 2) bcnt[t] = 0;
     if (t < ndone) done[t] = 0;
     if (t < ncz) cell_count[t] = 0;
@@ -226,13 +227,13 @@ __device__ bool write_row(const int *cj, const double *cd2, int *keep, int count
 __global__ void __launch_bounds__(64) k_nlist(const double *__restrict__ X, int n, const Grid *__restrict__ grids,
                                               const int *__restrict__ sys_of, double cut2,
                                               const int *__restrict__ cell_of, const int *__restrict__ cell_start,
-                                              const int *__restrict__ cell_atoms, int cap, int skin, int ncen,
-                                              int *__restrict__ nlist, int *__restrict__ nnei,
+                                              const int *__restrict__ cell_atoms, int cap, int skin, int i0,
+                                              int ncen, int *__restrict__ nlist, int *__restrict__ nnei,
                                               unsigned *__restrict__ flags) {
   __shared__ int cj[CAND_CAP];
   __shared__ double cd2[CAND_CAP];
   __shared__ int keep[CAND_CAP];
-  const int i = blockIdx.x;
+  const int i = i0 + blockIdx.x;
   if (i >= n) return;
   const int lane = threadIdx.x;
   if (i >= ncen) {  // not a centre (a ghost atom): an empty list
@@ -361,11 +362,12 @@ __global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ 
 
 }  // namespace
 
-void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, hipStream_t st) {
+void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, bool clear_flags, hipStream_t st) {
   const int work = std::max(n, ncells_zero);
   const int blocks = std::max(1, std::min((work + 255) / 256, 4096));
   hipLaunchKernelGGL(k_prologue, dim3(blocks), dim3(256), 0, st, ws.sys_off, nsys, n, ws.sys_of, ws.cell_count,
-                     ncells_zero, ws.flags, ws.done, 2 * ws.cap_sys + 1, ws.bcnt);
+                     ncells_zero, ws.flags, clear_flags ? 4 : 0, ws.done, clear_flags ? 2 * ws.cap_sys + 1 : 0,
+                     ws.bcnt);
 }
 
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
@@ -380,10 +382,10 @@ void launch_cells(const Workspace &ws, const double *coords, const int *types, i
                      ws.cell_atoms, n);
 }
 
-void launch_nlist(const Workspace &ws, const double *coords, int n, int ncen, double cutoff, bool skin,
+void launch_nlist(const Workspace &ws, const double *coords, int n, int i0, int i1, int ncen, double cutoff, bool skin,
                   hipStream_t st) {
-  hipLaunchKernelGGL(k_nlist, dim3(n), dim3(64), 0, st, coords, n, ws.grids, ws.sys_of, cutoff * cutoff, ws.cell_of,
-                     ws.cell_start, ws.cell_atoms, skin ? SKIN_CAP : SEL, skin ? 1 : 0, ncen,
+  hipLaunchKernelGGL(k_nlist, dim3(i1 - i0), dim3(64), 0, st, coords, n, ws.grids, ws.sys_of, cutoff * cutoff,
+                     ws.cell_of, ws.cell_start, ws.cell_atoms, skin ? SKIN_CAP : SEL, skin ? 1 : 0, i0, ncen,
                      skin ? ws.slist : ws.nlist, skin ? ws.snnei : ws.nnei, ws.flags);
 }
 

@@ -126,6 +126,26 @@ def test_graph_cache_follows_workspace_growth(model_path, prec, skin):
     graph.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_chunked_centres_equal_whole_step(model_path, prec):
+    """The centres of a system evaluated in chunks (each chunk its lists, descriptor,
+    fitting and backward; the last one the forces and reductions) give the whole step's
+    results bit for bit, with a ragged last chunk and energy-only calls too."""
+    from paper_2602_02234_amd import Model
+    whole, chunked = Model(model_path, prec), Model(model_path, prec)
+    chunked.set_chunk(700)
+    for name in ("chain3k", "water192"):
+        s = config_system(name)
+        a = whole.compute(s.coords, s.types, s.box, atom_energy=True)
+        b = chunked.compute(s.coords, s.types, s.box, atom_energy=True)
+        assert _same(a, b) and np.array_equal(a["E_i"], b["E_i"]), name
+        ea = whole.compute(s.coords, s.types, s.box, forces=False)["E"]
+        eb = chunked.compute(s.coords, s.types, s.box, forces=False)["E"]
+        assert ea == eb, name
+    whole.close()
+    chunked.close()
+
+
 def test_server_isolates_failing_requests(model_path):
     """Invalid requests fail alone: bad types, a non-finite coordinate or a small box are
     refused by dp_submit; two atoms at the same place are only found on the device, so
