@@ -163,14 +163,14 @@ def make_trace(n_req, workers):
     return trace, systems
 
 
-def serving_bench(model_path, trace_all, systems_all, legs, budget_bytes):
+def serving_bench(model_path, trace_all, systems_all, legs, budget_bytes, max_inflight=3):
     """The Poisson request trace (sizes log-uniform 192..40,000 atoms, water boxes or solvated
     chains) replayed in real time against the BF16 continuous-batching server and against the
     FP32 path evaluating one request at a time (host API).  legs: (arrival rate, number of
     requests from the start of the trace); the trace's arrival times are scaled to the rate."""
     import time as _t
     from paper_2602_02234_amd import Model, Server
-    out = {"hbm_budget_GB": budget_bytes / 2**30, "rates": {}}
+    out = {"hbm_budget_GB": budget_bytes / 2**30, "max_inflight": max_inflight, "rates": {}}
     for rate, n_req in legs:
         trace, systems = trace_all[:n_req], systems_all[:n_req]
         atoms = np.array([len(t) for _, t, _ in systems])
@@ -180,10 +180,10 @@ def serving_bench(model_path, trace_all, systems_all, legs, budget_bytes):
                "trace_seconds": float(arr[-1])}
         # BF16 server, continuous batching
         m = Model(model_path, "bf16")
-        srv = Server(m, budget_bytes)
+        srv = Server(m, budget_bytes, max_inflight)
         srv.wait(srv.submit(*systems[0]), 120.0)
         srv.close()
-        srv = Server(m, budget_bytes)
+        srv = Server(m, budget_bytes, max_inflight)
         t0 = _t.perf_counter()
         ids = []
         for a, sysk in zip(arr, systems):

@@ -236,26 +236,33 @@ int dp_set_chunk(dp_model *m, int64_t chunk_atoms);
 int dp_set_graph(dp_model *m, int enable);
 
 /* Continuous-batching server over one model (the model must not be used
- * otherwise while the server exists).  Requests are periodic systems; each is
- * copied on submit, queued, packed with other queued requests into one batched
- * step (dp_compute_batch_device semantics) as soon as one of two in-flight
- * slots is free, and completed asynchronously.  Admission by device memory:
- * a batch holds at most as many atoms as half of hbm_budget_bytes allows
- * (dp_server_footprint bytes per system), so the two in-flight batches stay
- * within the budget; a system that does not fit half the budget is rejected by
- * dp_submit with DP_ERR_TOO_LARGE.  dp_submit validates the request (types,
- * finite coordinates, box) and never waits for the GPU.  dp_wait blocks up to
+ * otherwise while the server exists; the serving extension of the paper's setting,
+ * Section III, where the engine hands the potential one system per step).
+ * Requests are periodic systems; each is copied on submit and queued.  Up to
+ * max_inflight (1..8) work items run at once, each on its own stream:
+ *   - requests of at most 8192 atoms are packed, in arrival order, into batched
+ *     steps of at most 8192 atoms (dp_compute_batch_device semantics);
+ *   - a larger request is split into chunks of 8192 centre atoms (dp_set_chunk
+ *     semantics) on a workspace of its own; after each chunk it goes to the back
+ *     of the queue, so requests that arrived meanwhile run first.
+ * Admission by device memory: the max_inflight batch workspaces (8192 atoms
+ * each, dp_server_footprint bytes per atom) plus the workspaces of the large
+ * requests in progress stay within hbm_budget_bytes; dp_server_create refuses a
+ * budget below max_inflight batches, and dp_submit refuses (DP_ERR_TOO_LARGE) a
+ * system that could never fit.  dp_submit validates the request (types, finite
+ * coordinates, box) and never waits for the GPU.  dp_wait blocks up to
  * timeout_s seconds (< 0: no limit; DP_ERR_TIMEOUT on expiry, the request stays
  * pending), copies energy (1), forces ([natoms][3]) and virial (9) to host
  * buffers (any may be NULL), gives the latency from submit to completion, and
- * releases the request.  A request whose batch fails is re-run alone so that
- * its own status is reported.  dp_server_stats: nearest-rank p50/p99 latency
- * over completed requests, atoms completed per second from the first submit to
- * the last completion, completed requests, batches launched, largest batch in
- * atoms (any output may be NULL).  dp_submit/dp_wait/dp_server_stats may be
- * called from any thread; dp_server_free waits for queued work to finish. */
+ * releases the request.  A request whose batch fails is re-run alone so that its
+ * own status is reported.  Results equal dp_compute on the request alone, bit
+ * for bit.  dp_server_stats: nearest-rank p50/p99 latency over completed
+ * requests, atoms completed per second from the first submit to the last
+ * completion, completed requests, work items launched, largest item in atoms
+ * (any output may be NULL).  dp_submit/dp_wait/dp_server_stats may be called
+ * from any thread; dp_server_free waits for queued work to finish. */
 size_t dp_server_footprint(const dp_model *m, int64_t natoms);
-int dp_server_create(dp_model *m, size_t hbm_budget_bytes, dp_server **out);
+int dp_server_create(dp_model *m, size_t hbm_budget_bytes, int max_inflight, dp_server **out);
 int dp_submit(dp_server *s, int64_t natoms, const double *coords, const int32_t *types,
               const double *box, uint64_t *request_id);
 int dp_wait(dp_server *s, uint64_t request_id, double timeout_s, double *energy, double *forces,

@@ -46,7 +46,7 @@ SIGNATURES = {
     "dp_set_graph": (C.c_int, [_P, C.c_int]),
     "dp_set_chunk": (C.c_int, [_P, _I64]),
     "dp_server_footprint": (C.c_size_t, [_P, _I64]),
-    "dp_server_create": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "dp_server_create": (C.c_int, [_P, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     "dp_submit": (C.c_int, [_P, _I64, _P, _P, _P, C.POINTER(C.c_uint64)]),
     "dp_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P, _P, _P]),
     "dp_server_stats": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),

@@ -256,10 +256,11 @@ class Model:
 class Server:
     """Continuous-batching server (dp_server_*): submit host systems, wait for results."""
 
-    def __init__(self, model: Model, hbm_budget_bytes: int):
+    def __init__(self, model: Model, hbm_budget_bytes: int, max_inflight: int = 3):
         lib = _lib.load()
         h = C.c_void_p()
-        check(lib.dp_server_create(model._h, int(hbm_budget_bytes), C.byref(h)), "dp_server_create")
+        check(lib.dp_server_create(model._h, int(hbm_budget_bytes), int(max_inflight), C.byref(h)),
+              "dp_server_create")
         self._h = h
         self.model = model
         self._n = {}

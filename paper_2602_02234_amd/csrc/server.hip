@@ -2,17 +2,25 @@
 //
 // Independent energy/force/virial requests (the paper's MD engine hands the model
 // one system per step; a serving loop sees many such systems at once) are queued on
-// submit and packed into batched steps: all atoms of the requests in a batch go
-// through each kernel of the step in one launch (concatenated atom arrays, one cell
-// grid per system).  Two lanes, each with its own stream, device workspace and
-// pinned staging, alternate: while one lane's batch runs, the worker packs, uploads
-// and launches the next batch on the other lane, so requests that arrive while the
-// GPU is busy are admitted as soon as a lane frees up and their work overlaps on
-// the device.  Admission is by device-memory footprint: a lane's batch never holds
-// more atoms than half the byte budget allows (the two lanes together stay within
-// the budget).  A request's result does not depend on the other requests of its
-// batch: every per-atom kernel computes each atom from that atom's data only, and
-// the per-system reductions run in the same fixed order at any offset.
+// submit and run as work items on up to max_inflight lanes, each with its own stream:
+//
+//  * requests of at most CHUNK atoms are packed, in arrival order, into batched steps
+//    of at most CHUNK atoms (all atoms of the batch go through each kernel in one
+//    launch: concatenated atom arrays, one cell grid per system);
+//  * a larger request is split into (request, centre chunk) items of CHUNK centre
+//    atoms, evaluated in order on a workspace of its own (lists, E_i and pair
+//    gradients of earlier chunks stay there; the last chunk gathers the forces).  After
+//    each chunk the request goes to the back of the queue, so the requests that arrived
+//    meanwhile run before its next chunk and a small request is never held behind a
+//    whole large one.
+//
+// While one lane's item runs, the worker packs, uploads and launches items on the
+// others, so requests that arrive while the GPU is busy are admitted as lanes free up
+// and their work overlaps on the device.  Admission is by device-memory footprint: the
+// lanes' batch workspaces plus the workspaces of the large requests in progress stay
+// within the byte budget.  A request's result does not depend on the other requests of
+// its batch nor on chunking: every per-atom kernel computes each atom from that atom's
+// data only, and the per-system reductions run in the same fixed order at any offset.
 #include <algorithm>
 #include <cmath>
 #include <chrono>
@@ -33,25 +41,11 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int LANES = 2;
+constexpr int MAX_LANES = 8;
+constexpr int64_t CHUNK = 8192;  // atoms per batch, and centre atoms per chunk of a large request
 constexpr int MAX_BATCH_SYSTEMS = 256;
 // device bytes per atom outside the workspace: coordinates, types, forces
 constexpr size_t IO_BYTES_PER_ATOM = 3 * sizeof(double) + sizeof(int) + 3 * sizeof(double);
-
-struct Request {
-  uint64_t id = 0;
-  int64_t n = 0;
-  std::vector<double> X;
-  std::vector<int32_t> T;
-  double box[9] = {};
-  bool solo = false;  // run alone (after its batch failed)
-  // results
-  int status = DP_OK;
-  bool done = false;
-  double E = 0.0, V[9] = {};
-  std::vector<double> F;
-  Clock::time_point t_submit, t_done;
-};
 
 template <typename T> int grow(T **p, int64_t &cap, int64_t need, bool pinned) {
   if (need <= cap) return DP_OK;
@@ -69,6 +63,35 @@ template <typename T> int grow(T **p, int64_t &cap, int64_t need, bool pinned) {
   return DP_OK;
 }
 
+// Device state of one large request while its chunks run: its own workspace and
+// input/output arrays.  Kept in a pool and reused.
+struct BigSlot {
+  bool used = false;
+  Workspace ws;
+  double *dX = nullptr, *dF = nullptr, *dE = nullptr, *dV = nullptr;
+  int *dT = nullptr;
+  int64_t cX = 0, cF = 0, cE = 0, cV = 0, cT = 0;
+};
+
+struct Request {
+  uint64_t id = 0;
+  int64_t n = 0;
+  std::vector<double> X;
+  std::vector<int32_t> T;
+  double box[9] = {};
+  bool solo = false;  // run alone (after its batch failed)
+  // a large request: progress of its chunks and its device state
+  bool chunked = false;
+  int64_t next_c0 = 0;
+  BigSlot *slot = nullptr;
+  // results
+  int status = DP_OK;
+  bool done = false;
+  double E = 0.0, V[9] = {};
+  std::vector<double> F;
+  Clock::time_point t_submit, t_done;
+};
+
 struct Lane {
   hipStream_t st = nullptr;
   hipEvent_t done_ev = nullptr;
@@ -77,8 +100,11 @@ struct Lane {
   int *dT = nullptr;
   double *hX = nullptr, *hF = nullptr, *hE = nullptr, *hV = nullptr;
   int *hT = nullptr;
-  int64_t cX = 0, cF = 0, cE = 0, cV = 0, cT = 0, chX = 0, chF = 0, chE = 0, chV = 0, chT = 0;
-  std::vector<Request *> batch;
+  unsigned *hflags = nullptr;  // status words of a chunk item
+  int64_t cX = 0, cF = 0, cE = 0, cV = 0, cT = 0, chX = 0, chF = 0, chE = 0, chV = 0, chT = 0, chflags = 0;
+  std::vector<Request *> batch;  // a batch of small requests, or the one large request of a chunk item
+  bool chunk_item = false;
+  bool last_chunk = false;
   int64_t atoms = 0;
   bool busy = false;
   int launch_status = DP_OK;
@@ -89,25 +115,39 @@ struct Lane {
 struct dp_server {
   dp_model *m = nullptr;
   size_t budget = 0;
-  int64_t lane_atoms = 0;  // admission limit per lane
+  int nlanes = 2;
+  size_t big_bytes = 0;       // budget left by the lanes for the workspaces of large requests
+  int64_t max_big_atoms = 0;  // largest request that budget admits
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
   std::unordered_map<uint64_t, Request *> reqs;
   uint64_t next_id = 1;
-  Lane lanes[LANES];
+  Lane lanes[MAX_LANES];
+  std::vector<BigSlot> big;
   std::thread worker;
   bool stop = false;
   // statistics
   std::vector<double> lat;
-  int64_t atoms_done = 0, completed = 0, batches = 0, max_batch_atoms = 0, max_inflight_atoms = 0;
+  int64_t atoms_done = 0, completed = 0, batches = 0, max_batch_atoms = 0;
   bool have_first = false;
   Clock::time_point t_first, t_last;
 };
 
 namespace {
 
-int lane_launch(dp_server *s, Lane &L) {
+size_t bytes_per_atom(const dp_model *m) { return ws_bytes_per_atom(m->prec) + IO_BYTES_PER_ATOM; }
+
+#define SRV_TRY(expr)                                \
+  do {                                               \
+    if ((expr) != hipSuccess) {                      \
+      set_error(std::string("dp_server: ") + #expr); \
+      return DP_ERR_HIP;                             \
+    }                                                \
+  } while (0)
+
+// A batch of small requests: one batched step on the lane's own workspace.
+int launch_batch(dp_server *s, Lane &L) {
   dp_model *m = s->m;
   const int nsys = (int)L.batch.size();
   int64_t tot = 0;
@@ -144,13 +184,6 @@ int lane_launch(dp_server *s, Lane &L) {
     set_error("dp_server: too many cells in one batch");
     return DP_ERR_TOO_LARGE;
   }
-#define SRV_TRY(expr)                             \
-  do {                                            \
-    if ((expr) != hipSuccess) {                   \
-      set_error(std::string("dp_server: ") + #expr); \
-      return DP_ERR_HIP;                          \
-    }                                             \
-  } while (0)
   SRV_TRY(hipMemcpyAsync(L.dX, L.hX, 3 * tot * sizeof(double), hipMemcpyHostToDevice, L.st));
   SRV_TRY(hipMemcpyAsync(L.dT, L.hT, tot * sizeof(int), hipMemcpyHostToDevice, L.st));
   StepArgs a;
@@ -170,15 +203,82 @@ int lane_launch(dp_server *s, Lane &L) {
   SRV_TRY(hipMemcpyAsync(L.hV, L.dV, 9 * nsys * sizeof(double), hipMemcpyDeviceToHost, L.st));
   SRV_TRY(hipMemcpyAsync(L.ws.flags_host, L.ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, L.st));
   SRV_TRY(hipEventRecord(L.done_ev, L.st));
-#undef SRV_TRY
   L.atoms = tot;
   return DP_OK;
 }
+
+// The next chunk of a large request, on the request's own workspace; the lane supplies
+// its stream and pinned staging.
+int launch_chunk(dp_server *s, Lane &L, Request *r, int64_t c0, int64_t c1) {
+  dp_model *m = s->m;
+  BigSlot &b = *r->slot;
+  const int64_t n = r->n;
+  const bool first = c0 == 0, last = c1 == n;
+  int st = DP_OK;
+  if (first) {
+    st = ensure_ws(b.ws, m->prec, n, 1, false);
+    if (st == DP_OK) st = grow(&b.dX, b.cX, 3 * n, false);
+    if (st == DP_OK) st = grow(&b.dF, b.cF, 3 * n, false);
+    if (st == DP_OK) st = grow(&b.dT, b.cT, n, false);
+    if (st == DP_OK) st = grow(&b.dE, b.cE, 1, false);
+    if (st == DP_OK) st = grow(&b.dV, b.cV, 9, false);
+    if (st == DP_OK) st = grow(&L.hX, L.chX, 3 * n, true);
+    if (st == DP_OK) st = grow(&L.hT, L.chT, n, true);
+    if (st != DP_OK) return st;
+    Grid g;
+    st = make_grid(m->rc, m->rc, r->box, g);
+    if (st != DP_OK) return st;
+    b.ws.grids_host[0] = g;
+    b.ws.off_host[0] = 0;
+    b.ws.off_host[1] = (int)n;
+    std::memcpy(L.hX, r->X.data(), 3 * n * sizeof(double));
+    std::memcpy(L.hT, r->T.data(), n * sizeof(int));
+    SRV_TRY(hipMemcpyAsync(b.dX, L.hX, 3 * n * sizeof(double), hipMemcpyHostToDevice, L.st));
+    SRV_TRY(hipMemcpyAsync(b.dT, L.hT, n * sizeof(int), hipMemcpyHostToDevice, L.st));
+  }
+  if (last) {
+    st = grow(&L.hF, L.chF, 3 * n, true);
+    if (st == DP_OK) st = grow(&L.hE, L.chE, 1, true);
+    if (st == DP_OK) st = grow(&L.hV, L.chV, 9, true);
+    if (st != DP_OK) return st;
+  }
+  if ((st = grow(&L.hflags, L.chflags, 4, true)) != DP_OK) return st;
+  StepArgs a;
+  a.n = n;
+  a.nsys = 1;
+  a.X = b.dX;
+  a.types = b.dT;
+  a.energy = b.dE;
+  a.forces = b.dF;
+  a.virial = b.dV;
+  a.ncells = b.ws.grids_host[0].ncells;
+  a.lists = LISTS_FRESH;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.first_chunk = first;
+  a.last_chunk = last;
+  st = enqueue_step(m, b.ws, a, L.st, false);
+  if (st != DP_OK) return st;
+  if (last) {
+    SRV_TRY(hipMemcpyAsync(L.hF, b.dF, 3 * n * sizeof(double), hipMemcpyDeviceToHost, L.st));
+    SRV_TRY(hipMemcpyAsync(L.hE, b.dE, sizeof(double), hipMemcpyDeviceToHost, L.st));
+    SRV_TRY(hipMemcpyAsync(L.hV, b.dV, 9 * sizeof(double), hipMemcpyDeviceToHost, L.st));
+  }
+  SRV_TRY(hipMemcpyAsync(L.hflags, b.ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, L.st));
+  SRV_TRY(hipEventRecord(L.done_ev, L.st));
+  L.atoms = c1 - c0;
+  return DP_OK;
+}
+#undef SRV_TRY
 
 void finish_request(dp_server *s, Request *r, int status, Clock::time_point now) {
   r->status = status;
   r->t_done = now;
   r->done = true;
+  if (r->slot) {
+    r->slot->used = false;
+    r->slot = nullptr;
+  }
   if (status >= 0) {
     s->lat.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
     s->atoms_done += r->n;
@@ -187,28 +287,51 @@ void finish_request(dp_server *s, Request *r, int status, Clock::time_point now)
   }
 }
 
+// Status of a finished step from copied-back flag words (as step_status reads them).
+int flags_to_status(const unsigned *f) {
+  Workspace tmp;
+  tmp.flags_host = const_cast<unsigned *>(f);
+  const int st = step_status(tmp);
+  return st == DP_RETRY ? DP_ERR_HIP : st;
+}
+
 // Called with the lock held once the lane's event has completed.
 void lane_complete(dp_server *s, Lane &L) {
   const auto now = Clock::now();
   int st = L.launch_status;
-  if (st == DP_OK) st = step_status(L.ws);
-  if (st < 0 && L.batch.size() > 1) {
-    // one request made the batch fail: run each alone to find out which
-    for (auto it = L.batch.rbegin(); it != L.batch.rend(); ++it) {
-      (*it)->solo = true;
-      s->queue.push_front(*it);
+  if (L.chunk_item) {
+    Request *r = L.batch[0];
+    if (st == DP_OK) st = flags_to_status(L.hflags);
+    if (st < 0) {
+      finish_request(s, r, st, now);
+    } else if (L.last_chunk) {
+      r->E = L.hE[0];
+      std::memcpy(r->V, L.hV, 9 * sizeof(double));
+      r->F.assign(L.hF, L.hF + 3 * r->n);
+      finish_request(s, r, st, now);
+    } else {
+      s->queue.push_back(r);  // its next chunk after the requests that arrived meanwhile
     }
   } else {
-    int64_t off = 0;
-    for (size_t k = 0; k < L.batch.size(); ++k) {
-      Request *r = L.batch[k];
-      if (st >= 0) {
-        r->E = L.hE[k];
-        std::memcpy(r->V, L.hV + 9 * k, 9 * sizeof(double));
-        r->F.assign(L.hF + 3 * off, L.hF + 3 * (off + r->n));
+    if (st == DP_OK) st = step_status(L.ws);
+    if (st < 0 && L.batch.size() > 1) {
+      // one request made the batch fail: run each alone to find out which
+      for (auto it = L.batch.rbegin(); it != L.batch.rend(); ++it) {
+        (*it)->solo = true;
+        s->queue.push_front(*it);
       }
-      off += r->n;
-      finish_request(s, r, st, now);
+    } else {
+      int64_t off = 0;
+      for (size_t k = 0; k < L.batch.size(); ++k) {
+        Request *r = L.batch[k];
+        if (st >= 0) {
+          r->E = L.hE[k];
+          std::memcpy(r->V, L.hV + 9 * k, 9 * sizeof(double));
+          r->F.assign(L.hF + 3 * off, L.hF + 3 * (off + r->n));
+        }
+        off += r->n;
+        finish_request(s, r, st, now);
+      }
     }
   }
   L.batch.clear();
@@ -218,41 +341,112 @@ void lane_complete(dp_server *s, Lane &L) {
   s->cv_work.notify_all();
 }
 
+void free_slot_memory(BigSlot &b) {
+  free_ws(b.ws);
+  void *d[] = {b.dX, b.dF, b.dE, b.dV, b.dT};
+  for (void *p : d)
+    if (p) (void)hipFree(p);
+  b = BigSlot{};
+}
+
+// A workspace for the large request r among the pool's unused ones, such that the pool's
+// device memory (grow-only workspaces) stays within the part of the budget the lanes
+// leave; unused workspaces are released when that makes room.  nullptr: r must wait.
+BigSlot *reserve_slot(dp_server *s, const Request *r) {
+  const size_t bpa = bytes_per_atom(s->m);
+  auto held = [&]() {
+    size_t t = 0;
+    for (const BigSlot &b : s->big) t += (size_t)b.ws.cap * bpa;
+    return t;
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    for (BigSlot &b : s->big) {
+      if (b.used) continue;
+      const size_t cap = (size_t)b.ws.cap * bpa;
+      const size_t need = (size_t)std::max<int64_t>(b.ws.cap, r->n) * bpa;
+      if (held() - cap + need <= s->big_bytes) return &b;
+    }
+    // release the memory of the unused workspaces, then try once more
+    bool freed = false;
+    for (BigSlot &b : s->big)
+      if (!b.used && b.ws.cap > 0) {
+        free_slot_memory(b);
+        freed = true;
+      }
+    if (!freed) break;
+  }
+  return nullptr;
+}
+
+// Takes the next work item for a free lane from the queue (lock held): the chunk of the
+// first large request that can run, or a batch of the small requests at the front.
+// Returns false when nothing can run now.
+bool take_item(dp_server *s, Lane &L, int64_t &c0, int64_t &c1) {
+  for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+    Request *r = *it;
+    if (r->chunked) {
+      if (!r->slot) {
+        BigSlot *b = reserve_slot(s, r);
+        if (!b) continue;  // no room for its workspace yet: serve what is behind it
+        b->used = true;
+        r->slot = b;
+      }
+      s->queue.erase(it);
+      c0 = r->next_c0;
+      c1 = std::min<int64_t>(r->n, c0 + CHUNK);
+      r->next_c0 = c1;
+      L.batch.push_back(r);
+      L.chunk_item = true;
+      L.last_chunk = c1 == r->n;
+      return true;
+    }
+    // small requests in arrival order from here while they fit one batch
+    int64_t atoms = 0;
+    auto jt = it;
+    while (jt != s->queue.end() && (int)L.batch.size() < MAX_BATCH_SYSTEMS) {
+      Request *q = *jt;
+      if (q->chunked) break;
+      if (!L.batch.empty() && (q->solo || L.batch.front()->solo)) break;
+      if (!L.batch.empty() && atoms + q->n > CHUNK) break;
+      L.batch.push_back(q);
+      atoms += q->n;
+      jt = s->queue.erase(jt);
+    }
+    L.chunk_item = false;
+    return true;
+  }
+  return false;
+}
+
 void worker_loop(dp_server *s) {
   (void)hipSetDevice(s->m->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     bool any_busy = false;
-    for (Lane &L : s->lanes) {
+    for (int k = 0; k < s->nlanes; ++k) {
+      Lane &L = s->lanes[k];
       if (L.busy && hipEventQuery(L.done_ev) == hipSuccess) lane_complete(s, L);
       any_busy |= L.busy;
     }
     Lane *free_lane = nullptr;
-    for (Lane &L : s->lanes)
-      if (!L.busy) {
-        free_lane = &L;
+    for (int k = 0; k < s->nlanes; ++k)
+      if (!s->lanes[k].busy) {
+        free_lane = &s->lanes[k];
         break;
       }
-    if (free_lane && !s->queue.empty()) {
-      // form a batch: requests in arrival order while they fit the lane
+    int64_t c0 = 0, c1 = 0;
+    if (free_lane && !s->queue.empty() && take_item(s, *free_lane, c0, c1)) {
       Lane &L = *free_lane;
-      int64_t atoms = 0;
-      while (!s->queue.empty() && (int)L.batch.size() < MAX_BATCH_SYSTEMS) {
-        Request *r = s->queue.front();
-        if (!L.batch.empty() && (r->solo || L.batch.front()->solo)) break;
-        if (!L.batch.empty() && atoms + r->n > s->lane_atoms) break;
-        s->queue.pop_front();
-        L.batch.push_back(r);
-        atoms += r->n;
-      }
       L.busy = true;
       s->batches += 1;
+      const int64_t atoms = L.chunk_item ? c1 - c0 : [&] {
+        int64_t t = 0;
+        for (Request *r : L.batch) t += r->n;
+        return t;
+      }();
       s->max_batch_atoms = std::max(s->max_batch_atoms, atoms);
-      int64_t inflight = 0;
-      for (Lane &K : s->lanes) inflight += K.busy ? (&K == &L ? atoms : K.atoms) : 0;
-      s->max_inflight_atoms = std::max(s->max_inflight_atoms, inflight);
       lk.unlock();
-      L.launch_status = lane_launch(s, L);
+      L.launch_status = L.chunk_item ? launch_chunk(s, L, L.batch[0], c0, c1) : launch_batch(s, L);
       if (L.launch_status != DP_OK) (void)hipStreamSynchronize(L.st);
       lk.lock();
       if (L.launch_status != DP_OK) lane_complete(s, L);
@@ -269,18 +463,25 @@ void worker_loop(dp_server *s) {
   }
 }
 
+
 }  // namespace
 
 extern "C" {
 
 size_t dp_server_footprint(const dp_model *m, int64_t natoms) {
   if (!m || natoms < 1) return 0;
-  return (size_t)natoms * (ws_bytes_per_atom(m->prec) + IO_BYTES_PER_ATOM);
+  return (size_t)natoms * bytes_per_atom(m);
 }
 
-int dp_server_create(dp_model *m, size_t hbm_budget_bytes, dp_server **out) {
-  if (!m || !out || hbm_budget_bytes == 0) {
-    set_error("dp_server_create: bad argument");
+int dp_server_create(dp_model *m, size_t hbm_budget_bytes, int max_inflight, dp_server **out) {
+  if (!m || !out || hbm_budget_bytes == 0 || max_inflight < 1 || max_inflight > MAX_LANES) {
+    set_error("dp_server_create: bad argument (max_inflight in 1..8)");
+    return DP_ERR_ARG;
+  }
+  const size_t lane_bytes = (size_t)CHUNK * bytes_per_atom(m);
+  if (hbm_budget_bytes < (size_t)max_inflight * lane_bytes) {
+    set_error("dp_server_create: the budget does not cover max_inflight batches of " + std::to_string(CHUNK) +
+              " atoms");
     return DP_ERR_ARG;
   }
   if (hipSetDevice(m->device) != hipSuccess) {
@@ -290,8 +491,14 @@ int dp_server_create(dp_model *m, size_t hbm_budget_bytes, dp_server **out) {
   dp_server *s = new dp_server();
   s->m = m;
   s->budget = hbm_budget_bytes;
-  s->lane_atoms = (int64_t)(hbm_budget_bytes / LANES / (ws_bytes_per_atom(m->prec) + IO_BYTES_PER_ATOM));
-  for (Lane &L : s->lanes) {
+  s->nlanes = max_inflight;
+  // what the lanes leave of the budget holds the workspaces of the large requests in
+  // progress (at most max_inflight of them)
+  s->big_bytes = hbm_budget_bytes - (size_t)max_inflight * lane_bytes;
+  s->max_big_atoms = (int64_t)(s->big_bytes / bytes_per_atom(m));
+  s->big.resize(max_inflight);
+  for (int k = 0; k < s->nlanes; ++k) {
+    Lane &L = s->lanes[k];
     if (hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&L.done_ev, hipEventDisableTiming) != hipSuccess) {
       set_error("dp_server_create: stream or event creation failed");
@@ -310,8 +517,8 @@ int dp_submit(dp_server *s, int64_t natoms, const double *coords, const int32_t 
     set_error("dp_submit: bad argument (a periodic box is required)");
     return DP_ERR_ARG;
   }
-  if (natoms > s->lane_atoms) {
-    set_error("dp_submit: the system needs more device memory than half the server budget");
+  if (natoms > CHUNK && natoms > s->max_big_atoms) {
+    set_error("dp_submit: the system needs more device memory than the server budget leaves for one request");
     return DP_ERR_TOO_LARGE;
   }
   Grid g;
@@ -329,6 +536,7 @@ int dp_submit(dp_server *s, int64_t natoms, const double *coords, const int32_t 
     }
   Request *r = new Request();
   r->n = natoms;
+  r->chunked = natoms > CHUNK;
   r->X.assign(coords, coords + 3 * natoms);
   r->T.assign(types, types + natoms);
   std::memcpy(r->box, box, 9 * sizeof(double));
@@ -415,18 +623,20 @@ void dp_server_free(dp_server *s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->m->device);
-  for (Lane &L : s->lanes) {
+  for (int k = 0; k < s->nlanes; ++k) {
+    Lane &L = s->lanes[k];
     if (L.st) (void)hipStreamSynchronize(L.st);
     free_ws(L.ws);
     void *d[] = {L.dX, L.dF, L.dE, L.dV, L.dT};
     for (void *p : d)
       if (p) (void)hipFree(p);
-    void *h[] = {L.hX, L.hF, L.hE, L.hV, L.hT};
+    void *h[] = {L.hX, L.hF, L.hE, L.hV, L.hT, L.hflags};
     for (void *p : h)
       if (p) (void)hipHostFree(p);
     if (L.done_ev) (void)hipEventDestroy(L.done_ev);
     if (L.st) (void)hipStreamDestroy(L.st);
   }
+  for (BigSlot &b : s->big) free_slot_memory(b);
   for (auto &kv : s->reqs) delete kv.second;
   delete s;
 }

@@ -217,22 +217,52 @@ def test_server_results_same_alone_and_in_mix(model_path):
 
 
 def test_server_admission_by_footprint(model_path):
+    """The budget must hold max_inflight batch workspaces of 8192 atoms; what is left holds
+    the large requests in progress, and a request that could never fit is refused.  Small
+    requests are packed into batches of at most 8192 atoms."""
     from paper_2602_02234_amd import DPError, Model, Server
     m = Model(model_path, "bf16")
-    s = config_system("chain1k")
-    probe = Server(m, 1 << 30)
-    budget = 2 * probe.footprint(1200)
+    s = config_system("chain3k")
+    probe = Server(m, 16 << 30, 1)
+    lane, room = probe.footprint(8192), probe.footprint(9000)
     probe.close()
-    srv = Server(m, budget)
-    ids = [srv.submit(s.coords + 0.001 * k, s.types, s.box) for k in range(6)]
-    outs = [srv.wait(i, 120.0) for i in ids]
-    ref = m.compute(s.coords, s.types, s.box)
-    assert outs[0]["E"] == ref["E"]
-    st = srv.stats()
-    assert st["completed"] == 6 and st["max_batch_atoms"] <= 1200 and st["batches"] == 6, st
-    big = config_system("chain3k")
+    with pytest.raises(DPError, match="DP_ERR_ARG"):
+        Server(m, 2 * lane - 1, 2)
+    srv = Server(m, lane + room, 1)
+    big = config_system("chain10k")
     with pytest.raises(DPError, match="DP_ERR_TOO_LARGE"):
         srv.submit(big.coords, big.types, big.box)
+    ids = [srv.submit(s.coords + 0.001 * k, s.types, s.box) for k in range(6)]
+    outs = [srv.wait(i, 120.0) for i in ids]
+    for k, o in enumerate(outs):
+        assert _same(o, m.compute(s.coords + 0.001 * k, s.types, s.box))
+    st = srv.stats()
+    assert st["completed"] == 6 and st["max_batch_atoms"] <= 8192 and 3 <= st["batches"] <= 6, st
+    srv.close()
+    m.close()
+
+
+def test_server_small_request_overtakes_a_chunked_large_one(model_path):
+    """A 40,001-atom request runs as five chunks of at most 8192 centre atoms; a 192-atom
+    request submitted just after it completes first, and both equal their results alone."""
+    import time
+    from paper_2602_02234_amd import Model, Server
+    m = Model(model_path, "bf16")
+    big, small = config_system("chain40k"), config_system("water192")
+    ref_big = m.compute(big.coords, big.types, big.box)
+    ref_small = m.compute(small.coords, small.types, small.box)
+    srv = Server(m, 16 << 30, 2)
+    srv.wait(srv.submit(small.coords, small.types, small.box), 120.0)  # warm the lanes
+    t0 = time.perf_counter()
+    ib = srv.submit(big.coords, big.types, big.box)
+    t1 = time.perf_counter()
+    i_s = srv.submit(small.coords, small.types, small.box)
+    ob = srv.wait(ib, 300.0)
+    os_ = srv.wait(i_s, 300.0)
+    print(f"large: {1e3 * ob['latency']:.1f} ms; small, submitted {1e3 * (t1 - t0):.2f} ms later: "
+          f"{1e3 * os_['latency']:.1f} ms")
+    assert (t1 - t0) + os_["latency"] < ob["latency"]
+    assert _same(ob, ref_big) and _same(os_, ref_small)
     srv.close()
     m.close()
 
