@@ -51,18 +51,6 @@ def mac_desc_bwd_alg(n):
     return M_EMB * n + N_LAYERS * (4 * n * M_ATT * D_ATT + 4 * n * n * D_ATT) + 800 * n + 12800
 
 
-def mac_desc_fwd_exec(n):
-    """As executed: Wqk = WQ WK^T / sqrt(d) and Wvo = WV WO are fused, so each layer costs
-    2 n M^2 + 2 n^2 M; the embedding runs 1250 + 5000 MAC per neighbour on MFMA."""
-    return 6250 * n + N_LAYERS * (2 * n * M_ATT * M_ATT + 2 * n * n * M_ATT) + 400 * n + 6400
-
-
-def mac_desc_bwd_exec(n):
-    """As executed: both layer forwards and the embedding are recomputed inside the backward."""
-    layer_bwd = 2 * n * M_ATT * M_ATT + 4 * n * n * M_ATT
-    return mac_desc_fwd_exec(n) + 6250 * n + N_LAYERS * layer_bwd + 800 * n + 12800
-
-
 def flop_per_atom_eval(n):
     return 2.0 * (mac_desc_fwd(n) + mac_desc_bwd_alg(n) + 2 * FIT_MAC)
 
@@ -113,8 +101,8 @@ def cpu_baseline(system, workload, budget_s=10.0):
     blas = [f"{d.get('internal_api')} {d.get('version')}" for d in threadpool_info() if d.get("user_api") == "blas"]
     return {"value": done / wall, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"random centre atoms of the {system.natoms:,}-atom {workload} box: E_i and dE_i/dDelta_ij "
-                      f"in float64 NumPy, {cores} processes x 1 BLAS thread for {budget_s:.0f} s each "
-                      f"({done} atoms in {wall:.1f} s wall); neighbour search excluded",
+                      f"in float64 NumPy, {cores} processes x 1 BLAS thread, each on its share of the atoms for "
+                      f"up to {budget_s:.0f} s ({done} atoms in {wall:.1f} s wall); neighbour search excluded",
             "single_thread": {"value": one / dt1, "cores": 1, "atoms": one, "seconds": dt1},
             "cpu_model": cpu_model, "blas": blas, "host_cores_visible": len(os.sched_getaffinity(0))}
 
@@ -221,10 +209,11 @@ def serving_bench(model_path, trace_all, systems_all, legs, budget_bytes, max_in
     return out
 
 
-def measured_traffic(phase, precision, workload):
+def measured_traffic(phase, precision, workload, key="hbm_bytes_per_launch"):
     """HBM bytes per launch of a phase from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading), or None when there
-    is none for this phase and workload or a kernel source changed since it was taken."""
+    is none for this phase and workload or a kernel source changed since it was taken.
+    key = "mfma_flop_per_launch": the executed MFMA FLOP from the same summary instead."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
@@ -234,7 +223,7 @@ def measured_traffic(phase, precision, workload):
     if rec is None:
         return None
     csrc = os.path.join(ROOT, "paper_2602_02234_amd", "csrc")
-    if not isinstance(rec.get("sources"), dict) or "hbm_bytes_per_launch" not in rec:
+    if not isinstance(rec.get("sources"), dict) or key not in rec:
         return None
     for name, digest in rec["sources"].items():
         if not os.path.exists(os.path.join(csrc, name)):
@@ -242,7 +231,7 @@ def measured_traffic(phase, precision, workload):
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    return rec["hbm_bytes_per_launch"]
+    return rec[key]
 
 
 def time_path(model, X, T, box, F, V, E, steps, warmup):
@@ -369,11 +358,6 @@ def main():
         "fitting": 2.0 * N * 2 * FIT_MAC,
         "descriptor_bwd": 2.0 * float(np.sum(mac_desc_bwd_alg(n))),
     }
-    executed = {
-        "descriptor_fwd": 2.0 * float(np.sum(mac_desc_fwd_exec(n))),
-        "fitting": 2.0 * N * 2 * FIT_MAC * (3 if args.precision == "bf16" else 1),
-        "descriptor_bwd": 2.0 * float(np.sum(mac_desc_bwd_exec(n))),
-    }
     prof = r["prof"]
     avg = {k: (ms / c if c else 0.0) for k, (ms, c) in prof.items()}
     dom = max(("descriptor_fwd", "fitting", "descriptor_bwd"), key=lambda k: avg[k])
@@ -399,7 +383,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
                      "traffic": measured_traffic(dom, args.precision, args.workload),
                      "avg_ms": avg[dom], "alg_flop_per_launch": alg[dom],
-                     "executed_flop_per_launch": executed[dom]},
+                     "executed_flop_per_launch": measured_traffic(dom, args.precision, args.workload,
+                                                                  "mfma_flop_per_launch")},
         "step_roofline": {"alg_flop_per_step": step_alg,
                           "frac": step_alg / (r["dt"] / r["steps"]) / PEAK[args.precision]},
         "phase_ms": avg,
