@@ -17,6 +17,8 @@ the potential; neighbour lists within a cutoff, Section II and IV):
 * :mod:`oracle.dp` -- the model forward, its reverse-mode gradient written by
   hand, forces by gather, virial, per-atom evaluation of a subset, and models
   with several fitting heads on one descriptor;
+* :mod:`oracle.gnn` -- the GNN-variant descriptor (message passing over edges and
+  angles, three layers) with its hand-written gradient;
 * :mod:`oracle.nve` -- a velocity-Verlet driver for the energy-drift check.
 
 The paper prints no model equations; the functional form follows the reading

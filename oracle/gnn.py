@@ -1,4 +1,5 @@
-"""The GNN-variant descriptor in plain float64 NumPy, with a hand-written gradient.
+"""The GNN-variant descriptor in plain float64 NumPy, with a hand-written gradient --
+TEST INFRASTRUCTURE ONLY (imported by tests and the smoke check, never by the library).
 
 The paper's second model family (DPA3, Section II) replaces attention by graph
 message passing over bonds and angles (a line-graph series).  It gives no
