@@ -283,6 +283,39 @@ int dp_nve_run(dp_model *m, int64_t natoms, double *d_coords, double *d_vel, con
                const double *masses, const double *box, double dt_fs, int nsteps, double *epot, double *ekin,
                void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * GNN-variant model (paper, Section II: the message-passing descriptor over
+ * bonds and angles of its second model family, in place of attention).
+ * Model: edges (i, j) within rc; angles at i are the ordered pairs (p, q), p != q,
+ * of the first asel neighbours of i (list order) closer than rca; node (64), edge
+ * (64) and angle (32) features, three layers each updating angles, then edges (with
+ * the switched angle messages), then nodes (with the switched mean of their edges);
+ * a fitting net 64 -> 128 -> 128 -> 1 on the final node features; E = sum E_i.
+ * Every term an edge or angle adds carries a switch that vanishes at its cutoff.
+ * The model file (magic DPGNNv01: a 128-byte header of sizes, rc, rcs, rca, then the
+ * float64 arrays) fixes node/edge/angle widths 64/64/32, three layers, fitting
+ * width 128, sel = 120, asel <= 48 and ntypes = 5.
+ *
+ * dp_gnn_load: precision DP_FP32 or DP_BF16 (operands of every feature-by-weight
+ *   product; features are stored and combined in float32 either way).
+ * dp_gnn_compute_device: arguments, units and outputs as dp_compute_device (device
+ *   pointers, box on the host or NULL, energy required, the rest may be NULL).  The
+ *   neighbour lists must be complete: an atom with more than sel neighbours within
+ *   rc gives DP_ERR_TOO_LARGE (outputs untouched).  The call sizes its angle buffers
+ *   from the step's angle count (one host round trip) and returns after the step
+ *   has finished on the stream.  A dp_gnn owns grow-only device buffers of about
+ *   190 KB per atom and 512 bytes per angle; it is not thread-safe.
+ * dp_gnn_info: rc, rca, sel, asel of the model (pointers may be NULL).
+ * dp_gnn_angles: number of angles of the last successful step. */
+typedef struct dp_gnn dp_gnn;
+int dp_gnn_load(const char *path, int precision, int device, dp_gnn **out);
+void dp_gnn_free(dp_gnn *m);
+int dp_gnn_info(const dp_gnn *m, double *rc, double *rca, int *sel, int *asel);
+int dp_gnn_compute_device(dp_gnn *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
+                          const double *box_host, double *d_energy, double *d_forces, double *d_virial,
+                          double *d_atom_energy, void *hip_stream);
+int dp_gnn_angles(const dp_gnn *m, int64_t *angles);
+
 /* Static description of a status code; never NULL. */
 const char *dp_status_string(int status);
 /* Thread-local detail of the last failure in this thread ("" if none). */

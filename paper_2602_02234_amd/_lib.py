@@ -52,6 +52,12 @@ SIGNATURES = {
     "dp_server_stats": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "dp_server_free": (None, [_P]),
     "dp_nve_run": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, C.c_double, C.c_int, _P, _P, _P]),
+    "dp_gnn_load": (C.c_int, [C.c_char_p, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "dp_gnn_free": (None, [_P]),
+    "dp_gnn_info": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int),
+                              C.POINTER(C.c_int)]),
+    "dp_gnn_compute_device": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dp_gnn_angles": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "dp_status_string": (C.c_char_p, [C.c_int]),
     "dp_last_error": (C.c_char_p, []),
 }

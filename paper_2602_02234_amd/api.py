@@ -306,6 +306,79 @@ class Server:
             pass
 
 
+class GnnModel:
+    """A GNN-variant model file (message passing over edges and angles) on one GPU,
+    in one precision ("fp32" or "bf16")."""
+
+    def __init__(self, path: str, precision: str = "fp32", device: int = 0):
+        lib = _lib.load()
+        h = C.c_void_p()
+        check(lib.dp_gnn_load(path.encode(), _PREC[precision], device, C.byref(h)), "dp_gnn_load")
+        self._h = h
+        self.precision = precision
+        self.device = device
+        rc, rca, sel, asel = C.c_double(), C.c_double(), C.c_int(), C.c_int()
+        check(lib.dp_gnn_info(h, C.byref(rc), C.byref(rca), C.byref(sel), C.byref(asel)), "dp_gnn_info")
+        self.rc, self.rca, self.sel, self.asel = rc.value, rca.value, sel.value, asel.value
+        self.last_status = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().dp_gnn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compute_device(self, coords, types, box=None, forces=None, virial=None, energy=None, atom_energy=None,
+                       stream=None):
+        """Evaluate on torch CUDA tensors (float64 coords [N][3], int32 types [N]); outputs written in place."""
+        import torch
+        n = coords.shape[0]
+        assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
+        assert types.is_cuda and types.dtype == torch.int32 and types.is_contiguous()
+        if energy is None:
+            energy = torch.empty(1, dtype=torch.float64, device=coords.device)
+        s = stream if stream is not None else torch.cuda.current_stream(coords.device).cuda_stream
+        b = _box9(box)
+
+        def dp(t):
+            return C.c_void_p(t.data_ptr()) if t is not None else None
+
+        st = _lib.load().dp_gnn_compute_device(self._h, n, dp(coords), dp(types), _ptr(b), dp(energy), dp(forces),
+                                               dp(virial), dp(atom_energy), C.c_void_p(s))
+        self.last_status = check(st, "dp_gnn_compute_device")
+        return energy
+
+    def compute(self, coords, types, box=None, forces: bool = True, atom_energy: bool = False):
+        """E, F, virial (and E_i) from host arrays, through device copies made with torch."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        X = torch.tensor(np.ascontiguousarray(coords, dtype=np.float64), device=dev)
+        T = torch.tensor(np.ascontiguousarray(types, dtype=np.int32), device=dev)
+        n = X.shape[0]
+        F = torch.zeros((n, 3), dtype=torch.float64, device=dev) if forces else None
+        V = torch.zeros(9, dtype=torch.float64, device=dev) if forces else None
+        AE = torch.zeros(n, dtype=torch.float64, device=dev) if atom_energy else None
+        E = self.compute_device(X, T, box, forces=F, virial=V, atom_energy=AE)
+        torch.cuda.synchronize(dev)
+        out = {"E": float(E.item())}
+        if forces:
+            out["F"], out["virial"] = F.cpu().numpy(), V.cpu().numpy().reshape(3, 3)
+        if atom_energy:
+            out["E_i"] = AE.cpu().numpy()
+        return out
+
+    def angles(self) -> int:
+        """Angles of the last successful step."""
+        v = C.c_int64()
+        check(_lib.load().dp_gnn_angles(self._h, C.byref(v)), "dp_gnn_angles")
+        return int(v.value)
+
+
 def _autograd_function():
     import torch
 

@@ -441,7 +441,7 @@ size_t ws_bytes_per_atom(int prec) {
   return b;
 }
 
-int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
+int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin, bool lists_only) {
   if (!ws.flags) {
     HIP_TRY(hipMalloc(&ws.flags, 4 * sizeof(unsigned)));
     HIP_TRY(hipHostMalloc(&ws.flags_host, 4 * sizeof(unsigned), hipHostMallocDefault));
@@ -491,13 +491,15 @@ int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin) {
     HIP_TRY(hipMalloc(&ws.sys_of, cap * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.nlist, cap * SEL * sizeof(int)));
     HIP_TRY(hipMalloc(&ws.nnei, cap * sizeof(int)));
-    HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * GSAVE_LAYER * sizeof(float)));
-    HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
-    HIP_TRY(hipMalloc(&ws.bidx, 2 * cap * sizeof(int)));
-    HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
-    HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
+    if (!lists_only) {  // the attention descriptor's buffers
+      HIP_TRY(hipMalloc(&ws.Gsave, cap * (size_t)NATTN * GSAVE_LAYER * sizeof(float)));
+      HIP_TRY(hipMalloc(&ws.Tsave, cap * (size_t)M * 4 * sizeof(float)));
+      HIP_TRY(hipMalloc(&ws.bidx, 2 * cap * sizeof(int)));
+      HIP_TRY(hipMalloc(&ws.D, (cap + 16) * (size_t)ND * sizeof(float)));  // 16 spare rows for batched readers
+      HIP_TRY(hipMemset(ws.D, 0, (cap + 16) * (size_t)ND * sizeof(float)));
+      HIP_TRY(hipMalloc(&ws.Eh, cap * MAXH * sizeof(double)));
+    }
     HIP_TRY(hipMalloc(&ws.Ei, cap * sizeof(double)));
-    HIP_TRY(hipMalloc(&ws.Eh, cap * MAXH * sizeof(double)));
     HIP_TRY(hipMalloc(&ws.g, cap * (size_t)SEL * sizeof(float4)));
     HIP_TRY(hipMalloc(&ws.vpart, cap * 9 * sizeof(double)));
     ws.cap = cap;

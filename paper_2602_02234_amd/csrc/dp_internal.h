@@ -275,7 +275,9 @@ void launch_sum(const Workspace &ws, const double *src, double *out, hipStream_t
 
 // Step orchestration (api.hip), shared with the serving loop.
 size_t ws_bytes_per_atom(int prec);
-int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin);
+// lists_only: only what the neighbour search, force gather and reductions use (no
+// attention-descriptor buffers).
+int ensure_ws(Workspace &ws, int prec, int64_t n, int nsys, bool skin, bool lists_only = false);
 void free_ws(Workspace &ws);
 int enqueue_step(dp_model *m, Workspace &ws, const StepArgs &a, hipStream_t st, bool profile);
 int step_status(const Workspace &ws);

@@ -1,0 +1,794 @@
+// GNN-variant descriptor kernels for gfx950: one workgroup (four waves) per centre atom
+// and one launch per message-passing layer, forward and backward (a layer's edge update
+// reads the neighbours' node features of the layer before, so layers meet at launch
+// boundaries).  Every product of a feature tile with a weight matrix runs on MFMA
+// (16 angles or 16 edges per tile; Mma<T> selects f32 or bf16 operands, f32
+// accumulation); features are stored in float32.
+//
+// Forward, layer l, centre i:
+//   angles  each wave owns angle rows p (p = wave, wave + 4, ...) and walks q in tiles
+//           of 16: a' = a + tanh([a, e_ip, e_iq] Waa + b), then the message tile
+//           tanh([a', e_iq] Wea + b) weighted by sw_a(r_ip) sw_a(r_iq) / asel and summed
+//           over q in a fixed order into m_ip;
+//   edges   tiles of 16 edges: e' = e + tanh([n_i, n_j, e] Wee + b) + m;
+//   node    n' = n + tanh([n, sum_j sw_e e' / sel] Wnn + b); after the last layer the
+//           fitting net, E_i in float64, and dE/dn_i.
+// Backward, layer l (reverse of the above, activations recomputed from the stored layer
+// inputs): dE/dn_i is gathered from the edges (j, i) of the neighbours in list order
+// (binary search of i in N(j)); per-angle terms that belong to edge (i, q) are summed
+// per wave in LDS and the wave sums added in wave order, so every sum has a fixed order
+// and the result is deterministic.  Layer 0 turns the accumulated gradients of s, sw_e,
+// sw_a and rhat into g_ij = dE/dDelta_ij for the shared force gather.
+#include "dp_env.h"
+#include "gnn.h"
+
+namespace dp {
+namespace gnn {
+namespace {
+
+constexpr int NWG = 4;          // waves per workgroup
+constexpr int NT = NWG * 64;
+constexpr int LDE = 68;         // row stride of [edge][64] LDS arrays
+constexpr int LDF = 196;        // forward slab row stride (192 columns used)
+constexpr int LDB = 228;        // backward slab row stride (224 columns used)
+constexpr int QLD = 36;         // per-edge angle accumulators: 32 features, sw_a, rhat
+
+__device__ __forceinline__ bool failed(const unsigned *flags) { return (flags[0] & FLAG_ERRORS) != 0u; }
+
+// Ordering of LDS traffic between the lanes of one wave (per-wave slabs).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over all 64 lanes, the same in every lane.
+__device__ __forceinline__ float wave_sum64(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+struct GEnv {
+  float r[SEL], swe[SEL], dswe[SEL], swa[SEL], dswa[SEL], s[SEL];
+  float rh[SEL * 3];
+  int jn[SEL], tj[SEL], cpos[SEL];  // neighbour, its type, its angle-list position (-1: none)
+  int cl[ASEL];                      // edge slot of each angle-list position
+  int nn, nc;
+};
+
+__device__ __forceinline__ float quintic(float r, float rc, float rcs, float &dsw) {
+  const float u = (r - rcs) / (rc - rcs);
+  dsw = 0.f;
+  if (r < rcs) return 1.f;
+  if (r >= rc) return 0.f;
+  dsw = -30.f * u * u * (1.f - u) * (1.f - u) / (rc - rcs);
+  return u * u * u * (-6.f * u * u + 15.f * u - 10.f) + 1.f;
+}
+
+// Geometry of centre i's edges and its angle list (the first asel neighbours, in list
+// order, closer than rca; the test is made in float64 on the minimum-image vector).
+__device__ void build_genv(GEnv &e, const double *__restrict__ X, const int *__restrict__ types,
+                           const int *__restrict__ nlist, const int *__restrict__ nnei, int i, int n,
+                           const Grid &g, const Geo &geo) {
+  const int nn = min(max(nnei[i], 0), SEL);
+  for (int j = threadIdx.x; j < SEL; j += NT) {
+    float r = 1.f, sw = 0.f, dsw = 0.f, sa = 0.f, dsa = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+    int nj = i, tj = 0, close = 0;
+    if (j < nn) {
+      nj = nlist[(size_t)i * SEL + j];
+      if (nj < 0 || nj >= n) nj = i;
+      tj = clamp_type(types[nj]);
+      double d[3];
+      for (int a = 0; a < 3; ++a) {
+        double v = X[3 * nj + a] - X[3 * i + a];
+        if (g.periodic) v -= g.L[a] * rint(v * g.invL[a]);
+        d[a] = v;
+      }
+      close = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < (double)geo.rca;
+      const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+      r = sqrtf(dx * dx + dy * dy + dz * dz);
+      sw = quintic(r, geo.rc, geo.rcs, dsw);
+      sa = quintic(r, geo.rca, geo.rcs, dsa);
+      hx = dx / r; hy = dy / r; hz = dz / r;
+    }
+    e.r[j] = r; e.swe[j] = sw; e.dswe[j] = dsw; e.swa[j] = sa; e.dswa[j] = dsa; e.s[j] = sw / r;
+    e.rh[3 * j] = hx; e.rh[3 * j + 1] = hy; e.rh[3 * j + 2] = hz;
+    e.jn[j] = nj; e.tj[j] = tj; e.cpos[j] = close;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int base = 0;
+    for (int j0 = 0; j0 < nn; j0 += 64) {
+      const int j = j0 + lane;
+      const bool flag = j < nn && e.cpos[j] != 0;
+      const unsigned long long mask = __ballot(flag);
+      const int rank = base + __popcll(mask & ((1ull << lane) - 1ull));
+      const bool in = flag && rank < geo.asel;
+      if (j < nn) e.cpos[j] = in ? rank : -1;
+      if (in) e.cl[rank] = j;
+      base += __popcll(mask);
+    }
+    if (lane == 0) {
+      e.nn = nn;
+      e.nc = min(base, geo.asel);
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ float cosang(const GEnv &e, int jp, int jq) {
+  return e.rh[3 * jp] * e.rh[3 * jq] + e.rh[3 * jp + 1] * e.rh[3 * jq + 1] + e.rh[3 * jp + 2] * e.rh[3 * jq + 2];
+}
+
+__device__ __forceinline__ size_t erow(const Buffers &b, int l, int i, int j) {
+  return (((size_t)l * b.cap + i) * SEL + j) * EDIM;
+}
+
+// ------------------------------------------------------------------ angle offsets
+__global__ void __launch_bounds__(256) k_angle_count(const double *__restrict__ X, const int *__restrict__ nlist,
+                                                     const int *__restrict__ nnei, const Grid *__restrict__ grids,
+                                                     int n, Geo geo, int64_t *__restrict__ aoff) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const Grid g = grids[0];
+  const int nn = min(max(nnei[i], 0), SEL);
+  int nc = 0;
+  for (int j = 0; j < nn && nc < geo.asel; ++j) {
+    int nj = nlist[(size_t)i * SEL + j];
+    if (nj < 0 || nj >= n) continue;
+    double d[3];
+    for (int a = 0; a < 3; ++a) {
+      double v = X[3 * nj + a] - X[3 * i + a];
+      if (g.periodic) v -= g.L[a] * rint(v * g.invL[a]);
+      d[a] = v;
+    }
+    nc += sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < (double)geo.rca;
+  }
+  aoff[i + 1] = (int64_t)nc * (nc - 1);
+  if (i == 0) aoff[0] = 0;
+}
+
+// Inclusive prefix of aoff[1 .. n] in one workgroup: each thread sums a contiguous run,
+// the 1024 run totals are scanned, then each run is rewritten.
+__global__ void __launch_bounds__(1024) k_angle_scan(int64_t *__restrict__ aoff, int n) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b0 = 1 + t * per, b1 = min(n + 1, b0 + per);
+  int64_t s = 0;
+  for (int k = b0; k < b1; ++k) s += aoff[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = t > 0 ? part[t - 1] : 0;
+  for (int k = b0; k < b1; ++k) {
+    run += aoff[k];
+    aoff[k] = run;
+  }
+}
+
+// ------------------------------------------------------------------ forward
+struct SmemF {
+  GEnv env;
+  float El[SEL * LDE];        // e of the layer's input
+  float Msg[ASEL * EDIM];     // m_ip
+  float slab[NWG][16 * LDF];  // per-wave operand tiles
+  float ni[NDIM], xs[2 * NDIM], aggw[NWG][NDIM];
+  float y1[FWID], t2[FWID], dp[FWID];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const double *__restrict__ X,
+                                                  const int *__restrict__ types, const int *__restrict__ nlist,
+                                                  const int *__restrict__ nnei, const Grid *__restrict__ grids,
+                                                  int n, int layer, Geo geo, double *__restrict__ Ei,
+                                                  const unsigned *__restrict__ flags) {
+  __shared__ SmemF sm;
+  const int i = blockIdx.x;
+  if (i >= n || failed(flags)) return;
+  const int tid = threadIdx.x, wv = wave_id(), ln = lane_id();
+  build_genv(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
+  const GEnv &e = sm.env;
+  const int nn = e.nn, nc = e.nc, l = layer;
+  const float *Waa = w.Waa[l], *baa = w.baa[l], *Wea = w.Wea[l], *bea = w.bea[l];
+  const float *Wee = w.Wee[l], *bee = w.bee[l], *Wnn = w.Wnn[l], *bnn = w.bnn[l];
+
+  for (int k = tid; k < nn * EDIM; k += NT) {
+    const int j = k >> 6, c = k & 63;
+    sm.El[j * LDE + c] = l == 0 ? tanhf(e.s[j] * w.We0[c] + w.be0[c]) : b.ef[erow(b, l - 1, i, j) + c];
+  }
+  if (tid < NDIM)
+    sm.ni[tid] = l == 0 ? w.TN[clamp_type(types[i]) * NDIM + tid] : b.nf[((size_t)(l - 1) * b.cap + i) * NDIM + tid];
+  __syncthreads();
+
+  float *sl = sm.slab[wv];
+  const int na = nc - 1;  // angles per row p
+  const int64_t abase = b.aoff[i];
+  // ---------------- angles and messages
+  for (int p = wv; p < nc; p += NWG) {
+    float mr[4] = {0.f, 0.f, 0.f, 0.f};
+    const int jp = e.cl[p];
+    for (int t0 = 0; t0 < na; t0 += 16) {
+      for (int k = ln; k < 16 * 96; k += 64) {
+        const int r = k / 96, c = k % 96, t = t0 + r;
+        float v = 0.f;
+        if (t < na) {
+          const int q = t + (t >= p);
+          if (c < 32)
+            v = l == 0 ? tanhf(cosang(e, jp, e.cl[q]) * w.Wa0[c] + w.ba0[c])
+                       : b.af[((size_t)(l - 1) * b.acap + abase + (int64_t)p * na + t) * ADIM + c];
+          else if (c < 64)
+            v = sm.El[jp * LDE + c - 32];
+          else
+            v = sm.El[e.cl[q] * LDE + c - 64];
+        }
+        sl[r * LDF + c] = v;
+      }
+      wave_sync();
+      f4 aa[2] = {};
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        Mma<T>::tile(aa[ct], [&](int r, int k) { return sl[r * LDF + k]; },
+                     [&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; }, 96);
+      wave_sync();
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int r = acc_row(ii), c = ct * 16 + acc_col(), t = t0 + r;
+          const float a1 = sl[r * LDF + c] + tanhf(aa[ct][ii] + baa[c]);
+          sl[r * LDF + c] = a1;
+          if (t < na) b.af[((size_t)l * b.acap + abase + (int64_t)p * na + t) * ADIM + c] = a1;
+        }
+      wave_sync();
+      f4 am[4] = {};
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        Mma<T>::tile(am[ct], [&](int r, int k) { return sl[r * LDF + (k < 32 ? k : k + 32)]; },
+                     [&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; }, 64);
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int t = t0 + acc_row(ii);
+        const float wr = t < na ? e.swa[jp] * e.swa[e.cl[t + (t >= p)]] * geo.inv_asel : 0.f;
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) mr[ct] += wr * tanhf(am[ct][ii] + bea[ct * 16 + acc_col()]);
+      }
+      wave_sync();
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const float v = sum_cols4(mr[ct]);
+      if (ln < 16) sm.Msg[p * EDIM + ct * 16 + ln] = v;
+    }
+  }
+  __syncthreads();
+
+  // ---------------- edges
+  float aw[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int j0 = wv * 16; j0 < nn; j0 += NWG * 16) {
+    for (int k = ln; k < 16 * 192; k += 64) {
+      const int r = k / 192, c = k % 192, j = j0 + r;
+      float v = 0.f;
+      if (j < nn) {
+        if (c < 64)
+          v = sm.ni[c];
+        else if (c < 128)
+          v = l == 0 ? w.TN[e.tj[j] * NDIM + c - 64] : b.nf[((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c - 64];
+        else
+          v = sm.El[j * LDE + c - 128];
+      }
+      sl[r * LDF + c] = v;
+    }
+    wave_sync();
+    f4 ae[4] = {};
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      Mma<T>::tile(ae[ct], [&](int r, int k) { return sl[r * LDF + k]; },
+                   [&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; }, 192);
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = j0 + acc_row(ii);
+      if (j < nn) {
+        const int cp = e.cpos[j];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          const int c = ct * 16 + acc_col();
+          const float e1 = sm.El[j * LDE + c] + tanhf(ae[ct][ii] + bee[c]) + (cp >= 0 ? sm.Msg[cp * EDIM + c] : 0.f);
+          b.ef[erow(b, l, i, j) + c] = e1;
+          aw[ct] += e.swe[j] * e1;
+        }
+      }
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const float v = sum_cols4(aw[ct]);
+    if (ln < 16) sm.aggw[wv][ct * 16 + ln] = v;
+  }
+  __syncthreads();
+
+  // ---------------- node
+  if (tid < NDIM) {
+    sm.xs[tid] = sm.ni[tid];
+    sm.xs[NDIM + tid] = (sm.aggw[0][tid] + sm.aggw[1][tid] + sm.aggw[2][tid] + sm.aggw[3][tid]) * geo.inv_sel;
+  }
+  __syncthreads();
+  float n1 = 0.f;
+  if (tid < NDIM) {
+    float z = bnn[tid];
+    for (int k = 0; k < 2 * NDIM; ++k) z += sm.xs[k] * Wnn[k * NDIM + tid];
+    n1 = sm.ni[tid] + tanhf(z);
+    if (l < NLAYER - 1) b.nf[((size_t)l * b.cap + i) * NDIM + tid] = n1;
+  }
+  if (l < NLAYER - 1) return;
+
+  // ---------------- fitting net, E_i and dE/dn_i
+  __syncthreads();
+  if (tid < NDIM) sm.ni[tid] = n1;
+  __syncthreads();
+  if (tid < FWID) {
+    float z = w.d1[tid];
+    for (int k = 0; k < NDIM; ++k) z += sm.ni[k] * w.G1[k * FWID + tid];
+    sm.y1[tid] = tanhf(z);
+  }
+  __syncthreads();
+  if (tid < FWID) {
+    float z = w.d2[tid];
+    for (int k = 0; k < FWID; ++k) z += sm.y1[k] * w.G2[k * FWID + tid];
+    const float t2 = tanhf(z);
+    sm.t2[tid] = t2;
+    sm.dp[tid] = w.G3[tid] * (1.f - t2 * t2);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double E = w.d3;
+    for (int k = 0; k < FWID; ++k) E += (double)(sm.t2[k] + sm.y1[k]) * w.G3d[k];
+    Ei[i] = E;
+  }
+  float dp1 = 0.f;
+  if (tid < FWID) {
+    float dy1 = w.G3[tid];
+    for (int k = 0; k < FWID; ++k) dy1 += sm.dp[k] * w.G2[tid * FWID + k];
+    dp1 = dy1 * (1.f - sm.y1[tid] * sm.y1[tid]);
+  }
+  __syncthreads();
+  if (tid < FWID) sm.dp[tid] = dp1;
+  __syncthreads();
+  if (tid < NDIM) {
+    float dn = 0.f;
+    for (int k = 0; k < FWID; ++k) dn += sm.dp[k] * w.G1[tid * FWID + k];
+    b.dnl[(size_t)i * NDIM + tid] = dn;
+  }
+}
+
+// ------------------------------------------------------------------ backward
+struct SmemB {
+  GEnv env;
+  float DEl[SEL * EDIM];      // dE/de of this layer's input edges
+  float DM[ASEL * EDIM];      // dE/dm_ip
+  float Ec[ASEL * ADIM];      // e[:32] of the angle-list edges
+  float slab[NWG][16 * LDB];
+  float Qacc[NWG][ASEL * QLD];  // per-wave sums of the terms of edge q
+  float Pacc[ASEL * QLD];       // terms of edge p from its own angle row
+  float dn[NDIM], ni[NDIM], xs[2 * NDIM], dagg[NDIM], dnsum[NWG][NDIM], zz[NDIM];
+  int slot[SEL];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const double *__restrict__ X,
+                                                  const int *__restrict__ types, const int *__restrict__ nlist,
+                                                  const int *__restrict__ nnei, const Grid *__restrict__ grids,
+                                                  int n, int layer, Geo geo, float4 *__restrict__ gout,
+                                                  const unsigned *__restrict__ flags) {
+  __shared__ SmemB sm;
+  const int i = blockIdx.x;
+  if (i >= n || failed(flags)) return;
+  const int tid = threadIdx.x, wv = wave_id(), ln = lane_id();
+  build_genv(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
+  const GEnv &e = sm.env;
+  const int nn = e.nn, nc = e.nc, l = layer;
+  const float *Waa = w.Waa[l], *baa = w.baa[l], *Wea = w.Wea[l], *bea = w.bea[l];
+  const float *Wee = w.Wee[l], *bee = w.bee[l], *Wnn = w.Wnn[l], *bnn = w.bnn[l];
+  const bool top = l == NLAYER - 1;
+
+  // ---------------- dE/dn_i after this layer: own part + the neighbours' edge parts
+  if (!top)
+    for (int j = tid; j < nn; j += NT) {
+      const int nj = e.jn[j];
+      const int len = min(max(nnei[nj], 0), SEL);
+      const int *row = nlist + (size_t)nj * SEL;
+      int lo = 0, hi = len - 1, s = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = row[mid];
+        if (x == i) { s = mid; break; }
+        if (x < i) lo = mid + 1; else hi = mid - 1;
+      }
+      sm.slot[j] = s;
+    }
+  for (int k = tid; k < nc * ADIM; k += NT) {
+    const int p = k >> 5, c = k & 31, j = e.cl[p];
+    sm.Ec[k] = l == 0 ? tanhf(e.s[j] * w.We0[c] + w.be0[c]) : b.ef[erow(b, l - 1, i, j) + c];
+  }
+  if (tid < NDIM)
+    sm.ni[tid] = l == 0 ? w.TN[clamp_type(types[i]) * NDIM + tid] : b.nf[((size_t)(l - 1) * b.cap + i) * NDIM + tid];
+  __syncthreads();
+  if (tid < NDIM) {
+    float dn = b.dnl[(size_t)i * NDIM + tid];
+    if (!top) {
+      const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * EDIM;
+      for (int j = 0; j < nn; ++j)
+        if (sm.slot[j] >= 0) dn += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * EDIM + tid];
+    }
+    sm.dn[tid] = dn;
+    // agg from the stored output edges
+    float agg = 0.f;
+    for (int j = 0; j < nn; ++j) agg += e.swe[j] * b.ef[erow(b, l, i, j) + tid];
+    sm.xs[tid] = sm.ni[tid];
+    sm.xs[NDIM + tid] = agg * geo.inv_sel;
+  }
+  __syncthreads();
+  // ---------------- node backward
+  if (tid < NDIM) {
+    float z = bnn[tid];
+    for (int k = 0; k < 2 * NDIM; ++k) z += sm.xs[k] * Wnn[k * NDIM + tid];
+    const float t = tanhf(z);
+    sm.zz[tid] = sm.dn[tid] * (1.f - t * t);
+  }
+  __syncthreads();
+  if (tid < NDIM) {
+    float dni = sm.dn[tid], dg = 0.f;
+    for (int k = 0; k < NDIM; ++k) {
+      dni += sm.zz[k] * Wnn[tid * NDIM + k];
+      dg += sm.zz[k] * Wnn[(NDIM + tid) * NDIM + k];
+    }
+    sm.dn[tid] = dni;  // now dE/dn_i of this layer's input, without the edge terms
+    sm.dagg[tid] = dg * geo.inv_sel;
+  }
+  __syncthreads();
+
+  float *sl = sm.slab[wv];
+  // ---------------- edges
+  float dns[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int j0 = wv * 16; j0 < nn; j0 += NWG * 16) {
+    for (int k = ln; k < 16 * 192; k += 64) {
+      const int r = k / 192, c = k % 192, j = j0 + r;
+      float v = 0.f;
+      if (j < nn) {
+        if (c < 64)
+          v = sm.ni[c];
+        else if (c < 128)
+          v = l == 0 ? w.TN[e.tj[j] * NDIM + c - 64] : b.nf[((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c - 64];
+        else
+          v = l == 0 ? tanhf(e.s[j] * w.We0[c - 128] + w.be0[c - 128]) : b.ef[erow(b, l - 1, i, j) + c - 128];
+      }
+      sl[r * LDB + c] = v;
+    }
+    wave_sync();
+    f4 ae[4] = {};
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      Mma<T>::tile(ae[ct], [&](int r, int k) { return sl[r * LDB + k]; },
+                   [&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; }, 192);
+    wave_sync();
+    float de1[4][4], rs[4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = acc_row(ii), j = j0 + r;
+      const bool ok = j < nn;
+      rs[ii] = 0.f;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int c = ct * 16 + acc_col();
+        float d = 0.f, dz = 0.f;
+        if (ok) {
+          d = (top ? 0.f : b.de[((size_t)i * SEL + j) * EDIM + c]) + e.swe[j] * sm.dagg[c];
+          rs[ii] += b.ef[erow(b, l, i, j) + c] * sm.dagg[c];
+          const float t = tanhf(ae[ct][ii] + bee[c]);
+          dz = d * (1.f - t * t);
+        }
+        de1[ct][ii] = d;
+        sl[r * LDB + c] = dz;  // dz_e over the n_i columns
+        dns[ct] += dz;
+      }
+      rs[ii] = sum16(rs[ii]);
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = j0 + acc_row(ii);
+      if (j < nn && acc_col() == 0) {
+        float *g = b.gs + ((size_t)i * SEL + j) * 2;
+        g[0] = top ? rs[ii] : g[0] + rs[ii];
+      }
+    }
+    wave_sync();
+    if (l > 0) {  // edge (i, j)'s part of dE/dn_j
+      float *dst = b.dnj + (size_t)(l & 1) * b.cap * SEL * EDIM;
+      f4 an[4] = {};
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        Mma<T>::tile(an[ct], [&](int r, int k) { return sl[r * LDB + k]; },
+                     [&](int c, int k) { return Wee[(NDIM + ct * 16 + c) * EDIM + k]; }, 64);
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int j = j0 + acc_row(ii);
+        if (j < nn)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) dst[((size_t)i * SEL + j) * EDIM + ct * 16 + acc_col()] = an[ct][ii];
+      }
+    }
+    f4 ad[4] = {};
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      Mma<T>::tile(ad[ct], [&](int r, int k) { return sl[r * LDB + k]; },
+                   [&](int c, int k) { return Wee[(2 * NDIM + ct * 16 + c) * EDIM + k]; }, 64);
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = j0 + acc_row(ii);
+      if (j < nn) {
+        const int cp = e.cpos[j];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          const int c = ct * 16 + acc_col();
+          sm.DEl[j * EDIM + c] = de1[ct][ii] + ad[ct][ii];
+          if (cp >= 0) sm.DM[cp * EDIM + c] = de1[ct][ii];
+        }
+      }
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const float v = sum_cols4(dns[ct]);
+    if (ln < 16) sm.dnsum[wv][ct * 16 + ln] = v;
+  }
+  float *Q = sm.Qacc[wv];
+  for (int k = ln; k < ASEL * QLD; k += 64) Q[k] = 0.f;
+  __syncthreads();
+
+  // ---------------- angles
+  const int na = nc - 1;
+  const int64_t abase = b.aoff[i];
+  for (int p = wv; p < nc; p += NWG) {
+    const int jp = e.cl[p];
+    float S[2] = {0.f, 0.f};      // column sums of dz_a
+    float sp = 0.f, hp[3] = {0.f, 0.f, 0.f};  // dE/dsw_a(r_ip), dE/drhat_ip from this row
+    for (int t0 = 0; t0 < na; t0 += 16) {
+      for (int k = ln; k < 16 * 128; k += 64) {
+        const int r = k >> 7, c = k & 127, t = t0 + r;
+        float v = 0.f;
+        if (t < na) {
+          const int q = t + (t >= p);
+          const size_t ai = (size_t)(abase + (int64_t)p * na + t);
+          if (c < 32)
+            v = b.af[((size_t)l * b.acap + ai) * ADIM + c];
+          else if (c < 64)
+            v = sm.Ec[q * ADIM + c - 32];
+          else if (c < 96)
+            v = l == 0 ? tanhf(cosang(e, jp, e.cl[q]) * w.Wa0[c - 64] + w.ba0[c - 64])
+                       : b.af[((size_t)(l - 1) * b.acap + ai) * ADIM + c - 64];
+          else
+            v = sm.Ec[p * ADIM + c - 96];
+        }
+        sl[r * LDB + c] = v;
+      }
+      wave_sync();
+      f4 am[4] = {}, aa[2] = {};
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        Mma<T>::tile(am[ct], [&](int r, int k) { return sl[r * LDB + k]; },
+                     [&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; }, 64);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)  // [a, e_ip, e_iq]: columns 64..127, then 32..63
+        Mma<T>::tile(aa[ct], [&](int r, int k) { return sl[r * LDB + (k < 64 ? 64 + k : k - 32)]; },
+                     [&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; }, 96);
+      float dwa[4], wr[4], ta[2][4];
+      int qv[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = acc_row(ii), t = t0 + r;
+        qv[ii] = t < na ? t + (t >= p) : -1;
+        wr[ii] = qv[ii] >= 0 ? e.swa[jp] * e.swa[e.cl[qv[ii]]] * geo.inv_asel : 0.f;
+        float d = 0.f;
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          const int c = ct * 16 + acc_col();
+          const float tm = tanhf(am[ct][ii] + bea[c]);
+          const float dm = qv[ii] >= 0 ? sm.DM[p * EDIM + c] : 0.f;
+          d += dm * tm;
+          sl[r * LDB + 128 + c] = wr[ii] * dm * (1.f - tm * tm);  // dz_m
+        }
+        dwa[ii] = sum16(d);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const float t = tanhf(aa[ct][ii] + baa[ct * 16 + acc_col()]);
+          ta[ct][ii] = t;
+        }
+      }
+      wave_sync();
+      f4 ax[2] = {};
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        Mma<T>::tile(ax[ct], [&](int r, int k) { return sl[r * LDB + 128 + k]; },
+                     [&](int c, int k) { return Wea[(ct * 16 + c) * EDIM + k]; }, 64);
+      float da1[2][4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = acc_row(ii);
+        const size_t ai = (size_t)(abase + (int64_t)p * na + (t0 + r));
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const int c = ct * 16 + acc_col();
+          float d = 0.f;
+          if (qv[ii] >= 0) d = (top ? 0.f : b.da[ai * ADIM + c]) + ax[ct][ii];
+          da1[ct][ii] = d;
+          const float dz = d * (1.f - ta[ct][ii] * ta[ct][ii]);
+          sl[r * LDB + 192 + c] = dz;  // dz_a
+          S[ct] += dz;
+        }
+      }
+      wave_sync();
+      f4 ay[2] = {}, av[2] = {};
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        Mma<T>::tile(ay[ct], [&](int r, int k) { return sl[r * LDB + 192 + k]; },
+                     [&](int c, int k) { return Waa[(ct * 16 + c) * ADIM + k]; }, 32);
+        Mma<T>::tile(av[ct], [&](int r, int k) { return sl[r * LDB + 128 + k]; },
+                     [&](int c, int k) {
+                       return k < 64 ? Wea[(32 + ct * 16 + c) * EDIM + k] : Waa[(64 + ct * 16 + c) * ADIM + k - 64];
+                     },
+                     96);
+      }
+      float dc[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = acc_row(ii);
+        const size_t ai = (size_t)(abase + (int64_t)p * na + (t0 + r));
+        float d = 0.f;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const int c = ct * 16 + acc_col();
+          const float dal = da1[ct][ii] + ay[ct][ii];
+          if (qv[ii] >= 0) {
+            if (l > 0) b.da[ai * ADIM + c] = dal;
+            Q[qv[ii] * QLD + c] += av[ct][ii];
+          }
+          const float a0 = sl[r * LDB + 64 + c];
+          d += dal * (1.f - a0 * a0) * w.Wa0[c];
+        }
+        dc[ii] = l == 0 ? sum16(d) : 0.f;
+      }
+      if (acc_col() == 0)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int q = qv[ii];
+          if (q < 0) continue;
+          const int jq = e.cl[q];
+          Q[q * QLD + 32] += dwa[ii] * e.swa[jp] * geo.inv_asel;
+          sp += dwa[ii] * e.swa[jq] * geo.inv_asel;
+          if (l == 0)
+            for (int a = 0; a < 3; ++a) {
+              Q[q * QLD + 33 + a] += dc[ii] * e.rh[3 * jp + a];
+              hp[a] += dc[ii] * e.rh[3 * jq + a];
+            }
+        }
+      wave_sync();
+    }
+    // row p: its own edge's terms
+    S[0] = sum_cols4(S[0]);
+    S[1] = sum_cols4(S[1]);
+    sp = wave_sum64(sp);
+    for (int a = 0; a < 3; ++a) hp[a] = wave_sum64(hp[a]);
+    if (ln < 16) {
+      sl[ln] = S[0];
+      sl[16 + ln] = S[1];
+    }
+    wave_sync();
+    if (ln < ADIM) {
+      float v = 0.f;
+      for (int k = 0; k < ADIM; ++k) v += sl[k] * Waa[(ADIM + ln) * ADIM + k];
+      sm.Pacc[p * QLD + ln] = v;
+    }
+    if (ln == 0) {
+      sm.Pacc[p * QLD + 32] = sp;
+      for (int a = 0; a < 3; ++a) sm.Pacc[p * QLD + 33 + a] = hp[a];
+    }
+    wave_sync();
+  }
+  __syncthreads();
+
+  // ---------------- the angle terms of each angle-list edge, in wave order
+  for (int k = tid; k < nc * QLD; k += NT) {
+    const int q = k / QLD, c = k % QLD;
+    float v = sm.Pacc[k];
+    for (int u = 0; u < NWG; ++u) v += sm.Qacc[u][k];
+    if (c < ADIM) sm.DEl[e.cl[q] * EDIM + c] += v;
+    else sm.Pacc[k] = v;  // sw_a and rhat terms, complete
+  }
+  if (tid < NDIM) {
+    float s = 0.f;
+    for (int u = 0; u < NWG; ++u) s += sm.dnsum[u][tid];
+    sm.zz[tid] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < nn; j += NT) {
+    const int cp = e.cpos[j];
+    float *g = b.gs + ((size_t)i * SEL + j) * 2;
+    const float dsa = cp >= 0 ? sm.Pacc[cp * QLD + 32] : 0.f;
+    g[1] = top ? dsa : g[1] + dsa;
+  }
+  if (l > 0) {
+    for (int k = tid; k < nn * EDIM; k += NT) b.de[(size_t)i * SEL * EDIM + k] = sm.DEl[k];
+    if (tid < NDIM) {
+      float v = sm.dn[tid];
+      for (int k = 0; k < NDIM; ++k) v += sm.zz[k] * Wee[tid * EDIM + k];
+      b.dnl[(size_t)i * NDIM + tid] = v;
+    }
+    return;
+  }
+  __syncthreads();
+  // ---------------- layer 0: g_ij = dE/dDelta_ij
+  for (int j = tid; j < nn; j += NT) {
+    float ds = 0.f;
+    for (int c = 0; c < EDIM; ++c) {
+      const float e0 = tanhf(e.s[j] * w.We0[c] + w.be0[c]);
+      ds += sm.DEl[j * EDIM + c] * (1.f - e0 * e0) * w.We0[c];
+    }
+    const float *g2 = b.gs + ((size_t)i * SEL + j) * 2;
+    const int cp = e.cpos[j];
+    const float rr = e.r[j], sw = e.swe[j];
+    const float dr = ds * (e.dswe[j] / rr - sw / (rr * rr)) + g2[0] * e.dswe[j] + g2[1] * e.dswa[j];
+    const float hx = e.rh[3 * j], hy = e.rh[3 * j + 1], hz = e.rh[3 * j + 2];
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (cp >= 0) {
+      gx = sm.Pacc[cp * QLD + 33];
+      gy = sm.Pacc[cp * QLD + 34];
+      gz = sm.Pacc[cp * QLD + 35];
+    }
+    const float proj = gx * hx + gy * hy + gz * hz;
+    gout[(size_t)i * SEL + j] = make_float4((gx - proj * hx) / rr + dr * hx, (gy - proj * hy) / rr + dr * hy,
+                                            (gz - proj * hz) / rr + dr * hz, 0.f);
+  }
+}
+
+}  // namespace
+
+void launch_angle_offsets(const Buffers &b, const Workspace &ws, const double *coords, int n, const Geo &geo,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_angle_count, dim3((n + 255) / 256), dim3(256), 0, st, coords, ws.nlist, ws.nnei, ws.grids, n,
+                     geo, b.aoff);
+  hipLaunchKernelGGL(k_angle_scan, dim3(1), dim3(1024), 0, st, b.aoff, n);
+}
+
+template <typename T>
+void launch_layer_fwd(const Weights &w, const Buffers &b, const Workspace &ws, const double *coords,
+                      const int *types, int n, int layer, const Geo &geo, double *Ei, hipStream_t st) {
+  hipLaunchKernelGGL(k_layer_fwd<T>, dim3(n), dim3(NT), 0, st, w, b, coords, types, ws.nlist, ws.nnei, ws.grids, n,
+                     layer, geo, Ei, ws.flags);
+}
+
+template <typename T>
+void launch_layer_bwd(const Weights &w, const Buffers &b, const Workspace &ws, const double *coords,
+                      const int *types, int n, int layer, const Geo &geo, hipStream_t st) {
+  hipLaunchKernelGGL(k_layer_bwd<T>, dim3(n), dim3(NT), 0, st, w, b, coords, types, ws.nlist, ws.nnei, ws.grids, n,
+                     layer, geo, ws.g, ws.flags);
+}
+
+template void launch_layer_fwd<float>(const Weights &, const Buffers &, const Workspace &, const double *,
+                                      const int *, int, int, const Geo &, double *, hipStream_t);
+template void launch_layer_fwd<bf16_t>(const Weights &, const Buffers &, const Workspace &, const double *,
+                                       const int *, int, int, const Geo &, double *, hipStream_t);
+template void launch_layer_bwd<float>(const Weights &, const Buffers &, const Workspace &, const double *,
+                                      const int *, int, int, const Geo &, hipStream_t);
+template void launch_layer_bwd<bf16_t>(const Weights &, const Buffers &, const Workspace &, const double *,
+                                       const int *, int, int, const Geo &, hipStream_t);
+
+}  // namespace gnn
+}  // namespace dp

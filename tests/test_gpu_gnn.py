@@ -1,0 +1,159 @@
+"""The GNN-variant model on the GPU (dp_gnn_compute_device) against the FP64 oracle
+(oracle/gnn.py), both precisions.
+
+* Whole systems, every output: the 192-atom water box (periodic), a 60-atom open
+  cluster (ragged edge and angle tiles, atoms with few angles) and the 1k-atom
+  solvated chain (periodic, 672 angles per atom, about 671k angles).
+* The 40k-atom solvated chain, the size the message-passing model is quoted on:
+  E_i of sampled atoms against the oracle evaluated on the atoms within 3 rc of each
+  (E_i depends on nothing farther: three layers, each one hop), and properties that
+  hold at any size (zero net force, symmetric virial, E = sum E_i).
+* Determinism (two calls agree bit for bit) and buffer reuse after a larger system.
+"""
+import numpy as np
+import pytest
+
+from oracle.gnn import build_graph, evaluate, forward, load_gnn_model
+from synth import config_system
+from synth.gnn_weights import default_gnn_file
+from tolerances import TOL_GNN, assert_within_gnn, compare
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "bf16"]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def gnn_path():
+    return default_gnn_file()
+
+
+@pytest.fixture(scope="module")
+def ognn(gnn_path):
+    return load_gnn_model(gnn_path)
+
+
+@pytest.fixture(scope="module")
+def gnn_models(torch_cuda, gnn_path):
+    from paper_2602_02234_amd import GnnModel
+    ms = {p: GnnModel(gnn_path, precision=p, device=0) for p in PRECS}
+    yield ms
+    for m in ms.values():
+        m.close()
+
+
+def _cluster(n, seed, spread, dmin=1.0):
+    rng = np.random.default_rng(seed)
+    X = []
+    while len(X) < n:
+        p = rng.uniform(-spread, spread, size=3)
+        if all(np.linalg.norm(p - q) > dmin for q in X):
+            X.append(p)
+    return np.array(X), rng.integers(0, 5, size=n).astype(np.int32)
+
+
+def _systems():
+    w = config_system("water192")
+    X, t = _cluster(60, 7, spread=5.0)
+    c = config_system("chain1k")
+    return {"water192": (w.coords, w.types, w.box), "cluster60": (X, t, None), "chain1k": (c.coords, c.types, c.box)}
+
+
+SYSTEMS = _systems()
+_REF = {}
+
+
+def _ref(ognn, name):
+    if name not in _REF:
+        X, t, box = SYSTEMS[name]
+        _REF[name] = evaluate(ognn, X, t, box)
+    return _REF[name]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_gnn_matches_oracle(gnn_models, ognn, name, prec):
+    X, t, box = SYSTEMS[name]
+    ref = _ref(ognn, name)
+    out = gnn_models[prec].compute(X, t, box, forces=True, atom_energy=True)
+    assert gnn_models[prec].angles() == ref["n_angles"]
+    m = compare(out, ref, len(X))
+    print(f"GNN {name} {len(X)} atoms, {ref['n_angles']} angles, {prec}: {m}")
+    assert_within_gnn(m, prec)
+
+
+def _cutout(s, i, R):
+    L = np.diag(s.box) if np.ndim(s.box) == 2 else np.asarray(s.box)
+    D = s.coords - s.coords[i]
+    D -= L * np.rint(D / L)
+    idx = np.nonzero(np.sqrt(np.sum(D * D, axis=1)) < R)[0]  # ascending: list order is kept
+    return s.coords[i] + D[idx], s.types[idx], int(np.nonzero(idx == i)[0][0])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gnn_chain40k(torch_cuda, gnn_models, ognn, prec):
+    torch = torch_cuda
+    s = config_system("chain40k")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(s.coords, device=dev)
+    T = torch.tensor(s.types, device=dev)
+    F = torch.zeros((s.natoms, 3), dtype=torch.float64, device=dev)
+    V = torch.zeros(9, dtype=torch.float64, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    Ei = torch.zeros(s.natoms, dtype=torch.float64, device=dev)
+    m = gnn_models[prec]
+    m.compute_device(X, T, s.box, forces=F, virial=V, energy=E, atom_energy=Ei)
+    torch.cuda.synchronize()
+    F, V, Ei = F.cpu().numpy(), V.cpu().numpy().reshape(3, 3), Ei.cpu().numpy()
+    print(f"GNN chain40k {prec}: {m.angles()} angles, E = {E.item():.6f}")
+    assert np.isfinite(F).all() and np.isfinite(V).all() and np.isfinite(Ei).all()
+    tol = TOL_GNN[prec]
+    scale = np.sqrt(np.mean(F ** 2))
+    assert np.abs(F.sum(0)).max() <= tol["f_max"] * scale * np.sqrt(s.natoms)
+    assert np.abs(V - V.T).max() <= tol["vir_rel"] * np.abs(V).max()
+    assert abs(E.item() - Ei.sum()) <= 1e-9 * abs(E.item())
+    # E_i of sampled atoms: the oracle on the atoms within 3 rc (+0.5 A) of each
+    for i in np.random.default_rng(5).choice(s.natoms, size=2, replace=False):
+        if ("cut", i) not in _REF:
+            Xc, tc, k = _cutout(s, i, 3 * ognn.rc + 0.5)
+            _REF[("cut", i)] = (len(Xc), forward(ognn, build_graph(ognn, Xc, tc, None))[k])
+        nc, e_ref = _REF[("cut", i)]
+        print(f"  atom {i}: cut-out {nc} atoms, E_i {Ei[i]:.6f} oracle {e_ref:.6f}")
+        assert abs(Ei[i] - e_ref) <= tol["e_atom"]
+
+
+def test_gnn_deterministic_and_reuse(torch_cuda, gnn_models, ognn):
+    m = gnn_models["fp32"]
+    X, t, box = SYSTEMS["water192"]
+    a = m.compute(X, t, box, atom_energy=True)
+    Xc, tc, _ = SYSTEMS["chain1k"]
+    m.compute(Xc, tc, SYSTEMS["chain1k"][2])  # larger system: buffers grow
+    b = m.compute(X, t, box, atom_energy=True)
+    assert a["E"] == b["E"]
+    assert np.array_equal(a["F"], b["F"]) and np.array_equal(a["E_i"], b["E_i"])
+    assert np.array_equal(a["virial"], b["virial"])
+
+
+def test_gnn_energy_only_and_errors(torch_cuda, gnn_models):
+    torch = torch_cuda
+    from paper_2602_02234_amd import DPError
+    m = gnn_models["fp32"]
+    X, t, box = SYSTEMS["water192"]
+    full = m.compute(X, t, box, atom_energy=True)
+    dev = torch.device("cuda:0")
+    Xd = torch.tensor(X, device=dev)
+    Td = torch.tensor(t, device=dev)
+    E = m.compute_device(Xd, Td, box)
+    assert E.item() == full["E"]
+    bad = Td.clone()
+    bad[3] = 7
+    with pytest.raises(DPError):
+        m.compute_device(Xd, bad, box)

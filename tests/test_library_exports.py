@@ -85,3 +85,14 @@ def test_three_head_model_binds_every_head(prec):
     assert lib.dp_check_model_file(path, prec, None, None) == 0, lib.dp_last_error()
     for name in (["F1T.2", "ebias.1"] if prec == 0 else ["b16.F3.2.lo", "F4d.2"]):
         assert lib.dp_check_model_file(path, prec, name.encode(), None) == -2, name
+
+
+def test_gnn_load_without_device_fails_cleanly():
+    """The GNN-variant entry point also reports an error without a GPU (no CPU path)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2602_02234_amd import GnnModel, DPError
+    from synth.gnn_weights import default_gnn_file
+    with pytest.raises(DPError):
+        GnnModel(default_gnn_file())

@@ -139,3 +139,9 @@ def test_smooth_through_cutoff(gm):
         Y[3, 0] = rr
         Es.append(energy(gm, Y, t, None))
     assert np.abs(np.diff(np.diff(Es))).max() < 1e-6
+
+
+def test_last_layer_norm(gm):
+    """||G3||_2 of the seeded GNN model, the constant the energy bounds of the GPU paths use."""
+    from tolerances import G3NORM
+    assert abs(np.linalg.norm(gm.p["G3"]) - G3NORM) < 0.05
