@@ -2,8 +2,9 @@
 // and one launch per message-passing layer, forward and backward (a layer's edge update
 // reads the neighbours' node features of the layer before, so layers meet at launch
 // boundaries).  Every product of a feature tile with a weight matrix runs on MFMA
-// (16 angles or 16 edges per tile; Mma<T> selects f32 or bf16 operands, f32
-// accumulation); features are stored in float32.
+// (16 angles or 16 edges per tile, f32 or bf16 operands, f32 accumulation); feature
+// tiles are staged in per-wave LDS slabs and the angle weights of a layer stay in each
+// wave's registers for all its tiles.  Features are stored in float32.
 //
 // Forward, layer l, centre i:
 //   angles  each wave owns angle rows p (p = wave, wave + 4, ...) and walks q in tiles
@@ -47,6 +48,69 @@ __device__ __forceinline__ float wave_sum64(float v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
+
+// Weight fragments held in registers for one 16-column tile of a product X W (X: 16
+// rows in an LDS slab, W: K x 16).  The k order inside each MFMA step is permuted
+// (the sum does not depend on it) so that a lane's A operands for consecutive steps
+// are adjacent in LDS and come in 128-bit reads: f32, steps s = 0..3 of block kb use
+// k = 16 kb + 4 (lane / 16) + s; bf16, block kb uses k = 32 kb + 8 (lane / 16) + e.
+// y(c, k) gives W[k][c]; col(k0) maps the first k of a block to its slab column
+// (operands may come from several column ranges, each a multiple of 32 wide).
+template <typename T, int K> struct Frag;
+
+template <int K> struct Frag<float, K> {
+  float v[K / 4];
+  template <class Y> __device__ __forceinline__ void load(const Y &y) {
+    const int c = lane_id() & 15, kq = lane_id() >> 4;
+#pragma unroll
+    for (int kb = 0; kb < K / 16; ++kb)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[kb * 4 + s] = y(c, kb * 16 + 4 * kq + s);
+  }
+  template <class C> __device__ __forceinline__ void mma(f4 &acc, const float *row, const C &col) const {
+    const int kq = lane_id() >> 4;
+#pragma unroll
+    for (int kb = 0; kb < K / 16; ++kb) {
+      const float4 a = *reinterpret_cast<const float4 *>(row + col(kb * 16) + 4 * kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v[kb * 4 + 0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, v[kb * 4 + 1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, v[kb * 4 + 2], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, v[kb * 4 + 3], acc, 0, 0, 0);
+    }
+  }
+};
+
+template <int K> struct Frag<bf16_t, K> {
+  bf8 v[K / 32];
+  template <class Y> __device__ __forceinline__ void load(const Y &y) {
+    const int c = lane_id() & 15, kq = lane_id() >> 4;
+#pragma unroll
+    for (int kb = 0; kb < K / 32; ++kb)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[kb][e] = (__bf16)y(c, kb * 32 + 8 * kq + e);
+  }
+  template <class C> __device__ __forceinline__ void mma(f4 &acc, const float *row, const C &col) const {
+    const int kq = lane_id() >> 4;
+#pragma unroll
+    for (int kb = 0; kb < K / 32; ++kb) {
+      const float *q = row + col(kb * 32) + 8 * kq;
+      const float4 a0 = *reinterpret_cast<const float4 *>(q);
+      const float4 a1 = *reinterpret_cast<const float4 *>(q + 4);
+      bf8 a;
+      a[0] = (__bf16)a0.x; a[1] = (__bf16)a0.y; a[2] = (__bf16)a0.z; a[3] = (__bf16)a0.w;
+      a[4] = (__bf16)a1.x; a[5] = (__bf16)a1.y; a[6] = (__bf16)a1.z; a[7] = (__bf16)a1.w;
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, v[kb], acc, 0, 0, 0);
+    }
+  }
+};
+
+// Compiler barrier: weight fragments loaded after it are not hoisted out of the loop
+// around it (they would then all be live at once).
+__device__ __forceinline__ void opaque() { asm volatile("" ::: "memory"); }
+
+struct Ident {
+  __device__ __forceinline__ int operator()(int k) const { return k; }
+};
 
 struct GEnv {
   float r[SEL], swe[SEL], dswe[SEL], swa[SEL], dswa[SEL], s[SEL];
@@ -176,12 +240,38 @@ __global__ void __launch_bounds__(1024) k_angle_scan(int64_t *__restrict__ aoff,
 // ------------------------------------------------------------------ forward
 struct SmemF {
   GEnv env;
-  float El[SEL * LDE];        // e of the layer's input
-  float Msg[ASEL * EDIM];     // m_ip
-  float slab[NWG][16 * LDF];  // per-wave operand tiles
-  float ni[NDIM], xs[2 * NDIM], aggw[NWG][NDIM];
+  float El[SEL * LDE] __attribute__((aligned(16)));  // e of the layer's input
+  float Msg[ASEL * EDIM];                            // m_ip
+  float slab[NWG][16 * LDF] __attribute__((aligned(16)));  // per-wave operand tiles
+  float ni[NDIM] __attribute__((aligned(16))), xs[2 * NDIM], aggw[NWG][NDIM];
   float y1[FWID], t2[FWID], dp[FWID];
 };
+
+// Stages 16 rows x 32 S floats into a slab: segment s (columns 32 s .. 32 s + 31) of
+// row r is src(s, r, c4), c4 = 0..7 the float4 within the segment (zero for rows past
+// the end).  Each lane moves two rows of one float4 column per segment; the reads of G
+// segments are issued before their writes, so their latencies overlap.  s is a
+// compile-time constant in every call of src (the loops are unrolled).
+template <int S, int G, class Src>
+__device__ __forceinline__ void stage(float *sl, int ld, const Src &src) {
+  const int c4 = lane_id() & 7, r0 = lane_id() >> 3;
+#pragma unroll
+  for (int g0 = 0; g0 < S; g0 += G) {
+    float4 v[G][2];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (g0 + g < S) v[g][h] = src(g0 + g, r0 + 8 * h, c4);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (g0 + g < S) *reinterpret_cast<float4 *>(sl + (r0 + 8 * h) * ld + 32 * (g0 + g) + 4 * c4) = v[g][h];
+  }
+}
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const double *__restrict__ X,
@@ -193,49 +283,74 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   const int i = blockIdx.x;
   if (i >= n || failed(flags)) return;
   const int tid = threadIdx.x, wv = wave_id(), ln = lane_id();
-  build_genv(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
-  const GEnv &e = sm.env;
-  const int nn = e.nn, nc = e.nc, l = layer;
+  const int l = layer;
   const float *Waa = w.Waa[l], *baa = w.baa[l], *Wea = w.Wea[l], *bea = w.bea[l];
   const float *Wee = w.Wee[l], *bee = w.bee[l], *Wnn = w.Wnn[l], *bnn = w.bnn[l];
+  // this layer's angle weights, held by every wave for all its tiles
+  Frag<T, 96> fa[2];
+  Frag<T, 64> fm[4];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) fa[ct].load([&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; });
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) fm[ct].load([&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; });
+  build_genv(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
+  const GEnv &e = sm.env;
+  const int nn = e.nn, nc = e.nc;
 
-  for (int k = tid; k < nn * EDIM; k += NT) {
-    const int j = k >> 6, c = k & 63;
-    sm.El[j * LDE + c] = l == 0 ? tanhf(e.s[j] * w.We0[c] + w.be0[c]) : b.ef[erow(b, l - 1, i, j) + c];
+  if (l == 0) {
+    for (int k = tid; k < nn * EDIM; k += NT) {
+      const int j = k >> 6, c = k & 63;
+      sm.El[j * LDE + c] = tanhf(e.s[j] * w.We0[c] + w.be0[c]);
+    }
+  } else {  // the input edges, all reads issued before the writes
+    constexpr int NI = (SEL * EDIM / 4 + NT - 1) / NT;
+    float4 v[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = tid + NT * it, j = k >> 4;
+      if (j < nn) v[it] = ld4(b.ef + erow(b, l - 1, i, j) + 4 * (k & 15));
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = tid + NT * it, j = k >> 4;
+      if (j < nn) *reinterpret_cast<float4 *>(sm.El + j * LDE + 4 * (k & 15)) = v[it];
+    }
   }
   if (tid < NDIM)
     sm.ni[tid] = l == 0 ? w.TN[clamp_type(types[i]) * NDIM + tid] : b.nf[((size_t)(l - 1) * b.cap + i) * NDIM + tid];
   __syncthreads();
 
   float *sl = sm.slab[wv];
+  const float *rowA = sl + (ln & 15) * LDF;
   const int na = nc - 1;  // angles per row p
   const int64_t abase = b.aoff[i];
   // ---------------- angles and messages
   for (int p = wv; p < nc; p += NWG) {
     float mr[4] = {0.f, 0.f, 0.f, 0.f};
     const int jp = e.cl[p];
+    const float *ap = b.af + ((size_t)(l > 0 ? l - 1 : 0) * b.acap + abase + (int64_t)p * na) * ADIM;
     for (int t0 = 0; t0 < na; t0 += 16) {
-      for (int k = ln; k < 16 * 96; k += 64) {
-        const int r = k / 96, c = k % 96, t = t0 + r;
-        float v = 0.f;
-        if (t < na) {
-          const int q = t + (t >= p);
-          if (c < 32)
-            v = l == 0 ? tanhf(cosang(e, jp, e.cl[q]) * w.Wa0[c] + w.ba0[c])
-                       : b.af[((size_t)(l - 1) * b.acap + abase + (int64_t)p * na + t) * ADIM + c];
-          else if (c < 64)
-            v = sm.El[jp * LDE + c - 32];
-          else
-            v = sm.El[e.cl[q] * LDE + c - 64];
+      // [a, e_ip[:32], e_iq[:32]]
+      stage<3, 3>(sl, LDF, [&](int sg, int r, int c4) -> float4 {
+        const int t = t0 + r;
+        if (t >= na) return make_float4(0.f, 0.f, 0.f, 0.f);
+        const int q = t + (t >= p);
+        if (sg == 0) {
+          if (l > 0) return ld4(ap + (size_t)t * ADIM + 4 * c4);
+          const float cs = cosang(e, jp, e.cl[q]);
+          float4 v;
+          v.x = tanhf(cs * w.Wa0[4 * c4] + w.ba0[4 * c4]);
+          v.y = tanhf(cs * w.Wa0[4 * c4 + 1] + w.ba0[4 * c4 + 1]);
+          v.z = tanhf(cs * w.Wa0[4 * c4 + 2] + w.ba0[4 * c4 + 2]);
+          v.w = tanhf(cs * w.Wa0[4 * c4 + 3] + w.ba0[4 * c4 + 3]);
+          return v;
         }
-        sl[r * LDF + c] = v;
-      }
+        return ld4(sm.El + (sg == 1 ? jp : e.cl[q]) * LDE + 4 * c4);
+      });
       wave_sync();
       f4 aa[2] = {};
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-        Mma<T>::tile(aa[ct], [&](int r, int k) { return sl[r * LDF + k]; },
-                     [&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; }, 96);
+      for (int ct = 0; ct < 2; ++ct) fa[ct].mma(aa[ct], rowA, Ident());
       wave_sync();
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct)
@@ -249,9 +364,7 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
       wave_sync();
       f4 am[4] = {};
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        Mma<T>::tile(am[ct], [&](int r, int k) { return sl[r * LDF + (k < 32 ? k : k + 32)]; },
-                     [&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; }, 64);
+      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, [](int k) { return k < 32 ? k : k + 32; });
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int t = t0 + acc_row(ii);
@@ -272,25 +385,25 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   // ---------------- edges
   float aw[4] = {0.f, 0.f, 0.f, 0.f};
   for (int j0 = wv * 16; j0 < nn; j0 += NWG * 16) {
-    for (int k = ln; k < 16 * 192; k += 64) {
-      const int r = k / 192, c = k % 192, j = j0 + r;
-      float v = 0.f;
-      if (j < nn) {
-        if (c < 64)
-          v = sm.ni[c];
-        else if (c < 128)
-          v = l == 0 ? w.TN[e.tj[j] * NDIM + c - 64] : b.nf[((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c - 64];
-        else
-          v = sm.El[j * LDE + c - 128];
-      }
-      sl[r * LDF + c] = v;
-    }
+    // [n_i, n_j, e_ij]
+    stage<6, 3>(sl, LDF, [&](int sg, int r, int c4) -> float4 {
+      const int j = j0 + r;
+      if (j >= nn) return make_float4(0.f, 0.f, 0.f, 0.f);
+      const int c = 32 * (sg & 1) + 4 * c4;
+      if (sg < 2) return ld4(sm.ni + c);
+      if (sg < 4)
+        return l == 0 ? ld4(w.TN + e.tj[j] * NDIM + c) : ld4(b.nf + ((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c);
+      return ld4(sm.El + j * LDE + c);
+    });
     wave_sync();
     f4 ae[4] = {};
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-      Mma<T>::tile(ae[ct], [&](int r, int k) { return sl[r * LDF + k]; },
-                   [&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; }, 192);
+    for (int ct = 0; ct < 4; ++ct) {
+      opaque();  // load each column tile's weights here, not once for all tiles
+      Frag<T, 192> f;
+      f.load([&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; });
+      f.mma(ae[ct], rowA, Ident());
+    }
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int j = j0 + acc_row(ii);
@@ -373,11 +486,11 @@ struct SmemB {
   GEnv env;
   float DEl[SEL * EDIM];      // dE/de of this layer's input edges
   float DM[ASEL * EDIM];      // dE/dm_ip
-  float Ec[ASEL * ADIM];      // e[:32] of the angle-list edges
-  float slab[NWG][16 * LDB];
+  float Ec[ASEL * ADIM] __attribute__((aligned(16)));  // e[:32] of the angle-list edges
+  float slab[NWG][16 * LDB] __attribute__((aligned(16)));
   float Qacc[NWG][ASEL * QLD];  // per-wave sums of the terms of edge q
   float Pacc[ASEL * QLD];       // terms of edge p from its own angle row
-  float dn[NDIM], ni[NDIM], xs[2 * NDIM], dagg[NDIM], dnsum[NWG][NDIM], zz[NDIM];
+  float dn[NDIM], ni[NDIM] __attribute__((aligned(16))), xs[2 * NDIM], dagg[NDIM], dnsum[NWG][NDIM], zz[NDIM];
   int slot[SEL];
 };
 
@@ -420,17 +533,27 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
   if (tid < NDIM)
     sm.ni[tid] = l == 0 ? w.TN[clamp_type(types[i]) * NDIM + tid] : b.nf[((size_t)(l - 1) * b.cap + i) * NDIM + tid];
   __syncthreads();
+  {
+    // each wave sums the rows j = wave, wave + 4, ... in list order (the neighbours' edge
+    // parts of dE/dn_i, and agg from the stored output edges); waves combine in order
+    float dn = 0.f, agg = 0.f;
+    const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * EDIM;
+#pragma unroll 4
+    for (int j = wv; j < nn; j += NWG) {
+      if (!top && sm.slot[j] >= 0) dn += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * EDIM + ln];
+      agg += e.swe[j] * b.ef[erow(b, l, i, j) + ln];
+    }
+    sm.dnsum[wv][ln] = dn;
+    sm.Pacc[wv * EDIM + ln] = agg;
+  }
+  __syncthreads();
   if (tid < NDIM) {
-    float dn = b.dnl[(size_t)i * NDIM + tid];
-    if (!top) {
-      const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * EDIM;
-      for (int j = 0; j < nn; ++j)
-        if (sm.slot[j] >= 0) dn += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * EDIM + tid];
+    float dn = b.dnl[(size_t)i * NDIM + tid], agg = 0.f;
+    for (int u = 0; u < NWG; ++u) {
+      dn += sm.dnsum[u][tid];
+      agg += sm.Pacc[u * EDIM + tid];
     }
     sm.dn[tid] = dn;
-    // agg from the stored output edges
-    float agg = 0.f;
-    for (int j = 0; j < nn; ++j) agg += e.swe[j] * b.ef[erow(b, l, i, j) + tid];
     sm.xs[tid] = sm.ni[tid];
     sm.xs[NDIM + tid] = agg * geo.inv_sel;
   }
@@ -455,28 +578,50 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
   __syncthreads();
 
   float *sl = sm.slab[wv];
+  const float *rowA = sl + (ln & 15) * LDB;
   // ---------------- edges
   float dns[4] = {0.f, 0.f, 0.f, 0.f};
   for (int j0 = wv * 16; j0 < nn; j0 += NWG * 16) {
-    for (int k = ln; k < 16 * 192; k += 64) {
-      const int r = k / 192, c = k % 192, j = j0 + r;
-      float v = 0.f;
-      if (j < nn) {
-        if (c < 64)
-          v = sm.ni[c];
-        else if (c < 128)
-          v = l == 0 ? w.TN[e.tj[j] * NDIM + c - 64] : b.nf[((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c - 64];
-        else
-          v = l == 0 ? tanhf(e.s[j] * w.We0[c - 128] + w.be0[c - 128]) : b.ef[erow(b, l - 1, i, j) + c - 128];
+    stage<6, 2>(sl, LDB, [&](int sg, int r, int c4) -> float4 {
+      const int j = j0 + r;
+      if (j >= nn) return make_float4(0.f, 0.f, 0.f, 0.f);
+      const int c = 32 * (sg & 1) + 4 * c4;
+      if (sg < 2) return ld4(sm.ni + c);
+      if (sg < 4)
+        return l == 0 ? ld4(w.TN + e.tj[j] * NDIM + c) : ld4(b.nf + ((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c);
+      if (l > 0) return ld4(b.ef + erow(b, l - 1, i, j) + c);
+      float4 v;
+      v.x = tanhf(e.s[j] * w.We0[c] + w.be0[c]);
+      v.y = tanhf(e.s[j] * w.We0[c + 1] + w.be0[c + 1]);
+      v.z = tanhf(e.s[j] * w.We0[c + 2] + w.be0[c + 2]);
+      v.w = tanhf(e.s[j] * w.We0[c + 3] + w.be0[c + 3]);
+      return v;
+    });
+    float pde[4][4], pef[4][4];  // dE/de and e of the layer's output, read ahead of their use
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int j = j0 + acc_row(ii);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int c = ct * 16 + acc_col();
+        pde[ct][ii] = (!top && j < nn) ? b.de[((size_t)i * SEL + j) * EDIM + c] : 0.f;
+        pef[ct][ii] = j < nn ? b.ef[erow(b, l, i, j) + c] : 0.f;
       }
-      sl[r * LDB + c] = v;
     }
     wave_sync();
     f4 ae[4] = {};
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-      Mma<T>::tile(ae[ct], [&](int r, int k) { return sl[r * LDB + k]; },
-                   [&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; }, 192);
+    for (int ct = 0; ct < 4; ++ct) {
+      if constexpr (sizeof(T) == 2) {
+        opaque();  // load each column tile's weights here, not once for all tiles
+        Frag<T, 192> f;
+        f.load([&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; });
+        f.mma(ae[ct], rowA, Ident());
+      } else {  // float32 operands: 48 more registers per lane would spill; read W as it goes
+        Mma<T>::tile(ae[ct], [&](int r, int k) { return sl[r * LDB + k]; },
+                     [&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; }, 192);
+      }
+    }
     wave_sync();
     float de1[4][4], rs[4];
 #pragma unroll
@@ -489,8 +634,8 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
         const int c = ct * 16 + acc_col();
         float d = 0.f, dz = 0.f;
         if (ok) {
-          d = (top ? 0.f : b.de[((size_t)i * SEL + j) * EDIM + c]) + e.swe[j] * sm.dagg[c];
-          rs[ii] += b.ef[erow(b, l, i, j) + c] * sm.dagg[c];
+          d = pde[ct][ii] + e.swe[j] * sm.dagg[c];
+          rs[ii] += pef[ct][ii] * sm.dagg[c];
           const float t = tanhf(ae[ct][ii] + bee[c]);
           dz = d * (1.f - t * t);
         }
@@ -513,9 +658,12 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
       float *dst = b.dnj + (size_t)(l & 1) * b.cap * SEL * EDIM;
       f4 an[4] = {};
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        Mma<T>::tile(an[ct], [&](int r, int k) { return sl[r * LDB + k]; },
-                     [&](int c, int k) { return Wee[(NDIM + ct * 16 + c) * EDIM + k]; }, 64);
+        for (int ct = 0; ct < 4; ++ct) {
+        opaque();
+        Frag<T, 64> f;
+        f.load([&](int c, int k) { return Wee[(NDIM + ct * 16 + c) * EDIM + k]; });
+        f.mma(an[ct], rowA, Ident());
+      }
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int j = j0 + acc_row(ii);
@@ -526,9 +674,12 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
     }
     f4 ad[4] = {};
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-      Mma<T>::tile(ad[ct], [&](int r, int k) { return sl[r * LDB + k]; },
-                   [&](int c, int k) { return Wee[(2 * NDIM + ct * 16 + c) * EDIM + k]; }, 64);
+    for (int ct = 0; ct < 4; ++ct) {
+      opaque();
+      Frag<T, 64> f;
+      f.load([&](int c, int k) { return Wee[(2 * NDIM + ct * 16 + c) * EDIM + k]; });
+      f.mma(ad[ct], rowA, Ident());
+    }
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int j = j0 + acc_row(ii);
@@ -554,48 +705,77 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
   __syncthreads();
 
   // ---------------- angles
+  // this layer's angle weights in registers: forward recomputation (Wea, Waa) and the
+  // transposed products (Wea^T, Waa^T, and [Wea; Waa]^T for the terms of edge q)
+  // ([Wea; Waa]^T stays in registers only for bf16 operands: as float32 it would not fit
+  // beside the rest and is reloaded for each tile)
+  constexpr bool FV_RESIDENT = sizeof(T) == 2;
+  auto wv_q = [&](int ct) {
+    return [=](int c, int k) {
+      return k < 64 ? Wea[(32 + ct * 16 + c) * EDIM + k] : Waa[(64 + ct * 16 + c) * ADIM + k - 64];
+    };
+  };
+  Frag<T, 64> fm[4], fx[2];
+  Frag<T, 96> fa[2], fv[FV_RESIDENT ? 2 : 1];
+  Frag<T, 32> fy[2];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) fm[ct].load([&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; });
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    fa[ct].load([&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; });
+    fx[ct].load([&](int c, int k) { return Wea[(ct * 16 + c) * EDIM + k]; });
+    fy[ct].load([&](int c, int k) { return Waa[(ct * 16 + c) * ADIM + k]; });
+    if constexpr (FV_RESIDENT) fv[ct].load(wv_q(ct));
+  }
   const int na = nc - 1;
   const int64_t abase = b.aoff[i];
   for (int p = wv; p < nc; p += NWG) {
     const int jp = e.cl[p];
     float S[2] = {0.f, 0.f};      // column sums of dz_a
     float sp = 0.f, hp[3] = {0.f, 0.f, 0.f};  // dE/dsw_a(r_ip), dE/drhat_ip from this row
+    const float *a1p = b.af + ((size_t)l * b.acap + abase + (int64_t)p * na) * ADIM;
+    const float *a0p = b.af + ((size_t)(l > 0 ? l - 1 : 0) * b.acap + abase + (int64_t)p * na) * ADIM;
     for (int t0 = 0; t0 < na; t0 += 16) {
-      for (int k = ln; k < 16 * 128; k += 64) {
-        const int r = k >> 7, c = k & 127, t = t0 + r;
-        float v = 0.f;
-        if (t < na) {
-          const int q = t + (t >= p);
-          const size_t ai = (size_t)(abase + (int64_t)p * na + t);
-          if (c < 32)
-            v = b.af[((size_t)l * b.acap + ai) * ADIM + c];
-          else if (c < 64)
-            v = sm.Ec[q * ADIM + c - 32];
-          else if (c < 96)
-            v = l == 0 ? tanhf(cosang(e, jp, e.cl[q]) * w.Wa0[c - 64] + w.ba0[c - 64])
-                       : b.af[((size_t)(l - 1) * b.acap + ai) * ADIM + c - 64];
-          else
-            v = sm.Ec[p * ADIM + c - 96];
-        }
-        sl[r * LDB + c] = v;
+      // [a', e_iq[:32], a, e_ip[:32]]
+      stage<4, 4>(sl, LDB, [&](int sg, int r, int c4) -> float4 {
+        const int t = t0 + r;
+        if (t >= na) return make_float4(0.f, 0.f, 0.f, 0.f);
+        const int q = t + (t >= p);
+        if (sg == 0) return ld4(a1p + (size_t)t * ADIM + 4 * c4);
+        if (sg == 1) return ld4(sm.Ec + q * ADIM + 4 * c4);
+        if (sg == 3) return ld4(sm.Ec + p * ADIM + 4 * c4);
+        if (l > 0) return ld4(a0p + (size_t)t * ADIM + 4 * c4);
+        const float cs = cosang(e, jp, e.cl[q]);
+        const int c = 4 * c4;
+        float4 v;
+        v.x = tanhf(cs * w.Wa0[c] + w.ba0[c]);
+        v.y = tanhf(cs * w.Wa0[c + 1] + w.ba0[c + 1]);
+        v.z = tanhf(cs * w.Wa0[c + 2] + w.ba0[c + 2]);
+        v.w = tanhf(cs * w.Wa0[c + 3] + w.ba0[c + 3]);
+        return v;
+      });
+      float dap[2][4];  // dE/da of the layer's output, read ahead of its use
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int t = t0 + acc_row(ii);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+          dap[ct][ii] = (!top && t < na) ? b.da[(size_t)(abase + (int64_t)p * na + t) * ADIM + ct * 16 + acc_col()] : 0.f;
       }
       wave_sync();
       f4 am[4] = {}, aa[2] = {};
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        Mma<T>::tile(am[ct], [&](int r, int k) { return sl[r * LDB + k]; },
-                     [&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; }, 64);
+      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, Ident());
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct)  // [a, e_ip, e_iq]: columns 64..127, then 32..63
-        Mma<T>::tile(aa[ct], [&](int r, int k) { return sl[r * LDB + (k < 64 ? 64 + k : k - 32)]; },
-                     [&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; }, 96);
-      float dwa[4], wr[4], ta[2][4];
+        fa[ct].mma(aa[ct], rowA, [](int k) { return k < 64 ? 64 + k : k - 32; });
+      float dwa[4], ta[2][4];
       int qv[4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int r = acc_row(ii), t = t0 + r;
         qv[ii] = t < na ? t + (t >= p) : -1;
-        wr[ii] = qv[ii] >= 0 ? e.swa[jp] * e.swa[e.cl[qv[ii]]] * geo.inv_asel : 0.f;
+        const float wr = qv[ii] >= 0 ? e.swa[jp] * e.swa[e.cl[qv[ii]]] * geo.inv_asel : 0.f;
         float d = 0.f;
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
@@ -603,31 +783,25 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
           const float tm = tanhf(am[ct][ii] + bea[c]);
           const float dm = qv[ii] >= 0 ? sm.DM[p * EDIM + c] : 0.f;
           d += dm * tm;
-          sl[r * LDB + 128 + c] = wr[ii] * dm * (1.f - tm * tm);  // dz_m
+          sl[r * LDB + 128 + c] = wr * dm * (1.f - tm * tm);  // dz_m
         }
         dwa[ii] = sum16(d);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          const float t = tanhf(aa[ct][ii] + baa[ct * 16 + acc_col()]);
-          ta[ct][ii] = t;
-        }
+        for (int ct = 0; ct < 2; ++ct) ta[ct][ii] = tanhf(aa[ct][ii] + baa[ct * 16 + acc_col()]);
       }
       wave_sync();
       f4 ax[2] = {};
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-        Mma<T>::tile(ax[ct], [&](int r, int k) { return sl[r * LDB + 128 + k]; },
-                     [&](int c, int k) { return Wea[(ct * 16 + c) * EDIM + k]; }, 64);
+      for (int ct = 0; ct < 2; ++ct) fx[ct].mma(ax[ct], rowA, [](int k) { return 128 + k; });
       float da1[2][4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int r = acc_row(ii);
-        const size_t ai = (size_t)(abase + (int64_t)p * na + (t0 + r));
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           const int c = ct * 16 + acc_col();
           float d = 0.f;
-          if (qv[ii] >= 0) d = (top ? 0.f : b.da[ai * ADIM + c]) + ax[ct][ii];
+          if (qv[ii] >= 0) d = dap[ct][ii] + ax[ct][ii];
           da1[ct][ii] = d;
           const float dz = d * (1.f - ta[ct][ii] * ta[ct][ii]);
           sl[r * LDB + 192 + c] = dz;  // dz_a
@@ -638,26 +812,27 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
       f4 ay[2] = {}, av[2] = {};
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
-        Mma<T>::tile(ay[ct], [&](int r, int k) { return sl[r * LDB + 192 + k]; },
-                     [&](int c, int k) { return Waa[(ct * 16 + c) * ADIM + k]; }, 32);
-        Mma<T>::tile(av[ct], [&](int r, int k) { return sl[r * LDB + 128 + k]; },
-                     [&](int c, int k) {
-                       return k < 64 ? Wea[(32 + ct * 16 + c) * EDIM + k] : Waa[(64 + ct * 16 + c) * ADIM + k - 64];
-                     },
-                     96);
+        fy[ct].mma(ay[ct], rowA, [](int k) { return 192 + k; });
+        if constexpr (FV_RESIDENT) {
+          fv[ct].mma(av[ct], rowA, [](int k) { return 128 + k; });
+        } else {
+          opaque();
+          Frag<T, 96> f;
+          f.load(wv_q(ct));
+          f.mma(av[ct], rowA, [](int k) { return 128 + k; });
+        }
       }
       float dc[4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int r = acc_row(ii);
-        const size_t ai = (size_t)(abase + (int64_t)p * na + (t0 + r));
         float d = 0.f;
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           const int c = ct * 16 + acc_col();
           const float dal = da1[ct][ii] + ay[ct][ii];
           if (qv[ii] >= 0) {
-            if (l > 0) b.da[ai * ADIM + c] = dal;
+            if (l > 0) b.da[(size_t)(abase + (int64_t)p * na + t0 + r) * ADIM + c] = dal;
             Q[qv[ii] * QLD + c] += av[ct][ii];
           }
           const float a0 = sl[r * LDB + 64 + c];
