@@ -145,3 +145,73 @@ def test_last_layer_norm(gm):
     """||G3||_2 of the seeded GNN model, the constant the energy bounds of the GPU paths use."""
     from tolerances import G3NORM
     assert abs(np.linalg.norm(gm.p["G3"]) - G3NORM) < 0.05
+
+
+def _scalar_energies(m, X, types):
+    """E_i of an open cluster by plain Python loops over atoms, edges, angles and
+    feature components, written from the model's definition (no arrays, no shared code
+    with oracle/gnn.py beyond the parameters)."""
+    import math
+    p = {k: v.tolist() for k, v in m.p.items()}
+    N = len(X)
+
+    def dist(i, j):
+        return math.sqrt(sum((X[j][a] - X[i][a]) ** 2 for a in range(3)))
+
+    def sw(r, rc):
+        if r < m.rcs:
+            return 1.0
+        if r >= rc:
+            return 0.0
+        u = (r - m.rcs) / (rc - m.rcs)
+        return u ** 3 * (-6 * u * u + 15 * u - 10) + 1
+
+    def lin(x, W, b):
+        return [sum(x[q] * W[q][c] for q in range(len(x))) + b[c] for c in range(len(b))]
+
+    nb = {i: [j for j in range(N) if j != i and dist(i, j) < m.rc] for i in range(N)}
+    close = {i: [j for j in nb[i] if dist(i, j) < m.rca][:m.asel] for i in range(N)}
+    n = {i: list(p["TN"][types[i]]) for i in range(N)}
+    e = {(i, j): [math.tanh(sw(dist(i, j), m.rc) / dist(i, j) * p["We0"][0][c] + p["be0"][c]) for c in range(64)]
+         for i in range(N) for j in nb[i]}
+    a = {}
+    for i in range(N):
+        for j in close[i]:
+            for k in close[i]:
+                if j != k:
+                    cs = sum((X[j][t] - X[i][t]) * (X[k][t] - X[i][t]) for t in range(3)) / (dist(i, j) * dist(i, k))
+                    a[(i, j, k)] = [math.tanh(cs * p["Wa0"][0][c] + p["ba0"][c]) for c in range(32)]
+    for l in range(3):
+        a1 = {key: [av[c] + math.tanh(z) for c, z in enumerate(
+            lin(av + e[key[0], key[1]][:32] + e[key[0], key[2]][:32], p[f"Waa{l}"], p[f"baa{l}"]))]
+            for key, av in a.items()}
+        msg = {key: [0.0] * 64 for key in e}
+        for (i, j, k), av in a1.items():
+            wgt = sw(dist(i, j), m.rca) * sw(dist(i, k), m.rca) / m.asel
+            z = lin(av + e[i, k][:32], p[f"Wea{l}"], p[f"bea{l}"])
+            for c in range(64):
+                msg[i, j][c] += wgt * math.tanh(z[c])
+        e1 = {(i, j): [ev[c] + math.tanh(z) + msg[i, j][c] for c, z in enumerate(
+            lin(n[i] + n[j] + ev, p[f"Wee{l}"], p[f"bee{l}"]))] for (i, j), ev in e.items()}
+        n1 = {}
+        for i in range(N):
+            agg = [sum(sw(dist(i, j), m.rc) * e1[i, j][c] for j in nb[i]) / m.sel for c in range(64)]
+            n1[i] = [n[i][c] + math.tanh(z) for c, z in enumerate(lin(n[i] + agg, p[f"Wnn{l}"], p[f"bnn{l}"]))]
+        a, e, n = a1, e1, n1
+    out = []
+    for i in range(N):
+        y1 = [math.tanh(z) for z in lin(n[i], p["G1"], p["d1"])]
+        y2 = [math.tanh(z) + y1[c] for c, z in enumerate(lin(y1, p["G2"], p["d2"]))]
+        out.append(lin(y2, p["G3"], p["d3"])[0])
+    return out
+
+
+def test_scalar_loop_reevaluation(gm):
+    """The vectorised forward equals a loop-by-loop evaluation of the model on a 7-atom
+    cluster with every pair within rca (42 angles at each atom)."""
+    X, t = _cluster(7, 21, spread=1.8, dmin=1.0)
+    d = np.sqrt(((X[:, None] - X[None]) ** 2).sum(-1))
+    assert d.max() < gm.rca
+    ref = np.array(_scalar_energies(gm, X.tolist(), t.tolist()))
+    Ei = forward(gm, build_graph(gm, X, t, None))
+    assert np.abs(Ei - ref).max() < 1e-9 * np.abs(ref).max()
