@@ -14,8 +14,12 @@ the same path at the other precision, the force error of the run on sampled
 atoms against the FP64 oracle, and the oracle's own throughput on the host
 cores (a bounded sample of the same workload).
 
+The GNN-variant model (message passing over edges and angles) is timed on the 40k-atom
+chain in both precisions as well, under "gnn".
+
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision bf16|fp32]
                        [--workload chain25k] [--serve-requests 2000] [--no-cpu-baseline]
+                       [--gnn-steps 5]
 """
 import argparse
 import json
@@ -53,6 +57,79 @@ def mac_desc_bwd_alg(n):
 
 def flop_per_atom_eval(n):
     return 2.0 * (mac_desc_fwd(n) + mac_desc_bwd_alg(n) + 2 * FIT_MAC)
+
+
+# GNN variant (message passing over edges and angles): algorithmic FLOP of its products.
+# Forward, per layer: an angle 2 (96*32 + 64*64), an edge 2 (192*64), a node 2 (128*64);
+# the fitting net and its gradient per atom 2 (64*128 + 128*128 + 128) + 2 (128*128 + 64*128).
+# Backward, per layer: an angle 2 (64*64 + 96*32 + 64*32 + 32*32 + 96*32) (recomputed
+# activations, the two transposed products and the terms of edge q), an edge 2 (192*64 +
+# 64*64 + 64*64) (2 (192*64 + 64*64) in layer 0, which needs no neighbour part), a node
+# 2 (128*64 + 2*64*64).
+GNN_F = dict(fwd_angle=2 * (96 * 32 + 64 * 64), fwd_edge=2 * 192 * 64, fwd_node=2 * 128 * 64,
+             fit=2 * (64 * 128 + 128 * 128 + 128) + 2 * (128 * 128 + 64 * 128),
+             bwd_angle=2 * (64 * 64 + 96 * 32 + 64 * 32 + 32 * 32 + 96 * 32),
+             bwd_edge=2 * (192 * 64 + 2 * 64 * 64), bwd_edge0=2 * (192 * 64 + 64 * 64), bwd_node=2 * (128 * 64 + 2 * 64 * 64))
+
+
+def gnn_flop(N, E, A):
+    """(forward, backward) algorithmic FLOP of one GNN step with N atoms, E edges, A angles."""
+    f = GNN_F
+    fwd = 3 * (A * f["fwd_angle"] + E * f["fwd_edge"] + N * f["fwd_node"]) + N * f["fit"]
+    bwd = 3 * A * f["bwd_angle"] + E * (2 * f["bwd_edge"] + f["bwd_edge0"]) + 3 * N * f["bwd_node"]
+    return float(fwd), float(bwd)
+
+
+def gnn_bench(steps, warmup):
+    """The GNN-variant model on the 40k-atom chain, both precisions: throughput, phase
+    times (HIP events on the launch stream) and the roofline of the backward layer kernel."""
+    import torch
+    from paper_2602_02234_amd import GnnModel
+    from synth import config_system
+    from synth.gnn_weights import default_gnn_file
+    s = config_system("chain40k")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(s.coords, device=dev)
+    T = torch.tensor(s.types, device=dev)
+    F = torch.empty((s.natoms, 3), dtype=torch.float64, device=dev)
+    V = torch.empty(9, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    out = {"workload": f"chain40k: seeded solvated chain, {s.natoms} atoms, periodic cubic {s.box[0, 0]:.2f} A box",
+           "model": "GNN variant: 3 layers over edges (rc 6 A, width 64) and angles (rca 4 A, width 32), "
+                    "node width 64, fitting 64-128-128-1, seeded random weights", "natoms": s.natoms}
+    for prec in ("bf16", "fp32"):
+        m = GnnModel(default_gnn_file(), precision=prec)
+        for _ in range(warmup):
+            m.compute_device(X, T, s.box, forces=F, virial=V, energy=E)
+        torch.cuda.synchronize()
+        m.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            m.compute_device(X, T, s.box, forces=F, virial=V, energy=E)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = m.profile_read()
+        m.profile(False)
+        ne, na = m.graph_size()
+        m.close()
+        fwd, bwd = gnn_flop(s.natoms, ne, na)
+        ph = {k: (ms / c if c else 0.0) for k, (ms, c) in prof.items()}
+        per_launch_ms = ph["layers_bwd"] / 3.0
+        achieved = (bwd / 3.0) / (per_launch_ms * 1e-3)
+        out.update(edges=ne, angles=na)
+        out[prec] = {
+            "value": s.natoms * steps / dt, "unit": "atom-evals/s", "ms_per_step": 1e3 * dt / steps, "steps": steps,
+            "phase_ms": ph,
+            "roofline": {"bound": "mfma", "kernel": "k_layer_bwd (three launches per step, one per layer)",
+                         "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK[prec], "avg_ms": per_launch_ms, "alg_flop_per_launch": bwd / 3.0,
+                         "traffic": None},
+            "step_roofline": {"alg_flop_per_step": fwd + bwd, "frac": (fwd + bwd) / (dt / steps) / PEAK[prec]},
+        }
+        print(f"[bench] GNN chain40k {prec}: {1e3 * dt / steps:.1f} ms/step -> {s.natoms * steps / dt:.4g} "
+              f"atom-evals/s; backward layer {per_launch_ms:.2f} ms = {achieved / 1e12:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def _cpu_worker(args):
@@ -286,6 +363,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving trace replayed at 200 req/s (0 = skip the serving run); "
                          "the first quarter of them is also replayed at 20 req/s")
+    ap.add_argument("--gnn-steps", type=int, default=5,
+                    help="steps of the GNN-variant model on the 40k-atom chain per precision (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -402,6 +481,8 @@ def main():
         out["serving"] = serving_bench(path, trace, systems_trace, legs, 16 << 30)
         r200 = out["serving"]["rates"]["200_req_per_s"]["bf16_server"]
         out["latency_p50_ms"], out["latency_p99_ms"] = r200["p50_ms"], r200["p99_ms"]
+    if args.gnn_steps > 0:
+        out["gnn"] = gnn_bench(args.gnn_steps, 1)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

@@ -306,7 +306,13 @@ int dp_nve_run(dp_model *m, int64_t natoms, double *d_coords, double *d_vel, con
  *   has finished on the stream.  A dp_gnn owns grow-only device buffers of about
  *   190 KB per atom and 512 bytes per angle; it is not thread-safe.
  * dp_gnn_info: rc, rca, sel, asel of the model (pointers may be NULL).
- * dp_gnn_angles: number of angles of the last successful step. */
+ * dp_gnn_graph_size: edges (sum of the list lengths) and angles of the last
+ *   successful step (pointers may be NULL).
+ * dp_gnn_profile_enable / dp_gnn_profile_read: per-phase device time from HIP events
+ *   on the step's stream, accumulated over calls since enabling (which clears it):
+ *   phase 0 lists (cell list, neighbour lists, angle offsets), 1 the three forward
+ *   layers with the fitting net, 2 the three backward layers, 3 forces and reductions.
+ *   read fills ms[k], calls[k] for k < min(max, 4) and returns that count. */
 typedef struct dp_gnn dp_gnn;
 int dp_gnn_load(const char *path, int precision, int device, dp_gnn **out);
 void dp_gnn_free(dp_gnn *m);
@@ -314,7 +320,9 @@ int dp_gnn_info(const dp_gnn *m, double *rc, double *rca, int *sel, int *asel);
 int dp_gnn_compute_device(dp_gnn *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
                           const double *box_host, double *d_energy, double *d_forces, double *d_virial,
                           double *d_atom_energy, void *hip_stream);
-int dp_gnn_angles(const dp_gnn *m, int64_t *angles);
+int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angles);
+int dp_gnn_profile_enable(dp_gnn *m, int enable);
+int dp_gnn_profile_read(const dp_gnn *m, double *ms, int64_t *calls, int max);
 
 /* Static description of a status code; never NULL. */
 const char *dp_status_string(int status);

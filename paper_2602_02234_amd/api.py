@@ -374,9 +374,25 @@ class GnnModel:
 
     def angles(self) -> int:
         """Angles of the last successful step."""
-        v = C.c_int64()
-        check(_lib.load().dp_gnn_angles(self._h, C.byref(v)), "dp_gnn_angles")
-        return int(v.value)
+        return self.graph_size()[1]
+
+    def graph_size(self):
+        """(edges, angles) of the last successful step."""
+        e, a = C.c_int64(), C.c_int64()
+        check(_lib.load().dp_gnn_graph_size(self._h, C.byref(e), C.byref(a)), "dp_gnn_graph_size")
+        return int(e.value), int(a.value)
+
+    PHASES = ("lists", "layers_fwd", "layers_bwd", "forces")
+
+    def profile(self, enable: bool = True):
+        check(_lib.load().dp_gnn_profile_enable(self._h, 1 if enable else 0), "dp_gnn_profile_enable")
+
+    def profile_read(self):
+        """{phase: (total ms, calls)} accumulated since profile(True)."""
+        ms = np.zeros(4)
+        calls = np.zeros(4, dtype=np.int64)
+        k = _lib.load().dp_gnn_profile_read(self._h, _ptr(ms), _ptr(calls), 4)
+        return {self.PHASES[i]: (float(ms[i]), int(calls[i])) for i in range(k)}
 
 
 def _autograd_function():

@@ -215,15 +215,27 @@ __global__ void __launch_bounds__(256) k_angle_count(const double *__restrict__ 
 
 // Inclusive prefix of aoff[1 .. n] in one workgroup: each thread sums a contiguous run,
 // the 1024 run totals are scanned, then each run is rewritten.
-__global__ void __launch_bounds__(1024) k_angle_scan(int64_t *__restrict__ aoff, int n) {
+// The same workgroup also writes the total edge count (sum of nnei) to *etot.
+__global__ void __launch_bounds__(1024) k_angle_scan(int64_t *__restrict__ aoff, const int *__restrict__ nnei, int n,
+                                                     int64_t *__restrict__ etot) {
   __shared__ int64_t part[1024];
+  __shared__ int64_t epart[1024];
   const int t = threadIdx.x;
   const int per = (n + 1023) / 1024;
   const int b0 = 1 + t * per, b1 = min(n + 1, b0 + per);
-  int64_t s = 0;
-  for (int k = b0; k < b1; ++k) s += aoff[k];
+  int64_t s = 0, se = 0;
+  for (int k = b0; k < b1; ++k) {
+    s += aoff[k];
+    se += min(max(nnei[k - 1], 0), SEL);
+  }
   part[t] = s;
+  epart[t] = se;
   __syncthreads();
+  if (t == 0) {
+    int64_t tot = 0;
+    for (int k = 0; k < 1024; ++k) tot += epart[k];
+    *etot = tot;
+  }
   for (int off = 1; off < 1024; off <<= 1) {
     const int64_t v = t >= off ? part[t - off] : 0;
     __syncthreads();
@@ -939,7 +951,7 @@ void launch_angle_offsets(const Buffers &b, const Workspace &ws, const double *c
                           hipStream_t st) {
   hipLaunchKernelGGL(k_angle_count, dim3((n + 255) / 256), dim3(256), 0, st, coords, ws.nlist, ws.nnei, ws.grids, n,
                      geo, b.aoff);
-  hipLaunchKernelGGL(k_angle_scan, dim3(1), dim3(1024), 0, st, b.aoff, n);
+  hipLaunchKernelGGL(k_angle_scan, dim3(1), dim3(1024), 0, st, b.aoff, ws.nnei, n, b.aoff + b.cap + 1);
 }
 
 template <typename T>

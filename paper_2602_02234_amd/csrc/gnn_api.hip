@@ -24,8 +24,15 @@ struct dp_gnn {
   gnn::Buffers b;
   double *fpark = nullptr;  // forces when only the virial is asked for
   int64_t fpark_cap = 0;
-  int64_t *tot_host = nullptr;
-  int64_t last_angles = 0;
+  int64_t *tot_host = nullptr;  // pinned: angles, edges
+  int64_t last_angles = 0, last_edges = 0;
+  // per-phase device time (dp_gnn_profile_enable): lists, forward layers, backward
+  // layers, forces and reductions
+  bool prof = false;
+  hipEvent_t ev[5] = {};
+  double prof_ms[4] = {};
+  int64_t prof_calls[4] = {};
+  double lists_ms = 0.0;
 };
 
 namespace {
@@ -169,7 +176,7 @@ int ensure_atoms(gnn::Buffers &b, int64_t n) {
   b.aoff = nullptr; b.nf = b.ef = b.de = b.dnj = b.dnl = b.gs = nullptr;
   b.cap = 0;
   const size_t c = (size_t)cap, e = c * SEL * EDIM;
-  G_TRY(hipMalloc(&b.aoff, (c + 1) * sizeof(int64_t)));
+  G_TRY(hipMalloc(&b.aoff, (c + 2) * sizeof(int64_t)));
   G_TRY(hipMalloc(&b.nf, 2 * c * NDIM * sizeof(float)));
   G_TRY(hipMalloc(&b.ef, 3 * e * sizeof(float)));
   G_TRY(hipMalloc(&b.de, e * sizeof(float)));
@@ -220,29 +227,39 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
   ws.off_host[1] = n;
   if (!open) G_TRY(hipMemcpyAsync(ws.grids, ws.grids_host, sizeof(Grid), hipMemcpyHostToDevice, st));
   G_TRY(hipMemcpyAsync(ws.sys_off, ws.off_host, 2 * sizeof(int), hipMemcpyHostToDevice, st));
+  if (m->prof) G_TRY(hipEventRecord(m->ev[0], st));
   launch_prologue(ws, 1, n, ncells + 1, true, st);
   launch_cells(ws, X, types, n, m->ntypes, open, ncells, m->rc, st);
   launch_nlist(ws, X, n, 0, n, n, m->rc, false, st);
   gnn::Geo geo{(float)m->rc, (float)m->rcs, (float)m->rca, 1.f / (float)m->sel, 1.f / (float)m->asel, m->asel};
   gnn::launch_angle_offsets(m->b, ws, X, n, geo, st);
   G_TRY(hipGetLastError());
+  if (m->prof) G_TRY(hipEventRecord(m->ev[1], st));
   // the angle count sizes the angle buffers: one host round trip per step
   G_TRY(hipMemcpyAsync(m->tot_host, m->b.aoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  G_TRY(hipMemcpyAsync(m->tot_host + 1, m->b.aoff + m->b.cap + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   G_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
   G_TRY(hipStreamSynchronize(st));
+  if (m->prof) {
+    float ms = 0.f;
+    m->lists_ms = hipEventElapsedTime(&ms, m->ev[0], m->ev[1]) == hipSuccess ? ms : 0.0;
+  }
   s = gnn_status(ws);
   if (s != DP_OK) return s;
-  const int64_t na = *m->tot_host;
+  const int64_t na = m->tot_host[0];
   m->last_angles = na;
+  m->last_edges = m->tot_host[1];
   s = ensure_angles(m->b, std::max<int64_t>(na, 1));
   if (s != DP_OK) return s;
   const bool bwd = forces || virial;
+  if (m->prof) G_TRY(hipEventRecord(m->ev[2], st));
   for (int l = 0; l < NLAYER; ++l) {
     if (m->prec == DP_BF16)
       gnn::launch_layer_fwd<bf16_t>(m->w, m->b, ws, X, types, n, l, geo, ws.Ei, st);
     else
       gnn::launch_layer_fwd<float>(m->w, m->b, ws, X, types, n, l, geo, ws.Ei, st);
   }
+  if (m->prof) G_TRY(hipEventRecord(m->ev[3], st));
   if (bwd) {
     for (int l = NLAYER - 1; l >= 0; --l) {
       if (m->prec == DP_BF16)
@@ -250,6 +267,9 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
       else
         gnn::launch_layer_bwd<float>(m->w, m->b, ws, X, types, n, l, geo, st);
     }
+  }
+  if (m->prof) G_TRY(hipEventRecord(m->ev[4], st));
+  if (bwd) {
     double *F = forces;
     if (!F) {
       if (m->fpark_cap < n) {
@@ -265,9 +285,23 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
   }
   launch_reduce(ws, ws.sys_off, 1, energy, atom_energy, virial, 1, st);
   G_TRY(hipGetLastError());
+  if (m->prof) G_TRY(hipEventRecord(m->ev[0], st));  // end of the last phase (ev[0] is free again)
   G_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
   G_TRY(hipStreamSynchronize(st));
-  return gnn_status(ws);
+  s = gnn_status(ws);
+  if (s >= 0 && m->prof) {
+    // phases: lists ev1 - (start), fwd ev3 - ev2, bwd ev4 - ev3, forces/reductions end - ev4
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m->ev[2], m->ev[3]) == hipSuccess) { m->prof_ms[1] += ms; m->prof_calls[1] += 1; }
+    if (bwd && hipEventElapsedTime(&ms, m->ev[3], m->ev[4]) == hipSuccess) {
+      m->prof_ms[2] += ms;
+      m->prof_calls[2] += 1;
+    }
+    if (hipEventElapsedTime(&ms, m->ev[4], m->ev[0]) == hipSuccess) { m->prof_ms[3] += ms; m->prof_calls[3] += 1; }
+    m->prof_ms[0] += m->lists_ms;
+    m->prof_calls[0] += 1;
+  }
+  return s;
 }
 
 }  // namespace
@@ -291,7 +325,7 @@ int dp_gnn_load(const char *path, int precision, int device, dp_gnn **out) {
   m->device = device;
   m->prec = precision;
   int s = load_weights(m, path);
-  if (s == DP_OK && hipHostMalloc(&m->tot_host, sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+  if (s == DP_OK && hipHostMalloc(&m->tot_host, 2 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
     set_error("dp_gnn_load: pinned allocation failed");
     s = DP_ERR_OOM;
   }
@@ -312,6 +346,8 @@ void dp_gnn_free(dp_gnn *m) {
   if (m->fpark) (void)hipFree(m->fpark);
   if (m->wbuf) (void)hipFree(m->wbuf);
   if (m->tot_host) (void)hipHostFree(m->tot_host);
+  for (auto &e : m->ev)
+    if (e) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -344,13 +380,43 @@ int dp_gnn_compute_device(dp_gnn *m, int64_t natoms, const double *d_coords, con
                   (hipStream_t)hip_stream);
 }
 
-int dp_gnn_angles(const dp_gnn *m, int64_t *angles) {
-  if (!m || !angles) {
-    set_error("dp_gnn_angles: bad argument");
+int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angles) {
+  if (!m) {
+    set_error("dp_gnn_graph_size: bad argument");
     return DP_ERR_ARG;
   }
-  *angles = m->last_angles;
+  if (edges) *edges = m->last_edges;
+  if (angles) *angles = m->last_angles;
   return DP_OK;
+}
+
+int dp_gnn_profile_enable(dp_gnn *m, int enable) {
+  if (!m) {
+    set_error("dp_gnn_profile_enable: bad argument");
+    return DP_ERR_ARG;
+  }
+  G_TRY(hipSetDevice(m->device));
+  if (enable && !m->ev[0])
+    for (auto &e : m->ev) G_TRY(hipEventCreate(&e));
+  m->prof = enable != 0;
+  for (int k = 0; k < 4; ++k) {
+    m->prof_ms[k] = 0.0;
+    m->prof_calls[k] = 0;
+  }
+  return DP_OK;
+}
+
+int dp_gnn_profile_read(const dp_gnn *m, double *ms, int64_t *calls, int max) {
+  if (!m || !ms || !calls || max < 0) {
+    set_error("dp_gnn_profile_read: bad argument");
+    return DP_ERR_ARG;
+  }
+  const int k = max < 4 ? max : 4;
+  for (int q = 0; q < k; ++q) {
+    ms[q] = m->prof_ms[q];
+    calls[q] = m->prof_calls[q];
+  }
+  return k;
 }
 
 }  // extern "C"
