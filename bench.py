@@ -123,7 +123,9 @@ def gnn_bench(steps, warmup):
             "roofline": {"bound": "mfma", "kernel": "k_layer_bwd (three launches per step, one per layer)",
                          "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
                          "frac": achieved / PEAK[prec], "avg_ms": per_launch_ms, "alg_flop_per_launch": bwd / 3.0,
-                         "traffic": None},
+                         "traffic": measured_traffic("layers_bwd", prec, "chain40k_gnn"),
+                         "executed_flop_per_launch": measured_traffic("layers_bwd", prec, "chain40k_gnn",
+                                                                      "mfma_flop_per_launch") if prec == "bf16" else None},
             "step_roofline": {"alg_flop_per_step": fwd + bwd, "frac": (fwd + bwd) / (dt / steps) / PEAK[prec]},
         }
         print(f"[bench] GNN chain40k {prec}: {1e3 * dt / steps:.1f} ms/step -> {s.natoms * steps / dt:.4g} "
