@@ -19,6 +19,9 @@ the potential; neighbour lists within a cutoff, Section II and IV):
   with several fitting heads on one descriptor;
 * :mod:`oracle.gnn` -- the GNN-variant descriptor (message passing over edges and
   angles, three layers) with its hand-written gradient;
+* :mod:`oracle.repformer` -- a repformer-style model (pair and node features, gated
+  self-attention over the neighbours' pair features, neighbour-to-neighbour message
+  passing, three layers) with its hand-written gradient;
 * :mod:`oracle.nve` -- a velocity-Verlet driver for the energy-drift check.
 
 The paper prints no model equations; the functional form follows the reading
