@@ -324,6 +324,38 @@ int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angles);
 int dp_gnn_profile_enable(dp_gnn *m, int enable);
 int dp_gnn_profile_read(const dp_gnn *m, double *ms, int64_t *calls, int max);
 
+/* ---------------------------------------------------------------------------
+ * Repformer-style model (paper, Section II: the DPA2 family, whose layers update a
+ * single-atom and a pair representation and pass messages from neighbour to
+ * neighbour, so the receptive field grows by rc per layer).
+ * Model: node features g1 (64) per atom and pair features g2 (32) per edge (j in
+ * the rc list of i); three layers, each: the pair update from the neighbour's g1,
+ * a switch-gated self-attention over i's pair features (one head, width 32,
+ * weights sw_k exp(Q_j.K_k / sqrt 32) normalised, times rhat_j.rhat_k), and the
+ * node update from the contraction T T[:4]^T (T = sum_j g2_ij R_ij^T / sel) and
+ * the convolution sum_j sw_ij g2_ij * g1_j[:32] / sel; fitting 64 -> 128 -> 128
+ * -> 1 on g1; E = sum E_i.  Model file: magic DPREPv01 (128-byte header of sizes,
+ * rc, rcs, then the float64 arrays); node/pair widths 64/32, 4 axis columns,
+ * three layers, fitting width 128, sel = 120, ntypes = 5.  Float32 arithmetic.
+ *
+ * dp_rep_compute_device: arguments, units and outputs as dp_compute_device.  Lists
+ *   must be complete (more than sel neighbours within rc: DP_ERR_TOO_LARGE).
+ *   Returns after the step has finished on the stream.  A dp_rep owns grow-only
+ *   device buffers of about 120 KB per atom; it is not thread-safe.
+ * dp_rep_edges: edges (sum of the list lengths) of the last successful step.
+ * dp_rep_profile_enable / dp_rep_profile_read: per-phase device time as for the GNN
+ *   model (0 lists, 1 forward layers with the fitting net, 2 backward layers, 3
+ *   forces and reductions). */
+typedef struct dp_rep dp_rep;
+int dp_rep_load(const char *path, int device, dp_rep **out);
+void dp_rep_free(dp_rep *m);
+int dp_rep_compute_device(dp_rep *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
+                          const double *box_host, double *d_energy, double *d_forces, double *d_virial,
+                          double *d_atom_energy, void *hip_stream);
+int dp_rep_edges(const dp_rep *m, int64_t *edges);
+int dp_rep_profile_enable(dp_rep *m, int enable);
+int dp_rep_profile_read(const dp_rep *m, double *ms, int64_t *calls, int max);
+
 /* Static description of a status code; never NULL. */
 const char *dp_status_string(int status);
 /* Thread-local detail of the last failure in this thread ("" if none). */

@@ -395,6 +395,86 @@ class GnnModel:
         return {self.PHASES[i]: (float(ms[i]), int(calls[i])) for i in range(k)}
 
 
+class RepModel:
+    """A repformer-style model file (pair and node features, gated self-attention over
+    the neighbours' pair features, neighbour-to-neighbour message passing) on one GPU,
+    float32."""
+
+    PHASES = ("lists", "layers_fwd", "layers_bwd", "forces")
+
+    def __init__(self, path: str, device: int = 0):
+        lib = _lib.load()
+        h = C.c_void_p()
+        check(lib.dp_rep_load(path.encode(), device, C.byref(h)), "dp_rep_load")
+        self._h = h
+        self.device = device
+        self.last_status = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().dp_rep_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compute_device(self, coords, types, box=None, forces=None, virial=None, energy=None, atom_energy=None,
+                       stream=None):
+        """Evaluate on torch CUDA tensors (float64 coords [N][3], int32 types [N]); outputs written in place."""
+        import torch
+        n = coords.shape[0]
+        assert coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
+        assert types.is_cuda and types.dtype == torch.int32 and types.is_contiguous()
+        if energy is None:
+            energy = torch.empty(1, dtype=torch.float64, device=coords.device)
+        s = stream if stream is not None else torch.cuda.current_stream(coords.device).cuda_stream
+        b = _box9(box)
+
+        def dp(t):
+            return C.c_void_p(t.data_ptr()) if t is not None else None
+
+        st = _lib.load().dp_rep_compute_device(self._h, n, dp(coords), dp(types), _ptr(b), dp(energy), dp(forces),
+                                               dp(virial), dp(atom_energy), C.c_void_p(s))
+        self.last_status = check(st, "dp_rep_compute_device")
+        return energy
+
+    def compute(self, coords, types, box=None, forces: bool = True, atom_energy: bool = False):
+        """E, F, virial (and E_i) from host arrays, through device copies made with torch."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        X = torch.tensor(np.ascontiguousarray(coords, dtype=np.float64), device=dev)
+        T = torch.tensor(np.ascontiguousarray(types, dtype=np.int32), device=dev)
+        n = X.shape[0]
+        F = torch.zeros((n, 3), dtype=torch.float64, device=dev) if forces else None
+        V = torch.zeros(9, dtype=torch.float64, device=dev) if forces else None
+        AE = torch.zeros(n, dtype=torch.float64, device=dev) if atom_energy else None
+        E = self.compute_device(X, T, box, forces=F, virial=V, atom_energy=AE)
+        torch.cuda.synchronize(dev)
+        out = {"E": float(E.item())}
+        if forces:
+            out["F"], out["virial"] = F.cpu().numpy(), V.cpu().numpy().reshape(3, 3)
+        if atom_energy:
+            out["E_i"] = AE.cpu().numpy()
+        return out
+
+    def edges(self) -> int:
+        v = C.c_int64()
+        check(_lib.load().dp_rep_edges(self._h, C.byref(v)), "dp_rep_edges")
+        return int(v.value)
+
+    def profile(self, enable: bool = True):
+        check(_lib.load().dp_rep_profile_enable(self._h, 1 if enable else 0), "dp_rep_profile_enable")
+
+    def profile_read(self):
+        ms = np.zeros(4)
+        calls = np.zeros(4, dtype=np.int64)
+        k = _lib.load().dp_rep_profile_read(self._h, _ptr(ms), _ptr(calls), 4)
+        return {self.PHASES[i]: (float(ms[i]), int(calls[i])) for i in range(k)}
+
+
 def _autograd_function():
     import torch
 

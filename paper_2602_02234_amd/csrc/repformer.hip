@@ -1,0 +1,617 @@
+// Repformer-style model kernels for gfx950: one workgroup (four waves) per centre atom
+// and one launch per layer, forward and backward (a layer's pair update and convolution
+// read the neighbours' g1 of the layer before, so layers meet at launch boundaries).
+// The products are small (pair width 32, at most 120 neighbours, node input 224), so
+// they run as float32 VALU dot products from LDS with a fixed summation order; the
+// attention is evaluated one query row per wave (scores for two keys per lane), and
+// its backward in a row pass (dQ, row terms of the gate) and a column pass (dK, dV and
+// the key terms of the switch and gate, with the scores recomputed), like the
+// attention descriptor.  Every sum has one owner and a fixed order: results are
+// deterministic.
+#include <cmath>
+
+#include "dp_env.h"
+#include "repformer.h"
+
+namespace dp {
+namespace rep {
+namespace {
+
+constexpr int NWG = 4;
+constexpr int NT = NWG * 64;
+constexpr int LQ = G2D + 1;   // row stride of [edge][32] LDS arrays (odd: rows fall in different banks)
+constexpr int LG = G1D + 1;   // row stride of [edge][64]
+
+__device__ __forceinline__ bool failed(const unsigned *flags) { return (flags[0] & FLAG_ERRORS) != 0u; }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterfly sum / max over the 64 lanes: the same value in every lane.
+__device__ __forceinline__ float wsum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float wmax(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+struct EnvR {
+  float r[SEL], sw[SEL], dsw[SEL], s[SEL], rh[SEL * 3];
+  int jn[SEL], tj[SEL];
+  int nn;
+};
+
+__device__ void build_env_r(EnvR &e, const double *__restrict__ X, const int *__restrict__ types,
+                            const int *__restrict__ nlist, const int *__restrict__ nnei, int i, int n, const Grid &g,
+                            const Geo &geo) {
+  const int nn = min(max(nnei[i], 0), SEL);
+  for (int j = threadIdx.x; j < SEL; j += NT) {
+    float r = 1.f, sw = 0.f, dsw = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+    int nj = i, tj = 0;
+    if (j < nn) {
+      nj = nlist[(size_t)i * SEL + j];
+      if (nj < 0 || nj >= n) nj = i;
+      tj = clamp_type(types[nj]);
+      double d[3];
+      for (int a = 0; a < 3; ++a) {
+        double v = X[3 * nj + a] - X[3 * i + a];
+        if (g.periodic) v -= g.L[a] * rint(v * g.invL[a]);
+        d[a] = v;
+      }
+      const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+      r = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float u = (r - geo.rcs) / (geo.rc - geo.rcs);
+      if (r < geo.rcs) {
+        sw = 1.f;
+      } else if (r < geo.rc) {
+        sw = u * u * u * (-6.f * u * u + 15.f * u - 10.f) + 1.f;
+        dsw = -30.f * u * u * (1.f - u) * (1.f - u) / (geo.rc - geo.rcs);
+      }
+      hx = dx / r; hy = dy / r; hz = dz / r;
+    }
+    e.r[j] = r; e.sw[j] = sw; e.dsw[j] = dsw; e.s[j] = sw / r;
+    e.rh[3 * j] = hx; e.rh[3 * j + 1] = hy; e.rh[3 * j + 2] = hz;
+    e.jn[j] = nj; e.tj[j] = tj;
+  }
+  if (threadIdx.x == 0) e.nn = nn;
+  __syncthreads();
+}
+
+__device__ __forceinline__ float gate(const EnvR &e, int j, int k) {
+  return e.rh[3 * j] * e.rh[3 * k] + e.rh[3 * j + 1] * e.rh[3 * k + 1] + e.rh[3 * j + 2] * e.rh[3 * k + 2];
+}
+__device__ __forceinline__ float Rcomp(const EnvR &e, int j, int a) { return a == 0 ? e.s[j] : e.s[j] * e.rh[3 * j + a - 1]; }
+
+__device__ __forceinline__ size_t erow2(const Buffers &b, int l, int i, int j) {
+  return (((size_t)l * b.cap + i) * SEL + j) * G2D;
+}
+
+// Layer input of atom i's features: g1 of the neighbours (G1J), g2 of its edges (G2) and
+// its own g1 (g1i).
+__device__ void load_inputs(const Weights &w, const Buffers &b, const EnvR &e, const int *types, int i, int l,
+                            float *G1J, float *G2, float *g1i) {
+  const int nn = e.nn;
+  for (int k = threadIdx.x; k < nn * G1D; k += NT) {
+    const int j = k >> 6, c = k & 63;
+    G1J[j * LG + c] = l == 0 ? w.TN[e.tj[j] * G1D + c] : b.g1f[((size_t)(l - 1) * b.cap + e.jn[j]) * G1D + c];
+  }
+  for (int k = threadIdx.x; k < nn * G2D; k += NT) {
+    const int j = k >> 5, c = k & 31;
+    G2[j * LQ + c] = l == 0 ? tanhf(e.s[j] * w.Wp0[c] + w.bp0[c]) : b.g2f[erow2(b, l - 1, i, j) + c];
+  }
+  if (threadIdx.x < G1D)
+    g1i[threadIdx.x] = l == 0 ? w.TN[clamp_type(types[i]) * G1D + threadIdx.x]
+                              : b.g1f[((size_t)(l - 1) * b.cap + i) * G1D + threadIdx.x];
+}
+
+// Pair update and projections: G2A = G2 + tanh([G2, G1J] Wa + ba) (TA = the tanh term,
+// written over G2 when `keep_ta`), Q, K, V = G2A Wq, Wk, Wv.  Ends synchronised.
+__device__ void pair_and_qkv(const Weights &w, int l, int nn, float *G2, const float *G1J, float *G2A, float *Q,
+                             float *K, float *V, bool keep_ta) {
+  const float *Wa = w.Wa[l], *ba = w.ba[l];
+  constexpr int PER = (SEL * G2D + NT - 1) / NT;
+  float ta[PER];
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int o = threadIdx.x + NT * it, j = o >> 5, c = o & 31;
+    ta[it] = 0.f;
+    if (j < nn) {
+      float z = ba[c];
+      for (int q = 0; q < G2D; ++q) z += G2[j * LQ + q] * Wa[q * G2D + c];
+      for (int q = 0; q < G1D; ++q) z += G1J[j * LG + q] * Wa[(G2D + q) * G2D + c];
+      ta[it] = tanhf(z);
+      G2A[j * LQ + c] = G2[j * LQ + c] + ta[it];
+    }
+  }
+  __syncthreads();
+  if (keep_ta)
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int o = threadIdx.x + NT * it, j = o >> 5, c = o & 31;
+      if (j < nn) G2[j * LQ + c] = ta[it];
+    }
+  const float *Wq = w.Wq[l], *Wk = w.Wk[l], *Wv = w.Wv[l];
+  for (int o = threadIdx.x; o < nn * G2D; o += NT) {
+    const int j = o >> 5, c = o & 31;
+    float q = 0.f, k = 0.f, v = 0.f;
+    for (int t = 0; t < G2D; ++t) {
+      const float x = G2A[j * LQ + t];
+      q += x * Wq[t * G2D + c];
+      k += x * Wk[t * G2D + c];
+      v += x * Wv[t * G2D + c];
+    }
+    Q[j * LQ + c] = q;
+    K[j * LQ + c] = k;
+    V[j * LQ + c] = v;
+  }
+  __syncthreads();
+}
+
+// T = sum_j g2_j R_j^T / sel (into T[32][4]), c = sum_j sw_j g2_j g1_j[:32] / sel, and the
+// node-update input xs = [g1i, D, c] with D = T T[:4]^T.  Ends synchronised.
+__device__ void node_inputs(const EnvR &e, int nn, const float *G2B, const float *G1J, const float *g1i,
+                            float inv_sel, float *T, float *xs) {
+  const int t = threadIdx.x;
+  if (t < G2D * 4) {
+    const int c = t >> 2, a = t & 3;
+    float v = 0.f;
+    for (int j = 0; j < nn; ++j) v += G2B[j * LQ + c] * Rcomp(e, j, a);
+    T[t] = v * inv_sel;
+  } else if (t < G2D * 4 + G2D) {
+    const int c = t - G2D * 4;
+    float v = 0.f;
+    for (int j = 0; j < nn; ++j) v += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
+    xs[G1D + G2D * NAX + c] = v * inv_sel;
+  } else if (t < G2D * 4 + G2D + G1D) {
+    const int c = t - G2D * 5;
+    xs[c] = g1i[c];
+  }
+  __syncthreads();
+  if (t < G2D * NAX) {
+    const int c = t >> 2, bb = t & 3;  // D[c][b], flattened c * 4 + b
+    float v = 0.f;
+    for (int a = 0; a < 4; ++a) v += T[c * 4 + a] * T[bb * 4 + a];
+    xs[G1D + t] = v;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ forward
+struct SmemF {
+  EnvR env;
+  float G1J[SEL * LG];
+  float G2[SEL * LQ];   // layer input, then the layer's output g2
+  float G2A[SEL * LQ];
+  float Q[SEL * LQ], K[SEL * LQ], V[SEL * LQ];
+  float arow[NWG][SEL];
+  float g1i[G1D], T[G2D * 4], xs[XD];
+  float y1[FWID], t2[FWID], dp[FWID];
+};
+
+__global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const double *__restrict__ X,
+                                                const int *__restrict__ types, const int *__restrict__ nlist,
+                                                const int *__restrict__ nnei, const Grid *__restrict__ grids, int n,
+                                                int l, Geo geo, double *__restrict__ Ei,
+                                                const unsigned *__restrict__ flags) {
+  __shared__ SmemF sm;
+  const int i = blockIdx.x;
+  if (i >= n || failed(flags)) return;
+  const int tid = threadIdx.x, wv = wave_id(), ln = lane_id();
+  build_env_r(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
+  const EnvR &e = sm.env;
+  const int nn = e.nn;
+  load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i);
+  __syncthreads();
+  pair_and_qkv(w, l, nn, sm.G2, sm.G1J, sm.G2A, sm.Q, sm.K, sm.V, false);
+
+  // attention, one query row per wave
+  const float isq = 1.f / sqrtf((float)G2D);
+  const int half = (nn + 1) >> 1;
+  for (int j = wv; j < nn; j += NWG) {
+    float sc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      sc[h] = -INFINITY;
+      if (k < nn) {
+        float d = 0.f;
+        for (int c = 0; c < G2D; ++c) d += sm.Q[j * LQ + c] * sm.K[k * LQ + c];
+        sc[h] = d * isq;
+      }
+    }
+    const float m = wmax(fmaxf(sc[0], sc[1]));
+    float ex[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      ex[h] = k < nn ? e.sw[k] * expf(sc[h] - m) : 0.f;
+    }
+    const float Z = wsum(ex[0] + ex[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      if (k < nn) sm.arow[wv][k] = ex[h] / Z * gate(e, j, k);
+    }
+    wave_sync();
+    // Y_j[c]: lanes c and c + 32 take the two halves of k, in order
+    const int c = ln & 31;
+    const int k0 = ln < 32 ? 0 : half, k1 = ln < 32 ? half : nn;
+    float y = 0.f;
+    for (int k = k0; k < k1; ++k) y += sm.arow[wv][k] * sm.V[k * LQ + c];
+    y += __shfl_xor(y, 32);
+    if (ln < 32) {
+      const float g2b = sm.G2A[j * LQ + c] + y;
+      sm.G2[j * LQ + c] = g2b;
+      b.g2f[erow2(b, l, i, j) + c] = g2b;
+    }
+    wave_sync();
+  }
+  __syncthreads();
+
+  node_inputs(e, nn, sm.G2, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs);
+  float g1n = 0.f;
+  if (tid < G1D) {
+    float z = w.b1[l][tid];
+    for (int q = 0; q < XD; ++q) z += sm.xs[q] * w.W1[l][q * G1D + tid];
+    g1n = sm.g1i[tid] + tanhf(z);
+    if (l < NLAYER - 1) b.g1f[((size_t)l * b.cap + i) * G1D + tid] = g1n;
+  }
+  if (l < NLAYER - 1) return;
+
+  // fitting net, E_i and dE/dg1_i
+  __syncthreads();
+  if (tid < G1D) sm.g1i[tid] = g1n;
+  __syncthreads();
+  if (tid < FWID) {
+    float z = w.d1[tid];
+    for (int k = 0; k < G1D; ++k) z += sm.g1i[k] * w.G1[k * FWID + tid];
+    sm.y1[tid] = tanhf(z);
+  }
+  __syncthreads();
+  if (tid < FWID) {
+    float z = w.d2[tid];
+    for (int k = 0; k < FWID; ++k) z += sm.y1[k] * w.G2[k * FWID + tid];
+    const float t2 = tanhf(z);
+    sm.t2[tid] = t2;
+    sm.dp[tid] = w.G3[tid] * (1.f - t2 * t2);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double E = w.d3;
+    for (int k = 0; k < FWID; ++k) E += (double)(sm.t2[k] + sm.y1[k]) * w.G3d[k];
+    Ei[i] = E;
+  }
+  float dp1 = 0.f;
+  if (tid < FWID) {
+    float dy1 = w.G3[tid];
+    for (int k = 0; k < FWID; ++k) dy1 += sm.dp[k] * w.G2[tid * FWID + k];
+    dp1 = dy1 * (1.f - sm.y1[tid] * sm.y1[tid]);
+  }
+  __syncthreads();
+  if (tid < FWID) sm.dp[tid] = dp1;
+  __syncthreads();
+  if (tid < G1D) {
+    float dn = 0.f;
+    for (int k = 0; k < FWID; ++k) dn += sm.dp[k] * w.G1[tid * FWID + k];
+    b.dnl[(size_t)i * G1D + tid] = dn;
+  }
+}
+
+// ------------------------------------------------------------------ backward
+struct SmemB {
+  EnvR env;
+  float G1J[SEL * LG];
+  float G2[SEL * LQ];    // layer input g2, then the pair update's tanh term
+  float G2A[SEL * LQ];   // after the pair update; later dE/dg2a
+  float Q[SEL * LQ], K[SEL * LQ], V[SEL * LQ];
+  float G2B[SEL * LQ];   // the layer's output g2
+  float DY[SEL * LQ];    // dE/dg2 of the output; later the pair update's dz
+  float EG[SEL * GSN];   // per-edge dE/ds, dE/dsw, dE/drhat
+  float stat[3][SEL];    // per query row: max score, normaliser, rho
+  float arow[NWG][2][SEL];
+  float qrow[NWG][2 * G2D];
+  float g1i[G1D], T[G2D * 4], xs[XD], dg1[G1D], dxn[XD], dT[G2D * 4], part[NWG][G1D];
+  int slot[SEL];
+};
+
+__global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const double *__restrict__ X,
+                                                const int *__restrict__ types, const int *__restrict__ nlist,
+                                                const int *__restrict__ nnei, const Grid *__restrict__ grids, int n,
+                                                int l, Geo geo, float4 *__restrict__ gout,
+                                                const unsigned *__restrict__ flags) {
+  __shared__ SmemB sm;
+  const int i = blockIdx.x;
+  if (i >= n || failed(flags)) return;
+  const int tid = threadIdx.x, wv = wave_id(), ln = lane_id();
+  const bool top = l == NLAYER - 1;
+  build_env_r(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
+  const EnvR &e = sm.env;
+  const int nn = e.nn;
+  load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i);
+  for (int k = tid; k < nn * G2D; k += NT) {
+    const int j = k >> 5, c = k & 31;
+    sm.G2B[j * LQ + c] = b.g2f[erow2(b, l, i, j) + c];
+    sm.DY[j * LQ + c] = top ? 0.f : b.dg2[((size_t)i * SEL + j) * G2D + c];
+  }
+  for (int k = tid; k < nn * GSN; k += NT) sm.EG[k] = top ? 0.f : b.gs[(size_t)i * SEL * GSN + k];
+  if (!top)
+    for (int j = tid; j < nn; j += NT) {
+      const int nj = e.jn[j];
+      const int len = min(max(nnei[nj], 0), SEL);
+      const int *row = nlist + (size_t)nj * SEL;
+      int lo = 0, hi = len - 1, s = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = row[mid];
+        if (x == i) { s = mid; break; }
+        if (x < i) lo = mid + 1; else hi = mid - 1;
+      }
+      sm.slot[j] = s;
+    }
+  __syncthreads();
+  {  // dE/dg1_i after this layer: own part + the neighbours' edge parts, rows by wave, waves in order
+    float v = 0.f;
+    if (!top) {
+      const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * G1D;
+      for (int j = wv; j < nn; j += NWG)
+        if (sm.slot[j] >= 0) v += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * G1D + ln];
+    }
+    sm.part[wv][ln] = v;
+  }
+  __syncthreads();
+  if (tid < G1D) {
+    float v = b.dnl[(size_t)i * G1D + tid];
+    for (int u = 0; u < NWG; ++u) v += sm.part[u][tid];
+    sm.dg1[tid] = v;
+  }
+  // recompute the layer's forward: pair update (tanh term kept in G2), projections, node input
+  pair_and_qkv(w, l, nn, sm.G2, sm.G1J, sm.G2A, sm.Q, sm.K, sm.V, true);
+  node_inputs(e, nn, sm.G2B, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs);
+  // node backward: dz = dg1 (1 - t^2), dxn = W1 dz
+  if (tid < G1D) {
+    float z = w.b1[l][tid];
+    for (int q = 0; q < XD; ++q) z += sm.xs[q] * w.W1[l][q * G1D + tid];
+    const float t = tanhf(z);
+    sm.part[0][tid] = sm.dg1[tid] * (1.f - t * t);
+  }
+  __syncthreads();
+  if (tid < XD) {
+    float v = 0.f;
+    for (int k = 0; k < G1D; ++k) v += sm.part[0][k] * w.W1[l][tid * G1D + k];
+    sm.dxn[tid] = v;
+  }
+  __syncthreads();
+  // dT from dD = dxn[64:192] (D[c][b] = sum_a T[c][a] T[b][a], b < 4), then / sel
+  if (tid < G2D * 4) {
+    const int c = tid >> 2, a = tid & 3;
+    float v = 0.f;
+    for (int bb = 0; bb < 4; ++bb) v += sm.dxn[G1D + c * 4 + bb] * sm.T[bb * 4 + a];
+    if (c < 4)
+      for (int m = 0; m < G2D; ++m) v += sm.dxn[G1D + m * 4 + c] * sm.T[m * 4 + a];
+    sm.dT[tid] = v * geo.inv_sel;
+  }
+  __syncthreads();
+  const float *dc = sm.dxn + G1D + G2D * NAX;  // dE/dc (times sel: divided where used)
+  // dE/dg2 of the output from the contraction and the convolution; edge terms of R and sw
+  for (int o = tid; o < nn * G2D; o += NT) {
+    const int j = o >> 5, c = o & 31;
+    float v = sm.DY[j * LQ + c] + e.sw[j] * dc[c] * geo.inv_sel * sm.G1J[j * LG + c];
+    for (int a = 0; a < 4; ++a) v += sm.dT[c * 4 + a] * Rcomp(e, j, a);
+    sm.DY[j * LQ + c] = v;
+  }
+  for (int j = tid; j < nn; j += NT) {
+    float dR[4] = {0.f, 0.f, 0.f, 0.f}, dswc = 0.f;
+    for (int c = 0; c < G2D; ++c) {
+      const float g = sm.G2B[j * LQ + c];
+      for (int a = 0; a < 4; ++a) dR[a] += sm.dT[c * 4 + a] * g;
+      dswc += dc[c] * geo.inv_sel * g * sm.G1J[j * LG + c];
+    }
+    float *eg = sm.EG + j * GSN;
+    eg[0] += dR[0] + dR[1] * e.rh[3 * j] + dR[2] * e.rh[3 * j + 1] + dR[3] * e.rh[3 * j + 2];
+    eg[1] += dswc;
+    for (int a = 0; a < 3; ++a) eg[2 + a] += e.s[j] * dR[1 + a];
+  }
+  __syncthreads();
+
+  // attention backward, row pass: one query row j per wave
+  const float isq = 1.f / sqrtf((float)G2D);
+  const int half = (nn + 1) >> 1;
+  for (int j = wv; j < nn; j += NWG) {
+    float sc[2], P[2], gt[2], dP[2], dGt[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      sc[h] = -INFINITY;
+      if (k < nn) {
+        float d = 0.f;
+        for (int c = 0; c < G2D; ++c) d += sm.Q[j * LQ + c] * sm.K[k * LQ + c];
+        sc[h] = d * isq;
+      }
+    }
+    const float m = wmax(fmaxf(sc[0], sc[1]));
+    float ex[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      ex[h] = k < nn ? e.sw[k] * expf(sc[h] - m) : 0.f;
+    }
+    const float Z = wsum(ex[0] + ex[1]);
+    float rho = 0.f, hr[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      P[h] = ex[h] / Z;
+      dP[h] = dGt[h] = gt[h] = 0.f;
+      if (k < nn) {
+        gt[h] = gate(e, j, k);
+        float dA = 0.f;
+        for (int c = 0; c < G2D; ++c) dA += sm.DY[j * LQ + c] * sm.V[k * LQ + c];
+        dP[h] = dA * gt[h];
+        dGt[h] = dA * P[h];
+        rho += dP[h] * P[h];
+        for (int a = 0; a < 3; ++a) hr[a] += dGt[h] * e.rh[3 * k + a];
+      }
+    }
+    rho = wsum(rho);
+    for (int a = 0; a < 3; ++a) hr[a] = wsum(hr[a]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = ln + 64 * h;
+      if (k < nn) sm.arow[wv][0][k] = P[h] * (dP[h] - rho) * isq;  // dS_jk
+    }
+    if (ln == 0) {
+      sm.stat[0][j] = m;
+      sm.stat[1][j] = Z;
+      sm.stat[2][j] = rho;
+      for (int a = 0; a < 3; ++a) sm.EG[j * GSN + 2 + a] += hr[a];
+    }
+    wave_sync();
+    const int c = ln & 31;
+    const int k0 = ln < 32 ? 0 : half, k1 = ln < 32 ? half : nn;
+    float dq = 0.f;
+    for (int k = k0; k < k1; ++k) dq += sm.arow[wv][0][k] * sm.K[k * LQ + c];
+    dq += __shfl_xor(dq, 32);
+    if (ln < 32) sm.qrow[wv][c] = dq;
+    wave_sync();
+    if (ln < 32) {
+      float v = sm.DY[j * LQ + c];
+      for (int q = 0; q < G2D; ++q) v += sm.qrow[wv][q] * w.Wq[l][c * G2D + q];
+      sm.G2A[j * LQ + c] = v;  // dE/dg2a, row terms
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  // column pass: one key k per wave, scores recomputed against every query row
+  for (int k = wv; k < nn; k += NWG) {
+    float dsk = 0.f, hk[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = ln + 64 * h;
+      if (j < nn) {
+        float d = 0.f, dA = 0.f;
+        for (int c = 0; c < G2D; ++c) {
+          d += sm.Q[j * LQ + c] * sm.K[k * LQ + c];
+          dA += sm.DY[j * LQ + c] * sm.V[k * LQ + c];
+        }
+        const float exz = expf(d * isq - sm.stat[0][j]) / sm.stat[1][j];
+        const float P = e.sw[k] * exz, gt = gate(e, j, k);
+        const float dP = dA * gt, dGt = dA * P, rho = sm.stat[2][j];
+        sm.arow[wv][0][j] = P * gt;                 // A_jk
+        sm.arow[wv][1][j] = P * (dP - rho) * isq;   // dS_jk
+        dsk += exz * (dP - rho);
+        for (int a = 0; a < 3; ++a) hk[a] += dGt * e.rh[3 * j + a];
+      }
+    }
+    dsk = wsum(dsk);
+    for (int a = 0; a < 3; ++a) hk[a] = wsum(hk[a]);
+    if (ln == 0) {
+      sm.EG[k * GSN + 1] += dsk;
+      for (int a = 0; a < 3; ++a) sm.EG[k * GSN + 2 + a] += hk[a];
+    }
+    wave_sync();
+    // lanes 0..31: dV_k[c] = sum_j A_jk dY_j[c]; lanes 32..63: dK_k[c] = sum_j dS_jk Q_j[c]
+    const int c = ln & 31;
+    float v = 0.f;
+    if (ln < 32)
+      for (int j = 0; j < nn; ++j) v += sm.arow[wv][0][j] * sm.DY[j * LQ + c];
+    else
+      for (int j = 0; j < nn; ++j) v += sm.arow[wv][1][j] * sm.Q[j * LQ + c];
+    sm.qrow[wv][ln] = v;
+    wave_sync();
+    if (ln < 32) {
+      float u = sm.G2A[k * LQ + c];
+      for (int q = 0; q < G2D; ++q)
+        u += sm.qrow[wv][q] * w.Wv[l][c * G2D + q] + sm.qrow[wv][G2D + q] * w.Wk[l][c * G2D + q];
+      sm.G2A[k * LQ + c] = u;  // dE/dg2a, complete
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  // pair update backward: dz = dE/dg2a (1 - ta^2) into DY
+  for (int o = tid; o < nn * G2D; o += NT) {
+    const int j = o >> 5, c = o & 31;
+    const float ta = sm.G2[j * LQ + c];
+    sm.DY[j * LQ + c] = sm.G2A[j * LQ + c] * (1.f - ta * ta);
+  }
+  __syncthreads();
+  // dxa = Wa dz: the first 32 go to dE/dg2 of the layer input, the other 64 (with the
+  // convolution's term) to the edge's part of dE/dg1_j
+  float *dnj = b.dnj + (size_t)(l & 1) * b.cap * SEL * G1D;
+  for (int o = tid; o < nn * (G2D + G1D); o += NT) {
+    const int j = o / (G2D + G1D), q = o % (G2D + G1D);
+    float v = 0.f;
+    for (int c = 0; c < G2D; ++c) v += sm.DY[j * LQ + c] * w.Wa[l][q * G2D + c];
+    if (q < G2D) {
+      const float dg2in = sm.G2A[j * LQ + q] + v;
+      if (l > 0) b.dg2[((size_t)i * SEL + j) * G2D + q] = dg2in;
+      else sm.V[j * LQ + q] = dg2in;  // kept for the initial-feature gradient below
+    } else if (l > 0) {
+      const int c1 = q - G2D;
+      if (c1 < G2D) v += e.sw[j] * dc[c1] * geo.inv_sel * sm.G2B[j * LQ + c1];
+      dnj[((size_t)i * SEL + j) * G1D + c1] = v;
+    }
+  }
+  if (l > 0) {
+    if (tid < G1D) {
+      float v = sm.dg1[tid] + sm.dxn[tid];
+      b.dnl[(size_t)i * G1D + tid] = v;
+    }
+    for (int k = tid; k < nn * GSN; k += NT) b.gs[(size_t)i * SEL * GSN + k] = sm.EG[k];
+    return;
+  }
+  __syncthreads();
+  // layer 0: g2 = tanh(s Wp0 + bp0) adds to dE/ds; then g_ij = dE/dDelta_ij
+  for (int j = tid; j < nn; j += NT) {
+    float ds = sm.EG[j * GSN];
+    for (int c = 0; c < G2D; ++c) {
+      const float g0 = tanhf(e.s[j] * w.Wp0[c] + w.bp0[c]);
+      ds += sm.V[j * LQ + c] * (1.f - g0 * g0) * w.Wp0[c];
+    }
+    const float rr = e.r[j], sw = e.sw[j];
+    const float dr = ds * (e.dsw[j] / rr - sw / (rr * rr)) + sm.EG[j * GSN + 1] * e.dsw[j];
+    const float hx = e.rh[3 * j], hy = e.rh[3 * j + 1], hz = e.rh[3 * j + 2];
+    const float gx = sm.EG[j * GSN + 2], gy = sm.EG[j * GSN + 3], gz = sm.EG[j * GSN + 4];
+    const float proj = gx * hx + gy * hy + gz * hz;
+    gout[(size_t)i * SEL + j] = make_float4((gx - proj * hx) / rr + dr * hx, (gy - proj * hy) / rr + dr * hy,
+                                            (gz - proj * hz) / rr + dr * hz, 0.f);
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_edge_count(const int *__restrict__ nnei, int n, int64_t *__restrict__ etot) {
+  __shared__ int64_t part[1024];
+  int64_t s = 0;
+  for (int k = threadIdx.x; k < n; k += 1024) s += min(max(nnei[k], 0), SEL);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int k = 0; k < 1024; ++k) t += part[k];
+    *etot = t;
+  }
+}
+
+}  // namespace
+
+void launch_edge_count(const Buffers &b, const Workspace &ws, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_edge_count, dim3(1), dim3(1024), 0, st, ws.nnei, n, b.etot);
+}
+
+void launch_layer_fwd(const Weights &w, const Buffers &b, const Workspace &ws, const double *coords,
+                      const int *types, int n, int layer, const Geo &geo, double *Ei, hipStream_t st) {
+  hipLaunchKernelGGL(k_rep_fwd, dim3(n), dim3(NT), 0, st, w, b, coords, types, ws.nlist, ws.nnei, ws.grids, n, layer,
+                     geo, Ei, ws.flags);
+}
+
+void launch_layer_bwd(const Weights &w, const Buffers &b, const Workspace &ws, const double *coords,
+                      const int *types, int n, int layer, const Geo &geo, hipStream_t st) {
+  hipLaunchKernelGGL(k_rep_bwd, dim3(n), dim3(NT), 0, st, w, b, coords, types, ws.nlist, ws.nnei, ws.grids, n, layer,
+                     geo, ws.g, ws.flags);
+}
+
+}  // namespace rep
+}  // namespace dp

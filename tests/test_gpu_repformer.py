@@ -1,0 +1,123 @@
+"""The repformer-style model on the GPU (dp_rep_compute_device, float32) against the
+FP64 oracle (oracle/repformer.py).
+
+* Whole systems, every output: the 192-atom water box, a 60-atom open cluster and the
+  1k-atom solvated chain.
+* The 40k-atom solvated chain: E_i of sampled atoms against the oracle run on the atoms
+  within 3 rc of each (three layers, one hop each), and properties that hold at any
+  size (zero net force, symmetric virial, E = sum E_i).
+* Determinism (two calls agree bit for bit, also after the buffers grew).
+"""
+import numpy as np
+import pytest
+
+from oracle.repformer import build_edges, evaluate, forward, load_rep_model
+from synth import config_system
+from synth.rep_weights import default_rep_file
+from tolerances import TOL_REP, compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def orep():
+    return load_rep_model(default_rep_file())
+
+
+@pytest.fixture(scope="module")
+def rep_model(torch_cuda):
+    from paper_2602_02234_amd import RepModel
+    m = RepModel(default_rep_file(), device=0)
+    yield m
+    m.close()
+
+
+def _cluster(n, seed, spread, dmin=1.0):
+    rng = np.random.default_rng(seed)
+    X = []
+    while len(X) < n:
+        p = rng.uniform(-spread, spread, size=3)
+        if all(np.linalg.norm(p - q) > dmin for q in X):
+            X.append(p)
+    return np.array(X), rng.integers(0, 5, size=n).astype(np.int32)
+
+
+def _systems():
+    w = config_system("water192")
+    X, t = _cluster(60, 7, spread=5.0)
+    c = config_system("chain1k")
+    return {"water192": (w.coords, w.types, w.box), "cluster60": (X, t, None), "chain1k": (c.coords, c.types, c.box)}
+
+
+SYSTEMS = _systems()
+_REF = {}
+
+
+def _check(metrics, tol):
+    bad = {k: (v, tol[k]) for k, v in metrics.items() if k in tol and not v <= tol[k]}
+    assert not bad, f"repformer fp32: outside tolerance {bad}; all metrics {metrics}"
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_repformer_matches_oracle(rep_model, orep, name):
+    X, t, box = SYSTEMS[name]
+    if name not in _REF:
+        _REF[name] = evaluate(orep, X, t, box)
+    ref = _REF[name]
+    out = rep_model.compute(X, t, box, forces=True, atom_energy=True)
+    assert rep_model.edges() == int(ref["nnei"].sum())
+    m = compare(out, ref, len(X))
+    print(f"repformer {name} {len(X)} atoms: {m}")
+    _check(m, TOL_REP["fp32"])
+
+
+def _cutout(s, i, R):
+    L = np.diag(s.box)
+    D = s.coords - s.coords[i]
+    D -= L * np.rint(D / L)
+    idx = np.nonzero(np.sqrt(np.sum(D * D, axis=1)) < R)[0]
+    return s.coords[i] + D[idx], s.types[idx], int(np.nonzero(idx == i)[0][0])
+
+
+def test_repformer_chain40k(torch_cuda, rep_model, orep):
+    torch = torch_cuda
+    s = config_system("chain40k")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(s.coords, device=dev)
+    T = torch.tensor(s.types, device=dev)
+    F = torch.zeros((s.natoms, 3), dtype=torch.float64, device=dev)
+    V = torch.zeros(9, dtype=torch.float64, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    Ei = torch.zeros(s.natoms, dtype=torch.float64, device=dev)
+    rep_model.compute_device(X, T, s.box, forces=F, virial=V, energy=E, atom_energy=Ei)
+    torch.cuda.synchronize()
+    F, V, Ei = F.cpu().numpy(), V.cpu().numpy().reshape(3, 3), Ei.cpu().numpy()
+    tol = TOL_REP["fp32"]
+    print(f"repformer chain40k: {rep_model.edges()} edges, E = {E.item():.6f}")
+    assert np.isfinite(F).all() and np.isfinite(V).all()
+    assert np.abs(F.sum(0)).max() <= tol["f_max"] * np.sqrt(np.mean(F ** 2)) * np.sqrt(s.natoms)
+    assert np.abs(V - V.T).max() <= tol["vir_rel"] * np.abs(V).max()
+    assert abs(E.item() - Ei.sum()) <= 1e-9 * abs(E.item())
+    for i in np.random.default_rng(5).choice(s.natoms, size=2, replace=False):
+        Xc, tc, k = _cutout(s, i, 3 * orep.rc + 0.5)
+        e_ref = forward(orep, build_edges(orep, Xc, tc, None))[k]
+        print(f"  atom {i}: cut-out {len(Xc)} atoms, E_i {Ei[i]:.6f} oracle {e_ref:.6f}")
+        assert abs(Ei[i] - e_ref) <= tol["e_atom"]
+
+
+def test_repformer_deterministic_and_reuse(rep_model):
+    X, t, box = SYSTEMS["water192"]
+    a = rep_model.compute(X, t, box, atom_energy=True)
+    Xc, tc, bc = SYSTEMS["chain1k"]
+    rep_model.compute(Xc, tc, bc)
+    b = rep_model.compute(X, t, box, atom_energy=True)
+    assert a["E"] == b["E"]
+    assert np.array_equal(a["F"], b["F"]) and np.array_equal(a["E_i"], b["E_i"])

@@ -96,3 +96,13 @@ def test_gnn_load_without_device_fails_cleanly():
     from synth.gnn_weights import default_gnn_file
     with pytest.raises(DPError):
         GnnModel(default_gnn_file())
+
+
+def test_rep_load_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2602_02234_amd import RepModel, DPError
+    from synth.rep_weights import default_rep_file
+    with pytest.raises(DPError):
+        RepModel(default_rep_file())
