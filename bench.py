@@ -15,7 +15,8 @@ atoms against the FP64 oracle, and the oracle's own throughput on the host
 cores (a bounded sample of the same workload).
 
 The GNN-variant model (message passing over edges and angles) is timed on the 40k-atom
-chain in both precisions as well, under "gnn".
+chain in both precisions as well, under "gnn", and the repformer-style model (float32)
+under "repformer".
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision bf16|fp32]
                        [--workload chain25k] [--serve-requests 2000] [--no-cpu-baseline]
@@ -132,6 +133,82 @@ def gnn_bench(steps, warmup):
               f"atom-evals/s; backward layer {per_launch_ms:.2f} ms = {achieved / 1e12:.1f} TFLOP/s",
               file=sys.stderr, flush=True)
     return out
+
+
+# Repformer-style model: algorithmic FLOP of its products (float32 VALU).  Forward, per
+# layer: an edge 2 (96*32 + 3*32*32 + 32*4 + 32) (pair update, projections, contraction,
+# convolution), an ordered neighbour pair (j, k) of one centre 2 (32 + 32) (score, A V),
+# an atom 2 (32*4*4 + 224*64) (D and the node update); the fitting net and its gradient
+# 98,560 per atom.  Backward, per layer: an edge 2 (96*32 + 3*32*32 + 3*32*4 + 2*32), a
+# pair 2 (4*32) (dA, dQ, dV, dK), an atom 2 (224*64 + 2*32*4*4).
+REP_F = dict(fwd_edge=2 * (96 * 32 + 3 * 32 * 32 + 32 * 4 + 32), fwd_pair=2 * 64, fwd_atom=2 * (32 * 16 + 224 * 64),
+             fit=GNN_F["fit"], bwd_edge=2 * (96 * 32 + 3 * 32 * 32 + 3 * 32 * 4 + 2 * 32), bwd_pair=2 * 4 * 32,
+             bwd_atom=2 * (224 * 64 + 2 * 32 * 16))
+VALU_FP32_PEAK = 157.3e12  # MI355X vector FP32, FLOP/s
+
+
+def rep_flop(N, E, P):
+    """(forward, backward) algorithmic FLOP of one repformer step: N atoms, E edges, P ordered pairs."""
+    f = REP_F
+    fwd = 3 * (E * f["fwd_edge"] + P * f["fwd_pair"] + N * f["fwd_atom"]) + N * f["fit"]
+    bwd = 3 * (E * f["bwd_edge"] + P * f["bwd_pair"] + N * f["bwd_atom"])
+    return float(fwd), float(bwd)
+
+
+def rep_bench(steps, warmup):
+    """The repformer-style model on the 40k-atom chain (float32): throughput, phase times
+    and the roofline of the backward layer kernel against the vector FP32 peak."""
+    import torch
+    from paper_2602_02234_amd import Model, RepModel
+    from synth import config_system, default_model_file
+    from synth.rep_weights import default_rep_file
+    s = config_system("chain40k")
+    lm = Model(default_model_file(), precision="fp32")
+    _, nnei, _ = lm.neighbors(s.coords, s.box)
+    lm.close()
+    pairs = float(np.sum(nnei.astype(np.float64) ** 2))
+    dev = torch.device("cuda:0")
+    X = torch.tensor(s.coords, device=dev)
+    T = torch.tensor(s.types, device=dev)
+    F = torch.empty((s.natoms, 3), dtype=torch.float64, device=dev)
+    V = torch.empty(9, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    m = RepModel(default_rep_file())
+    for _ in range(warmup):
+        m.compute_device(X, T, s.box, forces=F, virial=V, energy=E)
+    torch.cuda.synchronize()
+    m.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.compute_device(X, T, s.box, forces=F, virial=V, energy=E)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = m.profile_read()
+    m.profile(False)
+    ne = m.edges()
+    m.close()
+    fwd, bwd = rep_flop(s.natoms, ne, pairs)
+    ph = {k: (ms / c if c else 0.0) for k, (ms, c) in prof.items()}
+    per_launch_ms = ph["layers_bwd"] / 3.0
+    achieved = (bwd / 3.0) / (per_launch_ms * 1e-3)
+    print(f"[bench] repformer chain40k fp32: {1e3 * dt / steps:.1f} ms/step -> {s.natoms * steps / dt:.4g} "
+          f"atom-evals/s; backward layer {per_launch_ms:.2f} ms = {achieved / 1e12:.2f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": f"chain40k: seeded solvated chain, {s.natoms} atoms, periodic cubic {s.box[0, 0]:.2f} A box",
+        "model": "repformer-style: 3 layers, node width 64, pair width 32, gated self-attention over neighbours, "
+                 "fitting 64-128-128-1, seeded random weights",
+        "natoms": s.natoms, "edges": ne, "neighbor_pairs": pairs,
+        "fp32": {"value": s.natoms * steps / dt, "unit": "atom-evals/s", "ms_per_step": 1e3 * dt / steps,
+                 "steps": steps, "phase_ms": ph,
+                 "roofline": {"bound": "alu", "kernel": "k_rep_bwd (three launches per step, one per layer)",
+                              "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
+                              "frac": achieved / VALU_FP32_PEAK, "avg_ms": per_launch_ms,
+                              "alg_flop_per_launch": bwd / 3.0,
+                              "traffic": measured_traffic("layers_bwd", "fp32", "chain40k_rep")},
+                 "step_roofline": {"alg_flop_per_step": fwd + bwd,
+                                   "frac": (fwd + bwd) / (dt / steps) / VALU_FP32_PEAK}},
+    }
 
 
 def _cpu_worker(args):
@@ -366,7 +443,8 @@ def main():
                     help="requests of the serving trace replayed at 200 req/s (0 = skip the serving run); "
                          "the first quarter of them is also replayed at 20 req/s")
     ap.add_argument("--gnn-steps", type=int, default=5,
-                    help="steps of the GNN-variant model on the 40k-atom chain per precision (0 = skip)")
+                    help="steps of the GNN-variant model (per precision) and of the repformer-style model on the "
+                         "40k-atom chain (0 = skip both)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -485,6 +563,7 @@ def main():
         out["latency_p50_ms"], out["latency_p99_ms"] = r200["p50_ms"], r200["p99_ms"]
     if args.gnn_steps > 0:
         out["gnn"] = gnn_bench(args.gnn_steps, 1)
+        out["repformer"] = rep_bench(args.gnn_steps, 1)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
