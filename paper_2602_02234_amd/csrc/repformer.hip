@@ -91,18 +91,43 @@ __device__ __forceinline__ size_t erow2(const Buffers &b, int l, int i, int j) {
   return (((size_t)l * b.cap + i) * SEL + j) * G2D;
 }
 
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) {  // LDS rows have odd strides: four scalar stores
+  p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+}
+
+// Copies rows of `width` floats (a multiple of 4) from global memory (row j at src(j))
+// into LDS rows of stride ld, for j < nn; every read is issued before the writes.
+template <int WIDTH, class S>
+__device__ __forceinline__ void load_rows(float *dst, int ld, int nn, const S &src) {
+  constexpr int Q = WIDTH / 4, NI = (SEL * Q + NT - 1) / NT;
+  float4 v[NI];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int k = threadIdx.x + NT * it, j = k / Q;
+    if (j < nn) v[it] = ld4(src(j) + 4 * (k % Q));
+  }
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int k = threadIdx.x + NT * it, j = k / Q;
+    if (j < nn) st4(dst + j * ld + 4 * (k % Q), v[it]);
+  }
+}
+
 // Layer input of atom i's features: g1 of the neighbours (G1J), g2 of its edges (G2) and
 // its own g1 (g1i).
 __device__ void load_inputs(const Weights &w, const Buffers &b, const EnvR &e, const int *types, int i, int l,
                             float *G1J, float *G2, float *g1i) {
   const int nn = e.nn;
-  for (int k = threadIdx.x; k < nn * G1D; k += NT) {
-    const int j = k >> 6, c = k & 63;
-    G1J[j * LG + c] = l == 0 ? w.TN[e.tj[j] * G1D + c] : b.g1f[((size_t)(l - 1) * b.cap + e.jn[j]) * G1D + c];
-  }
-  for (int k = threadIdx.x; k < nn * G2D; k += NT) {
-    const int j = k >> 5, c = k & 31;
-    G2[j * LQ + c] = l == 0 ? tanhf(e.s[j] * w.Wp0[c] + w.bp0[c]) : b.g2f[erow2(b, l - 1, i, j) + c];
+  if (l == 0) {
+    load_rows<G1D>(G1J, LG, nn, [&](int j) { return w.TN + e.tj[j] * G1D; });
+    for (int k = threadIdx.x; k < nn * G2D; k += NT) {
+      const int j = k >> 5, c = k & 31;
+      G2[j * LQ + c] = tanhf(e.s[j] * w.Wp0[c] + w.bp0[c]);
+    }
+  } else {
+    load_rows<G1D>(G1J, LG, nn, [&](int j) { return b.g1f + ((size_t)(l - 1) * b.cap + e.jn[j]) * G1D; });
+    load_rows<G2D>(G2, LQ, nn, [&](int j) { return b.g2f + erow2(b, l - 1, i, j); });
   }
   if (threadIdx.x < G1D)
     g1i[threadIdx.x] = l == 0 ? w.TN[clamp_type(types[i]) * G1D + threadIdx.x]
@@ -110,44 +135,79 @@ __device__ void load_inputs(const Weights &w, const Buffers &b, const EnvR &e, c
 }
 
 // Pair update and projections: G2A = G2 + tanh([G2, G1J] Wa + ba) (TA = the tanh term,
-// written over G2 when `keep_ta`), Q, K, V = G2A Wq, Wk, Wv.  Ends synchronised.
+// written over G2 when `keep_ta`), Q, K, V = G2A Wq, Wk, Wv.  Each thread owns one output
+// column c = tid % 32 for rows tid / 32 + 8 k and holds that column of the weights in
+// registers.  Ends synchronised.
 __device__ void pair_and_qkv(const Weights &w, int l, int nn, float *G2, const float *G1J, float *G2A, float *Q,
                              float *K, float *V, bool keep_ta) {
-  const float *Wa = w.Wa[l], *ba = w.ba[l];
-  constexpr int PER = (SEL * G2D + NT - 1) / NT;
+  const int c = threadIdx.x & 31, j0 = threadIdx.x >> 5;
+  constexpr int PER = (SEL + 7) / 8;
   float ta[PER];
+  {
+    float wa[G2D + G1D];
 #pragma unroll
-  for (int it = 0; it < PER; ++it) {
-    const int o = threadIdx.x + NT * it, j = o >> 5, c = o & 31;
-    ta[it] = 0.f;
-    if (j < nn) {
-      float z = ba[c];
-      for (int q = 0; q < G2D; ++q) z += G2[j * LQ + q] * Wa[q * G2D + c];
-      for (int q = 0; q < G1D; ++q) z += G1J[j * LG + q] * Wa[(G2D + q) * G2D + c];
-      ta[it] = tanhf(z);
-      G2A[j * LQ + c] = G2[j * LQ + c] + ta[it];
+    for (int q = 0; q < G2D + G1D; ++q) wa[q] = w.Wa[l][q * G2D + c];
+    const float bc = w.ba[l][c];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int j = j0 + 8 * it;
+      ta[it] = 0.f;
+      if (j < nn) {
+        float z = bc;
+#pragma unroll
+        for (int q = 0; q < G2D; ++q) z += G2[j * LQ + q] * wa[q];
+#pragma unroll
+        for (int q = 0; q < G1D; ++q) z += G1J[j * LG + q] * wa[G2D + q];
+        ta[it] = tanhf(z);
+        G2A[j * LQ + c] = G2[j * LQ + c] + ta[it];
+      }
     }
   }
   __syncthreads();
   if (keep_ta)
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
-      const int o = threadIdx.x + NT * it, j = o >> 5, c = o & 31;
+      const int j = j0 + 8 * it;
       if (j < nn) G2[j * LQ + c] = ta[it];
     }
-  const float *Wq = w.Wq[l], *Wk = w.Wk[l], *Wv = w.Wv[l];
-  for (int o = threadIdx.x; o < nn * G2D; o += NT) {
-    const int j = o >> 5, c = o & 31;
+  float wq[G2D], wk[G2D], wvv[G2D];
+#pragma unroll
+  for (int t = 0; t < G2D; ++t) {
+    wq[t] = w.Wq[l][t * G2D + c];
+    wk[t] = w.Wk[l][t * G2D + c];
+    wvv[t] = w.Wv[l][t * G2D + c];
+  }
+  for (int j = j0; j < nn; j += 8) {
     float q = 0.f, k = 0.f, v = 0.f;
+#pragma unroll
     for (int t = 0; t < G2D; ++t) {
       const float x = G2A[j * LQ + t];
-      q += x * Wq[t * G2D + c];
-      k += x * Wk[t * G2D + c];
-      v += x * Wv[t * G2D + c];
+      q += x * wq[t];
+      k += x * wk[t];
+      v += x * wvv[t];
     }
     Q[j * LQ + c] = q;
     K[j * LQ + c] = k;
     V[j * LQ + c] = v;
+  }
+  __syncthreads();
+}
+
+// One column of the node update's product z_c = b1_c + xs . W1[:, c], split over the four
+// waves (wave u sums the inputs u*56 .. u*56+55, in order) and combined in wave order;
+// the result is in zc[c] for c < 64.  Ends synchronised.
+__device__ void node_product(const float *W1, const float *b1, const float *xs, float (*part)[G1D], float *zc) {
+  const int c = threadIdx.x & 63, u = threadIdx.x >> 6;
+  constexpr int QW = XD / NWG;
+  float v = 0.f;
+#pragma unroll 8
+  for (int q = u * QW; q < (u + 1) * QW; ++q) v += xs[q] * W1[q * G1D + c];
+  part[u][c] = v;
+  __syncthreads();
+  if (threadIdx.x < G1D) {
+    float z = b1[c];
+    for (int uu = 0; uu < NWG; ++uu) z += part[uu][c];
+    zc[c] = z;
   }
   __syncthreads();
 }
@@ -189,7 +249,7 @@ struct SmemF {
   float G2A[SEL * LQ];
   float Q[SEL * LQ], K[SEL * LQ], V[SEL * LQ];
   float arow[NWG][SEL];
-  float g1i[G1D], T[G2D * 4], xs[XD];
+  float g1i[G1D], T[G2D * 4], xs[XD], part[NWG][G1D], zc[G1D];
   float y1[FWID], t2[FWID], dp[FWID];
 };
 
@@ -254,11 +314,10 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
   __syncthreads();
 
   node_inputs(e, nn, sm.G2, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs);
+  node_product(w.W1[l], w.b1[l], sm.xs, sm.part, sm.zc);
   float g1n = 0.f;
   if (tid < G1D) {
-    float z = w.b1[l][tid];
-    for (int q = 0; q < XD; ++q) z += sm.xs[q] * w.W1[l][q * G1D + tid];
-    g1n = sm.g1i[tid] + tanhf(z);
+    g1n = sm.g1i[tid] + tanhf(sm.zc[tid]);
     if (l < NLAYER - 1) b.g1f[((size_t)l * b.cap + i) * G1D + tid] = g1n;
   }
   if (l < NLAYER - 1) return;
@@ -315,7 +374,7 @@ struct SmemB {
   float stat[3][SEL];    // per query row: max score, normaliser, rho
   float arow[NWG][2][SEL];
   float qrow[NWG][2 * G2D];
-  float g1i[G1D], T[G2D * 4], xs[XD], dg1[G1D], dxn[XD], dT[G2D * 4], part[NWG][G1D];
+  float g1i[G1D], T[G2D * 4], xs[XD], dg1[G1D], dxn[XD], dT[G2D * 4], part[NWG][G1D], zc[G1D];
   int slot[SEL];
 };
 
@@ -333,12 +392,14 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   const EnvR &e = sm.env;
   const int nn = e.nn;
   load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i);
-  for (int k = tid; k < nn * G2D; k += NT) {
-    const int j = k >> 5, c = k & 31;
-    sm.G2B[j * LQ + c] = b.g2f[erow2(b, l, i, j) + c];
-    sm.DY[j * LQ + c] = top ? 0.f : b.dg2[((size_t)i * SEL + j) * G2D + c];
+  load_rows<G2D>(sm.G2B, LQ, nn, [&](int j) { return b.g2f + erow2(b, l, i, j); });
+  if (top) {
+    for (int k = tid; k < nn * G2D; k += NT) sm.DY[(k >> 5) * LQ + (k & 31)] = 0.f;
+    for (int k = tid; k < nn * GSN; k += NT) sm.EG[k] = 0.f;
+  } else {
+    load_rows<G2D>(sm.DY, LQ, nn, [&](int j) { return b.dg2 + ((size_t)i * SEL + j) * G2D; });
+    load_rows<GSN>(sm.EG, GSN, nn, [&](int j) { return b.gs + ((size_t)i * SEL + j) * GSN; });
   }
-  for (int k = tid; k < nn * GSN; k += NT) sm.EG[k] = top ? 0.f : b.gs[(size_t)i * SEL * GSN + k];
   if (!top)
     for (int j = tid; j < nn; j += NT) {
       const int nj = e.jn[j];
@@ -358,6 +419,7 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     float v = 0.f;
     if (!top) {
       const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * G1D;
+#pragma unroll 4
       for (int j = wv; j < nn; j += NWG)
         if (sm.slot[j] >= 0) v += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * G1D + ln];
     }
@@ -373,16 +435,16 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   pair_and_qkv(w, l, nn, sm.G2, sm.G1J, sm.G2A, sm.Q, sm.K, sm.V, true);
   node_inputs(e, nn, sm.G2B, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs);
   // node backward: dz = dg1 (1 - t^2), dxn = W1 dz
+  node_product(w.W1[l], w.b1[l], sm.xs, sm.part, sm.zc);
   if (tid < G1D) {
-    float z = w.b1[l][tid];
-    for (int q = 0; q < XD; ++q) z += sm.xs[q] * w.W1[l][q * G1D + tid];
-    const float t = tanhf(z);
-    sm.part[0][tid] = sm.dg1[tid] * (1.f - t * t);
+    const float t = tanhf(sm.zc[tid]);
+    sm.zc[tid] = sm.dg1[tid] * (1.f - t * t);
   }
   __syncthreads();
   if (tid < XD) {
     float v = 0.f;
-    for (int k = 0; k < G1D; ++k) v += sm.part[0][k] * w.W1[l][tid * G1D + k];
+#pragma unroll 16
+    for (int k = 0; k < G1D; ++k) v += sm.zc[k] * w.W1[l][tid * G1D + k];
     sm.dxn[tid] = v;
   }
   __syncthreads();
@@ -418,6 +480,17 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   }
   __syncthreads();
 
+  // rows c = lane % 32 of Wq, Wk, Wv for the transposed products dE/dg2a += dQ Wq^T + ...
+  float rq[G2D], rk[G2D], rv[G2D];
+  {
+    const int c = ln & 31;
+#pragma unroll
+    for (int q = 0; q < G2D; ++q) {
+      rq[q] = w.Wq[l][c * G2D + q];
+      rk[q] = w.Wk[l][c * G2D + q];
+      rv[q] = w.Wv[l][c * G2D + q];
+    }
+  }
   // attention backward, row pass: one query row j per wave
   const float isq = 1.f / sqrtf((float)G2D);
   const int half = (nn + 1) >> 1;
@@ -480,7 +553,8 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     wave_sync();
     if (ln < 32) {
       float v = sm.DY[j * LQ + c];
-      for (int q = 0; q < G2D; ++q) v += sm.qrow[wv][q] * w.Wq[l][c * G2D + q];
+#pragma unroll
+      for (int q = 0; q < G2D; ++q) v += sm.qrow[wv][q] * rq[q];
       sm.G2A[j * LQ + c] = v;  // dE/dg2a, row terms
     }
     wave_sync();
@@ -525,8 +599,8 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     wave_sync();
     if (ln < 32) {
       float u = sm.G2A[k * LQ + c];
-      for (int q = 0; q < G2D; ++q)
-        u += sm.qrow[wv][q] * w.Wv[l][c * G2D + q] + sm.qrow[wv][G2D + q] * w.Wk[l][c * G2D + q];
+#pragma unroll
+      for (int q = 0; q < G2D; ++q) u += sm.qrow[wv][q] * rv[q] + sm.qrow[wv][G2D + q] * rk[q];
       sm.G2A[k * LQ + c] = u;  // dE/dg2a, complete
     }
     wave_sync();
@@ -542,10 +616,15 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   // dxa = Wa dz: the first 32 go to dE/dg2 of the layer input, the other 64 (with the
   // convolution's term) to the edge's part of dE/dg1_j
   float *dnj = b.dnj + (size_t)(l & 1) * b.cap * SEL * G1D;
-  for (int o = tid; o < nn * (G2D + G1D); o += NT) {
-    const int j = o / (G2D + G1D), q = o % (G2D + G1D);
+  if (tid < 2 * (G2D + G1D)) {  // thread: column q = tid % 96 of dxa, rows j = tid / 96 + 2 k
+    const int q = tid % (G2D + G1D);
+    float wr[G2D];
+#pragma unroll
+    for (int c = 0; c < G2D; ++c) wr[c] = w.Wa[l][q * G2D + c];
+    for (int j = tid / (G2D + G1D); j < nn; j += 2) {
     float v = 0.f;
-    for (int c = 0; c < G2D; ++c) v += sm.DY[j * LQ + c] * w.Wa[l][q * G2D + c];
+#pragma unroll
+    for (int c = 0; c < G2D; ++c) v += sm.DY[j * LQ + c] * wr[c];
     if (q < G2D) {
       const float dg2in = sm.G2A[j * LQ + q] + v;
       if (l > 0) b.dg2[((size_t)i * SEL + j) * G2D + q] = dg2in;
@@ -554,6 +633,7 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       const int c1 = q - G2D;
       if (c1 < G2D) v += e.sw[j] * dc[c1] * geo.inv_sel * sm.G2B[j * LQ + c1];
       dnj[((size_t)i * SEL + j) * G1D + c1] = v;
+    }
     }
   }
   if (l > 0) {
