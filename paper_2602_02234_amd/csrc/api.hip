@@ -649,6 +649,10 @@ int flags_status(unsigned f) {
   if (f & FLAG_TYPE) { set_error("atom type outside [0, ntypes)"); return DP_ERR_TYPE; }
   if (f & FLAG_OVERLAP) { set_error("two atoms at distance 0"); return DP_ERR_OVERLAP; }
   if (f & FLAG_TOO_DENSE) { set_error("more than DP_MAX_CANDIDATES neighbours within rc"); return DP_ERR_TOO_LARGE; }
+  if (f & FLAG_INCOMPLETE) {
+    set_error("an atom has more than sel neighbours within rc; the message-passing models need complete lists");
+    return DP_ERR_TOO_LARGE;
+  }
   return DP_OK;
 }
 

@@ -29,11 +29,13 @@ constexpr int SKIN_CAP = 192;  // entries per row of the skin list (within rc + 
 
 // Status bits written by kernels into the workspace flag word.  STALE: an atom moved by
 // half the skin since the skin list was built; SKIN_FULL: a skin row overflowed.  Both
-// make the host redo the step with a fresh search.
+// make the host redo the step with a fresh search.  INCOMPLETE: set only for the
+// message-passing models, which refuse truncated lists.
 enum : unsigned {
   FLAG_OVERLAP = 1u, FLAG_TYPE = 2u, FLAG_NONFINITE = 4u, FLAG_TOO_DENSE = 8u, FLAG_STALE = 16u,
   FLAG_SKIN_FULL = 32u,
-  FLAG_ERRORS = 63u,  // any of the above: outputs are not written
+  FLAG_INCOMPLETE = 64u,  // a list was truncated to sel and the model needs complete lists
+  FLAG_ERRORS = 127u,     // any of the above: outputs are not written
 };
 
 constexpr int MAXH = 4;  // fitting heads one model may carry
@@ -238,6 +240,9 @@ void launch_cells(const Workspace &ws, const double *coords, const int *types, i
 void launch_nlist(const Workspace &ws, const double *coords, int n, int i0, int i1, int ncen, double cutoff,
                   bool skin, hipStream_t st);
 void launch_filter(const Workspace &ws, const double *coords, int n, double rc, hipStream_t st);
+// For models that need complete lists: turns a truncation (overflow count > 0) into the
+// FLAG_INCOMPLETE error, so that the step's later kernels write nothing.
+void launch_require_complete(const Workspace &ws, hipStream_t st);
 void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
                        hipStream_t st);
 void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st);

@@ -231,6 +231,7 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
   launch_prologue(ws, 1, n, ncells + 1, true, st);
   launch_cells(ws, X, types, n, m->ntypes, open, ncells, m->rc, st);
   launch_nlist(ws, X, n, 0, n, n, m->rc, false, st);
+  launch_require_complete(ws, st);
   gnn::Geo geo{(float)m->rc, (float)m->rcs, (float)m->rca, 1.f / (float)m->sel, 1.f / (float)m->asel, m->asel};
   gnn::launch_angle_offsets(m->b, ws, X, n, geo, st);
   G_TRY(hipGetLastError());

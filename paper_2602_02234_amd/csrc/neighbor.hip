@@ -370,6 +370,16 @@ void launch_prologue(const Workspace &ws, int nsys, int n, int ncells_zero, bool
                      ws.bcnt);
 }
 
+namespace {
+__global__ void k_require_complete(unsigned *__restrict__ flags) {
+  if (threadIdx.x == 0 && flags[1] != 0u) flags[0] |= FLAG_INCOMPLETE;
+}
+}  // namespace
+
+void launch_require_complete(const Workspace &ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_require_complete, dim3(1), dim3(64), 0, st, ws.flags);
+}
+
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
                   int ncells_total, double cell_cutoff, hipStream_t st) {
   if (open_single)

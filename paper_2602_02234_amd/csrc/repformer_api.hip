@@ -214,6 +214,7 @@ int rep_step(dp_rep *m, int64_t natoms, const double *X, const int32_t *types, c
   launch_prologue(ws, 1, n, ncells + 1, true, st);
   launch_cells(ws, X, types, n, m->ntypes, open, ncells, m->rc, st);
   launch_nlist(ws, X, n, 0, n, n, m->rc, false, st);
+  launch_require_complete(ws, st);
   rep::launch_edge_count(m->b, ws, n, st);
   record(m, 1, st);
   rep::Geo geo{(float)m->rc, (float)m->rcs, 1.f / (float)m->sel};

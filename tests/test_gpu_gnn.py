@@ -157,3 +157,24 @@ def test_gnn_energy_only_and_errors(torch_cuda, gnn_models):
     bad[3] = 7
     with pytest.raises(DPError):
         m.compute_device(Xd, bad, box)
+
+
+def test_gnn_edge_cases(torch_cuda, gnn_models, ognn):
+    """A single atom (no edges, no angles) gives the fitting net of the type embedding
+    alone; an atom with more than sel neighbours is refused (the message passing needs
+    complete lists) and the outputs stay untouched."""
+    torch = torch_cuda
+    from paper_2602_02234_amd import DPError
+    m = gnn_models["fp32"]
+    X1 = np.zeros((1, 3))
+    t1 = np.array([2], dtype=np.int32)
+    out = m.compute(X1, t1, None, atom_energy=True)
+    ref = evaluate(ognn, X1, t1, None)
+    assert abs(out["E"] - ref["E"]) <= TOL_GNN["fp32"]["e_atom"]
+    assert np.all(out["F"] == 0.0) and m.graph_size() == (0, 0)
+    X, t = _cluster(200, 11, spread=3.2, dmin=0.8)  # every atom within rc of more than 120 others
+    dev = torch.device("cuda:0")
+    F = torch.full((200, 3), 7.0, dtype=torch.float64, device=dev)
+    with pytest.raises(DPError):
+        m.compute_device(torch.tensor(X, device=dev), torch.tensor(t, device=dev), None, forces=F)
+    assert torch.all(F == 7.0)

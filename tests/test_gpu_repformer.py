@@ -121,3 +121,20 @@ def test_repformer_deterministic_and_reuse(rep_model):
     b = rep_model.compute(X, t, box, atom_energy=True)
     assert a["E"] == b["E"]
     assert np.array_equal(a["F"], b["F"]) and np.array_equal(a["E_i"], b["E_i"])
+
+
+def test_repformer_edge_cases(torch_cuda, rep_model, orep):
+    torch = torch_cuda
+    from paper_2602_02234_amd import DPError
+    X1 = np.zeros((1, 3))
+    t1 = np.array([3], dtype=np.int32)
+    out = rep_model.compute(X1, t1, None, atom_energy=True)
+    ref = evaluate(orep, X1, t1, None)
+    assert abs(out["E"] - ref["E"]) <= TOL_REP["fp32"]["e_atom"]
+    assert np.all(out["F"] == 0.0) and rep_model.edges() == 0
+    X, t = _cluster(200, 11, spread=3.2, dmin=0.8)
+    dev = torch.device("cuda:0")
+    F = torch.full((200, 3), 7.0, dtype=torch.float64, device=dev)
+    with pytest.raises(DPError):
+        rep_model.compute_device(torch.tensor(X, device=dev), torch.tensor(t, device=dev), None, forces=F)
+    assert torch.all(F == 7.0)
