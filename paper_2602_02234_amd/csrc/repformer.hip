@@ -273,6 +273,9 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
   const float isq = 1.f / sqrtf((float)G2D);
   const int half = (nn + 1) >> 1;
   for (int j = wv; j < nn; j += NWG) {
+    float qj[G2D];  // the query row, the same in every lane
+#pragma unroll
+    for (int c = 0; c < G2D; ++c) qj[c] = sm.Q[j * LQ + c];
     float sc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -280,7 +283,8 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
       sc[h] = -INFINITY;
       if (k < nn) {
         float d = 0.f;
-        for (int c = 0; c < G2D; ++c) d += sm.Q[j * LQ + c] * sm.K[k * LQ + c];
+#pragma unroll
+        for (int c = 0; c < G2D; ++c) d += qj[c] * sm.K[k * LQ + c];
         sc[h] = d * isq;
       }
     }
@@ -495,6 +499,12 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   const float isq = 1.f / sqrtf((float)G2D);
   const int half = (nn + 1) >> 1;
   for (int j = wv; j < nn; j += NWG) {
+    float qj[G2D], dyj[G2D];  // the query row and its output gradient, the same in every lane
+#pragma unroll
+    for (int c = 0; c < G2D; ++c) {
+      qj[c] = sm.Q[j * LQ + c];
+      dyj[c] = sm.DY[j * LQ + c];
+    }
     float sc[2], P[2], gt[2], dP[2], dGt[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -502,7 +512,8 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       sc[h] = -INFINITY;
       if (k < nn) {
         float d = 0.f;
-        for (int c = 0; c < G2D; ++c) d += sm.Q[j * LQ + c] * sm.K[k * LQ + c];
+#pragma unroll
+        for (int c = 0; c < G2D; ++c) d += qj[c] * sm.K[k * LQ + c];
         sc[h] = d * isq;
       }
     }
@@ -523,7 +534,8 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       if (k < nn) {
         gt[h] = gate(e, j, k);
         float dA = 0.f;
-        for (int c = 0; c < G2D; ++c) dA += sm.DY[j * LQ + c] * sm.V[k * LQ + c];
+#pragma unroll
+        for (int c = 0; c < G2D; ++c) dA += dyj[c] * sm.V[k * LQ + c];
         dP[h] = dA * gt[h];
         dGt[h] = dA * P[h];
         rho += dP[h] * P[h];
@@ -562,15 +574,22 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   __syncthreads();
   // column pass: one key k per wave, scores recomputed against every query row
   for (int k = wv; k < nn; k += NWG) {
+    float kk[G2D], vk[G2D];  // the key row and its value row, the same in every lane
+#pragma unroll
+    for (int c = 0; c < G2D; ++c) {
+      kk[c] = sm.K[k * LQ + c];
+      vk[c] = sm.V[k * LQ + c];
+    }
     float dsk = 0.f, hk[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int j = ln + 64 * h;
       if (j < nn) {
         float d = 0.f, dA = 0.f;
+#pragma unroll
         for (int c = 0; c < G2D; ++c) {
-          d += sm.Q[j * LQ + c] * sm.K[k * LQ + c];
-          dA += sm.DY[j * LQ + c] * sm.V[k * LQ + c];
+          d += sm.Q[j * LQ + c] * kk[c];
+          dA += sm.DY[j * LQ + c] * vk[c];
         }
         const float exz = expf(d * isq - sm.stat[0][j]) / sm.stat[1][j];
         const float P = e.sw[k] * exz, gt = gate(e, j, k);
