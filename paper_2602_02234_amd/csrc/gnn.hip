@@ -104,6 +104,14 @@ template <int K> struct Frag<bf16_t, K> {
   }
 };
 
+// tanh of the layers' hot loops, from the hardware exponential and reciprocal:
+// tanh|x| = (1 - t) / (1 + t), t = exp(-2|x|); absolute error a few 1e-8, below the
+// float32 rounding of the products it follows (measured forces unchanged against tanhf).
+template <typename T> __device__ __forceinline__ float act(float x) {
+  const float t = __expf(-2.f * fabsf(x));
+  return copysignf((1.f - t) * __builtin_amdgcn_rcpf(1.f + t), x);
+}
+
 // Compiler barrier: weight fragments loaded after it are not hoisted out of the loop
 // around it (they would then all be live at once).
 __device__ __forceinline__ void opaque() { asm volatile("" ::: "memory"); }
@@ -369,7 +377,7 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
           const int r = acc_row(ii), c = ct * 16 + acc_col(), t = t0 + r;
-          const float a1 = sl[r * LDF + c] + tanhf(aa[ct][ii] + baa[c]);
+          const float a1 = sl[r * LDF + c] + act<T>(aa[ct][ii] + baa[c]);
           sl[r * LDF + c] = a1;
           if (t < na) b.af[((size_t)l * b.acap + abase + (int64_t)p * na + t) * ADIM + c] = a1;
         }
@@ -382,7 +390,7 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
         const int t = t0 + acc_row(ii);
         const float wr = t < na ? e.swa[jp] * e.swa[e.cl[t + (t >= p)]] * geo.inv_asel : 0.f;
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) mr[ct] += wr * tanhf(am[ct][ii] + bea[ct * 16 + acc_col()]);
+        for (int ct = 0; ct < 4; ++ct) mr[ct] += wr * act<T>(am[ct][ii] + bea[ct * 16 + acc_col()]);
       }
       wave_sync();
     }
@@ -424,7 +432,7 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
           const int c = ct * 16 + acc_col();
-          const float e1 = sm.El[j * LDE + c] + tanhf(ae[ct][ii] + bee[c]) + (cp >= 0 ? sm.Msg[cp * EDIM + c] : 0.f);
+          const float e1 = sm.El[j * LDE + c] + act<T>(ae[ct][ii] + bee[c]) + (cp >= 0 ? sm.Msg[cp * EDIM + c] : 0.f);
           b.ef[erow(b, l, i, j) + c] = e1;
           aw[ct] += e.swe[j] * e1;
         }
@@ -648,7 +656,7 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
         if (ok) {
           d = pde[ct][ii] + e.swe[j] * sm.dagg[c];
           rs[ii] += pef[ct][ii] * sm.dagg[c];
-          const float t = tanhf(ae[ct][ii] + bee[c]);
+          const float t = act<T>(ae[ct][ii] + bee[c]);
           dz = d * (1.f - t * t);
         }
         de1[ct][ii] = d;
@@ -792,14 +800,14 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
           const int c = ct * 16 + acc_col();
-          const float tm = tanhf(am[ct][ii] + bea[c]);
+          const float tm = act<T>(am[ct][ii] + bea[c]);
           const float dm = qv[ii] >= 0 ? sm.DM[p * EDIM + c] : 0.f;
           d += dm * tm;
           sl[r * LDB + 128 + c] = wr * dm * (1.f - tm * tm);  // dz_m
         }
         dwa[ii] = sum16(d);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) ta[ct][ii] = tanhf(aa[ct][ii] + baa[ct * 16 + acc_col()]);
+        for (int ct = 0; ct < 2; ++ct) ta[ct][ii] = act<T>(aa[ct][ii] + baa[ct * 16 + acc_col()]);
       }
       wave_sync();
       f4 ax[2] = {};
@@ -847,8 +855,10 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
             if (l > 0) b.da[(size_t)(abase + (int64_t)p * na + t0 + r) * ADIM + c] = dal;
             Q[qv[ii] * QLD + c] += av[ct][ii];
           }
-          const float a0 = sl[r * LDB + 64 + c];
-          d += dal * (1.f - a0 * a0) * w.Wa0[c];
+          if (l == 0) {
+            const float a0 = sl[r * LDB + 64 + c];
+            d += dal * (1.f - a0 * a0) * w.Wa0[c];
+          }
         }
         dc[ii] = l == 0 ? sum16(d) : 0.f;
       }
