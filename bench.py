@@ -60,24 +60,29 @@ def flop_per_atom_eval(n):
     return 2.0 * (mac_desc_fwd(n) + mac_desc_bwd_alg(n) + 2 * FIT_MAC)
 
 
-# GNN variant (message passing over edges and angles): algorithmic FLOP of its products.
-# Forward, per layer: an angle 2 (96*32 + 64*64), an edge 2 (192*64), a node 2 (128*64);
-# the fitting net and its gradient per atom 2 (64*128 + 128*128 + 128) + 2 (128*128 + 64*128).
-# Backward, per layer: an angle 2 (64*64 + 96*32 + 64*32 + 32*32 + 96*32) (recomputed
-# activations, the two transposed products and the terms of edge q), an edge 2 (192*64 +
-# 64*64 + 64*64) (2 (192*64 + 64*64) in layer 0, which needs no neighbour part), a node
-# 2 (128*64 + 2*64*64).
-GNN_F = dict(fwd_angle=2 * (96 * 32 + 64 * 64), fwd_edge=2 * 192 * 64, fwd_node=2 * 128 * 64,
-             fit=2 * (64 * 128 + 128 * 128 + 128) + 2 * (128 * 128 + 64 * 128),
-             bwd_angle=2 * (64 * 64 + 96 * 32 + 64 * 32 + 32 * 32 + 96 * 32),
-             bwd_edge=2 * (192 * 64 + 2 * 64 * 64), bwd_edge0=2 * (192 * 64 + 64 * 64), bwd_node=2 * (128 * 64 + 2 * 64 * 64))
+# GNN variant (message passing over edges and angles): algorithmic FLOP of its products
+# as the kernels evaluate them, with the terms an angle takes from its two edges formed
+# once per angle-list edge (e_x[:32] times Waa[32:96] and Wea[32:64], 2*32*128 per edge)
+# and the centre's part of every edge update once per atom (n_i Wee[0:64], 2*64*64).
+# Forward, per layer: an angle 2 (32*32 + 32*64), an edge 2 (128*64), an atom 2 (64*64 +
+# 128*64); the fitting net and its gradient per atom 2 (64*128 + 128*128 + 128) +
+# 2 (128*128 + 64*128).  Backward, per layer: an angle 2 (32*64 + 32*32 + 64*32 + 32*32 +
+# 96*32) (recomputed activations, the two transposed products and the terms of edge q),
+# an angle-list edge 2*32*128 (recomputed), an edge 2 (128*64 + 2*64*64) (2 (128*64 +
+# 64*64) in layer 0, which needs no neighbour part), an atom 2 (64*64 + 128*64 + 2*64*64).
+GNN_F = dict(fwd_angle=2 * (32 * 32 + 32 * 64), fwd_aedge=2 * 32 * 128, fwd_edge=2 * 128 * 64,
+             fwd_node=2 * (64 * 64 + 128 * 64), fit=2 * (64 * 128 + 128 * 128 + 128) + 2 * (128 * 128 + 64 * 128),
+             bwd_angle=2 * (32 * 64 + 32 * 32 + 64 * 32 + 32 * 32 + 96 * 32), bwd_aedge=2 * 32 * 128,
+             bwd_edge=2 * (128 * 64 + 2 * 64 * 64), bwd_edge0=2 * (128 * 64 + 64 * 64),
+             bwd_node=2 * (64 * 64 + 128 * 64 + 2 * 64 * 64))
 
 
-def gnn_flop(N, E, A):
-    """(forward, backward) algorithmic FLOP of one GNN step with N atoms, E edges, A angles."""
+def gnn_flop(N, E, C, A):
+    """(forward, backward) algorithmic FLOP of one GNN step: N atoms, E edges, C angle-list
+    edges, A angles."""
     f = GNN_F
-    fwd = 3 * (A * f["fwd_angle"] + E * f["fwd_edge"] + N * f["fwd_node"]) + N * f["fit"]
-    bwd = 3 * A * f["bwd_angle"] + E * (2 * f["bwd_edge"] + f["bwd_edge0"]) + 3 * N * f["bwd_node"]
+    fwd = 3 * (A * f["fwd_angle"] + C * f["fwd_aedge"] + E * f["fwd_edge"] + N * f["fwd_node"]) + N * f["fit"]
+    bwd = 3 * (A * f["bwd_angle"] + C * f["bwd_aedge"] + N * f["bwd_node"]) + E * (2 * f["bwd_edge"] + f["bwd_edge0"])
     return float(fwd), float(bwd)
 
 
@@ -111,13 +116,13 @@ def gnn_bench(steps, warmup):
         dt = time.perf_counter() - t0
         prof = m.profile_read()
         m.profile(False)
-        ne, na = m.graph_size()
+        ne, nce, na = m.graph_size()
         m.close()
-        fwd, bwd = gnn_flop(s.natoms, ne, na)
+        fwd, bwd = gnn_flop(s.natoms, ne, nce, na)
         ph = {k: (ms / c if c else 0.0) for k, (ms, c) in prof.items()}
         per_launch_ms = ph["layers_bwd"] / 3.0
         achieved = (bwd / 3.0) / (per_launch_ms * 1e-3)
-        out.update(edges=ne, angles=na)
+        out.update(edges=ne, angle_edges=nce, angles=na)
         out[prec] = {
             "value": s.natoms * steps / dt, "unit": "atom-evals/s", "ms_per_step": 1e3 * dt / steps, "steps": steps,
             "phase_ms": ph,

@@ -306,8 +306,9 @@ int dp_nve_run(dp_model *m, int64_t natoms, double *d_coords, double *d_vel, con
  *   has finished on the stream.  A dp_gnn owns grow-only device buffers of about
  *   190 KB per atom and 512 bytes per angle; it is not thread-safe.
  * dp_gnn_info: rc, rca, sel, asel of the model (pointers may be NULL).
- * dp_gnn_graph_size: edges (sum of the list lengths) and angles of the last
- *   successful step (pointers may be NULL).
+ * dp_gnn_graph_size: edges (sum of the list lengths), angle-list edges (sum of nc
+ *   over the atoms that have angles) and angles of the last successful step
+ *   (pointers may be NULL).
  * dp_gnn_profile_enable / dp_gnn_profile_read: per-phase device time from HIP events
  *   on the step's stream, accumulated over calls since enabling (which clears it):
  *   phase 0 lists (cell list, neighbour lists, angle offsets), 1 the three forward
@@ -320,7 +321,7 @@ int dp_gnn_info(const dp_gnn *m, double *rc, double *rca, int *sel, int *asel);
 int dp_gnn_compute_device(dp_gnn *m, int64_t natoms, const double *d_coords, const int32_t *d_types,
                           const double *box_host, double *d_energy, double *d_forces, double *d_virial,
                           double *d_atom_energy, void *hip_stream);
-int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angles);
+int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angle_edges, int64_t *angles);
 int dp_gnn_profile_enable(dp_gnn *m, int enable);
 int dp_gnn_profile_read(const dp_gnn *m, double *ms, int64_t *calls, int max);
 

@@ -57,7 +57,7 @@ SIGNATURES = {
     "dp_gnn_info": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int),
                               C.POINTER(C.c_int)]),
     "dp_gnn_compute_device": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
-    "dp_gnn_graph_size": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "dp_gnn_graph_size": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "dp_gnn_profile_enable": (C.c_int, [_P, C.c_int]),
     "dp_gnn_profile_read": (C.c_int, [_P, _P, _P, C.c_int]),
     "dp_rep_load": (C.c_int, [C.c_char_p, C.c_int, C.POINTER(C.c_void_p)]),

@@ -374,13 +374,13 @@ class GnnModel:
 
     def angles(self) -> int:
         """Angles of the last successful step."""
-        return self.graph_size()[1]
+        return self.graph_size()[2]
 
     def graph_size(self):
-        """(edges, angles) of the last successful step."""
-        e, a = C.c_int64(), C.c_int64()
-        check(_lib.load().dp_gnn_graph_size(self._h, C.byref(e), C.byref(a)), "dp_gnn_graph_size")
-        return int(e.value), int(a.value)
+        """(edges, angle-list edges, angles) of the last successful step."""
+        e, c, a = C.c_int64(), C.c_int64(), C.c_int64()
+        check(_lib.load().dp_gnn_graph_size(self._h, C.byref(e), C.byref(c), C.byref(a)), "dp_gnn_graph_size")
+        return int(e.value), int(c.value), int(a.value)
 
     PHASES = ("lists", "layers_fwd", "layers_bwd", "forces")
 

@@ -43,7 +43,7 @@ struct Weights {
 // i start at aoff[i] (p-major: angle (p, q) at aoff[i] + p (nc_i - 1) + q - (q > p)).
 struct Buffers {
   int64_t cap = 0, acap = 0;  // atoms, angles
-  int64_t *aoff = nullptr;    // [cap + 2]: angle offsets, then the step's edge count
+  int64_t *aoff = nullptr;    // [cap + 3]: angle offsets, then the step's edge and angle-list edge counts
   float *nf = nullptr;        // [2][cap][64]       n after layers 1, 2
   float *ef = nullptr;        // [3][cap][SEL][64]  e after layers 1, 2, 3
   float *af = nullptr;        // [3][acap][32]      a after layers 1, 2, 3
@@ -60,7 +60,8 @@ struct Geo {
 };
 
 // aoff[1 .. n]: angle counts of every atom, then their inclusive prefix (aoff[0] = 0);
-// aoff[cap + 1]: the number of edges (sum of the list lengths).
+// aoff[cap + 1]: the number of edges (sum of the list lengths); aoff[cap + 2]: the
+// number of angle-list edges of the atoms with angles.
 void launch_angle_offsets(const Buffers &b, const Workspace &ws, const double *coords, int n, const Geo &geo,
                           hipStream_t st);
 // Layer `layer` (0 .. 2) forward over all n atoms; the last layer also evaluates the

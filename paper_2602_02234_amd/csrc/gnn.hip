@@ -31,7 +31,7 @@ constexpr int NWG = 4;          // waves per workgroup
 constexpr int NT = NWG * 64;
 constexpr int LDE = 68;         // row stride of [edge][64] LDS arrays
 constexpr int LDF = 196;        // forward slab row stride (192 columns used)
-constexpr int LDB = 228;        // backward slab row stride (224 columns used)
+constexpr int LDB = 164;        // backward slab row stride (160 columns used)
 constexpr int QLD = 36;         // per-edge angle accumulators: 32 features, sw_a, rhat
 
 __device__ __forceinline__ bool failed(const unsigned *flags) { return (flags[0] & FLAG_ERRORS) != 0u; }
@@ -223,26 +223,37 @@ __global__ void __launch_bounds__(256) k_angle_count(const double *__restrict__ 
 
 // Inclusive prefix of aoff[1 .. n] in one workgroup: each thread sums a contiguous run,
 // the 1024 run totals are scanned, then each run is rewritten.
-// The same workgroup also writes the total edge count (sum of nnei) to *etot.
+// The same workgroup also writes the total edge count (sum of nnei) to etot[0] and the
+// number of angle-list edges of the atoms that have angles (sum of nc, from nc (nc - 1))
+// to etot[1].
 __global__ void __launch_bounds__(1024) k_angle_scan(int64_t *__restrict__ aoff, const int *__restrict__ nnei, int n,
                                                      int64_t *__restrict__ etot) {
   __shared__ int64_t part[1024];
-  __shared__ int64_t epart[1024];
+  __shared__ int64_t epart[1024], cpart[1024];
   const int t = threadIdx.x;
   const int per = (n + 1023) / 1024;
   const int b0 = 1 + t * per, b1 = min(n + 1, b0 + per);
-  int64_t s = 0, se = 0;
+  int64_t s = 0, se = 0, sc = 0;
   for (int k = b0; k < b1; ++k) {
-    s += aoff[k];
+    const int64_t cnt = aoff[k];
+    s += cnt;
     se += min(max(nnei[k - 1], 0), SEL);
+    int nc = 0;
+    while ((int64_t)nc * (nc - 1) < cnt) ++nc;  // cnt = nc (nc - 1), nc <= 48 (atoms with angles)
+    sc += nc;
   }
   part[t] = s;
   epart[t] = se;
+  cpart[t] = sc;
   __syncthreads();
   if (t == 0) {
-    int64_t tot = 0;
-    for (int k = 0; k < 1024; ++k) tot += epart[k];
-    *etot = tot;
+    int64_t tot = 0, totc = 0;
+    for (int k = 0; k < 1024; ++k) {
+      tot += epart[k];
+      totc += cpart[k];
+    }
+    etot[0] = tot;
+    etot[1] = totc;
   }
   for (int off = 1; off < 1024; off <<= 1) {
     const int64_t v = t >= off ? part[t - off] : 0;
@@ -257,13 +268,38 @@ __global__ void __launch_bounds__(1024) k_angle_scan(int64_t *__restrict__ aoff,
   }
 }
 
+// The terms an angle's products take from its two edges depend on the edge alone:
+// PQ[x] = [e_x[:32] Waa[32:64], e_x[:32] Waa[64:96], e_x[:32] Wea[32:64]] for every
+// angle-list edge x (rows of E at stride lde, first 32 columns), computed once per
+// layer instead of once per angle.  Each thread owns one of the 128 columns and holds
+// its 32 weights in registers.  Ends synchronised.
+constexpr int PQW = 2 * ADIM + EDIM;  // 128
+__device__ void edge_terms(const float *__restrict__ Waa, const float *__restrict__ Wea, const float *E, int lde,
+                           const int *cl, int nc, float *PQ) {
+  const int c = threadIdx.x & (PQW - 1);
+  float wc[ADIM];
+#pragma unroll
+  for (int k = 0; k < ADIM; ++k)
+    wc[k] = c < ADIM ? Waa[(ADIM + k) * ADIM + c]
+                     : (c < 2 * ADIM ? Waa[(2 * ADIM + k) * ADIM + c - ADIM] : Wea[(ADIM + k) * EDIM + c - 2 * ADIM]);
+  for (int x = threadIdx.x >> 7; x < nc; x += NT / PQW) {
+    const float *ex = E + (lde > 0 ? cl[x] * lde : x * ADIM);
+    float v = 0.f;
+#pragma unroll
+    for (int k = 0; k < ADIM; ++k) v += ex[k] * wc[k];
+    PQ[x * PQW + c] = v;
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ forward
 struct SmemF {
   GEnv env;
   float El[SEL * LDE] __attribute__((aligned(16)));  // e of the layer's input
   float Msg[ASEL * EDIM];                            // m_ip
+  float PQ[ASEL * PQW];                              // per-edge terms of the angle products
   float slab[NWG][16 * LDF] __attribute__((aligned(16)));  // per-wave operand tiles
-  float ni[NDIM] __attribute__((aligned(16))), xs[2 * NDIM], aggw[NWG][NDIM];
+  float ni[NDIM] __attribute__((aligned(16))), xs[2 * NDIM], aggw[NWG][NDIM], nbias[EDIM];
   float y1[FWID], t2[FWID], dp[FWID];
 };
 
@@ -306,9 +342,10 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   const int l = layer;
   const float *Waa = w.Waa[l], *baa = w.baa[l], *Wea = w.Wea[l], *bea = w.bea[l];
   const float *Wee = w.Wee[l], *bee = w.bee[l], *Wnn = w.Wnn[l], *bnn = w.bnn[l];
-  // this layer's angle weights, held by every wave for all its tiles
-  Frag<T, 96> fa[2];
-  Frag<T, 64> fm[4];
+  // the angle rows' parts of this layer's angle weights (the first 32 inputs), held by
+  // every wave for all its tiles
+  Frag<T, ADIM> fa[2];
+  Frag<T, ADIM> fm[4];
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) fa[ct].load([&](int c, int k) { return Waa[k * ADIM + ct * 16 + c]; });
 #pragma unroll
@@ -339,6 +376,12 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   if (tid < NDIM)
     sm.ni[tid] = l == 0 ? w.TN[clamp_type(types[i]) * NDIM + tid] : b.nf[((size_t)(l - 1) * b.cap + i) * NDIM + tid];
   __syncthreads();
+  if (tid < EDIM) {  // the centre's part of every edge update: bee + n_i Wee[0:64]
+    float v = bee[tid];
+    for (int k = 0; k < NDIM; ++k) v += sm.ni[k] * Wee[k * EDIM + tid];
+    sm.nbias[tid] = v;
+  }
+  edge_terms(Waa, Wea, sm.El, LDE, e.cl, nc, sm.PQ);
 
   float *sl = sm.slab[wv];
   const float *rowA = sl + (ln & 15) * LDF;
@@ -350,24 +393,26 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
     const int jp = e.cl[p];
     const float *ap = b.af + ((size_t)(l > 0 ? l - 1 : 0) * b.acap + abase + (int64_t)p * na) * ADIM;
     for (int t0 = 0; t0 < na; t0 += 16) {
-      // [a, e_ip[:32], e_iq[:32]]
-      stage<3, 3>(sl, LDF, [&](int sg, int r, int c4) -> float4 {
+      // a of the tile's 16 angles; the edge terms come from PQ
+      stage<1, 1>(sl, LDF, [&](int, int r, int c4) -> float4 {
         const int t = t0 + r;
         if (t >= na) return make_float4(0.f, 0.f, 0.f, 0.f);
-        const int q = t + (t >= p);
-        if (sg == 0) {
-          if (l > 0) return ld4(ap + (size_t)t * ADIM + 4 * c4);
-          const float cs = cosang(e, jp, e.cl[q]);
-          float4 v;
-          v.x = tanhf(cs * w.Wa0[4 * c4] + w.ba0[4 * c4]);
-          v.y = tanhf(cs * w.Wa0[4 * c4 + 1] + w.ba0[4 * c4 + 1]);
-          v.z = tanhf(cs * w.Wa0[4 * c4 + 2] + w.ba0[4 * c4 + 2]);
-          v.w = tanhf(cs * w.Wa0[4 * c4 + 3] + w.ba0[4 * c4 + 3]);
-          return v;
-        }
-        return ld4(sm.El + (sg == 1 ? jp : e.cl[q]) * LDE + 4 * c4);
+        if (l > 0) return ld4(ap + (size_t)t * ADIM + 4 * c4);
+        const float cs = cosang(e, jp, e.cl[t + (t >= p)]);
+        float4 v;
+        v.x = tanhf(cs * w.Wa0[4 * c4] + w.ba0[4 * c4]);
+        v.y = tanhf(cs * w.Wa0[4 * c4 + 1] + w.ba0[4 * c4 + 1]);
+        v.z = tanhf(cs * w.Wa0[4 * c4 + 2] + w.ba0[4 * c4 + 2]);
+        v.w = tanhf(cs * w.Wa0[4 * c4 + 3] + w.ba0[4 * c4 + 3]);
+        return v;
       });
       wave_sync();
+      int qrow[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int t = t0 + acc_row(ii);
+        qrow[ii] = t < na ? t + (t >= p) : p;  // rows past the end read a valid row, and are not used
+      }
       f4 aa[2] = {};
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) fa[ct].mma(aa[ct], rowA, Ident());
@@ -377,20 +422,24 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
           const int r = acc_row(ii), c = ct * 16 + acc_col(), t = t0 + r;
-          const float a1 = sl[r * LDF + c] + act<T>(aa[ct][ii] + baa[c]);
+          const float z = aa[ct][ii] + baa[c] + sm.PQ[p * PQW + c] + sm.PQ[qrow[ii] * PQW + ADIM + c];
+          const float a1 = sl[r * LDF + c] + act<T>(z);
           sl[r * LDF + c] = a1;
           if (t < na) b.af[((size_t)l * b.acap + abase + (int64_t)p * na + t) * ADIM + c] = a1;
         }
       wave_sync();
       f4 am[4] = {};
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, [](int k) { return k < 32 ? k : k + 32; });
+      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, Ident());
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int t = t0 + acc_row(ii);
-        const float wr = t < na ? e.swa[jp] * e.swa[e.cl[t + (t >= p)]] * geo.inv_asel : 0.f;
+        const float wr = t < na ? e.swa[jp] * e.swa[e.cl[qrow[ii]]] * geo.inv_asel : 0.f;
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) mr[ct] += wr * act<T>(am[ct][ii] + bea[ct * 16 + acc_col()]);
+        for (int ct = 0; ct < 4; ++ct) {
+          const int c = ct * 16 + acc_col();
+          mr[ct] += wr * act<T>(am[ct][ii] + bea[c] + sm.PQ[qrow[ii] * PQW + 2 * ADIM + c]);
+        }
       }
       wave_sync();
     }
@@ -406,12 +455,11 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   float aw[4] = {0.f, 0.f, 0.f, 0.f};
   for (int j0 = wv * 16; j0 < nn; j0 += NWG * 16) {
     // [n_i, n_j, e_ij]
-    stage<6, 3>(sl, LDF, [&](int sg, int r, int c4) -> float4 {
+    stage<4, 2>(sl, LDF, [&](int sg, int r, int c4) -> float4 {  // [n_j, e_ij]; n_i enters through nbias
       const int j = j0 + r;
       if (j >= nn) return make_float4(0.f, 0.f, 0.f, 0.f);
       const int c = 32 * (sg & 1) + 4 * c4;
-      if (sg < 2) return ld4(sm.ni + c);
-      if (sg < 4)
+      if (sg < 2)
         return l == 0 ? ld4(w.TN + e.tj[j] * NDIM + c) : ld4(b.nf + ((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c);
       return ld4(sm.El + j * LDE + c);
     });
@@ -420,8 +468,8 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
       opaque();  // load each column tile's weights here, not once for all tiles
-      Frag<T, 192> f;
-      f.load([&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; });
+      Frag<T, 128> f;
+      f.load([&](int c, int k) { return Wee[(NDIM + k) * EDIM + ct * 16 + c]; });
       f.mma(ae[ct], rowA, Ident());
     }
 #pragma unroll
@@ -432,7 +480,8 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
           const int c = ct * 16 + acc_col();
-          const float e1 = sm.El[j * LDE + c] + act<T>(ae[ct][ii] + bee[c]) + (cp >= 0 ? sm.Msg[cp * EDIM + c] : 0.f);
+          const float e1 =
+              sm.El[j * LDE + c] + act<T>(ae[ct][ii] + sm.nbias[c]) + (cp >= 0 ? sm.Msg[cp * EDIM + c] : 0.f);
           b.ef[erow(b, l, i, j) + c] = e1;
           aw[ct] += e.swe[j] * e1;
         }
@@ -510,7 +559,9 @@ struct SmemB {
   float slab[NWG][16 * LDB] __attribute__((aligned(16)));
   float Qacc[NWG][ASEL * QLD];  // per-wave sums of the terms of edge q
   float Pacc[ASEL * QLD];       // terms of edge p from its own angle row
-  float dn[NDIM], ni[NDIM] __attribute__((aligned(16))), xs[2 * NDIM], dagg[NDIM], dnsum[NWG][NDIM], zz[NDIM];
+  float PQ[ASEL * PQW];         // per-edge terms of the angle products
+  float dn[NDIM], ni[NDIM] __attribute__((aligned(16))), xs[2 * NDIM], dagg[NDIM], dnsum[NWG][NDIM], zz[NDIM],
+      nbias[EDIM];
   int slot[SEL];
 };
 
@@ -578,7 +629,12 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
     sm.xs[NDIM + tid] = agg * geo.inv_sel;
   }
   __syncthreads();
-  // ---------------- node backward
+  // ---------------- node backward (and the centre's part of every edge update)
+  if (tid < EDIM) {
+    float v = bee[tid];
+    for (int k = 0; k < NDIM; ++k) v += sm.ni[k] * Wee[k * EDIM + tid];
+    sm.nbias[tid] = v;
+  }
   if (tid < NDIM) {
     float z = bnn[tid];
     for (int k = 0; k < 2 * NDIM; ++k) z += sm.xs[k] * Wnn[k * NDIM + tid];
@@ -602,12 +658,11 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
   // ---------------- edges
   float dns[4] = {0.f, 0.f, 0.f, 0.f};
   for (int j0 = wv * 16; j0 < nn; j0 += NWG * 16) {
-    stage<6, 2>(sl, LDB, [&](int sg, int r, int c4) -> float4 {
+    stage<4, 2>(sl, LDB, [&](int sg, int r, int c4) -> float4 {  // [n_j, e_ij]; n_i enters through nbias
       const int j = j0 + r;
       if (j >= nn) return make_float4(0.f, 0.f, 0.f, 0.f);
       const int c = 32 * (sg & 1) + 4 * c4;
-      if (sg < 2) return ld4(sm.ni + c);
-      if (sg < 4)
+      if (sg < 2)
         return l == 0 ? ld4(w.TN + e.tj[j] * NDIM + c) : ld4(b.nf + ((size_t)(l - 1) * b.cap + e.jn[j]) * NDIM + c);
       if (l > 0) return ld4(b.ef + erow(b, l - 1, i, j) + c);
       float4 v;
@@ -634,12 +689,12 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
     for (int ct = 0; ct < 4; ++ct) {
       if constexpr (sizeof(T) == 2) {
         opaque();  // load each column tile's weights here, not once for all tiles
-        Frag<T, 192> f;
-        f.load([&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; });
+        Frag<T, 128> f;
+        f.load([&](int c, int k) { return Wee[(NDIM + k) * EDIM + ct * 16 + c]; });
         f.mma(ae[ct], rowA, Ident());
-      } else {  // float32 operands: 48 more registers per lane would spill; read W as it goes
+      } else {  // float32 operands: 32 more registers per lane would spill; read W as it goes
         Mma<T>::tile(ae[ct], [&](int r, int k) { return sl[r * LDB + k]; },
-                     [&](int c, int k) { return Wee[k * EDIM + ct * 16 + c]; }, 192);
+                     [&](int c, int k) { return Wee[(NDIM + k) * EDIM + ct * 16 + c]; }, 128);
       }
     }
     wave_sync();
@@ -656,11 +711,11 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
         if (ok) {
           d = pde[ct][ii] + e.swe[j] * sm.dagg[c];
           rs[ii] += pef[ct][ii] * sm.dagg[c];
-          const float t = act<T>(ae[ct][ii] + bee[c]);
+          const float t = act<T>(ae[ct][ii] + sm.nbias[c]);
           dz = d * (1.f - t * t);
         }
         de1[ct][ii] = d;
-        sl[r * LDB + c] = dz;  // dz_e over the n_i columns
+        sl[r * LDB + c] = dz;  // dz_e over the n_j columns (the products that read them are done)
         dns[ct] += dz;
       }
       rs[ii] = sum16(rs[ii]);
@@ -735,8 +790,9 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
       return k < 64 ? Wea[(32 + ct * 16 + c) * EDIM + k] : Waa[(64 + ct * 16 + c) * ADIM + k - 64];
     };
   };
-  Frag<T, 64> fm[4], fx[2];
-  Frag<T, 96> fa[2], fv[FV_RESIDENT ? 2 : 1];
+  Frag<T, ADIM> fm[4], fa[2];  // the angle rows' parts (first 32 inputs) of Wea, Waa
+  Frag<T, 64> fx[2];
+  Frag<T, 96> fv[FV_RESIDENT ? 2 : 1];
   Frag<T, 32> fy[2];
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) fm[ct].load([&](int c, int k) { return Wea[k * EDIM + ct * 16 + c]; });
@@ -747,6 +803,7 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
     fy[ct].load([&](int c, int k) { return Waa[(ct * 16 + c) * ADIM + k]; });
     if constexpr (FV_RESIDENT) fv[ct].load(wv_q(ct));
   }
+  edge_terms(Waa, Wea, sm.Ec, 0, e.cl, nc, sm.PQ);
   const int na = nc - 1;
   const int64_t abase = b.aoff[i];
   for (int p = wv; p < nc; p += NWG) {
@@ -756,16 +813,13 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
     const float *a1p = b.af + ((size_t)l * b.acap + abase + (int64_t)p * na) * ADIM;
     const float *a0p = b.af + ((size_t)(l > 0 ? l - 1 : 0) * b.acap + abase + (int64_t)p * na) * ADIM;
     for (int t0 = 0; t0 < na; t0 += 16) {
-      // [a', e_iq[:32], a, e_ip[:32]]
-      stage<4, 4>(sl, LDB, [&](int sg, int r, int c4) -> float4 {
+      // [a', a] of the tile's 16 angles; the edge terms come from PQ
+      stage<2, 2>(sl, LDB, [&](int sg, int r, int c4) -> float4 {
         const int t = t0 + r;
         if (t >= na) return make_float4(0.f, 0.f, 0.f, 0.f);
-        const int q = t + (t >= p);
         if (sg == 0) return ld4(a1p + (size_t)t * ADIM + 4 * c4);
-        if (sg == 1) return ld4(sm.Ec + q * ADIM + 4 * c4);
-        if (sg == 3) return ld4(sm.Ec + p * ADIM + 4 * c4);
         if (l > 0) return ld4(a0p + (size_t)t * ADIM + 4 * c4);
-        const float cs = cosang(e, jp, e.cl[q]);
+        const float cs = cosang(e, jp, e.cl[t + (t >= p)]);
         const int c = 4 * c4;
         float4 v;
         v.x = tanhf(cs * w.Wa0[c] + w.ba0[c]);
@@ -785,34 +839,37 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
       wave_sync();
       f4 am[4] = {}, aa[2] = {};
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, Ident());
+      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, Ident());  // a' (columns 0..31)
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)  // [a, e_ip, e_iq]: columns 64..127, then 32..63
-        fa[ct].mma(aa[ct], rowA, [](int k) { return k < 64 ? 64 + k : k - 32; });
+      for (int ct = 0; ct < 2; ++ct) fa[ct].mma(aa[ct], rowA, [](int k) { return ADIM + k; });  // a (32..63)
       float dwa[4], ta[2][4];
       int qv[4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int r = acc_row(ii), t = t0 + r;
         qv[ii] = t < na ? t + (t >= p) : -1;
+        const int qr = qv[ii] >= 0 ? qv[ii] : p;  // rows past the end read a valid row, unused
         const float wr = qv[ii] >= 0 ? e.swa[jp] * e.swa[e.cl[qv[ii]]] * geo.inv_asel : 0.f;
         float d = 0.f;
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
           const int c = ct * 16 + acc_col();
-          const float tm = act<T>(am[ct][ii] + bea[c]);
+          const float tm = act<T>(am[ct][ii] + bea[c] + sm.PQ[qr * PQW + 2 * ADIM + c]);
           const float dm = qv[ii] >= 0 ? sm.DM[p * EDIM + c] : 0.f;
           d += dm * tm;
-          sl[r * LDB + 128 + c] = wr * dm * (1.f - tm * tm);  // dz_m
+          sl[r * LDB + 64 + c] = wr * dm * (1.f - tm * tm);  // dz_m
         }
         dwa[ii] = sum16(d);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) ta[ct][ii] = act<T>(aa[ct][ii] + baa[ct * 16 + acc_col()]);
+        for (int ct = 0; ct < 2; ++ct) {
+          const int c = ct * 16 + acc_col();
+          ta[ct][ii] = act<T>(aa[ct][ii] + baa[c] + sm.PQ[p * PQW + c] + sm.PQ[qr * PQW + ADIM + c]);
+        }
       }
       wave_sync();
       f4 ax[2] = {};
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) fx[ct].mma(ax[ct], rowA, [](int k) { return 128 + k; });
+      for (int ct = 0; ct < 2; ++ct) fx[ct].mma(ax[ct], rowA, [](int k) { return 64 + k; });
       float da1[2][4];
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
@@ -824,7 +881,7 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
           if (qv[ii] >= 0) d = dap[ct][ii] + ax[ct][ii];
           da1[ct][ii] = d;
           const float dz = d * (1.f - ta[ct][ii] * ta[ct][ii]);
-          sl[r * LDB + 192 + c] = dz;  // dz_a
+          sl[r * LDB + 128 + c] = dz;  // dz_a
           S[ct] += dz;
         }
       }
@@ -832,14 +889,14 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
       f4 ay[2] = {}, av[2] = {};
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
-        fy[ct].mma(ay[ct], rowA, [](int k) { return 192 + k; });
+        fy[ct].mma(ay[ct], rowA, [](int k) { return 128 + k; });
         if constexpr (FV_RESIDENT) {
-          fv[ct].mma(av[ct], rowA, [](int k) { return 128 + k; });
+          fv[ct].mma(av[ct], rowA, [](int k) { return 64 + k; });
         } else {
           opaque();
           Frag<T, 96> f;
           f.load(wv_q(ct));
-          f.mma(av[ct], rowA, [](int k) { return 128 + k; });
+          f.mma(av[ct], rowA, [](int k) { return 64 + k; });
         }
       }
       float dc[4];
@@ -856,7 +913,7 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
             Q[qv[ii] * QLD + c] += av[ct][ii];
           }
           if (l == 0) {
-            const float a0 = sl[r * LDB + 64 + c];
+            const float a0 = sl[r * LDB + ADIM + c];
             d += dal * (1.f - a0 * a0) * w.Wa0[c];
           }
         }

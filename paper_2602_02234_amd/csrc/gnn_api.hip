@@ -24,8 +24,8 @@ struct dp_gnn {
   gnn::Buffers b;
   double *fpark = nullptr;  // forces when only the virial is asked for
   int64_t fpark_cap = 0;
-  int64_t *tot_host = nullptr;  // pinned: angles, edges
-  int64_t last_angles = 0, last_edges = 0;
+  int64_t *tot_host = nullptr;  // pinned: angles, edges, angle-list edges
+  int64_t last_angles = 0, last_edges = 0, last_aedges = 0;
   // per-phase device time (dp_gnn_profile_enable): lists, forward layers, backward
   // layers, forces and reductions
   bool prof = false;
@@ -176,7 +176,7 @@ int ensure_atoms(gnn::Buffers &b, int64_t n) {
   b.aoff = nullptr; b.nf = b.ef = b.de = b.dnj = b.dnl = b.gs = nullptr;
   b.cap = 0;
   const size_t c = (size_t)cap, e = c * SEL * EDIM;
-  G_TRY(hipMalloc(&b.aoff, (c + 2) * sizeof(int64_t)));
+  G_TRY(hipMalloc(&b.aoff, (c + 3) * sizeof(int64_t)));
   G_TRY(hipMalloc(&b.nf, 2 * c * NDIM * sizeof(float)));
   G_TRY(hipMalloc(&b.ef, 3 * e * sizeof(float)));
   G_TRY(hipMalloc(&b.de, e * sizeof(float)));
@@ -238,7 +238,7 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
   if (m->prof) G_TRY(hipEventRecord(m->ev[1], st));
   // the angle count sizes the angle buffers: one host round trip per step
   G_TRY(hipMemcpyAsync(m->tot_host, m->b.aoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  G_TRY(hipMemcpyAsync(m->tot_host + 1, m->b.aoff + m->b.cap + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  G_TRY(hipMemcpyAsync(m->tot_host + 1, m->b.aoff + m->b.cap + 1, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   G_TRY(hipMemcpyAsync(ws.flags_host, ws.flags, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
   G_TRY(hipStreamSynchronize(st));
   if (m->prof) {
@@ -250,6 +250,7 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
   const int64_t na = m->tot_host[0];
   m->last_angles = na;
   m->last_edges = m->tot_host[1];
+  m->last_aedges = m->tot_host[2];
   s = ensure_angles(m->b, std::max<int64_t>(na, 1));
   if (s != DP_OK) return s;
   const bool bwd = forces || virial;
@@ -326,7 +327,7 @@ int dp_gnn_load(const char *path, int precision, int device, dp_gnn **out) {
   m->device = device;
   m->prec = precision;
   int s = load_weights(m, path);
-  if (s == DP_OK && hipHostMalloc(&m->tot_host, 2 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+  if (s == DP_OK && hipHostMalloc(&m->tot_host, 3 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
     set_error("dp_gnn_load: pinned allocation failed");
     s = DP_ERR_OOM;
   }
@@ -381,12 +382,13 @@ int dp_gnn_compute_device(dp_gnn *m, int64_t natoms, const double *d_coords, con
                   (hipStream_t)hip_stream);
 }
 
-int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angles) {
+int dp_gnn_graph_size(const dp_gnn *m, int64_t *edges, int64_t *angle_edges, int64_t *angles) {
   if (!m) {
     set_error("dp_gnn_graph_size: bad argument");
     return DP_ERR_ARG;
   }
   if (edges) *edges = m->last_edges;
+  if (angle_edges) *angle_edges = m->last_aedges;
   if (angles) *angles = m->last_angles;
   return DP_OK;
 }

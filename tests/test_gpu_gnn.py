@@ -84,7 +84,8 @@ def test_gnn_matches_oracle(gnn_models, ognn, name, prec):
     X, t, box = SYSTEMS[name]
     ref = _ref(ognn, name)
     out = gnn_models[prec].compute(X, t, box, forces=True, atom_energy=True)
-    assert gnn_models[prec].angles() == ref["n_angles"]
+    g = build_graph(ognn, X, t, box)
+    assert gnn_models[prec].graph_size() == (len(g["src"]), len(np.unique(g["ep"])), ref["n_angles"])
     m = compare(out, ref, len(X))
     print(f"GNN {name} {len(X)} atoms, {ref['n_angles']} angles, {prec}: {m}")
     assert_within_gnn(m, prec)
@@ -171,7 +172,7 @@ def test_gnn_edge_cases(torch_cuda, gnn_models, ognn):
     out = m.compute(X1, t1, None, atom_energy=True)
     ref = evaluate(ognn, X1, t1, None)
     assert abs(out["E"] - ref["E"]) <= TOL_GNN["fp32"]["e_atom"]
-    assert np.all(out["F"] == 0.0) and m.graph_size() == (0, 0)
+    assert np.all(out["F"] == 0.0) and m.graph_size() == (0, 0, 0)
     X, t = _cluster(200, 11, spread=3.2, dmin=0.8)  # every atom within rc of more than 120 others
     dev = torch.device("cuda:0")
     F = torch.full((200, 3), 7.0, dtype=torch.float64, device=dev)
