@@ -25,7 +25,7 @@ the potential; neighbour lists within a cutoff, Section II and IV):
 * :mod:`oracle.nve` -- a velocity-Verlet driver for the energy-drift check.
 
 The paper prints no model equations; the functional form follows the reading
-listed in the design notes (quintic switch, switch-weighted gated softmax,
+stated in oracle/dp.py (quintic switch, switch-weighted gated softmax,
 residual LayerNorm update, 1/sel descriptor normalisation).  Every function
 here is pinned by tests under ``tests/`` against closed forms, brute force,
 special cases and finite differences; the agreement with the paper's trained

@@ -2,7 +2,7 @@
 
 Reading of the paper (Section II names the parts; the sizes are those of the
 attention model studied here; the functional form is the reading recorded in
-the design notes):
+the model definition below):
 
 Environment, per neighbour j of atom i (Delta = x_j - x_i, r = |Delta|):
     u = (r - rcs) / (rc - rcs);  sw = 1 for r < rcs, u^3 (-6u^2 + 15u - 10) + 1 below rc

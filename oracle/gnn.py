@@ -3,7 +3,7 @@ TEST INFRASTRUCTURE ONLY (imported by tests and the smoke check, never by the li
 
 The paper's second model family (DPA3, Section II) replaces attention by graph
 message passing over bonds and angles (a line-graph series).  It gives no
-equations; this is the reading used here (the design notes list it):
+equations; this is the reading used here:
 
 Graph.  Edges are the ordered pairs (i, j), j in N(i) (r_ij < rc = 6 A, the same
 lists as the attention model).  Angles at centre i are the ordered pairs (j, k) of

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (imported by tests and the smoke check, never by the li
 The paper's DPA2 models (Section II) stack repformer layers that update a single-atom
 representation g1 and a pair representation g2 and pass messages from neighbour to
 neighbour, so the receptive field grows by rc per layer; the paper names the parts
-only.  This is the reading used here (the design notes list it):
+only.  This is the reading used here:
 
 Environment as in the attention model: Delta_ij = x_j - x_i, r, sw(r) (quintic, smooth
 from rcs = 0.5 A to rc = 6 A), s = sw / r, rhat = Delta / r, R_ij = (s, s rhat).
