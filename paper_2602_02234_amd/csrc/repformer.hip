@@ -1,13 +1,13 @@
 // Repformer-style model kernels for gfx950: one workgroup (four waves) per centre atom
 // and one launch per layer, forward and backward (a layer's pair update and convolution
 // read the neighbours' g1 of the layer before, so layers meet at launch boundaries).
-// The products are small (pair width 32, at most 120 neighbours, node input 224), so
-// they run as float32 VALU dot products from LDS with a fixed summation order; the
-// attention is evaluated one query row per wave (scores for two keys per lane), and
-// its backward in a row pass (dQ, row terms of the gate) and a column pass (dK, dV and
-// the key terms of the switch and gate, with the scores recomputed), like the
-// attention descriptor.  Every sum has one owner and a fixed order: results are
-// deterministic.
+// The neighbour-to-neighbour attention, the largest product (every ordered pair of an
+// atom's up to 120 neighbours, width 32), runs on MFMA (16x16x4 f32): a wave takes a
+// tile of 16 queries in the forward and the backward's row pass (statistics, dQ, the
+// row terms of the gate), and a tile of 16 keys in the column pass (dK, dV, the key
+// terms of the switch and gate, with the scores recomputed).  The per-edge products
+// (pair width 32, node input 224) stay float32 VALU dot products from LDS.  Every sum
+// has one owner and a fixed order: results are deterministic.
 #include <cmath>
 
 #include "dp_env.h"
@@ -20,6 +20,7 @@ namespace {
 constexpr int NWG = 4;
 constexpr int NT = NWG * 64;
 constexpr int LQ = G2D + 1;   // row stride of [edge][32] LDS arrays (odd: rows fall in different banks)
+constexpr int LQA = G2D + 4;  // row stride of the attention operands Q, K, V, dY (16-byte aligned rows)
 constexpr int LG = G1D + 1;   // row stride of [edge][64]
 
 __device__ __forceinline__ bool failed(const unsigned *flags) { return (flags[0] & FLAG_ERRORS) != 0u; }
@@ -193,9 +194,9 @@ __device__ void pair_and_qkv(const Weights &w, int l, int nn, float *G2, const f
       k += x * wk[t];
       v += x * wvv[t];
     }
-    Q[j * LQ + c] = q;
-    K[j * LQ + c] = k;
-    V[j * LQ + c] = v;
+    Q[j * LQA + c] = q;
+    K[j * LQA + c] = k;
+    V[j * LQA + c] = v;
   }
   __syncthreads();
 }
@@ -248,14 +249,60 @@ __device__ void node_inputs(const EnvR &e, int nn, const float *G2B, const float
   __syncthreads();
 }
 
+// The attention on MFMA (16x16x4 f32).  Score tiles are kept transposed, keys x
+// queries: lane l holds S^T[key 16 kt + 4 (l / 16) + i][query q0 + l % 16], so the
+// weights of a query are reduced over i, over the key tiles and across l / 16, and they
+// are already the B operand of Y^T = V^T A^T with the k order permuted as in the
+// products below (step s of a key tile takes key 16 kt + 4 (l / 16) + s).
+// acc += sum_{c < 32} A[r][c] B[col][c] with lane's A row (r = l % 16) at arow and B row
+// (col = l % 16) at brow, 16-byte aligned rows of 32 floats; nullptr reads as zeros.
+__device__ __forceinline__ void dot32_tile(f4 &acc, const float *arow, const float *brow) {
+  const int kq = lane_id() >> 4;
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 a = arow ? ld4(arow + 16 * kb + 4 * kq) : z;
+    const float4 b = brow ? ld4(brow + 16 * kb + 4 * kq) : z;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+  }
+}
+constexpr int NKT = (SEL + 15) / 16;  // key (or query) tiles of 16
+
+// A operand of out^T = W dX^T for a row-major [32][32] W (dE/dx = dE/dy W^T for y = x W):
+// lane l holds W[16 ot + l % 16][16 ct + 4 (l / 16) + ii], the k order of the rows of an
+// accumulator tile, so a dX^T tile from a product above is the B operand as it stands.
+__device__ __forceinline__ void load_wt(const float *W, float (&r)[2][2][4]) {
+  const int kq = lane_id() >> 4, col = lane_id() & 15;
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) r[ot][ct][ii] = W[(16 * ot + col) * G2D + 16 * ct + 4 * kq + ii];
+}
+// out[ot] += W dX^T over the 32 features, x[ct][ii] = dX^T[16 ct + 4 (l / 16) + ii][l % 16].
+__device__ __forceinline__ void wt_product(f4 (&out)[2], const float (&r)[2][2][4], const f4 (&x)[2]) {
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+        out[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[ot][ct][ii], x[ct][ii], out[ot], 0, 0, 0);
+}
+
 // ------------------------------------------------------------------ forward
 struct SmemF {
   EnvR env;
   float G1J[SEL * LG];
   float G2[SEL * LQ];   // layer input, then the layer's output g2
   float G2A[SEL * LQ];
-  float Q[SEL * LQ], K[SEL * LQ], V[SEL * LQ];
-  float arow[NWG][SEL];
+  float Q[SEL * LQA] __attribute__((aligned(16)));
+  float K[SEL * LQA] __attribute__((aligned(16)));
+  float V[SEL * LQA] __attribute__((aligned(16)));
   float g1i[G1D], T[G2D * 4], xs[XD], part[NWG][G1D], zc[G1D];
   float y1[FWID], t2[FWID], dp[FWID];
 };
@@ -276,51 +323,80 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
   __syncthreads();
   pair_and_qkv(w, l, nn, sm.G2, sm.G1J, sm.G2A, sm.Q, sm.K, sm.V, false);
 
-  // attention, one query row per wave
+  // attention, one tile of 16 queries per wave
   const float isq = 1.f / sqrtf((float)G2D);
-  const int half = (nn + 1) >> 1;
-  for (int j = wv; j < nn; j += NWG) {
-    float qj[G2D];  // the query row, the same in every lane
+  const int nkt = (nn + 15) >> 4;
+  const int kq = ln >> 4, col = ln & 15;
+  for (int qt = wv; qt < nkt; qt += NWG) {
+    const int qme = 16 * qt + col;  // this lane's query
+    const bool qok = qme < nn;
+    f4 st[NKT];
 #pragma unroll
-    for (int c = 0; c < G2D; ++c) qj[c] = sm.Q[j * LQ + c];
-    float sc[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      sc[h] = -INFINITY;
-      if (k < nn) {
-        float d = 0.f;
-#pragma unroll
-        for (int c = 0; c < G2D; ++c) d += qj[c] * sm.K[k * LQ + c];
-        sc[h] = d * isq;
+    for (int kt = 0; kt < NKT; ++kt) {
+      st[kt] = f4{0.f, 0.f, 0.f, 0.f};
+      if (kt < nkt) {
+        const int kr = 16 * kt + col;
+        dot32_tile(st[kt], kr < nn ? sm.K + kr * LQA : nullptr, qok ? sm.Q + qme * LQA : nullptr);
       }
     }
-    const float m = wmax(fmaxf(sc[0], sc[1]));
-    float ex[2];
+    // weights of the lane's query over its keys: max, then sw_k exp(S - max) / sum, times the gate
+    float m = -INFINITY;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      ex[h] = k < nn ? e.sw[k] * __expf(sc[h] - m) : 0.f;
-    }
-    const float Z = wsum(ex[0] + ex[1]);
+    for (int kt = 0; kt < NKT; ++kt)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      if (k < nn) sm.arow[wv][k] = ex[h] / Z * gate(e, j, k);
+      for (int ii = 0; ii < 4; ++ii) {
+        const int k = 16 * kt + 4 * kq + ii;
+        if (kt < nkt && k < nn) m = fmaxf(m, st[kt][ii] * isq);
+      }
+    m = fmaxf(m, __shfl_xor(m, 16));
+    m = fmaxf(m, __shfl_xor(m, 32));
+    float z = 0.f;
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int k = 16 * kt + 4 * kq + ii;
+        const float ex = (kt < nkt && k < nn) ? e.sw[k] * __expf(st[kt][ii] * isq - m) : 0.f;
+        st[kt][ii] = ex;
+        z += ex;
+      }
+    z += __shfl_xor(z, 16);
+    z += __shfl_xor(z, 32);
+    const float iz = qok ? 1.f / z : 0.f;
+    const float hx = e.rh[3 * (qok ? qme : 0)], hy = e.rh[3 * (qok ? qme : 0) + 1], hz = e.rh[3 * (qok ? qme : 0) + 2];
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int k = 16 * kt + 4 * kq + ii;
+        const int kk = k < nn ? k : 0;
+        st[kt][ii] *= iz * (hx * e.rh[3 * kk] + hy * e.rh[3 * kk + 1] + hz * e.rh[3 * kk + 2]);
+      }
+    // Y^T[c][q] = sum_k V[k][c] A^T[k][q], two tiles of 16 features
+    f4 yt[2] = {};
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+      if (kt >= nkt) break;
+#pragma unroll
+      for (int ss = 0; ss < 4; ++ss) {
+        const int k = 16 * kt + 4 * kq + ss;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const float v = k < nn ? sm.V[k * LQA + 16 * ct + col] : 0.f;
+          yt[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(v, st[kt][ss], yt[ct], 0, 0, 0);
+        }
+      }
     }
-    wave_sync();
-    // Y_j[c]: lanes c and c + 32 take the two halves of k, in order
-    const int c = ln & 31;
-    const int k0 = ln < 32 ? 0 : half, k1 = ln < 32 ? half : nn;
-    float y = 0.f;
-    for (int k = k0; k < k1; ++k) y += sm.arow[wv][k] * sm.V[k * LQ + c];
-    y += __shfl_xor(y, 32);
-    if (ln < 32) {
-      const float g2b = sm.G2A[j * LQ + c] + y;
-      sm.G2[j * LQ + c] = g2b;
-      b.g2f[erow2(b, l, i, j) + c] = g2b;
-    }
-    wave_sync();
+    if (qok)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int c = 16 * ct + 4 * kq + ii;
+          const float g2b = sm.G2A[qme * LQ + c] + yt[ct][ii];
+          sm.G2[qme * LQ + c] = g2b;
+          b.g2f[erow2(b, l, i, qme) + c] = g2b;
+        }
   }
   __syncthreads();
 
@@ -378,13 +454,13 @@ struct SmemB {
   float G1J[SEL * LG];
   float G2[SEL * LQ];    // layer input g2, then the pair update's tanh term
   float G2A[SEL * LQ];   // after the pair update; later dE/dg2a
-  float Q[SEL * LQ], K[SEL * LQ], V[SEL * LQ];
+  float Q[SEL * LQA] __attribute__((aligned(16)));
+  float K[SEL * LQA] __attribute__((aligned(16)));
+  float V[SEL * LQA] __attribute__((aligned(16)));
   float G2B[SEL * LQ];   // the layer's output g2
-  float DY[SEL * LQ];    // dE/dg2 of the output; later the pair update's dz
+  float DY[SEL * LQA] __attribute__((aligned(16)));  // dE/dg2 of the output; later the pair update's dz
   float EG[SEL * GSN];   // per-edge dE/ds, dE/dsw, dE/drhat
-  float stat[3][SEL];    // per query row: max score, normaliser, rho
-  float arow[NWG][2][SEL];
-  float qrow[NWG][2 * G2D];
+  float stat[3][SEL];    // per query row: max score, 1 / normaliser, rho
   float g1i[G1D], T[G2D * 4], xs[XD], dg1[G1D], dxn[XD], dT[G2D * 4], part[NWG][G1D], zc[G1D];
   int slot[SEL];
 };
@@ -405,10 +481,10 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i);
   load_rows<G2D>(sm.G2B, LQ, nn, [&](int j) { return b.g2f + erow2(b, l, i, j); });
   if (top) {
-    for (int k = tid; k < nn * G2D; k += NT) sm.DY[(k >> 5) * LQ + (k & 31)] = 0.f;
+    for (int k = tid; k < nn * G2D; k += NT) sm.DY[(k >> 5) * LQA + (k & 31)] = 0.f;
     for (int k = tid; k < nn * GSN; k += NT) sm.EG[k] = 0.f;
   } else {
-    load_rows<G2D>(sm.DY, LQ, nn, [&](int j) { return b.dg2 + ((size_t)i * SEL + j) * G2D; });
+    load_rows<G2D>(sm.DY, LQA, nn, [&](int j) { return b.dg2 + ((size_t)i * SEL + j) * G2D; });
     load_rows<GSN>(sm.EG, GSN, nn, [&](int j) { return b.gs + ((size_t)i * SEL + j) * GSN; });
   }
   if (!top)
@@ -473,9 +549,9 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   // dE/dg2 of the output from the contraction and the convolution; edge terms of R and sw
   for (int o = tid; o < nn * G2D; o += NT) {
     const int j = o >> 5, c = o & 31;
-    float v = sm.DY[j * LQ + c] + e.sw[j] * dc[c] * geo.inv_sel * sm.G1J[j * LG + c];
+    float v = sm.DY[j * LQA + c] + e.sw[j] * dc[c] * geo.inv_sel * sm.G1J[j * LG + c];
     for (int a = 0; a < 4; ++a) v += sm.dT[c * 4 + a] * Rcomp(e, j, a);
-    sm.DY[j * LQ + c] = v;
+    sm.DY[j * LQA + c] = v;
   }
   for (int j = tid; j < nn; j += NT) {
     float dR[4] = {0.f, 0.f, 0.f, 0.f}, dswc = 0.f;
@@ -491,152 +567,210 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   }
   __syncthreads();
 
-  // rows c = lane % 32 of Wq, Wk, Wv for the transposed products dE/dg2a += dQ Wq^T + ...
-  float rq[G2D], rk[G2D], rv[G2D];
-  {
-    const int c = ln & 31;
-#pragma unroll
-    for (int q = 0; q < G2D; ++q) {
-      rq[q] = w.Wq[l][c * G2D + q];
-      rk[q] = w.Wk[l][c * G2D + q];
-      rv[q] = w.Wv[l][c * G2D + q];
-    }
-  }
-  // attention backward, row pass: one query row j per wave
+  // attention backward on MFMA.  Row pass: one tile of 16 queries per wave with the
+  // score tiles transposed as in the forward; the query's statistics (max, 1 / normaliser,
+  // rho), its terms of the gate gradient, dQ^T = K^T dS^T and the query rows of
+  // dE/dg2a = dY + dQ Wq^T.
   const float isq = 1.f / sqrtf((float)G2D);
-  const int half = (nn + 1) >> 1;
-  for (int j = wv; j < nn; j += NWG) {
-    float qj[G2D], dyj[G2D];  // the query row and its output gradient, the same in every lane
+  const int nkt = (nn + 15) >> 4;
+  const int kq = ln >> 4, col = ln & 15;
+  {
+    float wq[2][2][4];
+    load_wt(w.Wq[l], wq);
+    for (int qt = wv; qt < nkt; qt += NWG) {
+      const int qme = 16 * qt + col;
+      const bool qok = qme < nn;
+      f4 st[NKT], da[NKT];  // S^T and dA^T = V dY^T: [key 16 kt + 4 kq + ii][query qme]
 #pragma unroll
-    for (int c = 0; c < G2D; ++c) {
-      qj[c] = sm.Q[j * LQ + c];
-      dyj[c] = sm.DY[j * LQ + c];
-    }
-    float sc[2], P[2], gt[2], dP[2], dGt[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      sc[h] = -INFINITY;
-      if (k < nn) {
-        float d = 0.f;
-#pragma unroll
-        for (int c = 0; c < G2D; ++c) d += qj[c] * sm.K[k * LQ + c];
-        sc[h] = d * isq;
+      for (int kt = 0; kt < NKT; ++kt) {
+        st[kt] = f4{0.f, 0.f, 0.f, 0.f};
+        da[kt] = f4{0.f, 0.f, 0.f, 0.f};
+        if (kt < nkt) {
+          const int kr = 16 * kt + col;
+          dot32_tile(st[kt], kr < nn ? sm.K + kr * LQA : nullptr, qok ? sm.Q + qme * LQA : nullptr);
+          dot32_tile(da[kt], kr < nn ? sm.V + kr * LQA : nullptr, qok ? sm.DY + qme * LQA : nullptr);
+        }
       }
-    }
-    const float m = wmax(fmaxf(sc[0], sc[1]));
-    float ex[2];
+      float m = -INFINITY;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      ex[h] = k < nn ? e.sw[k] * __expf(sc[h] - m) : 0.f;
-    }
-    const float Z = wsum(ex[0] + ex[1]);
-    float rho = 0.f, hr[3] = {0.f, 0.f, 0.f};
+      for (int kt = 0; kt < NKT; ++kt)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      P[h] = ex[h] / Z;
-      dP[h] = dGt[h] = gt[h] = 0.f;
-      if (k < nn) {
-        gt[h] = gate(e, j, k);
-        float dA = 0.f;
+        for (int ii = 0; ii < 4; ++ii) {
+          const int k = 16 * kt + 4 * kq + ii;
+          if (kt < nkt && k < nn) m = fmaxf(m, st[kt][ii] * isq);
+        }
+      m = fmaxf(m, __shfl_xor(m, 16));
+      m = fmaxf(m, __shfl_xor(m, 32));
+      float z = 0.f;
 #pragma unroll
-        for (int c = 0; c < G2D; ++c) dA += dyj[c] * sm.V[k * LQ + c];
-        dP[h] = dA * gt[h];
-        dGt[h] = dA * P[h];
-        rho += dP[h] * P[h];
-        for (int a = 0; a < 3; ++a) hr[a] += dGt[h] * e.rh[3 * k + a];
+      for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int k = 16 * kt + 4 * kq + ii;
+          const float ex = (kt < nkt && k < nn) ? e.sw[k] * __expf(st[kt][ii] * isq - m) : 0.f;
+          st[kt][ii] = ex;
+          z += ex;
+        }
+      z += __shfl_xor(z, 16);
+      z += __shfl_xor(z, 32);
+      const float iz = qok ? 1.f / z : 0.f;
+      const int qq = qok ? qme : 0;
+      const float hx = e.rh[3 * qq], hy = e.rh[3 * qq + 1], hz = e.rh[3 * qq + 2];
+      // P, dP = dA gate, rho = sum_k dP P and the row terms sum_k dA P rhat_k of the gate
+      float rho = 0.f, h0 = 0.f, h1 = 0.f, h2 = 0.f;
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int k = 16 * kt + 4 * kq + ii;
+          const int kk = k < nn ? k : 0;
+          const float rx = e.rh[3 * kk], ry = e.rh[3 * kk + 1], rz = e.rh[3 * kk + 2];
+          const float P = st[kt][ii] * iz, dA = da[kt][ii];
+          const float dP = dA * (hx * rx + hy * ry + hz * rz), dG = dA * P;
+          rho += dP * P;
+          h0 += dG * rx;
+          h1 += dG * ry;
+          h2 += dG * rz;
+          st[kt][ii] = P;
+          da[kt][ii] = dP;
+        }
+#pragma unroll
+      for (int o = 16; o < 64; o <<= 1) {
+        rho += __shfl_xor(rho, o);
+        h0 += __shfl_xor(h0, o);
+        h1 += __shfl_xor(h1, o);
+        h2 += __shfl_xor(h2, o);
       }
-    }
-    rho = wsum(rho);
-    for (int a = 0; a < 3; ++a) hr[a] = wsum(hr[a]);
+      if (qok && kq == 0) {
+        sm.stat[0][qme] = m;
+        sm.stat[1][qme] = iz;
+        sm.stat[2][qme] = rho;
+        sm.EG[qme * GSN + 2] += h0;
+        sm.EG[qme * GSN + 3] += h1;
+        sm.EG[qme * GSN + 4] += h2;
+      }
+      // dS^T = P (dP - rho) / sqrt(32); dQ^T[c][q] = sum_k K[k][c] dS^T[k][q]
+      f4 dq[2] = {};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = ln + 64 * h;
-      if (k < nn) sm.arow[wv][0][k] = P[h] * (dP[h] - rho) * isq;  // dS_jk
-    }
-    if (ln == 0) {
-      sm.stat[0][j] = m;
-      sm.stat[1][j] = Z;
-      sm.stat[2][j] = rho;
-      for (int a = 0; a < 3; ++a) sm.EG[j * GSN + 2 + a] += hr[a];
-    }
-    wave_sync();
-    const int c = ln & 31;
-    const int k0 = ln < 32 ? 0 : half, k1 = ln < 32 ? half : nn;
-    float dq = 0.f;
-    for (int k = k0; k < k1; ++k) dq += sm.arow[wv][0][k] * sm.K[k * LQ + c];
-    dq += __shfl_xor(dq, 32);
-    if (ln < 32) sm.qrow[wv][c] = dq;
-    wave_sync();
-    if (ln < 32) {
-      float v = sm.DY[j * LQ + c];
+      for (int kt = 0; kt < NKT; ++kt) {
+        if (kt >= nkt) break;
 #pragma unroll
-      for (int q = 0; q < G2D; ++q) v += sm.qrow[wv][q] * rq[q];
-      sm.G2A[j * LQ + c] = v;  // dE/dg2a, row terms
+        for (int ss = 0; ss < 4; ++ss) {
+          const int k = 16 * kt + 4 * kq + ss;
+          const float ds = st[kt][ss] * (da[kt][ss] - rho) * isq;
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const float kv = k < nn ? sm.K[k * LQA + 16 * ct + col] : 0.f;
+            dq[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, ds, dq[ct], 0, 0, 0);
+          }
+        }
+      }
+      f4 o[2] = {};
+      wt_product(o, wq, dq);
+      if (qok)
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int c = 16 * ot + 4 * kq + ii;
+            sm.G2A[qme * LQ + c] = sm.DY[qme * LQA + c] + o[ot][ii];  // dE/dg2a, row terms
+          }
     }
-    wave_sync();
   }
   __syncthreads();
-  // column pass: one key k per wave, scores recomputed against every query row
-  for (int k = wv; k < nn; k += NWG) {
-    float kk[G2D], vk[G2D];  // the key row and its value row, the same in every lane
+  // column pass: one tile of 16 keys per wave, scores S[query][key] recomputed; the key
+  // terms of the switch and gate, dV^T = dY^T A, dK^T = Q^T dS and the key rows of
+  // dE/dg2a += dV Wv^T + dK Wk^T.
+  {
+    float wk[2][2][4], wvv[2][2][4];
+    load_wt(w.Wk[l], wk);
+    load_wt(w.Wv[l], wvv);
+    for (int kt = wv; kt < nkt; kt += NWG) {
+      const int kme = 16 * kt + col;
+      const bool kok = kme < nn;
+      f4 s[NKT], da[NKT];  // S and dA = dY V^T: [query 16 jt + 4 kq + ii][key kme]
 #pragma unroll
-    for (int c = 0; c < G2D; ++c) {
-      kk[c] = sm.K[k * LQ + c];
-      vk[c] = sm.V[k * LQ + c];
-    }
-    float dsk = 0.f, hk[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = ln + 64 * h;
-      if (j < nn) {
-        float d = 0.f, dA = 0.f;
-#pragma unroll
-        for (int c = 0; c < G2D; ++c) {
-          d += sm.Q[j * LQ + c] * kk[c];
-          dA += sm.DY[j * LQ + c] * vk[c];
+      for (int jt = 0; jt < NKT; ++jt) {
+        s[jt] = f4{0.f, 0.f, 0.f, 0.f};
+        da[jt] = f4{0.f, 0.f, 0.f, 0.f};
+        if (jt < nkt) {
+          const int jr = 16 * jt + col;
+          dot32_tile(s[jt], jr < nn ? sm.Q + jr * LQA : nullptr, kok ? sm.K + kme * LQA : nullptr);
+          dot32_tile(da[jt], jr < nn ? sm.DY + jr * LQA : nullptr, kok ? sm.V + kme * LQA : nullptr);
         }
-        const float exz = __expf(d * isq - sm.stat[0][j]) / sm.stat[1][j];
-        const float P = e.sw[k] * exz, gt = gate(e, j, k);
-        const float dP = dA * gt, dGt = dA * P, rho = sm.stat[2][j];
-        sm.arow[wv][0][j] = P * gt;                 // A_jk
-        sm.arow[wv][1][j] = P * (dP - rho) * isq;   // dS_jk
-        dsk += exz * (dP - rho);
-        for (int a = 0; a < 3; ++a) hk[a] += dGt * e.rh[3 * j + a];
       }
-    }
-    dsk = wsum(dsk);
-    for (int a = 0; a < 3; ++a) hk[a] = wsum(hk[a]);
-    if (ln == 0) {
-      sm.EG[k * GSN + 1] += dsk;
-      for (int a = 0; a < 3; ++a) sm.EG[k * GSN + 2 + a] += hk[a];
-    }
-    wave_sync();
-    // lanes 0..31: dV_k[c] = sum_j A_jk dY_j[c]; lanes 32..63: dK_k[c] = sum_j dS_jk Q_j[c]
-    const int c = ln & 31;
-    float v = 0.f;
-    if (ln < 32)
-      for (int j = 0; j < nn; ++j) v += sm.arow[wv][0][j] * sm.DY[j * LQ + c];
-    else
-      for (int j = 0; j < nn; ++j) v += sm.arow[wv][1][j] * sm.Q[j * LQ + c];
-    sm.qrow[wv][ln] = v;
-    wave_sync();
-    if (ln < 32) {
-      float u = sm.G2A[k * LQ + c];
+      const int kk = kok ? kme : 0;
+      const float kx = e.rh[3 * kk], ky = e.rh[3 * kk + 1], kz = e.rh[3 * kk + 2], swk = e.sw[kk];
+      float dsk = 0.f, h0 = 0.f, h1 = 0.f, h2 = 0.f;
 #pragma unroll
-      for (int q = 0; q < G2D; ++q) u += sm.qrow[wv][q] * rv[q] + sm.qrow[wv][G2D + q] * rk[q];
-      sm.G2A[k * LQ + c] = u;  // dE/dg2a, complete
+      for (int jt = 0; jt < NKT; ++jt)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = 16 * jt + 4 * kq + ii;
+          float A = 0.f, ds = 0.f;
+          if (kok && j < nn) {
+            const float exz = __expf(s[jt][ii] * isq - sm.stat[0][j]) * sm.stat[1][j];
+            const float rx = e.rh[3 * j], ry = e.rh[3 * j + 1], rz = e.rh[3 * j + 2];
+            const float P = swk * exz, g = rx * kx + ry * ky + rz * kz, dA = da[jt][ii];
+            const float dP = dA * g, dG = dA * P, rho = sm.stat[2][j];
+            A = P * g;
+            ds = P * (dP - rho) * isq;
+            dsk += exz * (dP - rho);
+            h0 += dG * rx;
+            h1 += dG * ry;
+            h2 += dG * rz;
+          }
+          s[jt][ii] = A;
+          da[jt][ii] = ds;
+        }
+#pragma unroll
+      for (int o = 16; o < 64; o <<= 1) {
+        dsk += __shfl_xor(dsk, o);
+        h0 += __shfl_xor(h0, o);
+        h1 += __shfl_xor(h1, o);
+        h2 += __shfl_xor(h2, o);
+      }
+      if (kok && kq == 0) {
+        sm.EG[kme * GSN + 1] += dsk;
+        sm.EG[kme * GSN + 2] += h0;
+        sm.EG[kme * GSN + 3] += h1;
+        sm.EG[kme * GSN + 4] += h2;
+      }
+      f4 dv[2] = {}, dk[2] = {};
+#pragma unroll
+      for (int jt = 0; jt < NKT; ++jt) {
+        if (jt >= nkt) break;
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+          const int j = 16 * jt + 4 * kq + ss;
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const float dy = j < nn ? sm.DY[j * LQA + 16 * ct + col] : 0.f;
+            const float qv = j < nn ? sm.Q[j * LQA + 16 * ct + col] : 0.f;
+            dv[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(dy, s[jt][ss], dv[ct], 0, 0, 0);
+            dk[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv, da[jt][ss], dk[ct], 0, 0, 0);
+          }
+        }
+      }
+      f4 o[2] = {};
+      wt_product(o, wvv, dv);
+      wt_product(o, wk, dk);
+      if (kok)
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int c = 16 * ot + 4 * kq + ii;
+            sm.G2A[kme * LQ + c] += o[ot][ii];  // dE/dg2a, complete
+          }
     }
-    wave_sync();
   }
   __syncthreads();
   // pair update backward: dz = dE/dg2a (1 - ta^2) into DY
   for (int o = tid; o < nn * G2D; o += NT) {
     const int j = o >> 5, c = o & 31;
     const float ta = sm.G2[j * LQ + c];
-    sm.DY[j * LQ + c] = sm.G2A[j * LQ + c] * (1.f - ta * ta);
+    sm.DY[j * LQA + c] = sm.G2A[j * LQ + c] * (1.f - ta * ta);
   }
   __syncthreads();
   // dxa = Wa dz: the first 32 go to dE/dg2 of the layer input, the other 64 (with the
@@ -650,11 +784,11 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     for (int j = tid / (G2D + G1D); j < nn; j += 2) {
     float v = 0.f;
 #pragma unroll
-    for (int c = 0; c < G2D; ++c) v += sm.DY[j * LQ + c] * wr[c];
+    for (int c = 0; c < G2D; ++c) v += sm.DY[j * LQA + c] * wr[c];
     if (q < G2D) {
       const float dg2in = sm.G2A[j * LQ + q] + v;
       if (l > 0) b.dg2[((size_t)i * SEL + j) * G2D + q] = dg2in;
-      else sm.V[j * LQ + q] = dg2in;  // kept for the initial-feature gradient below
+      else sm.V[j * LQA + q] = dg2in;  // kept for the initial-feature gradient below
     } else if (l > 0) {
       const int c1 = q - G2D;
       if (c1 < G2D) v += e.sw[j] * dc[c1] * geo.inv_sel * sm.G2B[j * LQ + c1];
@@ -676,7 +810,7 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     float ds = sm.EG[j * GSN];
     for (int c = 0; c < G2D; ++c) {
       const float g0 = tanhf(e.s[j] * w.Wp0[c] + w.bp0[c]);
-      ds += sm.V[j * LQ + c] * (1.f - g0 * g0) * w.Wp0[c];
+      ds += sm.V[j * LQA + c] * (1.f - g0 * g0) * w.Wp0[c];
     }
     const float rr = e.r[j], sw = e.sw[j];
     const float dr = ds * (e.dsw[j] / rr - sw / (rr * rr)) + sm.EG[j * GSN + 1] * e.dsw[j];
