@@ -1,12 +1,13 @@
-// Repformer-style model kernels for gfx950: one workgroup (four waves) per centre atom
+// Repformer-style model kernels for gfx950: one workgroup (eight waves) per centre atom
 // and one launch per layer, forward and backward (a layer's pair update and convolution
 // read the neighbours' g1 of the layer before, so layers meet at launch boundaries).
-// The neighbour-to-neighbour attention, the largest product (every ordered pair of an
-// atom's up to 120 neighbours, width 32), runs on MFMA (16x16x4 f32): a wave takes a
-// tile of 16 queries in the forward and the backward's row pass (statistics, dQ, the
-// row terms of the gate), and a tile of 16 keys in the column pass (dK, dV, the key
-// terms of the switch and gate, with the scores recomputed).  The per-edge products
-// (pair width 32, node input 224) stay float32 VALU dot products from LDS.  Every sum
+// The products run on MFMA (16x16x4 f32): the pair update and projections and the
+// backward's dE/d[g2, g1_j] over tiles of 16 edges, one tile per wave; the
+// neighbour-to-neighbour attention (every ordered pair of an atom's up to 120
+// neighbours, width 32) over tiles of 16 queries in the forward and the backward's row
+// pass (statistics, dQ, the row terms of the gate), and tiles of 16 keys in the column
+// pass (dK, dV, the key terms of the switch and gate, with the scores recomputed).
+// The node update (input 224) and the contraction stay float32 VALU work.  Every sum
 // has one owner and a fixed order: results are deterministic.
 #include <cmath>
 
@@ -17,7 +18,7 @@ namespace dp {
 namespace rep {
 namespace {
 
-constexpr int NWG = 4;
+constexpr int NWG = 8;
 constexpr int NT = NWG * 64;
 constexpr int LQ = G2D + 1;   // row stride of [edge][32] LDS arrays (odd: rows fall in different banks)
 constexpr int LQA = G2D + 4;  // row stride of the attention operands Q, K, V, dY (16-byte aligned rows)
@@ -142,61 +143,75 @@ __device__ void load_inputs(const Weights &w, const Buffers &b, const EnvR &e, c
                               : b.g1f[((size_t)(l - 1) * b.cap + i) * G1D + threadIdx.x];
 }
 
-// Pair update and projections: G2A = G2 + tanh([G2, G1J] Wa + ba) (TA = the tanh term,
-// written over G2 when `keep_ta`), Q, K, V = G2A Wq, Wk, Wv.  Each thread owns one output
-// column c = tid % 32 for rows tid / 32 + 8 k and holds that column of the weights in
-// registers.  Ends synchronised.
+// Pair update and projections on MFMA (16x16x4 f32), one tile of 16 edges per wave:
+// G2A = G2 + tanh([G2, G1J] Wa + ba) (TA, the tanh term, written over G2 when
+// `keep_ta`), then Q, K, V = G2A Wq, Wk, Wv.  The weights are B operands held in
+// registers (lane l holds W[4 s + l / 16][16 ct + l % 16] for k step s); a wave reads
+// and writes only the rows of its own tiles.  Ends synchronised.
 __device__ void pair_and_qkv(const Weights &w, int l, int nn, float *G2, const float *G1J, float *G2A, float *Q,
                              float *K, float *V, bool keep_ta) {
-  const int c = threadIdx.x & 31, j0 = threadIdx.x >> 5;
-  constexpr int PER = (SEL + 7) / 8;
-  float ta[PER];
-  {
-    float wa[G2D + G1D];
+  const int ln = lane_id(), wv = wave_id(), kq = ln >> 4, col = ln & 15;
+  const int nkt = (nn + 15) >> 4;
+  constexpr int KA = (G2D + G1D) / 4, KP = G2D / 4;  // k steps of the two products
+  float wa[KA][2], wq[KP][2], wk[KP][2], wvv[KP][2];
 #pragma unroll
-    for (int q = 0; q < G2D + G1D; ++q) wa[q] = w.Wa[l][q * G2D + c];
-    const float bc = w.ba[l][c];
+  for (int st = 0; st < KA; ++st)
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
-      const int j = j0 + 8 * it;
-      ta[it] = 0.f;
-      if (j < nn) {
-        float z = bc;
+    for (int ct = 0; ct < 2; ++ct) wa[st][ct] = w.Wa[l][(4 * st + kq) * G2D + 16 * ct + col];
 #pragma unroll
-        for (int q = 0; q < G2D; ++q) z += G2[j * LQ + q] * wa[q];
+  for (int st = 0; st < KP; ++st)
 #pragma unroll
-        for (int q = 0; q < G1D; ++q) z += G1J[j * LG + q] * wa[G2D + q];
-        ta[it] = ftanh(z);
-        G2A[j * LQ + c] = G2[j * LQ + c] + ta[it];
+    for (int ct = 0; ct < 2; ++ct) {
+      wq[st][ct] = w.Wq[l][(4 * st + kq) * G2D + 16 * ct + col];
+      wk[st][ct] = w.Wk[l][(4 * st + kq) * G2D + 16 * ct + col];
+      wvv[st][ct] = w.Wv[l][(4 * st + kq) * G2D + 16 * ct + col];
+    }
+  const float bias[2] = {w.ba[l][col], w.ba[l][16 + col]};
+  for (int et = wv; et < nkt; et += NWG) {
+    const int ra = 16 * et + col;  // this lane's A-operand row
+    const bool aok = ra < nn;
+    f4 z[2] = {};
+#pragma unroll
+    for (int st = 0; st < KA; ++st) {
+      const int k = 4 * st + kq;
+      const float x = aok ? (k < G2D ? G2[ra * LQ + k] : G1J[ra * LG + k - G2D]) : 0.f;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) z[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wa[st][ct], z[ct], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 16 * et + 4 * kq + ii, c = 16 * ct + col;
+        if (r < nn) {
+          const float ta = ftanh(z[ct][ii] + bias[ct]);
+          G2A[r * LQ + c] = G2[r * LQ + c] + ta;
+          if (keep_ta) G2[r * LQ + c] = ta;
+        }
+      }
+    wave_sync();
+    f4 q[2] = {}, k[2] = {}, v[2] = {};
+#pragma unroll
+    for (int st = 0; st < KP; ++st) {
+      const float x = aok ? G2A[ra * LQ + 4 * st + kq] : 0.f;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        q[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[st][ct], q[ct], 0, 0, 0);
+        k[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wk[st][ct], k[ct], 0, 0, 0);
+        v[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wvv[st][ct], v[ct], 0, 0, 0);
       }
     }
-  }
-  __syncthreads();
-  if (keep_ta)
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
-      const int j = j0 + 8 * it;
-      if (j < nn) G2[j * LQ + c] = ta[it];
-    }
-  float wq[G2D], wk[G2D], wvv[G2D];
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-  for (int t = 0; t < G2D; ++t) {
-    wq[t] = w.Wq[l][t * G2D + c];
-    wk[t] = w.Wk[l][t * G2D + c];
-    wvv[t] = w.Wv[l][t * G2D + c];
-  }
-  for (int j = j0; j < nn; j += 8) {
-    float q = 0.f, k = 0.f, v = 0.f;
-#pragma unroll
-    for (int t = 0; t < G2D; ++t) {
-      const float x = G2A[j * LQ + t];
-      q += x * wq[t];
-      k += x * wk[t];
-      v += x * wvv[t];
-    }
-    Q[j * LQA + c] = q;
-    K[j * LQA + c] = k;
-    V[j * LQA + c] = v;
+      for (int ii = 0; ii < 4; ++ii) {
+        const int r = 16 * et + 4 * kq + ii, c = 16 * ct + col;
+        if (r < nn) {
+          Q[r * LQA + c] = q[ct][ii];
+          K[r * LQA + c] = k[ct][ii];
+          V[r * LQA + c] = v[ct][ii];
+        }
+      }
   }
   __syncthreads();
 }
@@ -575,8 +590,6 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   const int nkt = (nn + 15) >> 4;
   const int kq = ln >> 4, col = ln & 15;
   {
-    float wq[2][2][4];
-    load_wt(w.Wq[l], wq);
     for (int qt = wv; qt < nkt; qt += NWG) {
       const int qme = 16 * qt + col;
       const bool qok = qme < nn;
@@ -665,6 +678,8 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
           }
         }
       }
+      float wq[2][2][4];  // loaded here, not before the score tiles: registers
+      load_wt(w.Wq[l], wq);
       f4 o[2] = {};
       wt_product(o, wq, dq);
       if (qok)
@@ -678,92 +693,79 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     }
   }
   __syncthreads();
-  // column pass: one tile of 16 keys per wave, scores S[query][key] recomputed; the key
-  // terms of the switch and gate, dV^T = dY^T A, dK^T = Q^T dS and the key rows of
-  // dE/dg2a += dV Wv^T + dK Wk^T.
-  {
+  // column pass: one tile of 16 keys per wave, streaming over the query tiles with the
+  // scores S[query][key] recomputed; the key terms of the switch and gate,
+  // dV^T = dY^T A, dK^T = Q^T dS and the key rows of dE/dg2a += dV Wv^T + dK Wk^T.
+  for (int kt = wv; kt < nkt; kt += NWG) {
+    const int kme = 16 * kt + col;
+    const bool kok = kme < nn;
+    const int kk = kok ? kme : 0;
+    const float kx = e.rh[3 * kk], ky = e.rh[3 * kk + 1], kz = e.rh[3 * kk + 2], swk = e.sw[kk];
+    float dsk = 0.f, h0 = 0.f, h1 = 0.f, h2 = 0.f;
+    f4 dv[2] = {}, dk[2] = {};
+    for (int jt = 0; jt < nkt; ++jt) {
+      f4 sc = {}, da = {};  // S and dA = dY V^T: [query 16 jt + 4 kq + ii][key kme]
+      const int jr = 16 * jt + col;
+      dot32_tile(sc, jr < nn ? sm.Q + jr * LQA : nullptr, kok ? sm.K + kme * LQA : nullptr);
+      dot32_tile(da, jr < nn ? sm.DY + jr * LQA : nullptr, kok ? sm.V + kme * LQA : nullptr);
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int j = 16 * jt + 4 * kq + ii;
+        float A = 0.f, ds = 0.f;
+        if (kok && j < nn) {
+          const float exz = __expf(sc[ii] * isq - sm.stat[0][j]) * sm.stat[1][j];
+          const float rx = e.rh[3 * j], ry = e.rh[3 * j + 1], rz = e.rh[3 * j + 2];
+          const float P = swk * exz, g = rx * kx + ry * ky + rz * kz, dA = da[ii];
+          const float dP = dA * g, dG = dA * P, rho = sm.stat[2][j];
+          A = P * g;
+          ds = P * (dP - rho) * isq;
+          dsk += exz * (dP - rho);
+          h0 += dG * rx;
+          h1 += dG * ry;
+          h2 += dG * rz;
+        }
+        sc[ii] = A;
+        da[ii] = ds;
+      }
+#pragma unroll
+      for (int ss = 0; ss < 4; ++ss) {
+        const int j = 16 * jt + 4 * kq + ss;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const float dy = j < nn ? sm.DY[j * LQA + 16 * ct + col] : 0.f;
+          const float qv = j < nn ? sm.Q[j * LQA + 16 * ct + col] : 0.f;
+          dv[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(dy, sc[ss], dv[ct], 0, 0, 0);
+          dk[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv, da[ss], dk[ct], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+      dsk += __shfl_xor(dsk, o);
+      h0 += __shfl_xor(h0, o);
+      h1 += __shfl_xor(h1, o);
+      h2 += __shfl_xor(h2, o);
+    }
+    if (kok && kq == 0) {
+      sm.EG[kme * GSN + 1] += dsk;
+      sm.EG[kme * GSN + 2] += h0;
+      sm.EG[kme * GSN + 3] += h1;
+      sm.EG[kme * GSN + 4] += h2;
+    }
     float wk[2][2][4], wvv[2][2][4];
     load_wt(w.Wk[l], wk);
     load_wt(w.Wv[l], wvv);
-    for (int kt = wv; kt < nkt; kt += NWG) {
-      const int kme = 16 * kt + col;
-      const bool kok = kme < nn;
-      f4 s[NKT], da[NKT];  // S and dA = dY V^T: [query 16 jt + 4 kq + ii][key kme]
+    f4 o[2] = {};
+    wt_product(o, wvv, dv);
+    wt_product(o, wk, dk);
+    if (kok)
 #pragma unroll
-      for (int jt = 0; jt < NKT; ++jt) {
-        s[jt] = f4{0.f, 0.f, 0.f, 0.f};
-        da[jt] = f4{0.f, 0.f, 0.f, 0.f};
-        if (jt < nkt) {
-          const int jr = 16 * jt + col;
-          dot32_tile(s[jt], jr < nn ? sm.Q + jr * LQA : nullptr, kok ? sm.K + kme * LQA : nullptr);
-          dot32_tile(da[jt], jr < nn ? sm.DY + jr * LQA : nullptr, kok ? sm.V + kme * LQA : nullptr);
-        }
-      }
-      const int kk = kok ? kme : 0;
-      const float kx = e.rh[3 * kk], ky = e.rh[3 * kk + 1], kz = e.rh[3 * kk + 2], swk = e.sw[kk];
-      float dsk = 0.f, h0 = 0.f, h1 = 0.f, h2 = 0.f;
-#pragma unroll
-      for (int jt = 0; jt < NKT; ++jt)
+      for (int ot = 0; ot < 2; ++ot)
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
-          const int j = 16 * jt + 4 * kq + ii;
-          float A = 0.f, ds = 0.f;
-          if (kok && j < nn) {
-            const float exz = __expf(s[jt][ii] * isq - sm.stat[0][j]) * sm.stat[1][j];
-            const float rx = e.rh[3 * j], ry = e.rh[3 * j + 1], rz = e.rh[3 * j + 2];
-            const float P = swk * exz, g = rx * kx + ry * ky + rz * kz, dA = da[jt][ii];
-            const float dP = dA * g, dG = dA * P, rho = sm.stat[2][j];
-            A = P * g;
-            ds = P * (dP - rho) * isq;
-            dsk += exz * (dP - rho);
-            h0 += dG * rx;
-            h1 += dG * ry;
-            h2 += dG * rz;
-          }
-          s[jt][ii] = A;
-          da[jt][ii] = ds;
+          const int c = 16 * ot + 4 * kq + ii;
+          sm.G2A[kme * LQ + c] += o[ot][ii];  // dE/dg2a, complete
         }
-#pragma unroll
-      for (int o = 16; o < 64; o <<= 1) {
-        dsk += __shfl_xor(dsk, o);
-        h0 += __shfl_xor(h0, o);
-        h1 += __shfl_xor(h1, o);
-        h2 += __shfl_xor(h2, o);
-      }
-      if (kok && kq == 0) {
-        sm.EG[kme * GSN + 1] += dsk;
-        sm.EG[kme * GSN + 2] += h0;
-        sm.EG[kme * GSN + 3] += h1;
-        sm.EG[kme * GSN + 4] += h2;
-      }
-      f4 dv[2] = {}, dk[2] = {};
-#pragma unroll
-      for (int jt = 0; jt < NKT; ++jt) {
-        if (jt >= nkt) break;
-#pragma unroll
-        for (int ss = 0; ss < 4; ++ss) {
-          const int j = 16 * jt + 4 * kq + ss;
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const float dy = j < nn ? sm.DY[j * LQA + 16 * ct + col] : 0.f;
-            const float qv = j < nn ? sm.Q[j * LQA + 16 * ct + col] : 0.f;
-            dv[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(dy, s[jt][ss], dv[ct], 0, 0, 0);
-            dk[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv, da[jt][ss], dk[ct], 0, 0, 0);
-          }
-        }
-      }
-      f4 o[2] = {};
-      wt_product(o, wvv, dv);
-      wt_product(o, wk, dk);
-      if (kok)
-#pragma unroll
-        for (int ot = 0; ot < 2; ++ot)
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii) {
-            const int c = 16 * ot + 4 * kq + ii;
-            sm.G2A[kme * LQ + c] += o[ot][ii];  // dE/dg2a, complete
-          }
-    }
   }
   __syncthreads();
   // pair update backward: dz = dE/dg2a (1 - ta^2) into DY
@@ -773,27 +775,44 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     sm.DY[j * LQA + c] = sm.G2A[j * LQ + c] * (1.f - ta * ta);
   }
   __syncthreads();
-  // dxa = Wa dz: the first 32 go to dE/dg2 of the layer input, the other 64 (with the
-  // convolution's term) to the edge's part of dE/dg1_j
+  // dxa = dz Wa^T on MFMA, one tile of 16 edges per wave (B operand: lane l holds
+  // Wa[16 qt + l % 16][4 s + l / 16]); its first 32 columns go to dE/dg2 of the layer
+  // input, the other 64 (with the convolution's term) to the edge's part of dE/dg1_j
   float *dnj = b.dnj + (size_t)(l & 1) * b.cap * SEL * G1D;
-  if (tid < 2 * (G2D + G1D)) {  // thread: column q = tid % 96 of dxa, rows j = tid / 96 + 2 k
-    const int q = tid % (G2D + G1D);
-    float wr[G2D];
+  {
+    constexpr int QT = (G2D + G1D) / 16;
+    float wt[G2D / 4][QT];
 #pragma unroll
-    for (int c = 0; c < G2D; ++c) wr[c] = w.Wa[l][q * G2D + c];
-    for (int j = tid / (G2D + G1D); j < nn; j += 2) {
-    float v = 0.f;
+    for (int st = 0; st < G2D / 4; ++st)
 #pragma unroll
-    for (int c = 0; c < G2D; ++c) v += sm.DY[j * LQA + c] * wr[c];
-    if (q < G2D) {
-      const float dg2in = sm.G2A[j * LQ + q] + v;
-      if (l > 0) b.dg2[((size_t)i * SEL + j) * G2D + q] = dg2in;
-      else sm.V[j * LQA + q] = dg2in;  // kept for the initial-feature gradient below
-    } else if (l > 0) {
-      const int c1 = q - G2D;
-      if (c1 < G2D) v += e.sw[j] * dc[c1] * geo.inv_sel * sm.G2B[j * LQ + c1];
-      dnj[((size_t)i * SEL + j) * G1D + c1] = v;
-    }
+      for (int qt = 0; qt < QT; ++qt) wt[st][qt] = w.Wa[l][(16 * qt + col) * G2D + 4 * st + kq];
+    for (int et = wv; et < nkt; et += NWG) {
+      const int ra = 16 * et + col;
+      const bool aok = ra < nn;
+      f4 acc[QT] = {};
+#pragma unroll
+      for (int st = 0; st < G2D / 4; ++st) {
+        const float x = aok ? sm.DY[ra * LQA + 4 * st + kq] : 0.f;
+#pragma unroll
+        for (int qt = 0; qt < QT; ++qt) acc[qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wt[st][qt], acc[qt], 0, 0, 0);
+      }
+#pragma unroll
+      for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = 16 * et + 4 * kq + ii, q = 16 * qt + col;
+          if (j >= nn) continue;
+          float v = acc[qt][ii];
+          if (q < G2D) {
+            const float dg2in = sm.G2A[j * LQ + q] + v;
+            if (l > 0) b.dg2[((size_t)i * SEL + j) * G2D + q] = dg2in;
+            else sm.V[j * LQA + q] = dg2in;  // kept for the initial-feature gradient below
+          } else if (l > 0) {
+            const int c1 = q - G2D;
+            if (c1 < G2D) v += e.sw[j] * dc[c1] * geo.inv_sel * sm.G2B[j * LQ + c1];
+            dnj[((size_t)i * SEL + j) * G1D + c1] = v;
+          }
+        }
     }
   }
   if (l > 0) {
