@@ -45,6 +45,7 @@ struct Buffers {
   float *dnj = nullptr;  // [2][cap][SEL][64]  edge (i, j)'s part of dE/dg1_j, by layer parity
   float *dnl = nullptr;  // [cap][64]          atom i's own part of dE/dg1_i
   float *gs = nullptr;   // [cap][SEL][GSN]    dE/ds, dE/dsw, dE/drhat per edge over the layers
+  int *slot = nullptr;   // [cap][SEL]         position of i in the list of its j-th neighbour, or -1
   int64_t *etot = nullptr;  // [1] edges of the step
 };
 
@@ -54,6 +55,8 @@ struct Geo {
 
 // *b.etot = sum of the list lengths of the n atoms.
 void launch_edge_count(const Buffers &b, const Workspace &ws, int n, hipStream_t st);
+// b.slot of the step's lists (read by the backward layers to gather dE/dg1_j by j).
+void launch_rev_slots(const Buffers &b, const Workspace &ws, int n, hipStream_t st);
 // Layer `layer` (0 .. 2) forward over all n atoms; the last layer also evaluates the
 // fitting net (E_i into Ei) and its gradient dE/dg1 (into dnl).  Layer `layer` backward
 // (called for 2, 1, 0); layer 0 writes g_ij = dE/dDelta_ij into ws.g.

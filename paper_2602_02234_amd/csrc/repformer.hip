@@ -49,17 +49,37 @@ __device__ __forceinline__ float ftanh(float x) {
   return copysignf((1.f - t) * __builtin_amdgcn_rcpf(1.f + t), x);
 }
 
+constexpr int SELP = 16 * ((SEL + 15) / 16);  // SEL rounded up to whole tiles of 16
+
+// Environment of atom i.  sw and rh are padded to SELP entries (zero past the list) so
+// that four consecutive neighbours of a tile are read with 16-byte loads.
 struct EnvR {
-  float r[SEL], sw[SEL], dsw[SEL], s[SEL], rh[SEL * 3];
+  float sw[SELP] __attribute__((aligned(16)));
+  float rh[SELP * 3] __attribute__((aligned(16)));
+  float r[SEL], dsw[SEL], s[SEL];
   int jn[SEL], tj[SEL];
   int nn;
 };
+
+// rh of the neighbours k0 .. k0 + 3 (k0 a multiple of 4): h[3 ii + a] = rhat_{k0 + ii}[a].
+__device__ __forceinline__ void rh_quad(const EnvR &e, int k0, float (&h)[12]) {
+  const float4 a = *reinterpret_cast<const float4 *>(e.rh + 3 * k0);
+  const float4 b = *reinterpret_cast<const float4 *>(e.rh + 3 * k0 + 4);
+  const float4 c = *reinterpret_cast<const float4 *>(e.rh + 3 * k0 + 8);
+  h[0] = a.x; h[1] = a.y; h[2] = a.z; h[3] = a.w;
+  h[4] = b.x; h[5] = b.y; h[6] = b.z; h[7] = b.w;
+  h[8] = c.x; h[9] = c.y; h[10] = c.z; h[11] = c.w;
+}
+__device__ __forceinline__ void quad(const float *p, float (&v)[4]) {
+  const float4 a = *reinterpret_cast<const float4 *>(p);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
 
 __device__ void build_env_r(EnvR &e, const double *__restrict__ X, const int *__restrict__ types,
                             const int *__restrict__ nlist, const int *__restrict__ nnei, int i, int n, const Grid &g,
                             const Geo &geo) {
   const int nn = min(max(nnei[i], 0), SEL);
-  for (int j = threadIdx.x; j < SEL; j += NT) {
+  for (int j = threadIdx.x; j < SELP; j += NT) {
     float r = 1.f, sw = 0.f, dsw = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
     int nj = i, tj = 0;
     if (j < nn) {
@@ -83,9 +103,12 @@ __device__ void build_env_r(EnvR &e, const double *__restrict__ X, const int *__
       }
       hx = dx / r; hy = dy / r; hz = dz / r;
     }
-    e.r[j] = r; e.sw[j] = sw; e.dsw[j] = dsw; e.s[j] = sw / r;
+    e.sw[j] = sw;
     e.rh[3 * j] = hx; e.rh[3 * j + 1] = hy; e.rh[3 * j + 2] = hz;
-    e.jn[j] = nj; e.tj[j] = tj;
+    if (j < SEL) {
+      e.r[j] = r; e.dsw[j] = dsw; e.s[j] = sw / r;
+      e.jn[j] = nj; e.tj[j] = tj;
+    }
   }
   if (threadIdx.x == 0) e.nn = nn;
   __syncthreads();
@@ -105,42 +128,63 @@ __device__ __forceinline__ void st4(float *p, float4 v) {  // LDS rows have odd 
   p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
 }
 
-// Copies rows of `width` floats (a multiple of 4) from global memory (row j at src(j))
-// into LDS rows of stride ld, for j < nn; every read is issued before the writes.
-template <int WIDTH, class S>
-__device__ __forceinline__ void load_rows(float *dst, int ld, int nn, const S &src) {
-  constexpr int Q = WIDTH / 4, NI = (SEL * Q + NT - 1) / NT;
+// Rows of WIDTH floats (a multiple of 4) for j < nn, copied from global memory (row j
+// at src(j)) into LDS rows of stride ld in two steps, so that the reads of several
+// arrays can all be issued before the first write.
+template <int WIDTH> struct Rows {
+  static constexpr int Q = WIDTH / 4, NI = (SEL * Q + NT - 1) / NT;
   float4 v[NI];
+  template <class S> __device__ __forceinline__ void issue(int nn, const S &src) {
 #pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int k = threadIdx.x + NT * it, j = k / Q;
-    if (j < nn) v[it] = ld4(src(j) + 4 * (k % Q));
+    for (int it = 0; it < NI; ++it) {
+      const int k = threadIdx.x + NT * it, j = k / Q;
+      if (j < nn) v[it] = ld4(src(j) + 4 * (k % Q));
+    }
   }
+  __device__ __forceinline__ void store(float *dst, int ld, int nn) const {
 #pragma unroll
-  for (int it = 0; it < NI; ++it) {
-    const int k = threadIdx.x + NT * it, j = k / Q;
-    if (j < nn) st4(dst + j * ld + 4 * (k % Q), v[it]);
+    for (int it = 0; it < NI; ++it) {
+      const int k = threadIdx.x + NT * it, j = k / Q;
+      if (j < nn) st4(dst + j * ld + 4 * (k % Q), v[it]);
+    }
   }
-}
+};
+
+struct NoRows {
+  __device__ void issue() {}
+  __device__ void store() {}
+};
 
 // Layer input of atom i's features: g1 of the neighbours (G1J), g2 of its edges (G2) and
-// its own g1 (g1i).
-__device__ void load_inputs(const Weights &w, const Buffers &b, const EnvR &e, const int *types, int i, int l,
-                            float *G1J, float *G2, float *g1i) {
+// its own g1 (g1i); `more` issues its own reads after these and stores after them.
+template <class More>
+__device__ __forceinline__ void load_inputs(const Weights &w, const Buffers &b, const EnvR &e, const int *types, int i,
+                                            int l, float *G1J, float *G2, float *g1i, More &more) {
   const int nn = e.nn;
+  Rows<G1D> a;
+  Rows<G2D> c;
   if (l == 0) {
-    load_rows<G1D>(G1J, LG, nn, [&](int j) { return w.TN + e.tj[j] * G1D; });
+    a.issue(nn, [&](int j) { return w.TN + e.tj[j] * G1D; });
+  } else {
+    a.issue(nn, [&](int j) { return b.g1f + ((size_t)(l - 1) * b.cap + e.jn[j]) * G1D; });
+    c.issue(nn, [&](int j) { return b.g2f + erow2(b, l - 1, i, j); });
+  }
+  float gi = 0.f;
+  if (threadIdx.x < G1D)
+    gi = l == 0 ? w.TN[clamp_type(types[i]) * G1D + threadIdx.x]
+                : b.g1f[((size_t)(l - 1) * b.cap + i) * G1D + threadIdx.x];
+  more.issue();
+  a.store(G1J, LG, nn);
+  if (l == 0) {
     for (int k = threadIdx.x; k < nn * G2D; k += NT) {
-      const int j = k >> 5, c = k & 31;
-      G2[j * LQ + c] = tanhf(e.s[j] * w.Wp0[c] + w.bp0[c]);
+      const int j = k >> 5, cc = k & 31;
+      G2[j * LQ + cc] = tanhf(e.s[j] * w.Wp0[cc] + w.bp0[cc]);
     }
   } else {
-    load_rows<G1D>(G1J, LG, nn, [&](int j) { return b.g1f + ((size_t)(l - 1) * b.cap + e.jn[j]) * G1D; });
-    load_rows<G2D>(G2, LQ, nn, [&](int j) { return b.g2f + erow2(b, l - 1, i, j); });
+    c.store(G2, LQ, nn);
   }
-  if (threadIdx.x < G1D)
-    g1i[threadIdx.x] = l == 0 ? w.TN[clamp_type(types[i]) * G1D + threadIdx.x]
-                              : b.g1f[((size_t)(l - 1) * b.cap + i) * G1D + threadIdx.x];
+  if (threadIdx.x < G1D) g1i[threadIdx.x] = gi;
+  more.store();
 }
 
 // Pair update and projections on MFMA (16x16x4 f32), one tile of 16 edges per wave:
@@ -236,23 +280,44 @@ __device__ void node_product(const float *W1, const float *b1, const float *xs, 
 }
 
 // T = sum_j g2_j R_j^T / sel (into T[32][4]), c = sum_j sw_j g2_j g1_j[:32] / sel, and the
-// node-update input xs = [g1i, D, c] with D = T T[:4]^T.  Ends synchronised.
+// node-update input xs = [g1i, D, c] with D = T T[:4]^T.  The 160 sums over the
+// neighbours are split into NT / 160 consecutive ranges of j (partials in `part`, at
+// least NT floats), added in range order.  Ends synchronised.
 __device__ void node_inputs(const EnvR &e, int nn, const float *G2B, const float *G1J, const float *g1i,
-                            float inv_sel, float *T, float *xs) {
+                            float inv_sel, float *T, float *xs, float *part) {
+  constexpr int NO = G2D * 4 + G2D, NS = NT / NO;
   const int t = threadIdx.x;
-  if (t < G2D * 4) {
-    const int c = t >> 2, a = t & 3;
-    float v = 0.f;
-    for (int j = 0; j < nn; ++j) v += G2B[j * LQ + c] * Rcomp(e, j, a);
-    T[t] = v * inv_sel;
-  } else if (t < G2D * 4 + G2D) {
-    const int c = t - G2D * 4;
-    float v = 0.f;
-    for (int j = 0; j < nn; ++j) v += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
-    xs[G1D + G2D * NAX + c] = v * inv_sel;
-  } else if (t < G2D * 4 + G2D + G1D) {
-    const int c = t - G2D * 5;
-    xs[c] = g1i[c];
+  if (t < NS * NO) {
+    const int o = t % NO, sg = t / NO;
+    const int j0 = sg * nn / NS, j1 = (sg + 1) * nn / NS;
+    float v0 = 0.f, v1 = 0.f;
+    if (o < G2D * 4) {
+      const int c = o >> 2, a = o & 3;
+      int j = j0;
+      for (; j + 1 < j1; j += 2) {
+        v0 += G2B[j * LQ + c] * Rcomp(e, j, a);
+        v1 += G2B[(j + 1) * LQ + c] * Rcomp(e, j + 1, a);
+      }
+      if (j < j1) v0 += G2B[j * LQ + c] * Rcomp(e, j, a);
+    } else {
+      const int c = o - G2D * 4;
+      int j = j0;
+      for (; j + 1 < j1; j += 2) {
+        v0 += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
+        v1 += e.sw[j + 1] * G2B[(j + 1) * LQ + c] * G1J[(j + 1) * LG + c];
+      }
+      if (j < j1) v0 += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
+    }
+    part[t] = v0 + v1;
+  }
+  __syncthreads();
+  if (t < NO) {
+    float v = part[t];
+    for (int sg = 1; sg < NS; ++sg) v += part[sg * NO + t];
+    if (t < G2D * 4) T[t] = v * inv_sel;
+    else xs[G1D + G2D * NAX + t - G2D * 4] = v * inv_sel;
+  } else if (t < NO + G1D) {
+    xs[t - NO] = g1i[t - NO];
   }
   __syncthreads();
   if (t < G2D * NAX) {
@@ -334,7 +399,8 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
   build_env_r(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
   const EnvR &e = sm.env;
   const int nn = e.nn;
-  load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i);
+  NoRows none;
+  load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i, none);
   __syncthreads();
   pair_and_qkv(w, l, nn, sm.G2, sm.G1J, sm.G2A, sm.Q, sm.K, sm.V, false);
 
@@ -367,26 +433,28 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
     m = fmaxf(m, __shfl_xor(m, 32));
     float z = 0.f;
 #pragma unroll
-    for (int kt = 0; kt < NKT; ++kt)
+    for (int kt = 0; kt < NKT; ++kt) {
+      float swv[4];
+      quad(e.sw + 16 * kt + 4 * kq, swv);
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int k = 16 * kt + 4 * kq + ii;
-        const float ex = (kt < nkt && k < nn) ? e.sw[k] * __expf(st[kt][ii] * isq - m) : 0.f;
+        const float ex = (kt < nkt && k < nn) ? swv[ii] * __expf(st[kt][ii] * isq - m) : 0.f;
         st[kt][ii] = ex;
         z += ex;
       }
+    }
     z += __shfl_xor(z, 16);
     z += __shfl_xor(z, 32);
     const float iz = qok ? 1.f / z : 0.f;
     const float hx = e.rh[3 * (qok ? qme : 0)], hy = e.rh[3 * (qok ? qme : 0) + 1], hz = e.rh[3 * (qok ? qme : 0) + 2];
 #pragma unroll
-    for (int kt = 0; kt < NKT; ++kt)
+    for (int kt = 0; kt < NKT; ++kt) {
+      float h[12];
+      rh_quad(e, 16 * kt + 4 * kq, h);
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int k = 16 * kt + 4 * kq + ii;
-        const int kk = k < nn ? k : 0;
-        st[kt][ii] *= iz * (hx * e.rh[3 * kk] + hy * e.rh[3 * kk + 1] + hz * e.rh[3 * kk + 2]);
-      }
+      for (int ii = 0; ii < 4; ++ii) st[kt][ii] *= iz * (hx * h[3 * ii] + hy * h[3 * ii + 1] + hz * h[3 * ii + 2]);
+    }
     // Y^T[c][q] = sum_k V[k][c] A^T[k][q], two tiles of 16 features
     f4 yt[2] = {};
 #pragma unroll
@@ -415,7 +483,7 @@ __global__ void __launch_bounds__(NT) k_rep_fwd(Weights w, Buffers b, const doub
   }
   __syncthreads();
 
-  node_inputs(e, nn, sm.G2, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs);
+  node_inputs(e, nn, sm.G2, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs, &sm.part[0][0]);
   node_product(w.W1[l], w.b1[l], sm.xs, sm.part, sm.zc);
   float g1n = 0.f;
   if (tid < G1D) {
@@ -475,7 +543,7 @@ struct SmemB {
   float G2B[SEL * LQ];   // the layer's output g2
   float DY[SEL * LQA] __attribute__((aligned(16)));  // dE/dg2 of the output; later the pair update's dz
   float EG[SEL * GSN];   // per-edge dE/ds, dE/dsw, dE/drhat
-  float stat[3][SEL];    // per query row: max score, 1 / normaliser, rho
+  float stat[3][SELP] __attribute__((aligned(16)));  // per query row: max score, 1 / normaliser, rho
   float g1i[G1D], T[G2D * 4], xs[XD], dg1[G1D], dxn[XD], dT[G2D * 4], part[NWG][G1D], zc[G1D];
   int slot[SEL];
 };
@@ -493,29 +561,37 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   build_env_r(sm.env, X, types, nlist, nnei, i, n, grids[0], geo);
   const EnvR &e = sm.env;
   const int nn = e.nn;
-  load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i);
-  load_rows<G2D>(sm.G2B, LQ, nn, [&](int j) { return b.g2f + erow2(b, l, i, j); });
-  if (top) {
-    for (int k = tid; k < nn * G2D; k += NT) sm.DY[(k >> 5) * LQA + (k & 31)] = 0.f;
-    for (int k = tid; k < nn * GSN; k += NT) sm.EG[k] = 0.f;
-  } else {
-    load_rows<G2D>(sm.DY, LQA, nn, [&](int j) { return b.dg2 + ((size_t)i * SEL + j) * G2D; });
-    load_rows<GSN>(sm.EG, GSN, nn, [&](int j) { return b.gs + ((size_t)i * SEL + j) * GSN; });
-  }
-  if (!top)
-    for (int j = tid; j < nn; j += NT) {
-      const int nj = e.jn[j];
-      const int len = min(max(nnei[nj], 0), SEL);
-      const int *row = nlist + (size_t)nj * SEL;
-      int lo = 0, hi = len - 1, s = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int x = row[mid];
-        if (x == i) { s = mid; break; }
-        if (x < i) lo = mid + 1; else hi = mid - 1;
+  // the layer's output g2, the output gradient and edge terms from the layer above and
+  // the reverse slots, read together with the layer input
+  struct More {
+    const Buffers &b;
+    SmemB &sm;
+    int i, l, nn;
+    bool top;
+    Rows<G2D> g2b, dy;
+    Rows<GSN> eg;
+    int sl;
+    __device__ void issue() {
+      g2b.issue(nn, [&](int j) { return b.g2f + erow2(b, l, i, j); });
+      if (!top) {
+        dy.issue(nn, [&](int j) { return b.dg2 + ((size_t)i * SEL + j) * G2D; });
+        eg.issue(nn, [&](int j) { return b.gs + ((size_t)i * SEL + j) * GSN; });
+        if ((int)threadIdx.x < nn) sl = b.slot[(size_t)i * SEL + threadIdx.x];
       }
-      sm.slot[j] = s;
     }
+    __device__ void store() {
+      g2b.store(sm.G2B, LQ, nn);
+      if (top) {
+        for (int k = threadIdx.x; k < nn * G2D; k += NT) sm.DY[(k >> 5) * LQA + (k & 31)] = 0.f;
+        for (int k = threadIdx.x; k < nn * GSN; k += NT) sm.EG[k] = 0.f;
+      } else {
+        dy.store(sm.DY, LQA, nn);
+        eg.store(sm.EG, GSN, nn);
+        if ((int)threadIdx.x < nn) sm.slot[threadIdx.x] = sl;
+      }
+    }
+  } more{b, sm, i, l, nn, top, {}, {}, {}, -1};
+  load_inputs(w, b, e, types, i, l, sm.G1J, sm.G2, sm.g1i, more);
   __syncthreads();
   {  // dE/dg1_i after this layer: own part + the neighbours' edge parts, rows by wave, waves in order
     float v = 0.f;
@@ -535,7 +611,7 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   }
   // recompute the layer's forward: pair update (tanh term kept in G2), projections, node input
   pair_and_qkv(w, l, nn, sm.G2, sm.G1J, sm.G2A, sm.Q, sm.K, sm.V, true);
-  node_inputs(e, nn, sm.G2B, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs);
+  node_inputs(e, nn, sm.G2B, sm.G1J, sm.g1i, geo.inv_sel, sm.T, sm.xs, &sm.part[0][0]);
   // node backward: dz = dg1 (1 - t^2), dxn = W1 dz
   node_product(w.W1[l], w.b1[l], sm.xs, sm.part, sm.zc);
   if (tid < G1D) {
@@ -616,14 +692,17 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       m = fmaxf(m, __shfl_xor(m, 32));
       float z = 0.f;
 #pragma unroll
-      for (int kt = 0; kt < NKT; ++kt)
+      for (int kt = 0; kt < NKT; ++kt) {
+        float swv[4];
+        quad(e.sw + 16 * kt + 4 * kq, swv);
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
           const int k = 16 * kt + 4 * kq + ii;
-          const float ex = (kt < nkt && k < nn) ? e.sw[k] * __expf(st[kt][ii] * isq - m) : 0.f;
+          const float ex = (kt < nkt && k < nn) ? swv[ii] * __expf(st[kt][ii] * isq - m) : 0.f;
           st[kt][ii] = ex;
           z += ex;
         }
+      }
       z += __shfl_xor(z, 16);
       z += __shfl_xor(z, 32);
       const float iz = qok ? 1.f / z : 0.f;
@@ -632,12 +711,12 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       // P, dP = dA gate, rho = sum_k dP P and the row terms sum_k dA P rhat_k of the gate
       float rho = 0.f, h0 = 0.f, h1 = 0.f, h2 = 0.f;
 #pragma unroll
-      for (int kt = 0; kt < NKT; ++kt)
+      for (int kt = 0; kt < NKT; ++kt) {
+        float h[12];
+        rh_quad(e, 16 * kt + 4 * kq, h);
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
-          const int k = 16 * kt + 4 * kq + ii;
-          const int kk = k < nn ? k : 0;
-          const float rx = e.rh[3 * kk], ry = e.rh[3 * kk + 1], rz = e.rh[3 * kk + 2];
+          const float rx = h[3 * ii], ry = h[3 * ii + 1], rz = h[3 * ii + 2];
           const float P = st[kt][ii] * iz, dA = da[kt][ii];
           const float dP = dA * (hx * rx + hy * ry + hz * rz), dG = dA * P;
           rho += dP * P;
@@ -647,6 +726,7 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
           st[kt][ii] = P;
           da[kt][ii] = dP;
         }
+      }
 #pragma unroll
       for (int o = 16; o < 64; o <<= 1) {
         rho += __shfl_xor(rho, o);
@@ -708,15 +788,20 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       const int jr = 16 * jt + col;
       dot32_tile(sc, jr < nn ? sm.Q + jr * LQA : nullptr, kok ? sm.K + kme * LQA : nullptr);
       dot32_tile(da, jr < nn ? sm.DY + jr * LQA : nullptr, kok ? sm.V + kme * LQA : nullptr);
+      float h[12], mx[4], iz[4], rh4[4];
+      rh_quad(e, 16 * jt + 4 * kq, h);
+      quad(sm.stat[0] + 16 * jt + 4 * kq, mx);
+      quad(sm.stat[1] + 16 * jt + 4 * kq, iz);
+      quad(sm.stat[2] + 16 * jt + 4 * kq, rh4);
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int j = 16 * jt + 4 * kq + ii;
         float A = 0.f, ds = 0.f;
         if (kok && j < nn) {
-          const float exz = __expf(sc[ii] * isq - sm.stat[0][j]) * sm.stat[1][j];
-          const float rx = e.rh[3 * j], ry = e.rh[3 * j + 1], rz = e.rh[3 * j + 2];
+          const float exz = __expf(sc[ii] * isq - mx[ii]) * iz[ii];
+          const float rx = h[3 * ii], ry = h[3 * ii + 1], rz = h[3 * ii + 2];
           const float P = swk * exz, g = rx * kx + ry * ky + rz * kz, dA = da[ii];
-          const float dP = dA * g, dG = dA * P, rho = sm.stat[2][j];
+          const float dP = dA * g, dG = dA * P, rho = rh4[ii];
           A = P * g;
           ds = P * (dP - rho) * isq;
           dsk += exz * (dP - rho);
@@ -775,26 +860,33 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     sm.DY[j * LQA + c] = sm.G2A[j * LQ + c] * (1.f - ta * ta);
   }
   __syncthreads();
-  // dxa = dz Wa^T on MFMA, one tile of 16 edges per wave (B operand: lane l holds
-  // Wa[16 qt + l % 16][4 s + l / 16]); its first 32 columns go to dE/dg2 of the layer
-  // input, the other 64 (with the convolution's term) to the edge's part of dE/dg1_j
+  // dxa = dz Wa^T on MFMA, one tile of 16 edges per wave; k step s of block kb takes
+  // k = 16 kb + 4 (l / 16) + s, so a lane's four B values (Wa[16 qt + l % 16][k]) and A
+  // values (dz[row][k]) are each one 16-byte load.  Its first 32 columns go to dE/dg2 of
+  // the layer input, the other 64 (with the convolution's term) to the edge's part of
+  // dE/dg1_j
   float *dnj = b.dnj + (size_t)(l & 1) * b.cap * SEL * G1D;
   {
     constexpr int QT = (G2D + G1D) / 16;
-    float wt[G2D / 4][QT];
+    float4 wt[2][QT];
 #pragma unroll
-    for (int st = 0; st < G2D / 4; ++st)
+    for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-      for (int qt = 0; qt < QT; ++qt) wt[st][qt] = w.Wa[l][(16 * qt + col) * G2D + 4 * st + kq];
+      for (int qt = 0; qt < QT; ++qt) wt[kb][qt] = ld4(w.Wa[l] + (16 * qt + col) * G2D + 16 * kb + 4 * kq);
     for (int et = wv; et < nkt; et += NWG) {
       const int ra = 16 * et + col;
       const bool aok = ra < nn;
       f4 acc[QT] = {};
 #pragma unroll
-      for (int st = 0; st < G2D / 4; ++st) {
-        const float x = aok ? sm.DY[ra * LQA + 4 * st + kq] : 0.f;
+      for (int kb = 0; kb < 2; ++kb) {
+        const float4 x = aok ? ld4(sm.DY + ra * LQA + 16 * kb + 4 * kq) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int qt = 0; qt < QT; ++qt) acc[qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wt[st][qt], acc[qt], 0, 0, 0);
+        for (int qt = 0; qt < QT; ++qt) {
+          acc[qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, wt[kb][qt].x, acc[qt], 0, 0, 0);
+          acc[qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, wt[kb][qt].y, acc[qt], 0, 0, 0);
+          acc[qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, wt[kb][qt].z, acc[qt], 0, 0, 0);
+          acc[qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, wt[kb][qt].w, acc[qt], 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int qt = 0; qt < QT; ++qt)
@@ -854,7 +946,37 @@ __global__ void __launch_bounds__(1024) k_edge_count(const int *__restrict__ nne
   }
 }
 
+// slot[i][j] = position of i in the list of its j-th neighbour (lists are sorted), or -1.
+__global__ void __launch_bounds__(256) k_rev_slots(const int *__restrict__ nlist, const int *__restrict__ nnei, int n,
+                                                   int *__restrict__ slot) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * SEL) return;
+  const int i = (int)(t / SEL), j = (int)(t % SEL);
+  int s = -1;
+  if (j < min(max(nnei[i], 0), SEL)) {
+    const int nj = nlist[t];
+    if (nj >= 0 && nj < n) {
+      const int len = min(max(nnei[nj], 0), SEL);
+      const int *row = nlist + (size_t)nj * SEL;
+      int lo = 0, hi = len - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = row[mid];
+        if (x == i) { s = mid; break; }
+        if (x < i) lo = mid + 1; else hi = mid - 1;
+      }
+    }
+  }
+  slot[t] = s;
+}
+
 }  // namespace
+
+void launch_rev_slots(const Buffers &b, const Workspace &ws, int n, hipStream_t st) {
+  const int64_t tot = (int64_t)n * SEL;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_rev_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.nlist, ws.nnei, n, b.slot);
+}
 
 void launch_edge_count(const Buffers &b, const Workspace &ws, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_edge_count, dim3(1), dim3(1024), 0, st, ws.nnei, n, b.etot);

@@ -153,7 +153,7 @@ int load_weights(dp_rep *m, const char *path) {
 }
 
 void free_buffers(rep::Buffers &b) {
-  void *ps[] = {b.g1f, b.g2f, b.dg2, b.dnj, b.dnl, b.gs, b.etot};
+  void *ps[] = {b.g1f, b.g2f, b.dg2, b.dnj, b.dnl, b.gs, b.slot, b.etot};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   b = rep::Buffers{};
@@ -163,10 +163,11 @@ int ensure_buffers(rep::Buffers &b, int64_t n) {
   if (!b.etot) R_TRY(hipMalloc(&b.etot, sizeof(int64_t)));
   if (n <= b.cap) return DP_OK;
   const int64_t cap = std::max<int64_t>(n, b.cap + b.cap / 4);
-  void *ps[] = {b.g1f, b.g2f, b.dg2, b.dnj, b.dnl, b.gs};
+  void *ps[] = {b.g1f, b.g2f, b.dg2, b.dnj, b.dnl, b.gs, b.slot};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   b.g1f = b.g2f = b.dg2 = b.dnj = b.dnl = b.gs = nullptr;
+  b.slot = nullptr;
   b.cap = 0;
   const size_t c = (size_t)cap, e = c * SEL;
   R_TRY(hipMalloc(&b.g1f, 2 * c * G1D * sizeof(float)));
@@ -175,6 +176,7 @@ int ensure_buffers(rep::Buffers &b, int64_t n) {
   R_TRY(hipMalloc(&b.dnj, 2 * e * G1D * sizeof(float)));
   R_TRY(hipMalloc(&b.dnl, c * G1D * sizeof(float)));
   R_TRY(hipMalloc(&b.gs, e * rep::GSN * sizeof(float)));
+  R_TRY(hipMalloc(&b.slot, e * sizeof(int)));
   b.cap = cap;
   return DP_OK;
 }
@@ -221,8 +223,10 @@ int rep_step(dp_rep *m, int64_t natoms, const double *X, const int32_t *types, c
   for (int l = 0; l < NLAYER; ++l) rep::launch_layer_fwd(m->w, m->b, ws, X, types, n, l, geo, ws.Ei, st);
   record(m, 2, st);
   const bool bwd = forces || virial;
-  if (bwd)
+  if (bwd) {
+    rep::launch_rev_slots(m->b, ws, n, st);
     for (int l = NLAYER - 1; l >= 0; --l) rep::launch_layer_bwd(m->w, m->b, ws, X, types, n, l, geo, st);
+  }
   record(m, 3, st);
   if (bwd) {
     double *F = forces;
