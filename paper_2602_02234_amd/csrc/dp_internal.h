@@ -243,6 +243,9 @@ void launch_filter(const Workspace &ws, const double *coords, int n, double rc, 
 // For models that need complete lists: turns a truncation (overflow count > 0) into the
 // FLAG_INCOMPLETE error, so that the step's later kernels write nothing.
 void launch_require_complete(const Workspace &ws, hipStream_t st);
+// slot[i][j] (n x SEL) = the position of i in the list of its j-th neighbour, or -1 (also
+// for j past the end of i's list); the lists are sorted, so each is a binary search.
+void launch_rev_slots(const Workspace &ws, int n, int *slot, hipStream_t st);
 void launch_skin_check(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, double lim2,
                        hipStream_t st);
 void launch_skin_ref(const Workspace &ws, const double *coords, int n, hipStream_t st);

@@ -52,6 +52,7 @@ struct Buffers {
   float *dnj = nullptr;       // [2][cap][SEL][64]  edge (i, j)'s part of dE/dn_j, by layer parity
   float *dnl = nullptr;       // [cap][64]          atom i's own part of dE/dn_i
   float *gs = nullptr;        // [cap][SEL][2]      dE/dsw_e, dE/dsw_a per edge over the layers
+  int *slot = nullptr;        // [cap][SEL]         position of i in the list of its j-th neighbour, or -1
 };
 
 struct Geo {

@@ -584,19 +584,7 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
 
   // ---------------- dE/dn_i after this layer: own part + the neighbours' edge parts
   if (!top)
-    for (int j = tid; j < nn; j += NT) {
-      const int nj = e.jn[j];
-      const int len = min(max(nnei[nj], 0), SEL);
-      const int *row = nlist + (size_t)nj * SEL;
-      int lo = 0, hi = len - 1, s = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int x = row[mid];
-        if (x == i) { s = mid; break; }
-        if (x < i) lo = mid + 1; else hi = mid - 1;
-      }
-      sm.slot[j] = s;
-    }
+    for (int j = tid; j < nn; j += NT) sm.slot[j] = b.slot[(size_t)i * SEL + j];
   for (int k = tid; k < nc * ADIM; k += NT) {
     const int p = k >> 5, c = k & 31, j = e.cl[p];
     sm.Ec[k] = l == 0 ? tanhf(e.s[j] * w.We0[c] + w.be0[c]) : b.ef[erow(b, l - 1, i, j) + c];

@@ -161,7 +161,7 @@ int load_weights(dp_gnn *m, const char *path) {
 }
 
 void free_buffers(gnn::Buffers &b) {
-  void *ps[] = {b.aoff, b.nf, b.ef, b.af, b.da, b.de, b.dnj, b.dnl, b.gs};
+  void *ps[] = {b.aoff, b.nf, b.ef, b.af, b.da, b.de, b.dnj, b.dnl, b.gs, b.slot};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   b = gnn::Buffers{};
@@ -170,10 +170,11 @@ void free_buffers(gnn::Buffers &b) {
 int ensure_atoms(gnn::Buffers &b, int64_t n) {
   if (n <= b.cap) return DP_OK;
   const int64_t cap = std::max<int64_t>(n, b.cap + b.cap / 4);
-  void *ps[] = {b.aoff, b.nf, b.ef, b.de, b.dnj, b.dnl, b.gs};
+  void *ps[] = {b.aoff, b.nf, b.ef, b.de, b.dnj, b.dnl, b.gs, b.slot};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   b.aoff = nullptr; b.nf = b.ef = b.de = b.dnj = b.dnl = b.gs = nullptr;
+  b.slot = nullptr;
   b.cap = 0;
   const size_t c = (size_t)cap, e = c * SEL * EDIM;
   G_TRY(hipMalloc(&b.aoff, (c + 3) * sizeof(int64_t)));
@@ -183,6 +184,7 @@ int ensure_atoms(gnn::Buffers &b, int64_t n) {
   G_TRY(hipMalloc(&b.dnj, 2 * e * sizeof(float)));
   G_TRY(hipMalloc(&b.dnl, c * NDIM * sizeof(float)));
   G_TRY(hipMalloc(&b.gs, c * SEL * 2 * sizeof(float)));
+  G_TRY(hipMalloc(&b.slot, c * SEL * sizeof(int)));
   b.cap = cap;
   return DP_OK;
 }
@@ -263,6 +265,7 @@ int gnn_step(dp_gnn *m, int64_t natoms, const double *X, const int32_t *types, c
   }
   if (m->prof) G_TRY(hipEventRecord(m->ev[3], st));
   if (bwd) {
+    launch_rev_slots(ws, n, m->b.slot, st);
     for (int l = NLAYER - 1; l >= 0; --l) {
       if (m->prec == DP_BF16)
         gnn::launch_layer_bwd<bf16_t>(m->w, m->b, ws, X, types, n, l, geo, st);

@@ -380,6 +380,37 @@ void launch_require_complete(const Workspace &ws, hipStream_t st) {
   hipLaunchKernelGGL(k_require_complete, dim3(1), dim3(64), 0, st, ws.flags);
 }
 
+namespace {
+__global__ void __launch_bounds__(256) k_rev_slots(const int *__restrict__ nlist, const int *__restrict__ nnei, int n,
+                                                   int *__restrict__ slot) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * SEL) return;
+  const int i = (int)(t / SEL), j = (int)(t % SEL);
+  int s = -1;
+  if (j < min(max(nnei[i], 0), SEL)) {
+    const int nj = nlist[t];
+    if (nj >= 0 && nj < n) {
+      const int len = min(max(nnei[nj], 0), SEL);
+      const int *row = nlist + (size_t)nj * SEL;
+      int lo = 0, hi = len - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = row[mid];
+        if (x == i) { s = mid; break; }
+        if (x < i) lo = mid + 1; else hi = mid - 1;
+      }
+    }
+  }
+  slot[t] = s;
+}
+}  // namespace
+
+void launch_rev_slots(const Workspace &ws, int n, int *slot, hipStream_t st) {
+  const int64_t tot = (int64_t)n * SEL;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_rev_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.nlist, ws.nnei, n, slot);
+}
+
 void launch_cells(const Workspace &ws, const double *coords, const int *types, int n, int ntypes, bool open_single,
                   int ncells_total, double cell_cutoff, hipStream_t st) {
   if (open_single)

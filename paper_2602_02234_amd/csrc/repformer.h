@@ -55,8 +55,6 @@ struct Geo {
 
 // *b.etot = sum of the list lengths of the n atoms.
 void launch_edge_count(const Buffers &b, const Workspace &ws, int n, hipStream_t st);
-// b.slot of the step's lists (read by the backward layers to gather dE/dg1_j by j).
-void launch_rev_slots(const Buffers &b, const Workspace &ws, int n, hipStream_t st);
 // Layer `layer` (0 .. 2) forward over all n atoms; the last layer also evaluates the
 // fitting net (E_i into Ei) and its gradient dE/dg1 (into dnl).  Layer `layer` backward
 // (called for 2, 1, 0); layer 0 writes g_ij = dE/dDelta_ij into ws.g.

@@ -669,6 +669,8 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     for (int qt = wv; qt < nkt; qt += NWG) {
       const int qme = 16 * qt + col;
       const bool qok = qme < nn;
+      float wq[2][2][4];  // issued first: their latency overlaps the score tiles
+      load_wt(w.Wq[l], wq);
       f4 st[NKT], da[NKT];  // S^T and dA^T = V dY^T: [key 16 kt + 4 kq + ii][query qme]
 #pragma unroll
       for (int kt = 0; kt < NKT; ++kt) {
@@ -758,8 +760,6 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
           }
         }
       }
-      float wq[2][2][4];  // loaded here, not before the score tiles: registers
-      load_wt(w.Wq[l], wq);
       f4 o[2] = {};
       wt_product(o, wq, dq);
       if (qok)
@@ -780,6 +780,9 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     const int kme = 16 * kt + col;
     const bool kok = kme < nn;
     const int kk = kok ? kme : 0;
+    float wk[2][2][4], wvv[2][2][4];  // issued first: their latency overlaps the query tiles
+    load_wt(w.Wk[l], wk);
+    load_wt(w.Wv[l], wvv);
     const float kx = e.rh[3 * kk], ky = e.rh[3 * kk + 1], kz = e.rh[3 * kk + 2], swk = e.sw[kk];
     float dsk = 0.f, h0 = 0.f, h1 = 0.f, h2 = 0.f;
     f4 dv[2] = {}, dk[2] = {};
@@ -837,9 +840,6 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
       sm.EG[kme * GSN + 3] += h1;
       sm.EG[kme * GSN + 4] += h2;
     }
-    float wk[2][2][4], wvv[2][2][4];
-    load_wt(w.Wk[l], wk);
-    load_wt(w.Wv[l], wvv);
     f4 o[2] = {};
     wt_product(o, wvv, dv);
     wt_product(o, wk, dk);
@@ -946,37 +946,7 @@ __global__ void __launch_bounds__(1024) k_edge_count(const int *__restrict__ nne
   }
 }
 
-// slot[i][j] = position of i in the list of its j-th neighbour (lists are sorted), or -1.
-__global__ void __launch_bounds__(256) k_rev_slots(const int *__restrict__ nlist, const int *__restrict__ nnei, int n,
-                                                   int *__restrict__ slot) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)n * SEL) return;
-  const int i = (int)(t / SEL), j = (int)(t % SEL);
-  int s = -1;
-  if (j < min(max(nnei[i], 0), SEL)) {
-    const int nj = nlist[t];
-    if (nj >= 0 && nj < n) {
-      const int len = min(max(nnei[nj], 0), SEL);
-      const int *row = nlist + (size_t)nj * SEL;
-      int lo = 0, hi = len - 1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int x = row[mid];
-        if (x == i) { s = mid; break; }
-        if (x < i) lo = mid + 1; else hi = mid - 1;
-      }
-    }
-  }
-  slot[t] = s;
-}
-
 }  // namespace
-
-void launch_rev_slots(const Buffers &b, const Workspace &ws, int n, hipStream_t st) {
-  const int64_t tot = (int64_t)n * SEL;
-  if (tot == 0) return;
-  hipLaunchKernelGGL(k_rev_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws.nlist, ws.nnei, n, b.slot);
-}
 
 void launch_edge_count(const Buffers &b, const Workspace &ws, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_edge_count, dim3(1), dim3(1024), 0, st, ws.nnei, n, b.etot);

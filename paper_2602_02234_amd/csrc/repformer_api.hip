@@ -224,7 +224,7 @@ int rep_step(dp_rep *m, int64_t natoms, const double *X, const int32_t *types, c
   record(m, 2, st);
   const bool bwd = forces || virial;
   if (bwd) {
-    rep::launch_rev_slots(m->b, ws, n, st);
+    launch_rev_slots(ws, n, m->b.slot, st);
     for (int l = NLAYER - 1; l >= 0; --l) rep::launch_layer_bwd(m->w, m->b, ws, X, types, n, l, geo, st);
   }
   record(m, 3, st);
