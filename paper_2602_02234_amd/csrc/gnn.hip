@@ -388,16 +388,33 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   const int na = nc - 1;  // angles per row p
   const int64_t abase = b.aoff[i];
   // ---------------- angles and messages
+  // A wave takes rows p = wv, wv + NWG, ... and tiles t0 = 0, 16, ... of each; for l > 0
+  // the input a of its next tile is read while the current tile is processed.
+  const int sc4 = ln & 7, sr0 = ln >> 3;  // the lane's float4 column and first row in a staged tile
+  auto tile_in = [&](int p, int t0, float4 (&v)[2]) {
+    const float *ap = b.af + ((size_t)(l - 1) * b.acap + abase + (int64_t)p * na) * ADIM;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = t0 + sr0 + 8 * h;
+      v[h] = t < na ? ld4(ap + (size_t)t * ADIM + 4 * sc4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  float4 nxt[2];
+  if (l > 0 && wv < nc && na > 0) tile_in(wv, 0, nxt);
   for (int p = wv; p < nc; p += NWG) {
     float mr[4] = {0.f, 0.f, 0.f, 0.f};
     const int jp = e.cl[p];
-    const float *ap = b.af + ((size_t)(l > 0 ? l - 1 : 0) * b.acap + abase + (int64_t)p * na) * ADIM;
     for (int t0 = 0; t0 < na; t0 += 16) {
       // a of the tile's 16 angles; the edge terms come from PQ
-      stage<1, 1>(sl, LDF, [&](int, int r, int c4) -> float4 {
+      if (l > 0) {
+        const float4 cur[2] = {nxt[0], nxt[1]};
+        const int pn = t0 + 16 < na ? p : p + NWG, tn = t0 + 16 < na ? t0 + 16 : 0;
+        if (pn < nc) tile_in(pn, tn, nxt);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) *reinterpret_cast<float4 *>(sl + (sr0 + 8 * h) * LDF + 4 * sc4) = cur[h];
+      } else stage<1, 1>(sl, LDF, [&](int, int r, int c4) -> float4 {
         const int t = t0 + r;
         if (t >= na) return make_float4(0.f, 0.f, 0.f, 0.f);
-        if (l > 0) return ld4(ap + (size_t)t * ADIM + 4 * c4);
         const float cs = cosang(e, jp, e.cl[t + (t >= p)]);
         float4 v;
         v.x = tanhf(cs * w.Wa0[4 * c4] + w.ba0[4 * c4]);
