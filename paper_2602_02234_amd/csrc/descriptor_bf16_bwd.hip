@@ -219,8 +219,32 @@ __device__ __forceinline__ void layer_bwd(const Tables &w, const WeightsB16 &wp,
       if (wv + NW * b < nb) load_rows(gs_next, gin[b], wv + NW * b, n);
   }
   __syncthreads();
+  // Token-major copies for the column pass, whose products contract over tokens: U^T into
+  // GbT (free until the next layer's input is put there) and, where the staging area
+  // holds it (seven waves), dH^T there; each wave transposes its own blocks.
+  constexpr bool HT = NW * 16 * LDT >= KM * LDT;
+  bf16_t *UT = sm.GbT, *HTs = &sm.stg[0][0];
+#pragma unroll
+  for (int b = 0; b < BPW; ++b) {
+    const int jb = wv + NW * b;
+    if (jb >= nb) continue;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+      s4 u, h;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int j = jb * 16 + 4 * q + ii;
+        const bf16_t vu = sm.Uall[j * LDK + 16 * t + cl], vh = sm.dHall[j * LDK + 16 * t + cl];
+        u[ii] = *(const short *)&vu;
+        h[ii] = *(const short *)&vh;
+      }
+      *(s4 *)(UT + (16 * t + cl) * LDT + jb * 16 + 4 * q) = u;
+      if constexpr (HT) *(s4 *)(HTs + (16 * t + cl) * LDT + jb * 16 + 4 * q) = h;
+    }
+  }
+  __syncthreads();
   // column pass: dG[k] += sum_j A_jk dH_j + dS_jk U_j for the wave's own token blocks
-  // (kb = wave and wave + NW); the U / dH rows of each block jb are gathered once for both
+  // (kb = wave and wave + NW); the U / dH columns of each block jb are read once for both
   {
     bool has[BPW];
     float swk[BPW], hk[BPW][3];
@@ -267,12 +291,15 @@ __device__ __forceinline__ void layer_bwd(const Tables &w, const WeightsB16 &wp,
 #pragma unroll
         for (int t = 0; t < 7; ++t) {
           const int m = 16 * t + cl;
+          yu[t] = ld4(UT + m * LDT + jb * 16 + 4 * q);
+          if constexpr (HT) {
+            yh[t] = ld4(HTs + m * LDT + jb * 16 + 4 * q);
+          } else {
 #pragma unroll
-          for (int ii = 0; ii < 4; ++ii) {
-            const int j = jb * 16 + 4 * q + ii;
-            const bf16_t vh = sm.dHall[j * LDK + m], vu = sm.Uall[j * LDK + m];
-            yh[t][ii] = *(const short *)&vh;
-            yu[t][ii] = *(const short *)&vu;
+            for (int ii = 0; ii < 4; ++ii) {
+              const bf16_t vh = sm.dHall[(jb * 16 + 4 * q + ii) * LDK + m];
+              yh[t][ii] = *(const short *)&vh;
+            }
           }
         }
 #pragma unroll
