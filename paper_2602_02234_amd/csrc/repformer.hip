@@ -280,44 +280,51 @@ __device__ void node_product(const float *W1, const float *b1, const float *xs, 
 }
 
 // T = sum_j g2_j R_j^T / sel (into T[32][4]), c = sum_j sw_j g2_j g1_j[:32] / sel, and the
-// node-update input xs = [g1i, D, c] with D = T T[:4]^T.  The 160 sums over the
-// neighbours are split into NT / 160 consecutive ranges of j (partials in `part`, at
-// least NT floats), added in range order.  Ends synchronised.
+// node-update input xs = [g1i, D, c] with D = T T[:4]^T.  Waves 0 and 1 form T^T = R^T G2B
+// on MFMA (16x16x4 f32, four neighbours per step, rows a < 4 of the 16 used) over the
+// two halves of j; waves 2 .. 5 split the sums of c into eight ranges of j.  Partials go
+// to `part` (at least 512 floats) and are added in order.  Ends synchronised.
 __device__ void node_inputs(const EnvR &e, int nn, const float *G2B, const float *G1J, const float *g1i,
                             float inv_sel, float *T, float *xs, float *part) {
-  constexpr int NO = G2D * 4 + G2D, NS = NT / NO;
-  const int t = threadIdx.x;
-  if (t < NS * NO) {
-    const int o = t % NO, sg = t / NO;
-    const int j0 = sg * nn / NS, j1 = (sg + 1) * nn / NS;
-    float v0 = 0.f, v1 = 0.f;
-    if (o < G2D * 4) {
-      const int c = o >> 2, a = o & 3;
-      int j = j0;
-      for (; j + 1 < j1; j += 2) {
-        v0 += G2B[j * LQ + c] * Rcomp(e, j, a);
-        v1 += G2B[(j + 1) * LQ + c] * Rcomp(e, j + 1, a);
+  static_assert(NWG >= 6, "node_inputs uses six waves");
+  constexpr int NSEG = 8;
+  const int t = threadIdx.x, wv = wave_id(), ln = lane_id();
+  if (wv < 2) {
+    const int kq = ln >> 4, col = ln & 15;
+    const int j0 = wv * nn / 2, j1 = (wv + 1) * nn / 2;
+    f4 acc[2] = {};
+    for (int jb = j0; jb < j1; jb += 4) {
+      const int j = jb + kq;
+      float ra = 0.f;  // A[a = col][j] = R_j[a]
+      if (j < j1 && col < 4) ra = col == 0 ? e.s[j] : e.s[j] * e.rh[3 * j + col - 1];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const float g = j < j1 ? G2B[j * LQ + 16 * ct + col] : 0.f;
+        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra, g, acc[ct], 0, 0, 0);
       }
-      if (j < j1) v0 += G2B[j * LQ + c] * Rcomp(e, j, a);
-    } else {
-      const int c = o - G2D * 4;
-      int j = j0;
-      for (; j + 1 < j1; j += 2) {
-        v0 += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
-        v1 += e.sw[j + 1] * G2B[(j + 1) * LQ + c] * G1J[(j + 1) * LG + c];
-      }
-      if (j < j1) v0 += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
     }
-    part[t] = v0 + v1;
+    if (kq == 0)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) part[wv * 128 + (16 * ct + col) * 4 + ii] = acc[ct][ii];
+  } else if (wv < 6) {
+    const int u = t - 128, c = u % G2D, sg = u / G2D;
+    const int j0 = sg * nn / NSEG, j1 = (sg + 1) * nn / NSEG;
+    float v = 0.f;
+    for (int j = j0; j < j1; ++j) v += e.sw[j] * G2B[j * LQ + c] * G1J[j * LG + c];
+    part[256 + u] = v;
   }
   __syncthreads();
-  if (t < NO) {
-    float v = part[t];
-    for (int sg = 1; sg < NS; ++sg) v += part[sg * NO + t];
-    if (t < G2D * 4) T[t] = v * inv_sel;
-    else xs[G1D + G2D * NAX + t - G2D * 4] = v * inv_sel;
-  } else if (t < NO + G1D) {
-    xs[t - NO] = g1i[t - NO];
+  if (t < G2D * 4) {
+    T[t] = (part[t] + part[128 + t]) * inv_sel;
+  } else if (t < G2D * 5) {
+    const int c = t - G2D * 4;
+    float v = part[256 + c];
+    for (int sg = 1; sg < NSEG; ++sg) v += part[256 + sg * G2D + c];
+    xs[G1D + G2D * NAX + c] = v * inv_sel;
+  } else if (t >= 256 && t < 256 + G1D) {
+    xs[t - 256] = g1i[t - 256];
   }
   __syncthreads();
   if (t < G2D * NAX) {
@@ -637,20 +644,43 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
   }
   __syncthreads();
   const float *dc = sm.dxn + G1D + G2D * NAX;  // dE/dc (times sel: divided where used)
-  // dE/dg2 of the output from the contraction and the convolution; edge terms of R and sw
+  // dE/dg2 of the output from the contraction and the convolution; edge terms of R and sw.
+  // dR = G2B dT runs on MFMA, one tile of 16 edges per wave (B operand dT[c][a], columns
+  // a < 4 of the 16 used), into part[4 j + a].
+  {
+    const int kq = ln >> 4, col = ln & 15, net = (nn + 15) >> 4;
+    float bv[G2D / 4];
+#pragma unroll
+    for (int st = 0; st < G2D / 4; ++st) bv[st] = col < 4 ? sm.dT[(4 * st + kq) * 4 + col] : 0.f;
+    float *dRs = &sm.part[0][0];
+    for (int et = wv; et < net; et += NWG) {
+      const int ra = 16 * et + col;
+      f4 acc = {};
+#pragma unroll
+      for (int st = 0; st < G2D / 4; ++st) {
+        const float x = ra < nn ? sm.G2B[ra * LQ + 4 * st + kq] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[st], acc, 0, 0, 0);
+      }
+      if (col < 4)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = 16 * et + 4 * kq + ii;
+          if (j < nn) dRs[4 * j + col] = acc[ii];
+        }
+    }
+  }
   for (int o = tid; o < nn * G2D; o += NT) {
     const int j = o >> 5, c = o & 31;
     float v = sm.DY[j * LQA + c] + e.sw[j] * dc[c] * geo.inv_sel * sm.G1J[j * LG + c];
     for (int a = 0; a < 4; ++a) v += sm.dT[c * 4 + a] * Rcomp(e, j, a);
     sm.DY[j * LQA + c] = v;
   }
+  __syncthreads();
   for (int j = tid; j < nn; j += NT) {
-    float dR[4] = {0.f, 0.f, 0.f, 0.f}, dswc = 0.f;
-    for (int c = 0; c < G2D; ++c) {
-      const float g = sm.G2B[j * LQ + c];
-      for (int a = 0; a < 4; ++a) dR[a] += sm.dT[c * 4 + a] * g;
-      dswc += dc[c] * geo.inv_sel * g * sm.G1J[j * LG + c];
-    }
+    const float *dR = &sm.part[0][0] + 4 * j;
+    float dswc = 0.f;
+#pragma unroll 8
+    for (int c = 0; c < G2D; ++c) dswc += dc[c] * geo.inv_sel * sm.G2B[j * LQ + c] * sm.G1J[j * LG + c];
     float *eg = sm.EG + j * GSN;
     eg[0] += dR[0] + dR[1] * e.rh[3 * j] + dR[2] * e.rh[3 * j + 1] + dR[3] * e.rh[3 * j + 2];
     eg[1] += dswc;
