@@ -7,8 +7,9 @@
 // neighbours, width 32) over tiles of 16 queries in the forward and the backward's row
 // pass (statistics, dQ, the row terms of the gate), and tiles of 16 keys in the column
 // pass (dK, dV, the key terms of the switch and gate, with the scores recomputed).
-// The node update (input 224) and the contraction stay float32 VALU work.  Every sum
-// has one owner and a fixed order: results are deterministic.
+// The contraction T = sum_j g2_j R_j^T and its gradient also run on MFMA; the node
+// update (input 224) and the convolution sums stay float32 VALU work.  Every sum has
+// one owner and a fixed order: results are deterministic.
 #include <cmath>
 
 #include "dp_env.h"
@@ -260,9 +261,9 @@ __device__ void pair_and_qkv(const Weights &w, int l, int nn, float *G2, const f
   __syncthreads();
 }
 
-// One column of the node update's product z_c = b1_c + xs . W1[:, c], split over the four
-// waves (wave u sums the inputs u*56 .. u*56+55, in order) and combined in wave order;
-// the result is in zc[c] for c < 64.  Ends synchronised.
+// One column of the node update's product z_c = b1_c + xs . W1[:, c], split over the
+// waves (wave u sums the XD / NWG consecutive inputs from u XD / NWG, in order) and
+// combined in wave order; the result is in zc[c] for c < 64.  Ends synchronised.
 __device__ void node_product(const float *W1, const float *b1, const float *xs, float (*part)[G1D], float *zc) {
   const int c = threadIdx.x & 63, u = threadIdx.x >> 6;
   constexpr int QW = XD / NWG;
