@@ -151,6 +151,22 @@ __device__ __forceinline__ f4 mma16(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
 }
 
+// Two 16x16x16 products summed into one accumulator, c + a0 b0 + a1 b1, through one
+// 16x16x32 instruction: lane group q places k = 4q + i of the first product at
+// k' = 8q + i and of the second at k' = 8q + 4 + i, so no half of either operand is zero.
+__device__ __forceinline__ f4 mma16x2(s4 a0, s4 b0, s4 a1, s4 b1, f4 c) {
+  bf8 x, y;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const short u0 = a0[i], v0 = b0[i], u1 = a1[i], v1 = b1[i];
+    x[i] = *(const __bf16 *)&u0;
+    y[i] = *(const __bf16 *)&v0;
+    x[i + 4] = *(const __bf16 *)&u1;
+    y[i + 4] = *(const __bf16 *)&v1;
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+}
+
 // acc[t] += A(16 x K) . B_t(16 x K)^T for t < nt; A rows at a (stride lda); B_t rows
 // at b + 16 t ldb (stride ldb); K a multiple of 16; operands bf16, k contiguous.
 template <int NT>

@@ -342,8 +342,7 @@ __device__ __forceinline__ void layer_bwd(const Tables &w, const WeightsB16 &wp,
           }
 #pragma unroll
           for (int t = 0; t < 7; ++t) {
-            cacc[b][t] = mma16(xa, yh[t], cacc[b][t]);
-            cacc[b][t] = mma16(xs, yu[t], cacc[b][t]);
+            cacc[b][t] = mma16x2(xa, yh[t], xs, yu[t], cacc[b][t]);  // A^T dH + dS^T U
           }
         }
       }

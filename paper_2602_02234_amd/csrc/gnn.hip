@@ -119,6 +119,10 @@ __device__ __forceinline__ void opaque() { asm volatile("" ::: "memory"); }
 struct Ident {
   __device__ __forceinline__ int operator()(int k) const { return k; }
 };
+struct Shift {  // operands at slab columns from `s` on
+  int s;
+  __device__ __forceinline__ int operator()(int k) const { return s + k; }
+};
 
 struct GEnv {
   float r[SEL], swe[SEL], dswe[SEL], swa[SEL], dswa[SEL], s[SEL];
@@ -388,32 +392,36 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
   const int na = nc - 1;  // angles per row p
   const int64_t abase = b.aoff[i];
   // ---------------- angles and messages
-  // A wave takes rows p = wv, wv + NWG, ... and tiles t0 = 0, 16, ... of each; for l > 0
-  // the input a of its next tile is read while the current tile is processed.
+  // A wave takes rows p = wv, wv + NWG, ... and the angles of each in pairs of tiles of
+  // 16 (t0 .. t0 + 15 at slab columns 0 .. 31, t0 + 16 .. t0 + 31 at columns 32 .. 63),
+  // whose product chains are independent and interleave; for l > 0 the input a of its
+  // next pair is read while the current pair is processed.
   const int sc4 = ln & 7, sr0 = ln >> 3;  // the lane's float4 column and first row in a staged tile
-  auto tile_in = [&](int p, int t0, float4 (&v)[2]) {
+  auto pair_in = [&](int p, int t0, float4 (&v)[4]) {
     const float *ap = b.af + ((size_t)(l - 1) * b.acap + abase + (int64_t)p * na) * ADIM;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int t = t0 + sr0 + 8 * h;
+    for (int h = 0; h < 4; ++h) {
+      const int t = t0 + 16 * (h >> 1) + sr0 + 8 * (h & 1);
       v[h] = t < na ? ld4(ap + (size_t)t * ADIM + 4 * sc4) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  float4 nxt[2];
-  if (l > 0 && wv < nc && na > 0) tile_in(wv, 0, nxt);
+  const Shift second{ADIM};
+  float4 nxt[4];
+  if (l > 0 && wv < nc && na > 0) pair_in(wv, 0, nxt);
   for (int p = wv; p < nc; p += NWG) {
     float mr[4] = {0.f, 0.f, 0.f, 0.f};
     const int jp = e.cl[p];
-    for (int t0 = 0; t0 < na; t0 += 16) {
-      // a of the tile's 16 angles; the edge terms come from PQ
+    for (int t0 = 0; t0 < na; t0 += 32) {
+      // a of the pair's 32 angles; the edge terms come from PQ
       if (l > 0) {
-        const float4 cur[2] = {nxt[0], nxt[1]};
-        const int pn = t0 + 16 < na ? p : p + NWG, tn = t0 + 16 < na ? t0 + 16 : 0;
-        if (pn < nc) tile_in(pn, tn, nxt);
+        const float4 cur[4] = {nxt[0], nxt[1], nxt[2], nxt[3]};
+        const int pn = t0 + 32 < na ? p : p + NWG, tn = t0 + 32 < na ? t0 + 32 : 0;
+        if (pn < nc) pair_in(pn, tn, nxt);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) *reinterpret_cast<float4 *>(sl + (sr0 + 8 * h) * LDF + 4 * sc4) = cur[h];
-      } else stage<1, 1>(sl, LDF, [&](int, int r, int c4) -> float4 {
-        const int t = t0 + r;
+        for (int h = 0; h < 4; ++h)
+          *reinterpret_cast<float4 *>(sl + (sr0 + 8 * (h & 1)) * LDF + ADIM * (h >> 1) + 4 * sc4) = cur[h];
+      } else stage<2, 2>(sl, LDF, [&](int sg, int r, int c4) -> float4 {
+        const int t = t0 + 16 * sg + r;
         if (t >= na) return make_float4(0.f, 0.f, 0.f, 0.f);
         const float cs = cosang(e, jp, e.cl[t + (t >= p)]);
         float4 v;
@@ -424,40 +432,52 @@ __global__ void __launch_bounds__(NT) k_layer_fwd(Weights w, Buffers b, const do
         return v;
       });
       wave_sync();
-      int qrow[4];
+      int qrow[2][4];
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int t = t0 + acc_row(ii);
-        qrow[ii] = t < na ? t + (t >= p) : p;  // rows past the end read a valid row, and are not used
-      }
-      f4 aa[2] = {};
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) fa[ct].mma(aa[ct], rowA, Ident());
-      wave_sync();
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
-          const int r = acc_row(ii), c = ct * 16 + acc_col(), t = t0 + r;
-          const float z = aa[ct][ii] + baa[c] + sm.PQ[p * PQW + c] + sm.PQ[qrow[ii] * PQW + ADIM + c];
-          const float a1 = sl[r * LDF + c] + act<T>(z);
-          sl[r * LDF + c] = a1;
-          if (t < na) b.af[((size_t)l * b.acap + abase + (int64_t)p * na + t) * ADIM + c] = a1;
+          const int t = t0 + 16 * h + acc_row(ii);
+          qrow[h][ii] = t < na ? t + (t >= p) : p;  // rows past the end read a valid row, and are not used
         }
-      wave_sync();
-      f4 am[4] = {};
+      f4 aa[2][2] = {};
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) fm[ct].mma(am[ct], rowA, Ident());
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int t = t0 + acc_row(ii);
-        const float wr = t < na ? e.swa[jp] * e.swa[e.cl[qrow[ii]]] * geo.inv_asel : 0.f;
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-          const int c = ct * 16 + acc_col();
-          mr[ct] += wr * act<T>(am[ct][ii] + bea[c] + sm.PQ[qrow[ii] * PQW + 2 * ADIM + c]);
-        }
+      for (int ct = 0; ct < 2; ++ct) {
+        fa[ct].mma(aa[0][ct], rowA, Ident());
+        fa[ct].mma(aa[1][ct], rowA, second);
       }
+      wave_sync();
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int r = acc_row(ii), c = ct * 16 + acc_col(), t = t0 + 16 * h + r;
+            const float z = aa[h][ct][ii] + baa[c] + sm.PQ[p * PQW + c] + sm.PQ[qrow[h][ii] * PQW + ADIM + c];
+            const float a1 = sl[r * LDF + ADIM * h + c] + act<T>(z);
+            sl[r * LDF + ADIM * h + c] = a1;
+            if (t < na) b.af[((size_t)l * b.acap + abase + (int64_t)p * na + t) * ADIM + c] = a1;
+          }
+      wave_sync();
+      f4 am[2][4] = {};
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        fm[ct].mma(am[0][ct], rowA, Ident());
+        fm[ct].mma(am[1][ct], rowA, second);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int t = t0 + 16 * h + acc_row(ii);
+          const float wr = t < na ? e.swa[jp] * e.swa[e.cl[qrow[h][ii]]] * geo.inv_asel : 0.f;
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            const int c = ct * 16 + acc_col();
+            mr[ct] += wr * act<T>(am[h][ct][ii] + bea[c] + sm.PQ[qrow[h][ii] * PQW + 2 * ADIM + c]);
+          }
+        }
       wave_sync();
     }
 #pragma unroll
