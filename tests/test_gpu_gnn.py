@@ -143,6 +143,44 @@ def test_gnn_deterministic_and_reuse(torch_cuda, gnn_models, ognn):
     assert np.array_equal(a["virial"], b["virial"])
 
 
+def _ball(n, R, dmin, seed):
+    """n atoms uniform in a ball of radius R, at least dmin apart (every pair within 2R)."""
+    rng = np.random.default_rng(seed)
+    X = []
+    while len(X) < n:
+        p = rng.normal(size=3)
+        p *= R * rng.uniform() ** (1.0 / 3.0) / np.linalg.norm(p)
+        if all(np.linalg.norm(p - q) > dmin for q in X):
+            X.append(p)
+    return np.array(X), rng.integers(0, 5, size=n).astype(np.int32)
+
+
+_BALL = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gnn_full_lists(gnn_models, ognn, prec):
+    """121 atoms in a ball of radius 2.95 A: every atom has the other 120 within rc (sel)
+    and asel = 48 angle neighbours, so its angle rows hold 47 angles (a pair of full
+    tiles and a pair with one partial tile) and every edge tile is full.  The forces are
+    larger than in water (RMS about 10 eV/A against about 1), and rounding scales with
+    them, so the metrics are taken relative to the oracle's force RMS (compare's
+    `scale`)."""
+    if not _BALL:
+        X, t = _ball(121, 2.95, 0.8, 5)
+        _BALL["sys"] = (X, t)
+        _BALL["ref"] = evaluate(ognn, X, t, None)
+    X, t = _BALL["sys"]
+    ref = _BALL["ref"]
+    assert ref["n_angles"] == 121 * 48 * 47
+    out = gnn_models[prec].compute(X, t, None, forces=True, atom_energy=True)
+    assert gnn_models[prec].graph_size()[0] == 121 * 120
+    scale = max(1.0, float(np.sqrt(np.mean(ref["F"] ** 2))))
+    m = compare(out, ref, len(X), scale=scale)
+    print(f"GNN ball121 {prec} (force RMS {scale:.3g} eV/A): {m}")
+    assert_within_gnn(m, prec)
+
+
 def test_gnn_energy_only_and_errors(torch_cuda, gnn_models):
     torch = torch_cuda
     from paper_2602_02234_amd import DPError

@@ -113,6 +113,35 @@ def test_repformer_chain40k(torch_cuda, rep_model, orep):
         assert abs(Ei[i] - e_ref) <= tol["e_atom"]
 
 
+def _ball(n, R, dmin, seed):
+    """n atoms uniform in a ball of radius R, at least dmin apart (every pair within 2R)."""
+    rng = np.random.default_rng(seed)
+    X = []
+    while len(X) < n:
+        p = rng.normal(size=3)
+        p *= R * rng.uniform() ** (1.0 / 3.0) / np.linalg.norm(p)
+        if all(np.linalg.norm(p - q) > dmin for q in X):
+            X.append(p)
+    return np.array(X), rng.integers(0, 5, size=n).astype(np.int32)
+
+
+def test_repformer_full_tiles(rep_model, orep):
+    """121 atoms in a ball of radius 2.95 A: every atom has the other 120 within rc, exactly
+    sel, so every atom's lists are complete and its attention runs on all eight tiles of
+    16 (the last one half padded).  The forces are larger than in water (RMS about
+    39 eV/A against about 1), and float32 rounding scales with them, so the metrics are
+    taken relative to the oracle's force RMS (compare's `scale`)."""
+    X, t = _ball(121, 2.95, 0.8, 5)
+    ref = evaluate(orep, X, t, None)
+    assert int(ref["nnei"].min()) == 120
+    out = rep_model.compute(X, t, None, forces=True, atom_energy=True)
+    assert rep_model.edges() == 121 * 120
+    scale = max(1.0, float(np.sqrt(np.mean(ref["F"] ** 2))))
+    m = compare(out, ref, len(X), scale=scale)
+    print(f"repformer ball121 (force RMS {scale:.3g} eV/A): {m}")
+    _check(m, TOL_REP["fp32"])
+
+
 def test_repformer_deterministic_and_reuse(rep_model):
     X, t, box = SYSTEMS["water192"]
     a = rep_model.compute(X, t, box, atom_energy=True)
