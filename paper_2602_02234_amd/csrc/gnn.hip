@@ -634,9 +634,13 @@ __global__ void __launch_bounds__(NT) k_layer_bwd(Weights w, Buffers b, const do
     // parts of dE/dn_i, and agg from the stored output edges); waves combine in order
     float dn = 0.f, agg = 0.f;
     const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * EDIM;
-#pragma unroll 4
+#pragma unroll 8
     for (int j = wv; j < nn; j += NWG) {
-      if (!top && sm.slot[j] >= 0) dn += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * EDIM + ln];
+      if (!top) {  // branch-free in j (a missing slot reads row 0 and adds 0), so the loads overlap
+        const int sj = sm.slot[j];
+        const float x = src[((size_t)e.jn[j] * SEL + max(sj, 0)) * EDIM + ln];
+        dn += sj >= 0 ? x : 0.f;
+      }
       agg += e.swe[j] * b.ef[erow(b, l, i, j) + ln];
     }
     sm.dnsum[wv][ln] = dn;

@@ -33,16 +33,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly sum / max over the 64 lanes: the same value in every lane.
-__device__ __forceinline__ float wsum(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ __forceinline__ float wmax(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
-}
-
 // tanh and exp of the hot loops from the hardware exponential and reciprocal
 // (absolute error a few 1e-8 for tanh; relative a few 1e-7 for the softmax weights).
 __device__ __forceinline__ float ftanh(float x) {
@@ -115,9 +105,6 @@ __device__ void build_env_r(EnvR &e, const double *__restrict__ X, const int *__
   __syncthreads();
 }
 
-__device__ __forceinline__ float gate(const EnvR &e, int j, int k) {
-  return e.rh[3 * j] * e.rh[3 * k] + e.rh[3 * j + 1] * e.rh[3 * k + 1] + e.rh[3 * j + 2] * e.rh[3 * k + 2];
-}
 __device__ __forceinline__ float Rcomp(const EnvR &e, int j, int a) { return a == 0 ? e.s[j] : e.s[j] * e.rh[3 * j + a - 1]; }
 
 __device__ __forceinline__ size_t erow2(const Buffers &b, int l, int i, int j) {
@@ -605,9 +592,12 @@ __global__ void __launch_bounds__(NT) k_rep_bwd(Weights w, Buffers b, const doub
     float v = 0.f;
     if (!top) {
       const float *src = b.dnj + (size_t)((l + 1) & 1) * b.cap * SEL * G1D;
-#pragma unroll 4
-      for (int j = wv; j < nn; j += NWG)
-        if (sm.slot[j] >= 0) v += src[((size_t)e.jn[j] * SEL + sm.slot[j]) * G1D + ln];
+#pragma unroll 8
+      for (int j = wv; j < nn; j += NWG) {  // branch-free (a missing slot reads row 0 and adds 0), so the loads overlap
+        const int sj = sm.slot[j];
+        const float x = src[((size_t)e.jn[j] * SEL + max(sj, 0)) * G1D + ln];
+        v += sj >= 0 ? x : 0.f;
+      }
     }
     sm.part[wv][ln] = v;
   }
