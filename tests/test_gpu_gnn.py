@@ -158,26 +158,27 @@ def _ball(n, R, dmin, seed):
 _BALL = {}
 
 
+@pytest.mark.parametrize("n", [17, 33, 121])
 @pytest.mark.parametrize("prec", PRECS)
-def test_gnn_full_lists(gnn_models, ognn, prec):
-    """121 atoms in a ball of radius 2.95 A: every atom has the other 120 within rc (sel)
-    and asel = 48 angle neighbours, so its angle rows hold 47 angles (a pair of full
-    tiles and a pair with one partial tile) and every edge tile is full.  The forces are
-    larger than in water (RMS about 10 eV/A against about 1), and rounding scales with
-    them, so the metrics are taken relative to the oracle's force RMS (compare's
-    `scale`)."""
-    if not _BALL:
-        X, t = _ball(121, 2.95, 0.8, 5)
-        _BALL["sys"] = (X, t)
-        _BALL["ref"] = evaluate(ognn, X, t, None)
-    X, t = _BALL["sys"]
-    ref = _BALL["ref"]
-    assert ref["n_angles"] == 121 * 48 * 47
+def test_gnn_full_lists(gnn_models, ognn, prec, n):
+    """n atoms in a ball of radius 2.95 A: every atom has the other n - 1 within rc, so
+    its edge tiles are exactly one (n = 17) or two (33) full tiles of 16, or all eight
+    (121: exactly sel neighbours, with asel = 48 angle neighbours, so the angle rows of
+    47 fill a pair of tiles and half of the next).  The forces are larger than in water
+    (RMS up to about 10 eV/A against about 1), and rounding scales with them, so the
+    metrics are taken relative to the oracle's force RMS (compare's `scale`)."""
+    if n not in _BALL:
+        X, t = _ball(n, 2.95, 0.8, 5)
+        _BALL[n] = (X, t, evaluate(ognn, X, t, None))
+    X, t, ref = _BALL[n]
+    if n == 121:
+        assert ref["n_angles"] == 121 * 48 * 47
     out = gnn_models[prec].compute(X, t, None, forces=True, atom_energy=True)
-    assert gnn_models[prec].graph_size()[0] == 121 * 120
+    assert gnn_models[prec].graph_size()[0] == n * (n - 1)
+    assert gnn_models[prec].graph_size()[2] == ref["n_angles"]
     scale = max(1.0, float(np.sqrt(np.mean(ref["F"] ** 2))))
     m = compare(out, ref, len(X), scale=scale)
-    print(f"GNN ball121 {prec} (force RMS {scale:.3g} eV/A): {m}")
+    print(f"GNN ball{n} {prec} (force RMS {scale:.3g} eV/A, {ref['n_angles']} angles): {m}")
     assert_within_gnn(m, prec)
 
 

@@ -125,20 +125,22 @@ def _ball(n, R, dmin, seed):
     return np.array(X), rng.integers(0, 5, size=n).astype(np.int32)
 
 
-def test_repformer_full_tiles(rep_model, orep):
-    """121 atoms in a ball of radius 2.95 A: every atom has the other 120 within rc, exactly
-    sel, so every atom's lists are complete and its attention runs on all eight tiles of
-    16 (the last one half padded).  The forces are larger than in water (RMS about
-    39 eV/A against about 1), and float32 rounding scales with them, so the metrics are
-    taken relative to the oracle's force RMS (compare's `scale`)."""
-    X, t = _ball(121, 2.95, 0.8, 5)
+@pytest.mark.parametrize("n", [17, 33, 121])
+def test_repformer_full_tiles(rep_model, orep, n):
+    """n atoms in a ball of radius 2.95 A: every atom has the other n - 1 within rc, so
+    its attention runs on exactly one (n = 17) or two (33) full tiles of 16, or on all
+    eight (121: exactly sel neighbours, the last tile half padded).  The forces are
+    larger than in water (RMS up to about 39 eV/A against about 1), and float32
+    rounding scales with them, so the metrics are taken relative to the oracle's force
+    RMS (compare's `scale`)."""
+    X, t = _ball(n, 2.95, 0.8, 5)
     ref = evaluate(orep, X, t, None)
-    assert int(ref["nnei"].min()) == 120
+    assert int(ref["nnei"].min()) == n - 1
     out = rep_model.compute(X, t, None, forces=True, atom_energy=True)
-    assert rep_model.edges() == 121 * 120
+    assert rep_model.edges() == n * (n - 1)
     scale = max(1.0, float(np.sqrt(np.mean(ref["F"] ** 2))))
     m = compare(out, ref, len(X), scale=scale)
-    print(f"repformer ball121 (force RMS {scale:.3g} eV/A): {m}")
+    print(f"repformer ball{n} (force RMS {scale:.3g} eV/A): {m}")
     _check(m, TOL_REP["fp32"])
 
 
